@@ -1,0 +1,238 @@
+"""Pins of the oracle's workflows (conventional, fKK-EC, ML:fKK-EC) against
+identities the paper's derivation fixes and physical closed forms."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators as op
+from oracle import workflows as wf
+
+LINEAR = dict(detrend=op.DETREND_WHITTAKER, als_lambda=1e4, ridge_rel=0.0)
+
+
+def _small_cube(m_side=24, n=256, key=11):
+    return synth.tissue_cube(rows=m_side, cols=m_side, n=n, map_key=key, noise_key=key,
+                             blur=3.0, dtype=np.float64)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+# --------------------------------------------------------------------------
+# Factorisation (Eq. 6)
+# --------------------------------------------------------------------------
+
+def test_svd_routes_agree_and_full_rank_reconstructs():
+    cube = _small_cube()
+    ell, _ = wf.log_ratio(cube.i_cars, cube.i_ref, 1e-6)
+    u1, s1, v1 = wf.truncated_svd(ell, 8, "gesdd")
+    u2, s2, v2 = wf.truncated_svd(ell, 8, "gram")
+    np.testing.assert_allclose(s1, s2, rtol=1e-10)
+    # principal angles between the two 8-dim subspaces
+    # distance between the two 8-dim subspaces (projector difference)
+    assert np.linalg.norm(v1 @ v1.T - v2 @ v2.T, 2) < 1e-9
+    # sign convention: largest-magnitude entry of each v positive
+    idx = np.argmax(np.abs(v1), axis=0)
+    assert np.all(v1[idx, np.arange(8)] > 0)
+    n = ell.shape[1]
+    u, s, v = wf.truncated_svd(ell, n, "gesdd")
+    np.testing.assert_allclose((u * s) @ v.T, ell, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Factorisation identity: with a linear detrender and unregularised
+# regression, fKK-EC on k vectors equals the conventional workflow on the
+# rank-k log ratio (Eq. 7, 12, 16-18, 21-23 chained); at full rank it is the
+# conventional workflow itself.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sec_mode", [op.SEC_SAVGOL, op.SEC_MEAN])
+def test_factorised_equals_conventional_on_rank_k_data(sec_mode):
+    cube = _small_cube()
+    p = wf.Params(k=6, sec_mode=sec_mode, **LINEAR)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    b = res["basis"]
+    assert len(b["q"]) >= p.k
+    ell_k = res["z"] @ b["v"].T / b["f"]            # rank-k log ratio
+    i_k = cube.i_ref * np.exp(2.0 * ell_k)
+    ref = wf.plain(i_k, cube.i_ref, p)
+    for key in ("im", "re", "abs"):
+        assert _rel(res[key], ref[key]) < 1e-11
+
+
+def test_factorised_equals_conventional_at_full_rank_with_noise_scaling():
+    cube = _small_cube(m_side=16, n=64, key=12)
+    p = wf.Params(k=64, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
+                  sg_window=21, **LINEAR)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    assert not np.allclose(res["basis"]["f"], res["basis"]["f"][0])
+    ref = wf.plain(cube.i_cars, cube.i_ref, p)
+    assert _rel(res["im"], ref["im"]) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# NRB-only inputs (spec closed form): no Raman signal -> zero output.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("detrend", [op.DETREND_ALS, op.DETREND_WHITTAKER])
+def test_nrb_only_returns_zero(detrend):
+    w = synth.wavenumbers(200)
+    ref = synth.reference(w)
+    cube = np.tile(ref, (50, 1))
+    p = wf.Params(k=5, detrend=detrend, als_lambda=1e4)
+    assert np.abs(wf.fit(cube, ref, p)["im"]).max() == 0.0
+    assert np.abs(wf.plain(cube, ref, p)["im"]).max() < 1e-15
+
+
+def test_nrb_only_with_surrogate_error_is_small():
+    # I = I_NRB but I_ref = Xi xi(w) I_NRB: only the smooth phase error
+    # remains, which PEC removes up to the detrender's fit error.
+    w = synth.wavenumbers(400)
+    env = synth.envelope(w)
+    ref = synth.reference(w)
+    cube = np.tile(env, (40, 1)) * np.linspace(0.9, 1.1, 40)[:, None]
+    p = wf.Params(k=3)
+    no_pec = np.sin(op.hilbert(0.5 * np.log(env / ref)))
+    assert np.abs(no_pec).max() > 0.2
+    assert np.abs(wf.plain(cube, ref, p)["im"]).max() < 0.02
+    assert np.abs(wf.fit(cube, ref, p)["im"]).max() < 0.02
+
+
+# --------------------------------------------------------------------------
+# Physics: retrieval of the known Im{chi/chi_nr}.
+# --------------------------------------------------------------------------
+
+def _mixture(n=1000, m=100, xi_slope=0.2, key=13):
+    w = synth.wavenumbers(n)
+    chi = synth.components(n, 3, key=key)
+    ab = synth.rng_for(key, 99).dirichlet(np.ones(3), m)
+    chi_r = ab @ chi
+    env = synth.envelope(w)
+    i_cars = np.abs(chi_r + 1.0) ** 2 * env
+    ref = synth.reference(w, 1.1, xi_slope)
+    return i_cars, ref, chi_r.imag
+
+
+def _kk_floor(i_cars, ideal):
+    """RSS of KK alone with the exact reference: the discretisation floor of
+    a Hilbert transform over a finite window (Sec. 2.1)."""
+    w = synth.wavenumbers(i_cars.shape[1])
+    ell, _ = wf.log_ratio(i_cars, synth.envelope(w), 1e-6)
+    kk = np.exp(ell) * np.sin(op.hilbert(ell))
+    return ((kk - ideal) ** 2).sum(axis=1).mean()
+
+
+def test_conventional_retrieves_raman_with_surrogate_reference():
+    # RSS against the known Im{chi/chi_nr} (the paper's metric, Sec. 4.1).
+    i_cars, ref, ideal = _mixture()
+    p = wf.Params(k=20)
+    out = wf.plain(i_cars, ref, p)["im"]
+    rss = ((out - ideal) ** 2).sum(axis=1).mean()
+    null = (ideal ** 2).sum(axis=1).mean()
+    assert _kk_floor(i_cars, ideal) < 0.01 * null
+    assert rss < 0.04 * null
+    # without PEC/SEC (KK alone) the error is much larger
+    ell, _ = wf.log_ratio(i_cars, ref, 1e-6)
+    kk_only = np.exp(ell) * np.sin(op.hilbert(ell))
+    assert ((kk_only - ideal) ** 2).sum(axis=1).mean() > 5 * rss
+
+
+def test_factorised_close_to_conventional_and_ideal():
+    # Sec. 4.1: similar RSS, the factorised one slightly lower.
+    i_cars, ref, ideal = _mixture()
+    p = wf.Params(k=20)
+    fk = wf.fit(i_cars, ref, p)["im"]
+    cv = wf.plain(i_cars, ref, p)["im"]
+    null = (ideal ** 2).sum(axis=1).mean()
+    rss_f = ((fk - ideal) ** 2).sum(axis=1).mean()
+    rss_c = ((cv - ideal) ** 2).sum(axis=1).mean()
+    assert rss_f < 0.04 * null and rss_c < 0.04 * null
+    assert rss_f <= 1.05 * rss_c
+
+
+def test_constant_nrb_agreement():
+    # Sec. 4.1: with constant NRBs (xi = 1) the ideal, conventional and
+    # factorised results agree.  Over a finite window they agree with the
+    # ideal only down to the KK discretisation floor; with each other, far
+    # below it.
+    i_cars, ref, ideal = _mixture(xi_slope=0.0)
+    p = wf.Params(k=40)
+    fk = wf.fit(i_cars, ref, p)["im"]
+    cv = wf.plain(i_cars, ref, p)["im"]
+    floor = _kk_floor(i_cars, ideal)
+    for out in (fk, cv):
+        assert ((out - ideal) ** 2).sum(axis=1).mean() < 2.0 * floor
+    assert ((fk - cv) ** 2).sum(axis=1).mean() < 0.05 * floor
+
+
+# --------------------------------------------------------------------------
+# SEC invariant, ML reuse, symmetries.
+# --------------------------------------------------------------------------
+
+def test_sec_mean_mode_zeroes_mean_log_magnitude():
+    cube = _small_cube(key=14)
+    p = wf.Params(k=8, sec_mode=op.SEC_MEAN, als_lambda=1e4)
+    for res in (wf.fit(cube.i_cars, cube.i_ref, p), wf.plain(cube.i_cars, cube.i_ref, p)):
+        assert np.abs(np.log(res["abs"]).mean(axis=1)).max() < 1e-13
+
+
+def test_ml_transform_of_training_data_equals_fit():
+    cube = _small_cube(key=15)
+    p = wf.Params(k=10, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g, als_lambda=1e4)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    tr = wf.transform(cube.i_cars, res["basis"])
+    assert _rel(tr["im"], res["im"]) < 1e-10
+    # ridge in the regression shrinks Z by s^2/(s^2+lam) (Eq. 25 push-through)
+    b = dict(res["basis"], ml_lambda=float(res["basis"]["s"][-1] ** 2))
+    z = wf.regress_z(cube.i_cars, b)
+    shrink = b["s"] ** 2 / (b["s"] ** 2 + b["ml_lambda"])
+    np.testing.assert_allclose(z, res["z"] * shrink, atol=1e-10 * np.abs(res["z"]).max())
+
+
+def test_scale_of_f_cancels():
+    cube = _small_cube(key=16)
+    p = wf.Params(k=8, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g, als_lambda=1e4)
+    a = wf.fit(cube.i_cars, cube.i_ref, p)
+    c = 7.0  # f(alpha / c^2, sigma / c) = c f
+    b = wf.fit(cube.i_cars, cube.i_ref, p.with_(alpha=cube.alpha / c ** 2, sigma_g=cube.sigma_g / c))
+    np.testing.assert_allclose(b["basis"]["f"], c * a["basis"]["f"], rtol=1e-12)
+    assert _rel(b["im"], a["im"]) < 1e-9
+
+
+def test_singular_vector_sign_flip_invariance():
+    cube = _small_cube(key=17)
+    p = wf.Params(k=8, als_lambda=1e4)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    b = res["basis"]
+    flip = np.where(np.arange(8) % 3 == 0, -1.0, 1.0)
+    b2 = wf.basis_from_factors(b["f"], b["s"], b["v"] * flip, res["z"] * flip, p)
+    np.testing.assert_array_equal(np.sort(b2["q"]), np.sort(b["q"]))
+    out2 = wf.reconstruct(res["z"] * flip, b2)
+    assert _rel(out2["im"], res["im"]) < 1e-10
+
+
+def test_rows_are_independent_under_transform_and_permutation():
+    cube = _small_cube(key=18)
+    p = wf.Params(k=8, als_lambda=1e4)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    perm = synth.rng_for(18, 1).permutation(cube.shape[0])
+    tr = wf.transform(cube.i_cars[perm], res["basis"])
+    assert _rel(tr["im"], res["im"][perm]) < 1e-10
+    refit = wf.fit(cube.i_cars[perm], cube.i_ref, p)
+    assert _rel(refit["im"], res["im"][perm]) < 1e-8
+
+
+def test_clamping_of_invalid_ratios():
+    ref = np.ones(5)
+    i = np.array([[1.0, 0.0, -1.0, np.nan, np.inf]])
+    ell, n_bad = wf.log_ratio(i, ref, 1e-6)
+    assert n_bad == 4
+    np.testing.assert_allclose(ell[0, 1:], 0.5 * np.log(1e-6))
+    assert ell[0, 0] == 0.0
+
+
+def test_q_is_union_of_column_extrema():
+    z = np.array([[0.0, 5.0], [3.0, -1.0], [3.0, 2.0], [-2.0, -1.0]])
+    # col 0: max first at row 1, min at row 3; col 1: max row 0, min first at row 1
+    np.testing.assert_array_equal(wf.subsample_rows(z), [0, 1, 3])
