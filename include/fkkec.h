@@ -1,0 +1,236 @@
+/*
+ * fkkec.h -- C ABI of the MI355X (gfx950) implementation of fKK-EC:
+ * factorized Kramers-Kronig and error correction for CARS hyperspectral
+ * images (C. H. Camp Jr., J. S. Bender, Y. J. Lee, arXiv 2005.07132).
+ *
+ * Orientation (Sec. 2.2): a spectral matrix has M rows (spectra, pixels) and
+ * N columns (wavenumbers).  Matrices are row-major; "ld" is the distance in
+ * elements between the starts of consecutive rows (ld >= N).
+ *
+ * Memory: pointers named d_* are device pointers on the context's device,
+ * h_* are host pointers.  The caller owns every buffer it passes and keeps it
+ * alive until the call's work has finished on the context's stream.  The
+ * library owns only what it returns (contexts and bases) and its internal
+ * workspace, which lives in the context.
+ *
+ * Errors: every call returns an fkk_status; no exception crosses the ABI.
+ * Arguments are checked before any launch.  fkk_ctx_last_error() returns a
+ * text description of the last failure on that context.
+ *
+ * Threads: a context is used by one host thread at a time.  A basis is
+ * immutable after creation and may be used by several contexts on the same
+ * device.
+ */
+#ifndef FKKEC_H
+#define FKKEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FKK_API_VERSION 1
+
+typedef struct fkk_ctx fkk_ctx;
+typedef struct fkk_basis fkk_basis;
+
+typedef enum {
+    FKK_OK = 0,
+    FKK_EINVAL = -1,     /* bad argument (NULL, size, range)                */
+    FKK_ENOMEM = -2,     /* device or host allocation failed                */
+    FKK_EDEVICE = -3,    /* a HIP call failed                                */
+    FKK_EDOMAIN = -4,    /* invalid intensities while strict mode is on      */
+    FKK_EMISMATCH = -5,  /* basis and data disagree (N, device)              */
+    FKK_ERANK = -7,      /* the requested rank is not available              */
+    FKK_EINTERNAL = -8   /* numerical failure inside the library             */
+} fkk_status;
+
+/* Detrending operator D of PEC (Sec. 2.1, Eq. 12, 16). */
+enum { FKK_DETREND_ALS = 0, FKK_DETREND_WHITTAKER = 1 };
+/* Trendline operator M of SEC (Eq. 4, Eq. 22). */
+enum { FKK_SEC_SAVGOL = 0, FKK_SEC_MEAN = 1 };
+/* Padding of the discrete Hilbert transform. */
+enum { FKK_PAD_EDGE = 0, FKK_PAD_ZERO = 1 };
+/* Variance scaling f(w) of Eq. 9-10. */
+enum { FKK_F_ONE = 0, FKK_F_NOISE = 1 };
+/* Which plane of K_CARS (Eq. 23) the output holds. */
+enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
+/* Input precision of the matrix-core contractions (FP32 accumulation). */
+enum { FKK_PREC_FP32 = 0 };
+
+/*
+ * Method parameters.  Fill with fkk_params_default() and override fields.
+ * Values the paper leaves open take the documented readings:
+ *   fft_len 0     -> smallest power of two >= 3N (padding of H)
+ *   als_lambda 0  -> 1e5 * (N/1000)^4
+ *   sg_window 0   -> largest odd number <= N/2
+ */
+typedef struct {
+    int32_t k;             /* retained singular vectors, 1..N (Sec. 2.2)   */
+    int32_t f_mode;        /* FKK_F_ONE or FKK_F_NOISE (Eq. 9)             */
+    double alpha;          /* Poisson multiplier of Eq. 9                  */
+    double sigma_g;        /* Gaussian noise std of Eq. 9                  */
+    int32_t pad_mode;      /* FKK_PAD_EDGE / FKK_PAD_ZERO                  */
+    int32_t fft_len;       /* Hilbert FFT length, 0 = automatic           */
+    int32_t detrend;       /* FKK_DETREND_*                                */
+    double als_lambda;     /* ALS / Whittaker smoothness, 0 = automatic    */
+    double als_p;          /* ALS asymmetry p (weight above the baseline)  */
+    int32_t als_iters;     /* ALS solves (fixed count)                     */
+    double ridge_rel;      /* Eq. 17: lambda = ridge_rel * max eig(X^T X)  */
+    int32_t sec_mode;      /* FKK_SEC_*                                    */
+    int32_t sg_window;     /* Savitzky-Golay window (odd), 0 = automatic   */
+    int32_t sg_order;      /* Savitzky-Golay polynomial order              */
+    double ml_lambda;      /* Eq. 25 ridge weight of the stored basis      */
+    double ratio_floor;    /* ratios I/I_ref not above it are clamped      */
+    int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
+    int32_t gram_prec;     /* FKK_PREC_*                                   */
+    int32_t recon_prec;    /* FKK_PREC_*                                   */
+    int32_t output;        /* FKK_OUT_*                                    */
+    const int64_t* q_override; /* host, optional: rows used as U_ss       */
+    int32_t n_q_override;  /* length of q_override (0 = use Eq. 13-15)    */
+} fkk_params;
+
+/* Per-fit diagnostics (all fields written by fkk_fit when non-NULL). */
+typedef struct {
+    int64_t clamps;        /* ratios replaced by ratio_floor               */
+    int32_t n_q;           /* rows of U_ss used by fPEC                    */
+    double ridge_lambda;   /* lambda of Eq. 17 actually used               */
+    double ms_gram;        /* log-ratio + Gram + reduction (device)        */
+    double ms_eig;         /* FP64 eigensolve (host)                       */
+    double ms_project;     /* projection + sub-sampling (device)          */
+    double ms_basis;       /* fKK / fPEC / fSEC on the basis (host FP64)   */
+    double ms_recon;       /* reconstruction + epilogue (device)           */
+    double ms_total;
+    /* device time of the three large kernels, from HIP events recorded on
+     * the context's stream around each launch */
+    double dev_ms_gram;    /* log ratio + Gram kernel                      */
+    double dev_ms_project; /* projection + arg-extrema kernel              */
+    double dev_ms_recon;   /* reconstruction + epilogue kernel             */
+} fkk_fit_report;
+
+/* Host description of a basis set (Sec. 2.6: f, S, V and the corrected
+ * bases).  Arrays are row-major FP64. */
+typedef struct {
+    int32_t N, k;
+    const double* i_ref;   /* N      reference spectrum I_ref              */
+    const double* f;       /* N      scaling f(w) of the training data     */
+    const double* s;       /* k      singular values                       */
+    const double* v;       /* N x k  right singular vectors V_k            */
+    const double* b_re;    /* k x N  V^T/f + H{Phi_PEC^T} - V_SEC^T        */
+    const double* b_im;    /* k x N  H{V^T/f} - Phi_PEC^T                  */
+    double ml_lambda;      /* Eq. 25 ridge weight used by fkk_transform    */
+    double ratio_floor;
+} fkk_basis_desc;
+
+int fkk_version(void);
+const char* fkk_status_string(fkk_status s);
+void fkk_params_default(fkk_params* p);
+
+/* Context: one device and one HIP stream (NULL = the default stream). */
+fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out);
+void fkk_ctx_destroy(fkk_ctx* ctx);
+const char* fkk_ctx_last_error(const fkk_ctx* ctx);
+/* Bytes of device workspace the context currently holds. */
+size_t fkk_ctx_workspace_bytes(const fkk_ctx* ctx);
+
+/*
+ * fKK-EC on a dataset ("training", Fig. 1b; Eq. 6-23).
+ * d_I: M x N FP32 intensities I_CARS (device, stride ld).  h_iref: N FP64
+ * reference I_ref (host).  Runs the log ratio and Gram on the device, the
+ * eigensolve and the basis-vector KK/PEC/SEC in FP64 on the host, then the
+ * projection and (if d_out != NULL) the reconstruction of Eq. 23 into d_out
+ * (M x N FP32, stride ld_out, plane selected by p->output).  Returns a new
+ * basis in *out_basis (may be NULL if the caller does not want it).
+ * Synchronous: returns after d_out is written.
+ */
+fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
+                   const double* h_iref, const fkk_params* p, fkk_basis** out_basis,
+                   float* d_out, int64_t ld_out, fkk_fit_report* rep);
+
+/*
+ * ML:fKK-EC (Fig. 1c; Eq. 24-25 then Eq. 23): applies a stored basis to new
+ * spectra.  Z_new = A_new V diag(s^2/(s^2+ml_lambda)), out = plane of
+ * exp(Z B_re + i Z B_im).  d_I: M x basis.N FP32 (stride ld); d_out: M x N
+ * FP32 (stride ld_out).  Asynchronous on the context's stream; no host
+ * synchronisation.  Each output row depends only on its input row.
+ */
+fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M,
+                         int64_t ld, float* d_out, int64_t ld_out);
+
+/*
+ * Conventional per-spectrum KK -> PEC -> SEC (Eq. 2-5, SEC in the log form
+ * of Eq. 19) for every row: the comparator of Fig. 1a without the SVD
+ * denoising.  Same data conventions as fkk_fit.  Asynchronous.
+ */
+fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
+                     const double* h_iref, const fkk_params* p, float* d_out, int64_t ld_out);
+
+/* ---- stages of the fit (each step of Fig. 1b on its own) ---------------- */
+
+/*
+ * Log ratio and Gram (Eq. 2, Eq. 6): G = l^T l (N x N, FP64, row-major,
+ * symmetric) with l = 1/2 ln(I / I_ref) computed in FP32 on load, plus the
+ * column sums of I (FP64, N) and the number of clamped ratios.  Synchronous.
+ */
+fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
+                    const double* h_iref, double ratio_floor, double* h_gram,
+                    double* h_colsum, int64_t* h_clamps);
+
+/*
+ * Top-k eigenpairs of a symmetric N x N FP64 matrix (host): eigenvalues in
+ * descending order, eigenvectors as the columns of h_evecs (N x k row-major),
+ * each with its largest-magnitude entry positive.  Householder
+ * tridiagonalisation, bisection and inverse iteration.
+ */
+fkk_status fkk_eigh_topk(const double* h_a, int32_t N, int32_t k, double* h_evals,
+                         double* h_evecs);
+
+/*
+ * fKK, fPEC and fSEC on the basis vectors (Eq. 7-22) on the host in FP64,
+ * given the factors: f (N), s (k), v (N x k), the sub-sampled rows
+ * x = Z[q,:] (n_q x k) of Z = U S.  Creates a basis (device copies included).
+ */
+fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const double* h_iref,
+                                  const double* h_f, const double* h_s, const double* h_v,
+                                  const double* h_x, int32_t n_q, const fkk_params* p,
+                                  fkk_basis** out_basis);
+
+/*
+ * Projection and sub-sampling (Eq. 13-15): Z = A V_k = l diag(f) V_k for the
+ * rows of d_I (M x N, stride ld) into d_z (M x k FP32, stride ld_z >= k), and
+ * the per-column argmax / argmin rows of Z (first row on ties) into h_qmax,
+ * h_qmin (k each, host, may be NULL).  Synchronous when h_qmax or h_qmin is
+ * given, else asynchronous.
+ */
+fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M,
+                       int64_t ld, float* d_z, int64_t ld_z, int64_t* h_qmax,
+                       int64_t* h_qmin);
+
+/*
+ * Reconstruction (Eq. 23): out = plane of exp(Z B_re) exp(i Z B_im) for Z
+ * (M x k FP32 device, stride ld_z).  plane: FKK_OUT_*.  Asynchronous.
+ */
+fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* basis, const float* d_z, int64_t M,
+                           int64_t ld_z, float* d_out, int64_t ld_out, int32_t plane);
+
+/* ---- basis objects (the stored model of ML:fKK-EC, Sec. 2.6) ------------ */
+
+fkk_status fkk_basis_import(fkk_ctx* ctx, const fkk_basis_desc* desc, fkk_basis** out);
+/* Sizes of a basis: N, k and the number of sub-sampled rows used by fPEC. */
+fkk_status fkk_basis_info(const fkk_basis* b, int32_t* N, int32_t* k, int32_t* n_q);
+/*
+ * Copies FP64 host arrays out of a basis; every pointer may be NULL.
+ * Sizes: i_ref, f: N; s: k; v: N x k; b_re, b_im, phi_pec_t, v_sec_t, h_v:
+ * k x N; q: n_q; scalars: ml_lambda, ratio_floor, ridge_lambda.
+ */
+fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double* s,
+                            double* v, double* b_re, double* b_im, double* phi_pec_t,
+                            double* v_sec_t, double* h_v, int64_t* q, double* scalars3);
+void fkk_basis_free(fkk_basis* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FKKEC_H */

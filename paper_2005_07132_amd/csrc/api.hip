@@ -1,0 +1,745 @@
+// C ABI of the fKK-EC library (include/fkkec.h): argument checking, device
+// workspace, and the orchestration of the fit
+//   device: log ratio + Gram  ->  host FP64: eigensolve, fKK / fPEC / fSEC
+//   device: projection + arg-extrema  ->  device: reconstruction + epilogue
+// and of the stored-basis transform.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fkkec.h"
+#include "host_math.h"
+#include "kernels.h"
+#include "plain.h"
+
+namespace {
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) n = std::max<size_t>(count, 1);
+        return e;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+template <class T>
+struct PinnedBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        if (p) hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T),
+                                     hipHostMallocDefault);
+        if (e == hipSuccess) n = std::max<size_t>(count, 1);
+        return e;
+    }
+    void release() {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+int kp_for(int k) {
+    if (k <= 16) return 16;
+    if (k <= 32) return 32;
+    if (k <= 64) return 64;
+    return 128;
+}
+
+int host_threads() {
+    unsigned hw = std::thread::hardware_concurrency();
+    if (hw == 0) hw = 1;
+    return (int)std::min(16u, hw);
+}
+
+}  // namespace
+
+struct fkk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    DevBuf<float> partial;
+    DevBuf<double> colsum_part, G, colsum;
+    DevBuf<unsigned long long> clamps;
+    DevBuf<int> tiles;
+    DevBuf<float> rinv, Z, X;
+    DevBuf<float> pmaxv, pminv;
+    DevBuf<long long> pmaxi, pmini, qext, qdev;
+    PinnedBuf<double> hG;
+    fkk::plain::Workspace plain_ws;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+
+    hipError_t events() {
+        for (auto& e : ev)
+            if (!e) {
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+            }
+        return hipSuccess;
+    }
+    float elapsed(int a, int b) const {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return -1.f;
+        return ms;
+    }
+
+    fkk_status fail(fkk_status s, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+    size_t bytes() const {
+        return partial.n * 4 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 + clamps.n * 8 + tiles.n * 4 +
+               rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
+               qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
+    }
+};
+
+struct fkk_basis {
+    int device = -1;
+    int N = 0, k = 0, kp = 0, npad = 0;
+    std::vector<double> i_ref, f, s, v, b_re, b_im, phi_pec_t, v_sec_t, h_v;
+    std::vector<int64_t> q;
+    double ml_lambda = 0.0, ratio_floor = 1e-6, ridge_lambda = 0.0;
+    float* d_rinv = nullptr;
+    float* d_wt = nullptr;      // kp x npad: f(j) V(j,c) shrink(c)
+    float* d_bre_t = nullptr;   // npad x kp
+    float* d_bim_t = nullptr;   // npad x kp
+    ~fkk_basis() {
+        if (d_rinv) hipFree(d_rinv);
+        if (d_wt) hipFree(d_wt);
+        if (d_bre_t) hipFree(d_bre_t);
+        if (d_bim_t) hipFree(d_bim_t);
+    }
+};
+
+#define FKK_HIP(ctx, call)                                                                          \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return (ctx)->fail(FKK_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+namespace {
+
+fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N) {
+    if (!p) return ctx->fail(FKK_EINVAL, "params is NULL");
+    if (p->k < 1 || p->k > N) return ctx->fail(FKK_EINVAL, "k=%d outside 1..N=%d", p->k, N);
+    if (p->k > 128) return ctx->fail(FKK_ERANK, "k=%d above the supported 128", p->k);
+    if (p->f_mode != FKK_F_ONE && p->f_mode != FKK_F_NOISE) return ctx->fail(FKK_EINVAL, "bad f_mode");
+    if (p->pad_mode != FKK_PAD_EDGE && p->pad_mode != FKK_PAD_ZERO) return ctx->fail(FKK_EINVAL, "bad pad_mode");
+    const int len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
+    if (len < N || (len & (len - 1)) != 0)
+        return ctx->fail(FKK_EINVAL, "fft_len=%d must be a power of two >= N", p->fft_len);
+    if (p->detrend != FKK_DETREND_ALS && p->detrend != FKK_DETREND_WHITTAKER)
+        return ctx->fail(FKK_EINVAL, "bad detrend");
+    if (!(p->als_lambda >= 0.0) || !(p->als_p > 0.0 && p->als_p < 1.0) || p->als_iters < 1)
+        return ctx->fail(FKK_EINVAL, "bad ALS parameters");
+    if (!(p->ridge_rel >= 0.0) || !(p->ml_lambda >= 0.0)) return ctx->fail(FKK_EINVAL, "negative ridge weight");
+    if (p->sec_mode != FKK_SEC_SAVGOL && p->sec_mode != FKK_SEC_MEAN) return ctx->fail(FKK_EINVAL, "bad sec_mode");
+    if (p->sec_mode == FKK_SEC_SAVGOL) {
+        const int w = p->sg_window ? p->sg_window : fkk::default_sg_window(N);
+        if (w % 2 == 0 || w > N || w <= p->sg_order || p->sg_order < 0)
+            return ctx->fail(FKK_EINVAL, "Savitzky-Golay window %d / order %d invalid for N=%d", w, p->sg_order, N);
+    }
+    if (!(p->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
+    if (p->output < FKK_OUT_IM || p->output > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad output plane");
+    if (p->gram_prec != FKK_PREC_FP32 || p->recon_prec != FKK_PREC_FP32)
+        return ctx->fail(FKK_EINVAL, "only FP32 matrix-core precision is built");
+    if (p->f_mode == FKK_F_NOISE && !(p->alpha >= 0.0 && p->sigma_g >= 0.0 && (p->alpha > 0.0 || p->sigma_g > 0.0)))
+        return ctx->fail(FKK_EINVAL, "f_mode=noise needs alpha >= 0, sigma_g >= 0, not both 0");
+    return FKK_OK;
+}
+
+fkk_status check_matrix(fkk_ctx* ctx, const void* d, int64_t M, int N, int64_t ld, const char* what) {
+    if (!d) return ctx->fail(FKK_EINVAL, "%s is NULL", what);
+    if (M < 1) return ctx->fail(FKK_EINVAL, "%s: M=%lld < 1", what, (long long)M);
+    if (N < 4) return ctx->fail(FKK_EINVAL, "%s: N=%d < 4", what, N);
+    if (ld < N) return ctx->fail(FKK_EINVAL, "%s: ld=%lld < N=%d", what, (long long)ld, N);
+    return FKK_OK;
+}
+
+fkk_status check_iref(fkk_ctx* ctx, const double* h_iref, int N) {
+    if (!h_iref) return ctx->fail(FKK_EINVAL, "I_ref is NULL");
+    for (int j = 0; j < N; ++j)
+        if (!(h_iref[j] > 0.0) || !std::isfinite(h_iref[j]))
+            return ctx->fail(FKK_EINVAL, "I_ref[%d] must be positive and finite", j);
+    return FKK_OK;
+}
+
+// Device copies of a basis: 1/I_ref, the projection weights and the
+// corrected bases (transposed, zero padded to kp columns and npad rows).
+fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
+    const int N = b->N, k = b->k, kp = b->kp, np = b->npad;
+    std::vector<float> rinv(N), wt((size_t)kp * np, 0.f), bre((size_t)np * kp, 0.f), bim((size_t)np * kp, 0.f);
+    for (int j = 0; j < N; ++j) rinv[j] = (float)(1.0 / b->i_ref[j]);
+    double smax = 0.0;
+    for (int c = 0; c < k; ++c) smax = std::max(smax, b->s[c]);
+    for (int c = 0; c < k; ++c) {
+        double shrink;
+        if (shrink_lambda > 0.0) shrink = b->s[c] * b->s[c] / (b->s[c] * b->s[c] + shrink_lambda);
+        else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
+        for (int j = 0; j < N; ++j) wt[(size_t)c * np + j] = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
+    }
+    for (int j = 0; j < N; ++j)
+        for (int c = 0; c < k; ++c) {
+            bre[(size_t)j * kp + c] = (float)b->b_re[(size_t)c * N + j];
+            bim[(size_t)j * kp + c] = (float)b->b_im[(size_t)c * N + j];
+        }
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    auto alloc_copy = [&](float** dst, const std::vector<float>& src) -> hipError_t {
+        if (!*dst) {
+            hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(float));
+            if (e != hipSuccess) return e;
+        }
+        return hipMemcpy(*dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice);
+    };
+    FKK_HIP(ctx, alloc_copy(&b->d_rinv, rinv));
+    FKK_HIP(ctx, alloc_copy(&b->d_wt, wt));
+    FKK_HIP(ctx, alloc_copy(&b->d_bre_t, bre));
+    FKK_HIP(ctx, alloc_copy(&b->d_bim_t, bim));
+    b->device = ctx->device;
+    return FKK_OK;
+}
+
+// fKK, fPEC and fSEC on the basis vectors (Eq. 7, 11, 16-18, 21-23), FP64.
+void basis_math(fkk_basis* b, const double* X, int n_q, const fkk_params* p) {
+    const int N = b->N, k = b->k;
+    const int len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
+    const double lam = p->als_lambda > 0.0 ? p->als_lambda : fkk::default_als_lambda(N);
+    const int window = p->sg_window ? p->sg_window : fkk::default_sg_window(N);
+    std::vector<double> vt_f((size_t)k * N);
+    for (int c = 0; c < k; ++c)
+        for (int j = 0; j < N; ++j) vt_f[(size_t)c * N + j] = b->v[(size_t)j * k + c] / b->f[j];
+    b->h_v.assign((size_t)k * N, 0.0);
+    fkk::hilbert_rows(vt_f.data(), b->h_v.data(), k, N, len, p->pad_mode);
+    // Phi_raw = X H{V^T/f}; Phi_err = D{Phi_raw} row by row
+    std::vector<double> raw((size_t)n_q * N, 0.0), err((size_t)n_q * N);
+    for (int r = 0; r < n_q; ++r)
+        for (int c = 0; c < k; ++c) {
+            const double x = X[(size_t)r * k + c];
+            const double* hv = &b->h_v[(size_t)c * N];
+            double* dst = &raw[(size_t)r * N];
+            for (int j = 0; j < N; ++j) dst[j] += x * hv[j];
+        }
+    for (int r = 0; r < n_q; ++r)
+        fkk::detrend_row(&raw[(size_t)r * N], &err[(size_t)r * N], N, p->detrend, lam, p->als_p, p->als_iters);
+    b->phi_pec_t.assign((size_t)k * N, 0.0);
+    b->ridge_lambda = fkk::ridge_rel_solve(X, err.data(), b->phi_pec_t.data(), n_q, k, N, p->ridge_rel);
+    std::vector<double> h_phi((size_t)k * N), t((size_t)k * N);
+    fkk::hilbert_rows(b->phi_pec_t.data(), h_phi.data(), k, N, len, p->pad_mode);
+    for (size_t i = 0; i < t.size(); ++i) t[i] = vt_f[i] + h_phi[i];
+    b->v_sec_t.assign((size_t)k * N, 0.0);
+    fkk::trendline_rows(t.data(), b->v_sec_t.data(), k, N, p->sec_mode, window, p->sg_order);
+    b->b_re.resize((size_t)k * N);
+    b->b_im.resize((size_t)k * N);
+    for (size_t i = 0; i < t.size(); ++i) {
+        b->b_re[i] = t[i] - b->v_sec_t[i];
+        b->b_im[i] = b->h_v[i] - b->phi_pec_t[i];
+    }
+}
+
+fkk_basis* new_basis(int N, int k, const double* iref, const double* f, const double* s, const double* v,
+                     double ml_lambda, double floor) {
+    fkk_basis* b = new fkk_basis;
+    b->N = N;
+    b->k = k;
+    b->kp = kp_for(k);
+    b->npad = round_up(N, 64);
+    b->i_ref.assign(iref, iref + N);
+    b->f.assign(f, f + N);
+    b->s.assign(s, s + k);
+    b->v.assign(v, v + (size_t)N * k);
+    b->ml_lambda = ml_lambda;
+    b->ratio_floor = floor;
+    return b;
+}
+
+// Gram pass into ctx->G (device) and the column sums; copies G to h_gram.
+fkk_status run_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
+                    double floor, double* h_gram, double* h_colsum, int64_t* h_clamps, bool timed = false) {
+    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64);
+    std::vector<int> pairs(2 * plan.tiles);
+    fkk::dev::gram_tile_list(plan.nb, pairs.data());
+    std::vector<float> rinv(N);
+    for (int j = 0; j < N; ++j) rinv[j] = (float)(1.0 / h_iref[j]);
+    FKK_HIP(ctx, ctx->partial.ensure(plan.partial_floats()));
+    FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)plan.chunks * N));
+    FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
+    FKK_HIP(ctx, ctx->colsum.ensure(N));
+    FKK_HIP(ctx, ctx->clamps.ensure(1));
+    FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
+    FKK_HIP(ctx, ctx->rinv.ensure(N));
+    FKK_HIP(ctx, ctx->hG.ensure((size_t)N * N + N + 1));
+    hipStream_t s = ctx->stream;
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->rinv.p, rinv.data(), N * sizeof(float), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemsetAsync(ctx->clamps.p, 0, sizeof(unsigned long long), s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+    FKK_HIP(ctx, fkk::dev::launch_gram(d_I, M, N, ld, ctx->rinv.p, (float)floor, plan, ctx->tiles.p, ctx->partial.p,
+                                       ctx->colsum_part.p, ctx->clamps.p, s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+    FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, ctx->colsum_part.p, plan, ctx->tiles.p, N, ctx->G.p,
+                                              ctx->colsum.p, s));
+    double* hg = ctx->hG.p;
+    FKK_HIP(ctx, hipMemcpyAsync(hg, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg + (size_t)N * N, ctx->colsum.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg + (size_t)N * N + N, ctx->clamps.p, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipStreamSynchronize(s));
+    if (h_gram) std::memcpy(h_gram, hg, (size_t)N * N * sizeof(double));
+    if (h_colsum) std::memcpy(h_colsum, hg + (size_t)N * N, N * sizeof(double));
+    if (h_clamps) {
+        unsigned long long c;
+        std::memcpy(&c, hg + (size_t)N * N + N, sizeof c);
+        *h_clamps = (int64_t)c;
+    }
+    return FKK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fkk_version(void) { return FKK_API_VERSION; }
+
+const char* fkk_status_string(fkk_status s) {
+    switch (s) {
+        case FKK_OK: return "ok";
+        case FKK_EINVAL: return "invalid argument";
+        case FKK_ENOMEM: return "out of memory";
+        case FKK_EDEVICE: return "device error";
+        case FKK_EDOMAIN: return "invalid intensities";
+        case FKK_EMISMATCH: return "basis / data mismatch";
+        case FKK_ERANK: return "rank not available";
+        case FKK_EINTERNAL: return "internal numerical failure";
+    }
+    return "unknown status";
+}
+
+void fkk_params_default(fkk_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->k = 50;
+    p->f_mode = FKK_F_ONE;
+    p->alpha = 0.0;
+    p->sigma_g = 1.0;
+    p->pad_mode = FKK_PAD_EDGE;
+    p->fft_len = 0;
+    p->detrend = FKK_DETREND_ALS;
+    p->als_lambda = 0.0;
+    p->als_p = 1e-3;
+    p->als_iters = 10;
+    p->ridge_rel = 1e-6;
+    p->sec_mode = FKK_SEC_SAVGOL;
+    p->sg_window = 0;
+    p->sg_order = 2;
+    p->ml_lambda = 0.0;
+    p->ratio_floor = 1e-6;
+    p->strict = 0;
+    p->gram_prec = FKK_PREC_FP32;
+    p->recon_prec = FKK_PREC_FP32;
+    p->output = FKK_OUT_IM;
+    p->q_override = nullptr;
+    p->n_q_override = 0;
+}
+
+fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
+    if (!out) return FKK_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return FKK_EDEVICE;
+    if (device < 0 || device >= count) return FKK_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return FKK_EDEVICE;
+    fkk_ctx* c = new fkk_ctx;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return FKK_OK;
+}
+
+void fkk_ctx_destroy(fkk_ctx* ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    ctx->partial.release();
+    ctx->colsum_part.release();
+    ctx->G.release();
+    ctx->colsum.release();
+    ctx->clamps.release();
+    ctx->tiles.release();
+    ctx->rinv.release();
+    ctx->Z.release();
+    ctx->X.release();
+    ctx->pmaxv.release();
+    ctx->pminv.release();
+    ctx->pmaxi.release();
+    ctx->pmini.release();
+    ctx->qext.release();
+    ctx->qdev.release();
+    ctx->hG.release();
+    ctx->plain_ws.release();
+    for (auto& e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    delete ctx;
+}
+
+const char* fkk_ctx_last_error(const fkk_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+size_t fkk_ctx_workspace_bytes(const fkk_ctx* ctx) { return ctx ? ctx->bytes() : 0; }
+
+fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                    double ratio_floor, double* h_gram, double* h_colsum, int64_t* h_clamps) {
+    if (!ctx) return FKK_EINVAL;
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
+    if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
+    if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    return run_gram(ctx, d_I, M, N, ld, h_iref, ratio_floor, h_gram, h_colsum, h_clamps);
+}
+
+fkk_status fkk_eigh_topk(const double* h_a, int32_t N, int32_t k, double* h_evals, double* h_evecs) {
+    if (!h_a || !h_evals || !h_evecs || N < 1 || k < 1 || k > N) return FKK_EINVAL;
+    return fkk::eigh_topk(h_a, N, k, h_evals, h_evecs, host_threads()) == 0 ? FKK_OK : FKK_EINTERNAL;
+}
+
+fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const double* h_iref, const double* h_f,
+                                  const double* h_s, const double* h_v, const double* h_x, int32_t n_q,
+                                  const fkk_params* p, fkk_basis** out_basis) {
+    fkk_ctx scratch;  // error sink when ctx is NULL (host-only basis)
+    fkk_ctx* c = ctx ? ctx : &scratch;
+    if (!out_basis || !h_iref || !h_f || !h_s || !h_v || !h_x || n_q < 1 || N < 4)
+        return c->fail(FKK_EINVAL, "NULL argument or bad size");
+    *out_basis = nullptr;
+    fkk_status st;
+    if ((st = check_params(c, p, N)) != FKK_OK) return st;
+    if (p->k != k) return c->fail(FKK_EINVAL, "params.k != k");
+    fkk_basis* b = new_basis(N, k, h_iref, h_f, h_s, h_v, p->ml_lambda, p->ratio_floor);
+    basis_math(b, h_x, n_q, p);
+    if (ctx) {
+        if ((st = upload_basis(ctx, b, p->ml_lambda)) != FKK_OK) {
+            delete b;
+            return st;
+        }
+    }
+    *out_basis = b;
+    return FKK_OK;
+}
+
+fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                   const fkk_params* p, fkk_basis** out_basis, float* d_out, int64_t ld_out, fkk_fit_report* rep) {
+    if (!ctx) return FKK_EINVAL;
+    const auto t_all = std::chrono::steady_clock::now();
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
+    if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
+    if ((st = check_params(ctx, p, N)) != FKK_OK) return st;
+    if (d_out && ld_out < N) return ctx->fail(FKK_EINVAL, "ld_out=%lld < N", (long long)ld_out);
+    if (p->n_q_override > 0) {
+        if (!p->q_override) return ctx->fail(FKK_EINVAL, "q_override is NULL");
+        for (int i = 0; i < p->n_q_override; ++i)
+            if (p->q_override[i] < 0 || p->q_override[i] >= M)
+                return ctx->fail(FKK_EINVAL, "q_override[%d] out of range", i);
+    }
+    if (out_basis) *out_basis = nullptr;
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int k = p->k, kp = kp_for(k);
+    fkk_fit_report r{};
+
+    // 1. log ratio, Gram and column sums on the device (Eq. 2, 6, 9)
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> G((size_t)N * N), colsum(N);
+    int64_t clamps = 0;
+    FKK_HIP(ctx, ctx->events());
+    if ((st = run_gram(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, G.data(), colsum.data(), &clamps, true)) != FKK_OK)
+        return st;
+    r.dev_ms_gram = ctx->elapsed(0, 1);
+    r.clamps = clamps;
+    r.ms_gram = ms_since(t0);
+    if (p->strict && clamps > 0) return ctx->fail(FKK_EDOMAIN, "%lld intensity ratios clamped", (long long)clamps);
+
+    // 2. f and the FP64 eigensolve of G_A = diag(f) G_L diag(f)
+    t0 = std::chrono::steady_clock::now();
+    std::vector<double> f(N, 1.0);
+    if (p->f_mode == FKK_F_NOISE)
+        for (int j = 0; j < N; ++j) {
+            const double mean = colsum[j] / (double)M;
+            f[j] = 2.0 * mean / std::sqrt(p->alpha * mean + p->sigma_g * p->sigma_g);
+        }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) G[(size_t)i * N + j] *= f[i] * f[j];
+    std::vector<double> lam(k), V((size_t)N * k), sv(k);
+    if (fkk::eigh_topk(G.data(), N, k, lam.data(), V.data(), host_threads()) != 0)
+        return ctx->fail(FKK_EINTERNAL, "eigensolver failed");
+    for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    r.ms_eig = ms_since(t0);
+
+    // 3. projection Z = A V_k and per-column arg-extrema (Eq. 13-15)
+    t0 = std::chrono::steady_clock::now();
+    fkk_basis* b = new_basis(N, k, h_iref, f.data(), sv.data(), V.data(), p->ml_lambda, p->ratio_floor);
+    std::vector<float> wt((size_t)kp * b->npad, 0.f);
+    for (int c = 0; c < k; ++c)
+        for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(f[j] * V[(size_t)j * k + c]);
+    auto cleanup = [&](fkk_status e) { delete b; return e; };
+    const int64_t nblk = fkk::dev::proj_blocks(M);
+    if (ctx->Z.ensure((size_t)M * kp) != hipSuccess || ctx->X.ensure((size_t)kp * b->npad) != hipSuccess ||
+        ctx->pmaxv.ensure((size_t)nblk * kp) != hipSuccess || ctx->pminv.ensure((size_t)nblk * kp) != hipSuccess ||
+        ctx->pmaxi.ensure((size_t)nblk * kp) != hipSuccess || ctx->pmini.ensure((size_t)nblk * kp) != hipSuccess ||
+        ctx->qext.ensure(2 * (size_t)kp) != hipSuccess)
+        return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
+    float* d_wt = ctx->X.p;  // the fit's projection weights (no ML shrink)
+    if (hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
+    fkk::dev::ArgPart part{ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
+    if (hipEventRecord(ctx->ev[2], s) != hipSuccess ||
+        fkk::dev::launch_project(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp, kp, ctx->Z.p,
+                                 kp, part, k, s) != hipSuccess ||
+        hipEventRecord(ctx->ev[3], s) != hipSuccess ||
+        fkk::dev::launch_argext_reduce(part, nblk, kp, k, ctx->qext.p, ctx->qext.p + kp, s) != hipSuccess)
+        return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));
+    std::vector<long long> qe(2 * (size_t)kp);
+    if (hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(ctx->fail(FKK_EDEVICE, "projection failed"));
+    r.dev_ms_project = ctx->elapsed(2, 3);
+    std::vector<long long> q;
+    if (p->n_q_override > 0) {
+        q.assign(p->q_override, p->q_override + p->n_q_override);
+    } else {
+        for (int c = 0; c < k; ++c) {
+            if (qe[c] >= 0) q.push_back(qe[c]);
+            if (qe[kp + c] >= 0) q.push_back(qe[kp + c]);
+        }
+        std::sort(q.begin(), q.end());
+        q.erase(std::unique(q.begin(), q.end()), q.end());
+    }
+    const int n_q = (int)q.size();
+    std::vector<float> xf((size_t)n_q * k);
+    if (ctx->qdev.ensure(std::max(n_q, 1)) != hipSuccess)
+        return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
+    float* d_x = ctx->pmaxv.p;  // reuse: n_q * k <= nblk * kp is not guaranteed, checked below
+    DevBuf<float> xtmp;
+    if ((size_t)n_q * k > ctx->pmaxv.n) {
+        if (xtmp.ensure((size_t)n_q * k) != hipSuccess) return cleanup(ctx->fail(FKK_ENOMEM, "allocation failed"));
+        d_x = xtmp.p;
+    }
+    if (hipMemcpyAsync(ctx->qdev.p, q.data(), n_q * sizeof(long long), hipMemcpyHostToDevice, s) != hipSuccess ||
+        fkk::dev::launch_gather_rows(ctx->Z.p, kp, k, ctx->qdev.p, n_q, d_x, s) != hipSuccess ||
+        hipMemcpyAsync(xf.data(), d_x, xf.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(ctx->fail(FKK_EDEVICE, "gather of sub-sampled rows failed"));
+    xtmp.release();
+    r.ms_project = ms_since(t0);
+
+    // 4. fKK, fPEC, fSEC on the basis vectors (host FP64)
+    t0 = std::chrono::steady_clock::now();
+    std::vector<double> X(xf.begin(), xf.end());
+    b->q.assign(q.begin(), q.end());
+    basis_math(b, X.data(), n_q, p);
+    if ((st = upload_basis(ctx, b, p->ml_lambda)) != FKK_OK) return cleanup(st);
+    r.n_q = n_q;
+    r.ridge_lambda = b->ridge_lambda;
+    r.ms_basis = ms_since(t0);
+
+    // 5. reconstruction of Eq. 23 for the training rows
+    t0 = std::chrono::steady_clock::now();
+    if (d_out) {
+        if (hipEventRecord(ctx->ev[4], s) != hipSuccess ||
+            fkk::dev::launch_reconstruct(ctx->Z.p, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out, p->output,
+                                         s) != hipSuccess ||
+            hipEventRecord(ctx->ev[5], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return cleanup(ctx->fail(FKK_EDEVICE, "reconstruction failed"));
+        r.dev_ms_recon = ctx->elapsed(4, 5);
+    }
+    r.ms_recon = ms_since(t0);
+    r.ms_total = ms_since(t_all);
+    if (rep) *rep = r;
+    if (out_basis) *out_basis = b;
+    else delete b;
+    return FKK_OK;
+}
+
+fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld, float* d_out,
+                         int64_t ld_out) {
+    if (!ctx) return FKK_EINVAL;
+    if (!b) return ctx->fail(FKK_EINVAL, "basis is NULL");
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, b->N, ld, "I")) != FKK_OK) return st;
+    if (!d_out || ld_out < b->N) return ctx->fail(FKK_EINVAL, "bad output");
+    if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
+                                            b->kp, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM, ctx->stream));
+    return FKK_OK;
+}
+
+fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld, float* d_z,
+                       int64_t ld_z, int64_t* h_qmax, int64_t* h_qmin) {
+    if (!ctx) return FKK_EINVAL;
+    if (!b) return ctx->fail(FKK_EINVAL, "basis is NULL");
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, b->N, ld, "I")) != FKK_OK) return st;
+    if (!d_z || ld_z < b->k) return ctx->fail(FKK_EINVAL, "bad Z output");
+    if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t nblk = fkk::dev::proj_blocks(M);
+    fkk::dev::ArgPart part{nullptr, nullptr, nullptr, nullptr};
+    const bool want = h_qmax || h_qmin;
+    if (want) {
+        FKK_HIP(ctx, ctx->pmaxv.ensure((size_t)nblk * b->kp));
+        FKK_HIP(ctx, ctx->pminv.ensure((size_t)nblk * b->kp));
+        FKK_HIP(ctx, ctx->pmaxi.ensure((size_t)nblk * b->kp));
+        FKK_HIP(ctx, ctx->pmini.ensure((size_t)nblk * b->kp));
+        FKK_HIP(ctx, ctx->qext.ensure(2 * (size_t)b->kp));
+        part = {ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
+    }
+    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
+                                          b->k, d_z, ld_z, part, b->k, s));
+    if (!want) return FKK_OK;
+    FKK_HIP(ctx, fkk::dev::launch_argext_reduce(part, nblk, b->kp, b->k, ctx->qext.p, ctx->qext.p + b->kp, s));
+    std::vector<long long> qe(2 * (size_t)b->kp);
+    FKK_HIP(ctx, hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipStreamSynchronize(s));
+    for (int c = 0; c < b->k; ++c) {
+        if (h_qmax) h_qmax[c] = qe[c];
+        if (h_qmin) h_qmin[c] = qe[b->kp + c];
+    }
+    return FKK_OK;
+}
+
+fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, int64_t M, int64_t ld_z,
+                           float* d_out, int64_t ld_out, int32_t plane) {
+    if (!ctx) return FKK_EINVAL;
+    if (!b) return ctx->fail(FKK_EINVAL, "basis is NULL");
+    if (!d_z || M < 1 || ld_z < b->k) return ctx->fail(FKK_EINVAL, "bad Z");
+    if (!d_out || ld_out < b->N) return ctx->fail(FKK_EINVAL, "bad output");
+    if (plane < FKK_OUT_IM || plane > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad plane");
+    if (b->device != ctx->device || !b->d_bre_t) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    FKK_HIP(ctx, fkk::dev::launch_reconstruct(d_z, M, ld_z, b->k, b->d_bre_t, b->d_bim_t, b->kp, b->N, d_out, ld_out,
+                                              plane, ctx->stream));
+    return FKK_OK;
+}
+
+fkk_status fkk_basis_import(fkk_ctx* ctx, const fkk_basis_desc* d, fkk_basis** out) {
+    if (!ctx) return FKK_EINVAL;
+    if (!d || !out || !d->i_ref || !d->f || !d->s || !d->v || !d->b_re || !d->b_im)
+        return ctx->fail(FKK_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->N < 4 || d->k < 1 || d->k > d->N || d->k > 128) return ctx->fail(FKK_EINVAL, "bad N / k");
+    if (!(d->ml_lambda >= 0.0) || !(d->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "bad scalars");
+    fkk_status st;
+    if ((st = check_iref(ctx, d->i_ref, d->N)) != FKK_OK) return st;
+    fkk_basis* b = new_basis(d->N, d->k, d->i_ref, d->f, d->s, d->v, d->ml_lambda, d->ratio_floor);
+    b->b_re.assign(d->b_re, d->b_re + (size_t)d->k * d->N);
+    b->b_im.assign(d->b_im, d->b_im + (size_t)d->k * d->N);
+    if ((st = upload_basis(ctx, b, d->ml_lambda)) != FKK_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FKK_OK;
+}
+
+fkk_status fkk_basis_info(const fkk_basis* b, int32_t* N, int32_t* k, int32_t* n_q) {
+    if (!b) return FKK_EINVAL;
+    if (N) *N = b->N;
+    if (k) *k = b->k;
+    if (n_q) *n_q = (int32_t)b->q.size();
+    return FKK_OK;
+}
+
+fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double* s, double* v, double* b_re,
+                            double* b_im, double* phi_pec_t, double* v_sec_t, double* h_v, int64_t* q,
+                            double* scalars3) {
+    if (!b) return FKK_EINVAL;
+    auto put = [](double* dst, const std::vector<double>& src) {
+        if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(double));
+    };
+    put(i_ref, b->i_ref);
+    put(f, b->f);
+    put(s, b->s);
+    put(v, b->v);
+    put(b_re, b->b_re);
+    put(b_im, b->b_im);
+    put(phi_pec_t, b->phi_pec_t);
+    put(v_sec_t, b->v_sec_t);
+    put(h_v, b->h_v);
+    if (q && !b->q.empty()) std::memcpy(q, b->q.data(), b->q.size() * sizeof(int64_t));
+    if (scalars3) {
+        scalars3[0] = b->ml_lambda;
+        scalars3[1] = b->ratio_floor;
+        scalars3[2] = b->ridge_lambda;
+    }
+    return FKK_OK;
+}
+
+void fkk_basis_free(fkk_basis* b) { delete b; }
+
+fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                     const fkk_params* p, float* d_out, int64_t ld_out) {
+    if (!ctx) return FKK_EINVAL;
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
+    if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
+    if ((st = check_params(ctx, p, N)) != FKK_OK) return st;
+    if (!d_out || ld_out < N) return ctx->fail(FKK_EINVAL, "bad output");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    fkk::plain::Config cfg;
+    cfg.N = N;
+    cfg.len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
+    cfg.pad_mode = p->pad_mode;
+    cfg.detrend = p->detrend;
+    cfg.lam = p->als_lambda > 0.0 ? p->als_lambda : fkk::default_als_lambda(N);
+    cfg.p = p->als_p;
+    cfg.iters = p->als_iters;
+    cfg.sec_mode = p->sec_mode;
+    cfg.window = p->sg_window ? p->sg_window : fkk::default_sg_window(N);
+    cfg.order = p->sg_order;
+    cfg.floor = p->ratio_floor;
+    cfg.plane = p->output;
+    std::string why;
+    const hipError_t e = fkk::plain::run(ctx->plain_ws, cfg, d_I, M, ld, h_iref, d_out, ld_out, ctx->stream, &why);
+    if (e != hipSuccess)
+        return ctx->fail(FKK_EDEVICE, "plain path: %s (%s)", hipGetErrorString(e), why.c_str());
+    return FKK_OK;
+}
+
+}  // extern "C"

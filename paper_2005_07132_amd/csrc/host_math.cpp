@@ -1,0 +1,667 @@
+// FP64 host numerics of fKK-EC on the basis vectors and the Gram matrix.
+// See host_math.h for the contracts.
+#include "host_math.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <condition_variable>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <mutex>
+#include <thread>
+
+namespace fkk {
+
+using cplx = std::complex<double>;
+
+int default_fft_len(int n) {
+    int len = 1;
+    while (len < 3 * n) len *= 2;
+    return len;
+}
+
+double default_als_lambda(int n) {
+    const double r = n / 1000.0;
+    return 1.0e5 * r * r * r * r;
+}
+
+int default_sg_window(int n) {
+    int w = n / 2;
+    if (w % 2 == 0) w -= 1;
+    return std::max(w, 3);
+}
+
+// ---------------------------------------------------------------------------
+// Radix-2 complex FFT (decimation in time, iterative), length a power of two.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FftPlan {
+    int n = 0;
+    std::vector<int> rev;
+    std::vector<cplx> tw;  // exp(-2 pi i j / n), j < n/2
+    explicit FftPlan(int len) : n(len), rev(len), tw(len / 2) {
+        int bits = 0;
+        while ((1 << bits) < n) ++bits;
+        for (int i = 0; i < n; ++i) {
+            int r = 0;
+            for (int b = 0; b < bits; ++b)
+                if (i & (1 << b)) r |= 1 << (bits - 1 - b);
+            rev[i] = r;
+        }
+        for (int j = 0; j < n / 2; ++j) {
+            const double ang = -2.0 * M_PI * (double)j / (double)n;
+            tw[j] = cplx(std::cos(ang), std::sin(ang));
+        }
+    }
+    void run(cplx* a, bool inverse) const {
+        for (int i = 0; i < n; ++i)
+            if (i < rev[i]) std::swap(a[i], a[rev[i]]);
+        for (int half = 1; half < n; half *= 2) {
+            const int step = n / (2 * half);
+            for (int s = 0; s < n; s += 2 * half) {
+                for (int j = 0; j < half; ++j) {
+                    cplx w = tw[j * step];
+                    if (inverse) w = std::conj(w);
+                    const cplx t = w * a[s + j + half];
+                    a[s + j + half] = a[s + j] - t;
+                    a[s + j] = a[s + j] + t;
+                }
+            }
+        }
+        if (inverse) {
+            const double inv = 1.0 / n;
+            for (int i = 0; i < n; ++i) a[i] *= inv;
+        }
+    }
+};
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+void hilbert_rows(const double* x, double* y, int rows, int n, int len, int pad_mode) {
+    if (!is_pow2(len) || len < n) return;
+    FftPlan plan(len);
+    const int pl = (len - n) / 2;
+    std::vector<cplx> buf(len);
+    // -i sgn(nu): bins 1..len/2-1 positive, len/2+1..len-1 negative.
+    auto pad_value = [&](const double* row, int i) -> double {
+        const int src = i - pl;
+        if (src >= 0 && src < n) return row[src];
+        if (pad_mode == 1) return 0.0;
+        return src < 0 ? row[0] : row[n - 1];
+    };
+    // Two real rows per complex transform: H is real and complex-linear, so
+    // H{a + i b} = H{a} + i H{b}.
+    for (int r = 0; r < rows; r += 2) {
+        const double* ra = x + (size_t)r * n;
+        const double* rb = (r + 1 < rows) ? x + (size_t)(r + 1) * n : nullptr;
+        for (int i = 0; i < len; ++i)
+            buf[i] = cplx(pad_value(ra, i), rb ? pad_value(rb, i) : 0.0);
+        plan.run(buf.data(), false);
+        buf[0] = 0.0;
+        buf[len / 2] = 0.0;
+        for (int b = 1; b < len / 2; ++b) buf[b] *= cplx(0.0, -1.0);
+        for (int b = len / 2 + 1; b < len; ++b) buf[b] *= cplx(0.0, 1.0);
+        plan.run(buf.data(), true);
+        for (int i = 0; i < n; ++i) {
+            y[(size_t)r * n + i] = buf[pl + i].real();
+            if (rb) y[(size_t)(r + 1) * n + i] = buf[pl + i].imag();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Detrending: (diag(w) + lam D^T D) z = w y, D the second-difference matrix.
+// The matrix is symmetric positive definite and pentadiagonal; it is solved
+// by an LDL^T factorisation with unit lower factor of bandwidth two.
+// ---------------------------------------------------------------------------
+namespace {
+
+void penta_solve(const double* w, const double* y, double* z, int n, double lam,
+                 std::vector<double>& dd, std::vector<double>& l1, std::vector<double>& l2) {
+    dd.assign(n, 0.0);
+    l1.assign(n + 1, 0.0);
+    l2.assign(n + 2, 0.0);
+    auto a0 = [&](int i) {  // diagonal of lam D^T D plus w
+        double c = 6.0;
+        if (i == 0 || i == n - 1) c = 1.0;
+        else if (i == 1 || i == n - 2) c = 5.0;
+        return w[i] + lam * c;
+    };
+    auto a1 = [&](int i) {  // A[i+1][i]
+        double c = -4.0;
+        if (i == 0 || i == n - 2) c = -2.0;
+        return lam * c;
+    };
+    const double a2 = lam;  // A[i+2][i]
+    for (int i = 0; i < n; ++i) {
+        double d = a0(i);
+        if (i >= 1) d -= l1[i] * l1[i] * dd[i - 1];
+        if (i >= 2) d -= l2[i] * l2[i] * dd[i - 2];
+        dd[i] = d;
+        if (i + 1 < n) {
+            double v = a1(i);
+            if (i >= 1) v -= l2[i + 1] * l1[i] * dd[i - 1];
+            l1[i + 1] = v / d;
+        }
+        if (i + 2 < n) l2[i + 2] = a2 / d;
+    }
+    // L u = w y ; D v = u ; L^T z = v
+    for (int i = 0; i < n; ++i) {
+        double u = w[i] * y[i];
+        if (i >= 1) u -= l1[i] * z[i - 1];
+        if (i >= 2) u -= l2[i] * z[i - 2];
+        z[i] = u;
+    }
+    for (int i = 0; i < n; ++i) z[i] /= dd[i];
+    for (int i = n - 1; i >= 0; --i) {
+        double v = z[i];
+        if (i + 1 < n) v -= l1[i + 1] * z[i + 1];
+        if (i + 2 < n) v -= l2[i + 2] * z[i + 2];
+        z[i] = v;
+    }
+}
+
+}  // namespace
+
+void detrend_row(const double* y, double* z, int n, int mode, double lam, double p, int n_iter) {
+    std::vector<double> w(n, 1.0), dd, l1, l2;
+    if (n < 4) {  // D^T D needs at least 4 points to be pentadiagonal
+        for (int i = 0; i < n; ++i) z[i] = y[i];
+        return;
+    }
+    const int iters = (mode == 1) ? 1 : n_iter;
+    for (int it = 0; it < iters; ++it) {
+        penta_solve(w.data(), y, z, n, lam, dd, l1, l2);
+        for (int i = 0; i < n; ++i) w[i] = (y[i] > z[i]) ? p : 1.0 - p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Savitzky-Golay trendline.  The weights of output point i are those of the
+// least-squares polynomial of degree `order` through the window evaluated at
+// i: c = V (V^T V)^-1 e_0 with V the Vandermonde matrix of the window
+// positions relative to i (scaled by the half window for conditioning).
+// ---------------------------------------------------------------------------
+namespace {
+
+// Solve the small SPD system g x = b in place (Gaussian elimination with
+// partial pivoting; g is (order+1)^2).
+void small_solve(std::vector<double>& g, std::vector<double>& b, int m) {
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (std::fabs(g[r * m + c]) > std::fabs(g[piv * m + c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < m; ++j) std::swap(g[c * m + j], g[piv * m + j]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < m; ++r) {
+            const double f = g[r * m + c] / g[c * m + c];
+            for (int j = c; j < m; ++j) g[r * m + j] -= f * g[c * m + j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = m - 1; c >= 0; --c) {
+        double v = b[c];
+        for (int j = c + 1; j < m; ++j) v -= g[c * m + j] * b[j];
+        b[c] = v / g[c * m + c];
+    }
+}
+
+void sg_weights(int start, int window, int at, int order, double scale, double* out) {
+    const int m = order + 1;
+    std::vector<double> g(m * m, 0.0), b(m, 0.0);
+    for (int j = 0; j < window; ++j) {
+        const double x = (start + j - at) / scale;
+        double pi = 1.0;
+        std::vector<double> pw(2 * m - 1);
+        for (int e = 0; e < 2 * m - 1; ++e) { pw[e] = pi; pi *= x; }
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) g[r * m + c] += pw[r + c];
+    }
+    b[0] = 1.0;
+    small_solve(g, b, m);  // b = (V^T V)^-1 e0
+    for (int j = 0; j < window; ++j) {
+        const double x = (start + j - at) / scale;
+        double pi = 1.0, v = 0.0;
+        for (int e = 0; e < m; ++e) { v += b[e] * pi; pi *= x; }
+        out[j] = v;
+    }
+}
+
+}  // namespace
+
+void trendline_rows(const double* x, double* y, int rows, int n, int mode, int window, int order) {
+    if (mode == 1) {
+        for (int r = 0; r < rows; ++r) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += x[(size_t)r * n + i];
+            s /= n;
+            for (int i = 0; i < n; ++i) y[(size_t)r * n + i] = s;
+        }
+        return;
+    }
+    const int half = window / 2;
+    const double scale = std::max(1, half);
+    // weights for every output position (interior ones are all equal)
+    std::vector<double> wmid(window);
+    sg_weights(0, window, half, order, scale, wmid.data());
+    std::vector<double> wedge((size_t)2 * half * window);
+    std::vector<int> estart(2 * half), eat(2 * half);
+    for (int i = 0; i < half; ++i) {
+        sg_weights(0, window, i, order, scale, &wedge[(size_t)i * window]);
+        estart[i] = 0;
+        eat[i] = i;
+        const int at = n - half + i;
+        sg_weights(n - window, window, at, order, scale, &wedge[(size_t)(half + i) * window]);
+        estart[half + i] = n - window;
+        eat[half + i] = at;
+    }
+    for (int r = 0; r < rows; ++r) {
+        const double* xr = x + (size_t)r * n;
+        double* yr = y + (size_t)r * n;
+        for (int i = half; i < n - half; ++i) {
+            double s = 0.0;
+            const double* src = xr + i - half;
+            for (int j = 0; j < window; ++j) s += wmid[j] * src[j];
+            yr[i] = s;
+        }
+        for (int e = 0; e < 2 * half; ++e) {
+            double s = 0.0;
+            const double* wts = &wedge[(size_t)e * window];
+            const double* src = xr + estart[e];
+            for (int j = 0; j < window; ++j) s += wts[j] * src[j];
+            yr[eat[e]] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ridge regression through the thin SVD of X (one-sided Jacobi):
+//   B = W diag(sigma / (sigma^2 + lam)) U^T Y,  lam = rel * sigma_max^2,
+// with singular values below eps * max(m, k) * sigma_max dropped when
+// lam = 0 (the minimum-norm least-squares solution).
+// ---------------------------------------------------------------------------
+double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k, int n, double rel) {
+    // columns of X as contiguous vectors
+    std::vector<double> cols((size_t)k * m), W((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        for (int i = 0; i < m; ++i) cols[(size_t)j * m + i] = X[(size_t)i * k + j];
+        W[(size_t)j * k + j] = 1.0;  // W stored column-major: column j at j*k
+    }
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p < k - 1; ++p) {
+            for (int q = p + 1; q < k; ++q) {
+                double* cp = &cols[(size_t)p * m];
+                double* cq = &cols[(size_t)q * m];
+                double alpha = 0, beta = 0, gamma = 0;
+                for (int i = 0; i < m; ++i) {
+                    alpha += cp[i] * cp[i];
+                    beta += cq[i] * cq[i];
+                    gamma += cp[i] * cq[i];
+                }
+                if (std::fabs(gamma) <= eps * std::sqrt(alpha * beta) || gamma == 0.0) continue;
+                rotated = true;
+                const double zeta = (beta - alpha) / (2.0 * gamma);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                for (int i = 0; i < m; ++i) {
+                    const double a = cp[i], b = cq[i];
+                    cp[i] = c * a - s * b;
+                    cq[i] = s * a + c * b;
+                }
+                double* wp = &W[(size_t)p * k];
+                double* wq = &W[(size_t)q * k];
+                for (int i = 0; i < k; ++i) {
+                    const double a = wp[i], b = wq[i];
+                    wp[i] = c * a - s * b;
+                    wq[i] = s * a + c * b;
+                }
+            }
+        }
+        if (!rotated) break;
+    }
+    std::vector<double> sig(k);
+    double smax = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += cols[(size_t)j * m + i] * cols[(size_t)j * m + i];
+        sig[j] = std::sqrt(s);
+        smax = std::max(smax, sig[j]);
+    }
+    std::fill(B, B + (size_t)k * n, 0.0);
+    if (smax == 0.0) return 0.0;
+    const double lam = rel * smax * smax;
+    const double cutoff = eps * std::max(m, k) * smax;
+    std::vector<double> uty(n);
+    for (int j = 0; j < k; ++j) {
+        if (lam == 0.0 && sig[j] <= cutoff) continue;
+        const double g = (lam == 0.0) ? 1.0 / sig[j] : sig[j] / (sig[j] * sig[j] + lam);
+        // u_j^T Y with u_j = col_j / sigma_j
+        std::fill(uty.begin(), uty.end(), 0.0);
+        for (int i = 0; i < m; ++i) {
+            const double u = cols[(size_t)j * m + i] / sig[j];
+            const double* yr = Y + (size_t)i * n;
+            for (int c = 0; c < n; ++c) uty[c] += u * yr[c];
+        }
+        const double* wj = &W[(size_t)j * k];
+        for (int r = 0; r < k; ++r) {
+            const double f = wj[r] * g;
+            double* br = B + (size_t)r * n;
+            for (int c = 0; c < n; ++c) br[c] += f * uty[c];
+        }
+    }
+    return lam;
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver for the top k eigenpairs.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Fork-join pool whose workers spin between back-to-back parallel regions
+// (the tridiagonalisation issues two regions per column) and sleep when the
+// pool is released.
+class Pool {
+  public:
+    explicit Pool(int n) : n_(std::max(1, n)) {
+        for (int t = 1; t < n_; ++t) th_.emplace_back([this, t] { worker(t); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    int size() const { return n_; }
+    // run fn(tid, nthreads) on every thread, return when all are done
+    void run(const std::function<void(int, int)>& fn) {
+        job_ = &fn;
+        done_.store(0);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        fn(0, n_);
+        while (done_.load(std::memory_order_acquire) != n_ - 1) std::this_thread::yield();
+    }
+
+  private:
+    void worker(int tid) {
+        int64_t seen = 0;
+        for (;;) {
+            int spins = 0;
+            while (gen_.load(std::memory_order_acquire) == seen) {
+                if (++spins > 20000) {
+                    std::unique_lock<std::mutex> lk(mu_);
+                    cv_.wait(lk, [&] { return gen_.load() != seen; });
+                    break;
+                }
+                std::this_thread::yield();
+            }
+            seen = gen_.load(std::memory_order_acquire);
+            if (stop_) return;
+            (*job_)(tid, n_);
+            done_.fetch_add(1, std::memory_order_release);
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::atomic<int64_t> gen_{0};
+    std::atomic<int> done_{0};
+    const std::function<void(int, int)>* job_ = nullptr;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    bool stop_ = false;
+};
+
+inline void split(int lo, int hi, int tid, int nt, int* a, int* b) {
+    const int len = hi - lo;
+    *a = lo + (int)((int64_t)len * tid / nt);
+    *b = lo + (int)((int64_t)len * (tid + 1) / nt);
+}
+
+// Number of eigenvalues of the tridiagonal (d, e) that are smaller than x.
+int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+    int count = 0;
+    double q = d[0] - x;
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++count;
+    for (int i = 1; i < n; ++i) {
+        q = d[i] - x - e2[i - 1] / q;
+        if (std::fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) ++count;
+    }
+    return count;
+}
+
+// Solve (T - lam I) x = b for tridiagonal T by Gaussian elimination with
+// partial pivoting (row interchanges between neighbours).  b is overwritten.
+void tri_shift_solve(const double* d, const double* e, int n, double lam, double pivmin, double* b,
+                     std::vector<double>& dl, std::vector<double>& dd, std::vector<double>& du,
+                     std::vector<double>& du2, std::vector<char>& swap) {
+    dl.assign(e, e + n - 1);
+    dd.resize(n);
+    for (int i = 0; i < n; ++i) dd[i] = d[i] - lam;
+    du.assign(e, e + n - 1);
+    du2.assign(std::max(n - 2, 0), 0.0);
+    swap.assign(n, 0);
+    for (int i = 0; i + 1 < n; ++i) {
+        if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+            if (std::fabs(dd[i]) < pivmin) dd[i] = (dd[i] < 0 ? -pivmin : pivmin);
+            const double f = dl[i] / dd[i];
+            dl[i] = f;
+            dd[i + 1] -= f * du[i];
+        } else {
+            const double f = dd[i] / dl[i];
+            dd[i] = dl[i];
+            dl[i] = f;
+            const double t = du[i];
+            du[i] = dd[i + 1];
+            dd[i + 1] = t - f * dd[i + 1];
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
+            }
+            swap[i] = 1;
+        }
+    }
+    if (std::fabs(dd[n - 1]) < pivmin) dd[n - 1] = (dd[n - 1] < 0 ? -pivmin : pivmin);
+    for (int i = 0; i + 1 < n; ++i) {
+        if (swap[i]) std::swap(b[i], b[i + 1]);
+        b[i + 1] -= dl[i] * b[i];
+    }
+    b[n - 1] /= dd[n - 1];
+    if (n >= 2) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
+    for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+}
+
+}  // namespace
+
+int eigh_topk(const double* a_in, int n, int k, double* vals, double* vecs, int threads) {
+    if (n <= 0 || k <= 0 || k > n) return -1;
+    std::vector<double> A(a_in, a_in + (size_t)n * n);
+    std::vector<double> d(n), e(std::max(n - 1, 1), 0.0);
+    std::vector<double> vstore;          // Householder vectors, packed
+    std::vector<size_t> voff(std::max(n - 2, 0));
+    std::vector<double> beta(std::max(n - 2, 0), 0.0);
+    Pool pool(std::max(1, std::min(threads, n / 64 + 1)));
+    const int nt = pool.size();
+    std::vector<double> p(n), w(n), v(n);
+    std::vector<double> partial(nt);
+
+    // ---- Householder reduction to tridiagonal form: A <- H A H ----
+    size_t total = 0;
+    for (int i = 0; i + 2 < n; ++i) { voff[i] = total; total += n - i - 1; }
+    vstore.resize(std::max<size_t>(total, 1));
+    for (int i = 0; i + 2 < n; ++i) {
+        const int lo = i + 1, m = n - lo;
+        const double* x = &A[(size_t)i * n + lo];  // row i == column i
+        double sig2 = 0.0;
+        for (int j = 1; j < m; ++j) sig2 += x[j] * x[j];
+        const double x0 = x[0];
+        d[i] = A[(size_t)i * n + i];
+        if (sig2 == 0.0) {
+            e[i] = x0;
+            beta[i] = 0.0;
+            double* vs = &vstore[voff[i]];
+            for (int j = 0; j < m; ++j) vs[j] = 0.0;
+            continue;
+        }
+        const double norm = std::sqrt(x0 * x0 + sig2);
+        const double alpha = (x0 >= 0) ? -norm : norm;
+        for (int j = 0; j < m; ++j) v[j] = x[j];
+        v[0] = x0 - alpha;
+        const double vtv = v[0] * v[0] + sig2;
+        const double b = 2.0 / vtv;
+        e[i] = alpha;
+        beta[i] = b;
+        std::copy(v.begin(), v.begin() + m, vstore.begin() + voff[i]);
+        // p = b * B v, B the trailing block (rows/cols lo..n-1)
+        pool.run([&](int tid, int nthr) {
+            int r0, r1;
+            split(lo, n, tid, nthr, &r0, &r1);
+            double dot = 0.0;
+            for (int r = r0; r < r1; ++r) {
+                const double* row = &A[(size_t)r * n + lo];
+                double s = 0.0;
+                for (int c = 0; c < m; ++c) s += row[c] * v[c];
+                p[r - lo] = b * s;
+                dot += p[r - lo] * v[r - lo];
+            }
+            partial[tid] = dot;
+        });
+        double ptv = 0.0;
+        for (int t = 0; t < nt; ++t) ptv += partial[t];
+        const double kk = 0.5 * b * ptv;
+        for (int j = 0; j < m; ++j) w[j] = p[j] - kk * v[j];
+        // B <- B - v w^T - w v^T
+        pool.run([&](int tid, int nthr) {
+            int r0, r1;
+            split(lo, n, tid, nthr, &r0, &r1);
+            for (int r = r0; r < r1; ++r) {
+                double* row = &A[(size_t)r * n + lo];
+                const double vr = v[r - lo], wr = w[r - lo];
+                for (int c = 0; c < m; ++c) row[c] -= vr * w[c] + wr * v[c];
+            }
+        });
+    }
+    if (n >= 2) {
+        d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)];
+        e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+    }
+    d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
+
+    // ---- eigenvalues by bisection (Sturm counts) ----
+    double tnorm = 0.0, lo = std::numeric_limits<double>::max(), hi = -lo;
+    std::vector<double> e2(std::max(n - 1, 1), 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+        tnorm = std::max(tnorm, std::fabs(d[i]) + r);
+        if (i + 1 < n) e2[i] = e[i] * e[i];
+    }
+    const double eps = std::numeric_limits<double>::epsilon();
+    const double pivmin = std::max(std::numeric_limits<double>::min(), tnorm * eps * eps);
+    if (tnorm == 0.0) {  // zero matrix: eigenvalues 0, unit vectors
+        for (int j = 0; j < k; ++j) vals[j] = 0.0;
+        for (int r = 0; r < n; ++r)
+            for (int j = 0; j < k; ++j) vecs[(size_t)r * k + j] = (r == j) ? 1.0 : 0.0;
+        return 0;
+    }
+    lo -= 2 * eps * tnorm;
+    hi += 2 * eps * tnorm;
+    pool.run([&](int tid, int nthr) {
+        int j0, j1;
+        split(0, k, tid, nthr, &j0, &j1);
+        for (int j = j0; j < j1; ++j) {
+            const int idx = n - 1 - j;  // ascending index of the j-th largest
+            double a = lo, b = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (a + b);
+                if (b - a <= 2 * eps * std::max(std::fabs(a), std::fabs(b)) + pivmin) break;
+                if (mid <= a || mid >= b) break;
+                if (sturm_count(d.data(), e2.data(), n, mid, pivmin) > idx) b = mid;
+                else a = mid;
+            }
+            vals[j] = 0.5 * (a + b);
+        }
+    });
+
+    // ---- eigenvectors of T by inverse iteration, re-orthogonalised within
+    //      clusters of close eigenvalues ----
+    std::vector<double> Y((size_t)k * n);  // vector j at j*n
+    {
+        std::vector<double> dl, dd, du, du2, b(n);
+        std::vector<char> sw;
+        const double ortol = 1e-3 * tnorm;
+        int cluster_start = 0;
+        for (int j = 0; j < k; ++j) {
+            if (j > 0 && std::fabs(vals[j - 1] - vals[j]) > ortol) cluster_start = j;
+            // deterministic start vector
+            uint64_t state = 0x9E3779B97F4A7C15ull + (uint64_t)j;
+            for (int i = 0; i < n; ++i) {
+                state = state * 6364136223846793005ull + 1442695040888963407ull;
+                b[i] = 0.5 + (double)(state >> 11) * (1.0 / 9007199254740992.0);
+            }
+            // a tiny shift separates equal eigenvalues of a cluster
+            double lam = vals[j];
+            const int iters = (j > cluster_start) ? 5 : 3;
+            for (int it = 0; it < iters; ++it) {
+                tri_shift_solve(d.data(), e.data(), n, lam, pivmin + eps * tnorm, b.data(), dl, dd, du, du2, sw);
+                for (int c = cluster_start; c < j; ++c) {
+                    const double* yc = &Y[(size_t)c * n];
+                    double s = 0.0;
+                    for (int i = 0; i < n; ++i) s += yc[i] * b[i];
+                    for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
+                }
+                double nrm = 0.0;
+                for (int i = 0; i < n; ++i) nrm += b[i] * b[i];
+                nrm = std::sqrt(nrm);
+                if (!(nrm > 0.0) || !std::isfinite(nrm)) return -2;
+                for (int i = 0; i < n; ++i) b[i] /= nrm;
+            }
+            std::copy(b.begin(), b.end(), Y.begin() + (size_t)j * n);
+        }
+    }
+
+    // ---- back-transformation x = H_0 H_1 ... H_{n-3} y ----
+    pool.run([&](int tid, int nthr) {
+        int j0, j1;
+        split(0, k, tid, nthr, &j0, &j1);
+        for (int j = j0; j < j1; ++j) {
+            double* y = &Y[(size_t)j * n];
+            for (int i = n - 3; i >= 0; --i) {
+                if (beta[i] == 0.0) continue;
+                const int lo2 = i + 1, m = n - lo2;
+                const double* vs = &vstore[voff[i]];
+                double s = 0.0;
+                for (int c = 0; c < m; ++c) s += vs[c] * y[lo2 + c];
+                s *= beta[i];
+                for (int c = 0; c < m; ++c) y[lo2 + c] -= s * vs[c];
+            }
+            // sign: largest-magnitude entry positive (first on ties)
+            int imax = 0;
+            for (int r = 1; r < n; ++r)
+                if (std::fabs(y[r]) > std::fabs(y[imax])) imax = r;
+            const double sg = (y[imax] < 0) ? -1.0 : 1.0;
+            for (int r = 0; r < n; ++r) vecs[(size_t)r * k + j] = sg * y[r];
+        }
+    });
+    return 0;
+}
+
+}  // namespace fkk

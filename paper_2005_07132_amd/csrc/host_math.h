@@ -1,0 +1,46 @@
+// FP64 host-side numerics of fKK-EC that act on the k basis vectors or on
+// the N x N Gram matrix (never on the M spectra): FFT-based Hilbert
+// transform, ALS / Whittaker detrending, Savitzky-Golay trendline, ridge
+// regression through a one-sided Jacobi SVD, and a top-k symmetric
+// eigensolver.  Plain C++ (no HIP), so it can be built and checked on any
+// host.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace fkk {
+
+// Discrete Hilbert transform of each of `rows` rows of x (rows x n,
+// row-major) into y: centred padding to `len` points (edge replication or
+// zeros), multiplication of DFT bin nu by -i sgn(nu) (0 at DC and Nyquist),
+// inverse DFT, real part, crop.  len must be a power of two >= n.
+void hilbert_rows(const double* x, double* y, int rows, int n, int len, int pad_mode);
+
+// Baseline by asymmetric least squares: n_iter solves of
+// (diag(w) + lam D^T D) z = w * y, weights p above the baseline, 1 - p
+// elsewhere, starting from w = 1.  detrend == 1 (Whittaker) is one solve
+// with w = 1.
+void detrend_row(const double* y, double* z, int n, int mode, double lam, double p, int n_iter);
+
+// Trendline of each row: Savitzky-Golay (window, order) with least-squares
+// polynomial fits on the first / last window near the ends, or the mean.
+void trendline_rows(const double* x, double* y, int rows, int n, int mode, int window, int order);
+
+// Ridge regression B = (X^T X + lam I)^-1 X^T Y (X: m x k, Y: m x n,
+// B: k x n) with lam = rel * sigma_max(X)^2; rel = 0 gives the minimum-norm
+// least-squares solution.  Returns lam.  X = 0 gives B = 0.
+double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k, int n, double rel);
+
+// Top-k eigenpairs of the symmetric n x n matrix a (row-major): values in
+// descending order, vectors as the columns of vecs (n x k row-major), each
+// with its largest-magnitude entry positive.  Uses `threads` host threads.
+// Returns 0 on success.
+int eigh_topk(const double* a, int n, int k, double* vals, double* vecs, int threads);
+
+// Default readings of parameters the paper leaves open.
+int default_fft_len(int n);
+double default_als_lambda(int n);
+int default_sg_window(int n);
+
+}  // namespace fkk

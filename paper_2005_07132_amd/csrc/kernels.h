@@ -1,0 +1,66 @@
+// Launch interface of the gfx950 kernels of the fKK-EC hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fkk {
+namespace dev {
+
+// Gram of the log ratio: tiles of 128 x 128 over the upper triangle, split
+// over chunks of rows (a multiple of 8 chunks so that all tiles of a chunk
+// run on one XCD).
+constexpr int kGramTile = 128;
+
+struct GramPlan {
+    int nb = 0;        // column blocks of 128
+    int tiles = 0;     // upper-triangle tiles nb(nb+1)/2
+    int chunks = 0;    // row chunks (multiple of 8)
+    int64_t rows_per_chunk = 0;
+    size_t partial_floats() const { return (size_t)chunks * tiles * kGramTile * kGramTile; }
+};
+GramPlan gram_plan(int64_t M, int N, int target_chunks);
+
+// d_tiles: int2[tiles] (bi <= bj) written by the caller from gram_tile_list.
+void gram_tile_list(int nb, int* host_pairs /* 2 * tiles */);
+
+hipError_t launch_gram(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                       const GramPlan& plan, const int* d_tiles, float* partial, double* colsum_part,
+                       unsigned long long* clamps, hipStream_t s);
+hipError_t launch_gram_reduce(const float* partial, const double* colsum_part, const GramPlan& plan,
+                              const int* d_tiles, int N, double* G, double* colsum, hipStream_t s);
+
+// Projection Z = l W (W given transposed: Wt is kp x ldw, zero beyond k / N),
+// with per-block column arg-extrema partials when part != nullptr.
+struct ArgPart {
+    float* maxv;
+    float* minv;
+    long long* maxi;
+    long long* mini;
+};
+constexpr int kProjRows = 128;
+inline int64_t proj_blocks(int64_t M) { return (M + kProjRows - 1) / kProjRows; }
+hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                          const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z,
+                          ArgPart part, int k_arg, hipStream_t s);
+hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
+                                long long* qmin, hipStream_t s);
+
+// Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im); BT holds
+// [B_re^T | B_im^T] as two (ldb_rows x kp) blocks (rows = wavenumbers).
+hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, const float* BreT,
+                              const float* BimT, int kp, int N, float* out, int64_t ld_out, int plane,
+                              hipStream_t s);
+
+// Fused stored-basis transform: projection onto Wt then reconstruction.
+hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                            const float* Wt, int ldw, int kp, const float* BreT, const float* BimT,
+                            float* out, int64_t ld_out, int plane, hipStream_t s);
+
+// Gather rows q of Z (k columns) into X (n_q x k, FP32).
+hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long long* q, int n_q, float* X,
+                              hipStream_t s);
+
+}  // namespace dev
+}  // namespace fkk

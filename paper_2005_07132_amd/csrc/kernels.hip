@@ -1,0 +1,764 @@
+// gfx950 kernels of the fKK-EC hot path: log ratio + Gram (Eq. 2, 6),
+// projection with per-column arg-extrema (Eq. 13-15, 25), and the
+// reconstruction GEMM fused with the exp / sin epilogue (Eq. 23).
+//
+// Matrix products use v_mfma_f32_16x16x4_f32 (FP32 in, FP32 accumulate).
+// For a 16x16x4 block, lane l holds A[l%16][l/16] and B[l/16][l%16] and
+// receives D[4*(l/16)+v][l%16] in accumulator element v.  Which physical
+// row or column plays "k" inside a block is free as long as A and B agree,
+// which lets every lane read four consecutive k values with one 128-bit
+// LDS load.
+#include "kernels.h"
+
+#include <climits>
+#include <cmath>
+
+namespace fkk {
+namespace dev {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// l = 1/2 ln(x r); ratios that are not finite or not above the floor are
+// replaced by the floor.
+__device__ __forceinline__ float log_ratio(float x, float r, float floor, bool& bad) {
+    float q = x * r;
+    bad = !(q > floor && q < INFINITY);
+    q = bad ? floor : q;
+    return 0.5f * logf(q);
+}
+
+__device__ __forceinline__ float4 load4_guarded(const float* row, int col, int N, bool vec) {
+    if (vec && col + 3 < N) return *reinterpret_cast<const float4*>(row + col);
+    float4 v;
+    v.x = (col + 0 < N) ? row[col + 0] : 0.f;
+    v.y = (col + 1 < N) ? row[col + 1] : 0.f;
+    v.z = (col + 2 < N) ? row[col + 2] : 0.f;
+    v.w = (col + 3 < N) ? row[col + 3] : 0.f;
+    return v;
+}
+
+__device__ __forceinline__ float f4get(const float4& v, int q) {
+    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// ===========================================================================
+// Gram of the log ratio.
+// ===========================================================================
+constexpr int GT = kGramTile;  // output tile
+constexpr int GKC = 32;        // rows per LDS stage
+constexpr int GLD = GT + 16;   // LDS row stride: rows 0/1 of a wave read hit disjoint banks
+
+GramPlan gram_plan(int64_t M, int N, int target_chunks) {
+    GramPlan p;
+    p.nb = (N + GT - 1) / GT;
+    p.tiles = p.nb * (p.nb + 1) / 2;
+    int64_t want = target_chunks > 0 ? target_chunks : 64;
+    int64_t rpc = (M + want - 1) / want;
+    rpc = ((rpc + GKC - 1) / GKC) * GKC;
+    if (rpc < GKC) rpc = GKC;
+    int64_t chunks = (M + rpc - 1) / rpc;
+    if (chunks < 1) chunks = 1;
+    chunks = ((chunks + 7) / 8) * 8;
+    p.chunks = (int)chunks;
+    p.rows_per_chunk = rpc;
+    return p;
+}
+
+void gram_tile_list(int nb, int* pairs) {
+    int t = 0;
+    for (int bi = 0; bi < nb; ++bi)
+        for (int bj = bi; bj < nb; ++bj) {
+            pairs[2 * t] = bi;
+            pairs[2 * t + 1] = bj;
+            ++t;
+        }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                   const float* __restrict__ rinv, float floor, int T,
+                                                   int64_t rpc, const int* __restrict__ tiles,
+                                                   float* __restrict__ partial,
+                                                   double* __restrict__ colsum_part,
+                                                   unsigned long long* __restrict__ clamps) {
+    __shared__ __attribute__((aligned(16))) float sA[2][GKC][GLD];
+    __shared__ __attribute__((aligned(16))) float sB[2][GKC][GLD];
+
+    // blockIdx -> (chunk, tile): consecutive blocks go to different XCDs, so
+    // the 8 XCDs each take every 8th chunk and run all tiles of a chunk.
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int rr = b >> 3;
+    const int tile = rr % T;
+    const int chunk = (rr / T) * 8 + xcd;
+    const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
+    const bool diag = (bi == bj);
+    const int64_t m0 = (int64_t)chunk * rpc;
+    const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = tid >> 5;
+    const int lc = (tid & 31) * 4;
+    const int ca = bi * GT + lc, cb = bj * GT + lc;
+
+    float ra[4], rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ra[q] = (ca + q < N) ? rinv[ca + q] : 0.f;
+        rb[q] = (cb + q < N) ? rinv[cb + q] : 0.f;
+    }
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 xa[4], xb[4];
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
+    unsigned int cnt = 0;
+
+    auto load = [&](int64_t base) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int64_t row = base + lr + 8 * p;
+            if (row < m1) {
+                const float* src = I + row * ld;
+                xa[p] = load4_guarded(src, ca, N, VEC);
+                if (!diag) xb[p] = load4_guarded(src, cb, N, VEC);
+            } else {
+                xa[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                xb[p] = xa[p];
+            }
+        }
+    };
+    auto store = [&](int buf, int64_t base) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int64_t row = base + lr + 8 * p;
+            const bool rv = row < m1;
+            float la[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                la[q] = 0.f;
+                if (rv && ca + q < N) {
+                    bool bad;
+                    const float x = f4get(xa[p], q);
+                    la[q] = log_ratio(x, ra[q], floor, bad);
+                    if (diag) {
+                        cnt += bad ? 1u : 0u;
+                        cs[q] += (double)x;
+                    }
+                }
+            }
+            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) = make_float4(la[0], la[1], la[2], la[3]);
+            if (!diag) {
+                float lb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lb[q] = 0.f;
+                    if (rv && cb + q < N) {
+                        bool bad;
+                        lb[q] = log_ratio(f4get(xb[p], q), rb[q], floor, bad);
+                    }
+                }
+                *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) = make_float4(lb[0], lb[1], lb[2], lb[3]);
+            }
+        }
+    };
+
+    const int64_t nst = (m1 > m0) ? (m1 - m0 + GKC - 1) / GKC : 0;
+    if (nst > 0) {
+        load(m0);
+        store(0, m0);
+    }
+    __syncthreads();
+    for (int64_t s = 0; s < nst; ++s) {
+        const int buf = (int)(s & 1);
+        if (s + 1 < nst) load(m0 + (s + 1) * GKC);
+        const float(*A)[GLD] = sA[buf];
+        const float(*B)[GLD] = diag ? sA[buf] : sB[buf];
+#pragma unroll
+        for (int ks = 0; ks < GKC / 4; ++ks) {
+            const int row = ks * 4 + (lane >> 4);
+            float av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = A[row][wr * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = B[row][wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(av[i], bv[j], acc[i][j]);
+        }
+        if (s + 1 < nst) store(buf ^ 1, m0 + (s + 1) * GKC);
+        __syncthreads();
+    }
+
+    float* P = partial + ((size_t)chunk * T + tile) * (size_t)(GT * GT);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr * 64 + i * 16 + 4 * (lane >> 4) + v;
+                const int c = wc * 64 + j * 16 + (lane & 15);
+                P[r * GT + c] = acc[i][j][v];
+            }
+
+    if (diag) {
+        double* scs = reinterpret_cast<double*>(&sA[0][0][0]);  // 8 x GT doubles
+#pragma unroll
+        for (int q = 0; q < 4; ++q) scs[lr * GT + lc + q] = cs[q];
+        __syncthreads();
+        if (tid < GT) {
+            double t = 0.0;
+            for (int g = 0; g < 8; ++g) t += scs[g * GT + tid];
+            const int col = bi * GT + tid;
+            if (col < N) colsum_part[(size_t)chunk * N + col] = t;
+        }
+        unsigned int c = cnt;
+        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0 && c) atomicAdd(clamps, (unsigned long long)c);
+    }
+}
+
+__global__ void gram_reduce_kernel(const float* __restrict__ partial, int T, int C,
+                                   const int* __restrict__ tiles, int N, double* __restrict__ G) {
+    const int tile = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= GT * GT) return;
+    const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
+    double s = 0.0;
+    for (int ch = 0; ch < C; ++ch) s += (double)partial[((size_t)ch * T + tile) * (size_t)(GT * GT) + e];
+    const int r = e / GT, c = e % GT;
+    const int gi = bi * GT + r, gj = bj * GT + c;
+    if (gi >= N || gj >= N) return;
+    if (bi != bj || r <= c) {
+        G[(size_t)gi * N + gj] = s;
+        G[(size_t)gj * N + gi] = s;
+    }
+}
+
+__global__ void colsum_reduce_kernel(const double* __restrict__ part, int C, int N, double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int ch = 0; ch < C; ++ch) s += part[(size_t)ch * N + j];
+    out[j] = s;
+}
+
+hipError_t launch_gram(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                       const GramPlan& plan, const int* d_tiles, float* partial, double* colsum_part,
+                       unsigned long long* clamps, hipStream_t s) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(256);
+    if (vec)
+        hipLaunchKernelGGL(gram_kernel<true>, grid, block, 0, s, I, M, N, ld, rinv, floor, plan.tiles,
+                           plan.rows_per_chunk, d_tiles, partial, colsum_part, clamps);
+    else
+        hipLaunchKernelGGL(gram_kernel<false>, grid, block, 0, s, I, M, N, ld, rinv, floor, plan.tiles,
+                           plan.rows_per_chunk, d_tiles, partial, colsum_part, clamps);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const float* partial, const double* colsum_part, const GramPlan& plan,
+                              const int* d_tiles, int N, double* G, double* colsum, hipStream_t s) {
+    dim3 grid(GT * GT / 256, plan.tiles);
+    hipLaunchKernelGGL(gram_reduce_kernel, grid, dim3(256), 0, s, partial, plan.tiles, plan.chunks, d_tiles, N, G);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, colsum_part, plan.chunks, N,
+                       colsum);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Projection Z = l W with per-column arg-extrema.
+// ===========================================================================
+constexpr int PR = kProjRows;  // rows per block (4 waves x 32)
+constexpr int PNC = 64;        // wavenumbers per LDS stage
+constexpr int PLD = PNC + 4;
+
+// Stage one 128 x 64 tile of l = 1/2 ln(I r) into LDS (zeros outside).
+template <bool VEC>
+__device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __restrict__ I, int64_t r0,
+                                               int64_t M, int N, int64_t ld, int j0,
+                                               const float* __restrict__ rinv, float floor) {
+    const int tid = threadIdx.x;
+    const int lrow = tid >> 4;
+    const int lcol = (tid & 15) * 4;
+    const int col = j0 + lcol;
+    float r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = (col + q < N) ? rinv[col + q] : 0.f;
+    float4 x[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int64_t row = r0 + lrow + 16 * p;
+        x[p] = (row < M) ? load4_guarded(I + row * ld, col, N, VEC) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int64_t row = r0 + lrow + 16 * p;
+        float l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bool bad;
+            l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], floor, bad) : 0.f;
+        }
+        *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
+    }
+}
+
+template <int KB>
+__device__ __forceinline__ void stage_weights(float (*sW)[PLD], const float* __restrict__ Wt, int ldw, int j0) {
+    const int tid = threadIdx.x;
+    const int lcol = (tid & 15) * 4;
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        const int c = (tid >> 4) + 16 * p;
+        *reinterpret_cast<float4*>(&sW[c][lcol]) =
+            *reinterpret_cast<const float4*>(Wt + (size_t)c * ldw + j0 + lcol);
+    }
+}
+
+// acc[rb][cb] += l(rows of this wave) * W over one 64-wide stage
+template <int KB>
+__device__ __forceinline__ void project_stage(floatx4 (&acc)[2][KB], const float (*sL)[PLD],
+                                              const float (*sW)[PLD], int wave, int lane) {
+#pragma unroll
+    for (int gq = 0; gq < PNC / 16; ++gq) {
+        float4 a[2], w[KB];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            a[rb] = *reinterpret_cast<const float4*>(&sL[wave * 32 + rb * 16 + (lane & 15)][gq * 16 + 4 * (lane >> 4)]);
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb)
+            w[cb] = *reinterpret_cast<const float4*>(&sW[cb * 16 + (lane & 15)][gq * 16 + 4 * (lane >> 4)]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = mfma4(f4get(a[rb], q), f4get(w[cb], q), acc[rb][cb]);
+    }
+}
+
+__device__ __forceinline__ void better_max(float& v, int& i, float ov, int oi) {
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+__device__ __forceinline__ void better_min(float& v, int& i, float ov, int oi) {
+    if (ov < v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+template <int KB, bool VEC>
+__global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                      const float* __restrict__ rinv, float floor,
+                                                      const float* __restrict__ Wt, int ldw, int k_store,
+                                                      float* __restrict__ Z, int64_t ld_z, float* pmaxv,
+                                                      float* pminv, long long* pmaxi, long long* pmini,
+                                                      int k_arg) {
+    constexpr int KP = KB * 16;
+    __shared__ __attribute__((aligned(16))) float sL[PR][PLD];
+    __shared__ __attribute__((aligned(16))) float sW[KP][PLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * PR;
+
+    floatx4 acc[2][KB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int j0 = 0; j0 < N; j0 += PNC) {
+        stage_logratio<VEC>(sL, I, r0, M, N, ld, j0, rinv, floor);
+        stage_weights<KB>(sW, Wt, ldw, j0);
+        __syncthreads();
+        project_stage<KB>(acc, sL, sW, wave, lane);
+        __syncthreads();
+    }
+
+    // Z[row][c]: acc[rb][cb][v], row = wave*32 + rb*16 + 4*(lane/16) + v, c = cb*16 + lane%16
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+                const int c = cb * 16 + (lane & 15);
+                if (row < M && c < k_store) Z[row * ld_z + c] = acc[rb][cb][v];
+            }
+
+    if (pmaxv == nullptr) return;
+    __shared__ float smx[4][KP], smn[4][KP];
+    __shared__ int smxi[4][KP], smni[4][KP];
+#pragma unroll
+    for (int cb = 0; cb < KB; ++cb) {
+        float mx = -INFINITY, mn = INFINITY;
+        int ix = INT_MAX, in = INT_MAX;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+                if (r0 + rl < M) {
+                    better_max(mx, ix, acc[rb][cb][v], rl);
+                    better_min(mn, in, acc[rb][cb][v], rl);
+                }
+            }
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+            const float omx = __shfl_xor(mx, off), omn = __shfl_xor(mn, off);
+            const int oix = __shfl_xor(ix, off), oin = __shfl_xor(in, off);
+            better_max(mx, ix, omx, oix);
+            better_min(mn, in, omn, oin);
+        }
+        if (lane < 16) {
+            smx[wave][cb * 16 + lane] = mx;
+            smxi[wave][cb * 16 + lane] = ix;
+            smn[wave][cb * 16 + lane] = mn;
+            smni[wave][cb * 16 + lane] = in;
+        }
+    }
+    __syncthreads();
+    if (tid < KP && tid < k_arg) {
+        float mx = smx[0][tid], mn = smn[0][tid];
+        int ix = smxi[0][tid], in = smni[0][tid];
+        for (int w = 1; w < 4; ++w) {
+            better_max(mx, ix, smx[w][tid], smxi[w][tid]);
+            better_min(mn, in, smn[w][tid], smni[w][tid]);
+        }
+        const size_t o = (size_t)blockIdx.x * KP + tid;
+        pmaxv[o] = mx;
+        pminv[o] = mn;
+        pmaxi[o] = (ix == INT_MAX) ? -1 : (long long)(r0 + ix);
+        pmini[o] = (in == INT_MAX) ? -1 : (long long)(r0 + in);
+    }
+}
+
+__global__ void argext_reduce_kernel(ArgPart part, int64_t nblocks, int kp, long long* qmax, long long* qmin) {
+    const int c = blockIdx.x;
+    float mx = -INFINITY, mn = INFINITY;
+    long long ix = LLONG_MAX, in = LLONG_MAX;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        const size_t o = (size_t)b * kp + c;
+        const long long bi = part.maxi[o], ni = part.mini[o];
+        if (bi >= 0 && (part.maxv[o] > mx || (part.maxv[o] == mx && bi < ix))) { mx = part.maxv[o]; ix = bi; }
+        if (ni >= 0 && (part.minv[o] < mn || (part.minv[o] == mn && ni < in))) { mn = part.minv[o]; in = ni; }
+    }
+    __shared__ float smx[256], smn[256];
+    __shared__ long long sx[256], sn[256];
+    smx[threadIdx.x] = mx; smn[threadIdx.x] = mn; sx[threadIdx.x] = ix; sn[threadIdx.x] = in;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            const int o = threadIdx.x + st;
+            if (smx[o] > smx[threadIdx.x] || (smx[o] == smx[threadIdx.x] && sx[o] < sx[threadIdx.x])) {
+                smx[threadIdx.x] = smx[o]; sx[threadIdx.x] = sx[o];
+            }
+            if (smn[o] < smn[threadIdx.x] || (smn[o] == smn[threadIdx.x] && sn[o] < sn[threadIdx.x])) {
+                smn[threadIdx.x] = smn[o]; sn[threadIdx.x] = sn[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        qmax[c] = (sx[0] == LLONG_MAX) ? -1 : sx[0];
+        qmin[c] = (sn[0] == LLONG_MAX) ? -1 : sn[0];
+    }
+}
+
+template <int KB>
+static hipError_t project_dispatch(bool vec, dim3 grid, hipStream_t s, const float* I, int64_t M, int N, int64_t ld,
+                                   const float* rinv, float floor, const float* Wt, int ldw, int k_store, float* Z,
+                                   int64_t ld_z, ArgPart part, int k_arg) {
+    if (vec)
+        hipLaunchKernelGGL((project_kernel<KB, true>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,
+                           k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);
+    else
+        hipLaunchKernelGGL((project_kernel<KB, false>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,
+                           k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                          const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z, ArgPart part,
+                          int k_arg, hipStream_t s) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    dim3 grid((unsigned)proj_blocks(M));
+    switch (kp) {
+        case 16: return project_dispatch<1>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 32: return project_dispatch<2>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 64: return project_dispatch<4>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 128: return project_dispatch<8>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax, long long* qmin,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(argext_reduce_kernel, dim3(k), dim3(256), 0, s, part, nblocks, kp, qmax, qmin);
+    return hipGetLastError();
+}
+
+__global__ void gather_rows_kernel(const float* __restrict__ Z, int64_t ld_z, int k, const long long* __restrict__ q,
+                                   int n_q, float* __restrict__ X) {
+    const int r = blockIdx.x;
+    if (r >= n_q) return;
+    const long long row = q[r];
+    for (int c = threadIdx.x; c < k; c += blockDim.x) X[(size_t)r * k + c] = Z[row * ld_z + c];
+}
+
+hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long long* q, int n_q, float* X,
+                              hipStream_t s) {
+    if (n_q <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(n_q), dim3(64), 0, s, Z, ld_z, k, q, n_q, X);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im).
+// The product is formed transposed (A = B^T, B = Z^T) so that every lane
+// ends with four consecutive wavenumbers of one spectrum: one 128-bit store.
+// ===========================================================================
+constexpr int RR = 128;  // rows per block (4 waves x 32)
+constexpr int RCN = 64;  // wavenumbers per chunk
+
+__device__ __forceinline__ float epilogue(float re, float im, int plane) {
+    const float mag = expf(re);
+    if (plane == 0) return mag * sinf(im);
+    if (plane == 1) return mag * cosf(im);
+    return mag;
+}
+
+template <int KB>
+__device__ __forceinline__ void recon_chunk(const float4 (&zf)[2][KB], const float* sRe, const float* sIm, int bld,
+                                            int lane, floatx4 (&are)[4][2], floatx4 (&aim)[4][2]) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            are[ib][jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            aim[ib][jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+    for (int kg = 0; kg < KB; ++kg)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const int off = (ib * 16 + (lane & 15)) * bld + kg * 16 + 4 * (lane >> 4);
+            const float4 bre = *reinterpret_cast<const float4*>(sRe + off);
+            const float4 bim = *reinterpret_cast<const float4*>(sIm + off);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) {
+                    are[ib][jb] = mfma4(f4get(bre, q), f4get(zf[jb][kg], q), are[ib][jb]);
+                    aim[ib][jb] = mfma4(f4get(bim, q), f4get(zf[jb][kg], q), aim[ib][jb]);
+                }
+        }
+}
+
+template <int KB>
+__device__ __forceinline__ void stage_basis_chunk(float* sRe, float* sIm, int bld, const float* __restrict__ BreT,
+                                                  const float* __restrict__ BimT, int j0) {
+    constexpr int KP = KB * 16;
+    constexpr int PER_ROW = KP / 4;  // float4 per row
+    constexpr int TOTAL = RCN * PER_ROW;
+    for (int idx = threadIdx.x; idx < TOTAL; idx += 256) {
+        const int jr = idx / PER_ROW, c4 = (idx % PER_ROW) * 4;
+        const size_t src = (size_t)(j0 + jr) * KP + c4;
+        *reinterpret_cast<float4*>(sRe + jr * bld + c4) = *reinterpret_cast<const float4*>(BreT + src);
+        *reinterpret_cast<float4*>(sIm + jr * bld + c4) = *reinterpret_cast<const float4*>(BimT + src);
+    }
+}
+
+template <bool VEC_OUT>
+__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
+                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
+                                          const floatx4 (&aim)[4][2], int plane) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
+            const int col = j0 + ib * 16 + 4 * (lane >> 4);
+            if (row >= M) continue;
+            float o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = epilogue(are[ib][jb][v], aim[ib][jb][v], plane);
+            float* dst = out + row * ld_out + col;
+            if (VEC_OUT && col + 3 < N) {
+                *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (col + v < N) dst[v] = o[v];
+            }
+        }
+}
+
+template <int KB, bool VEC_OUT>
+__global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
+                                                    const float* __restrict__ BreT, const float* __restrict__ BimT,
+                                                    int N, float* __restrict__ out, int64_t ld_out, int plane) {
+    constexpr int KP = KB * 16;
+    constexpr int BLD = KP + 4;
+    __shared__ __attribute__((aligned(16))) float sRe[RCN * BLD];
+    __shared__ __attribute__((aligned(16))) float sIm[RCN * BLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * RR;
+
+    float4 zf[2][KB];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kg = 0; kg < KB; ++kg) {
+            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
+            const int c = kg * 16 + 4 * (lane >> 4);
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (row < M && c + q < k) ? Z[row * ld_z + c + q] : 0.f;
+            zf[jb][kg] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+
+    floatx4 are[4][2], aim[4][2];
+    for (int j0 = 0; j0 < N; j0 += RCN) {
+        stage_basis_chunk<KB>(sRe, sIm, BLD, BreT, BimT, j0);
+        __syncthreads();
+        recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
+        __syncthreads();
+        store_out<VEC_OUT>(out, ld_out, M, N, r0, wave, lane, j0, are, aim, plane);
+    }
+}
+
+template <int KB>
+static hipError_t recon_dispatch(bool vec, dim3 grid, hipStream_t s, const float* Z, int64_t M, int64_t ld_z, int k,
+                                 const float* BreT, const float* BimT, int N, float* out, int64_t ld_out, int plane) {
+    if (vec)
+        hipLaunchKernelGGL((recon_kernel<KB, true>), grid, dim3(256), 0, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out,
+                           plane);
+    else
+        hipLaunchKernelGGL((recon_kernel<KB, false>), grid, dim3(256), 0, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out,
+                           plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, const float* BreT, const float* BimT,
+                              int kp, int N, float* out, int64_t ld_out, int plane, hipStream_t s) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
+    dim3 grid((unsigned)((M + RR - 1) / RR));
+    switch (kp) {
+        case 16: return recon_dispatch<1>(vec, grid, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out, plane);
+        case 32: return recon_dispatch<2>(vec, grid, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out, plane);
+        case 64: return recon_dispatch<4>(vec, grid, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out, plane);
+        case 128: return recon_dispatch<8>(vec, grid, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out, plane);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ===========================================================================
+// Fused stored-basis transform: each block projects its 128 spectra onto W
+// (Z tile kept in LDS) and reconstructs them; I is read once, out written
+// once.
+// ===========================================================================
+template <int KB, bool VEC_IN, bool VEC_OUT>
+__global__ __launch_bounds__(256) void transform_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                        const float* __restrict__ rinv, float floor,
+                                                        const float* __restrict__ Wt, int ldw,
+                                                        const float* __restrict__ BreT,
+                                                        const float* __restrict__ BimT, float* __restrict__ out,
+                                                        int64_t ld_out, int plane) {
+    constexpr int KP = KB * 16;
+    constexpr int BLD = KP + 4;
+    constexpr int P1 = PR * PLD + KP * PLD;             // projection phase
+    constexpr int P2 = PR * BLD + 2 * RCN * BLD;         // reconstruction phase
+    constexpr int SMEM = P1 > P2 ? P1 : P2;
+    __shared__ __attribute__((aligned(16))) float smem[SMEM];
+    float(*sL)[PLD] = reinterpret_cast<float(*)[PLD]>(smem);
+    float(*sW)[PLD] = reinterpret_cast<float(*)[PLD]>(smem + PR * PLD);
+    float* sZ = smem;
+    float* sRe = smem + PR * BLD;
+    float* sIm = sRe + RCN * BLD;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * PR;
+
+    floatx4 acc[2][KB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < N; j0 += PNC) {
+        stage_logratio<VEC_IN>(sL, I, r0, M, N, ld, j0, rinv, floor);
+        stage_weights<KB>(sW, Wt, ldw, j0);
+        __syncthreads();
+        project_stage<KB>(acc, sL, sW, wave, lane);
+        __syncthreads();
+    }
+    // Z tile to LDS: sZ[row][c]
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+                sZ[row * BLD + cb * 16 + (lane & 15)] = acc[rb][cb][v];
+            }
+    __syncthreads();
+    float4 zf[2][KB];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kg = 0; kg < KB; ++kg)
+            zf[jb][kg] = *reinterpret_cast<const float4*>(sZ + (wave * 32 + jb * 16 + (lane & 15)) * BLD + kg * 16 +
+                                                          4 * (lane >> 4));
+    // sRe / sIm live beyond sZ, so no barrier is needed before staging them.
+    floatx4 are[4][2], aim[4][2];
+    for (int j0 = 0; j0 < N; j0 += RCN) {
+        stage_basis_chunk<KB>(sRe, sIm, BLD, BreT, BimT, j0);
+        __syncthreads();
+        recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
+        __syncthreads();
+        store_out<VEC_OUT>(out, ld_out, M, N, r0, wave, lane, j0, are, aim, plane);
+    }
+}
+
+template <int KB>
+static hipError_t transform_dispatch(bool vin, bool vout, dim3 grid, hipStream_t s, const float* I, int64_t M, int N,
+                                     int64_t ld, const float* rinv, float floor, const float* Wt, int ldw,
+                                     const float* BreT, const float* BimT, float* out, int64_t ld_out, int plane) {
+#define FKK_TR(a, b)                                                                                              \
+    hipLaunchKernelGGL((transform_kernel<KB, a, b>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, \
+                       BimT, out, ld_out, plane)
+    if (vin && vout) FKK_TR(true, true);
+    else if (vin) FKK_TR(true, false);
+    else if (vout) FKK_TR(false, true);
+    else FKK_TR(false, false);
+#undef FKK_TR
+    return hipGetLastError();
+}
+
+hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                            const float* Wt, int ldw, int kp, const float* BreT, const float* BimT, float* out,
+                            int64_t ld_out, int plane, hipStream_t s) {
+    const bool vin = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    const bool vout = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
+    dim3 grid((unsigned)proj_blocks(M));
+    switch (kp) {
+        case 16: return transform_dispatch<1>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
+        case 32: return transform_dispatch<2>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
+        case 64: return transform_dispatch<4>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
+        case 128: return transform_dispatch<8>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dev
+}  // namespace fkk

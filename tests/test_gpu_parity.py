@@ -1,0 +1,362 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerance (FP32 matrix-core path): per spectrum, max |y - y*| / max |y*|
+<= 1e-5, where y* is the oracle's FP64 result on the same FP32 input.
+Stage checks use the oracle's FP64 evaluation of the same stage on the same
+inputs; the Gram is held to 2e-6 of its largest entry (FP32 log ratio and
+FP32 accumulation over the rows of one chunk).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators as op
+from oracle import workflows as wf
+
+torch = pytest.importorskip("torch")
+fk = pytest.importorskip("paper_2005_07132_amd")
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def spectrum_err(y, ref):
+    num = np.abs(y - ref).max(axis=1)
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-30)
+    return num / den
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fk.Context(0)
+    yield c
+    c.close()
+
+
+def tissue(rows=48, cols=40, n=256, key=3):
+    return synth.tissue_cube(rows=rows, cols=cols, n=n, map_key=key, noise_key=key, blur=4.0)
+
+
+def oracle_params(cube, **kw):
+    base = dict(k=12, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    base.update(kw)
+    return wf.Params(**base)
+
+
+def lib_params(p: wf.Params, **extra):
+    kw = {name: getattr(p, name) for name in ("k", "f_mode", "alpha", "sigma_g", "pad_mode", "fft_len", "detrend",
+                                              "als_lambda", "als_p", "als_iters", "ridge_rel", "sec_mode",
+                                              "sg_window", "sg_order", "ml_lambda", "ratio_floor")}
+    kw.update(extra)
+    return fk.params(**kw)
+
+
+# --------------------------------------------------------------------------
+# Stage: log ratio + Gram (Eq. 2, 6)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3), (128, 128, 0)])
+def test_gram_matches_oracle(ctx, m, n, ld_pad):
+    say(f"gram m={m} n={n} ld_pad={ld_pad}")
+    cube = synth.tissue_cube(rows=1, cols=m, n=n, blur=1.0)
+    data = cube.i_cars
+    if ld_pad:
+        full = np.zeros((m, n + ld_pad), dtype=np.float32)
+        full[:, :n] = data
+        t = dev(full)[:, :n]
+    else:
+        t = dev(data)
+    g, cs, clamps = ctx.gram(t, cube.i_ref)
+    ell, bad = wf.log_ratio(data.astype(np.float64), cube.i_ref, 1e-6)
+    ref = ell.T @ ell
+    assert np.abs(g - ref).max() / np.abs(ref).max() < 2e-6
+    np.testing.assert_allclose(g, g.T, rtol=0, atol=0)
+    np.testing.assert_allclose(cs, data.astype(np.float64).sum(axis=0), rtol=1e-12)
+    assert clamps == bad == 0
+
+
+def test_gram_counts_and_clamps_invalid_ratios(ctx):
+    say("gram clamps")
+    cube = tissue(rows=20, cols=20, n=64)
+    data = cube.i_cars.copy()
+    data[3, 5] = 0.0
+    data[7, 9] = -1.0
+    data[11, 60] = np.nan
+    data[12, 0] = np.inf
+    g, cs, clamps = ctx.gram(dev(data), cube.i_ref)
+    ell, bad = wf.log_ratio(data.astype(np.float64), cube.i_ref, 1e-6)
+    assert clamps == bad == 4
+    ref = ell.T @ ell
+    assert np.abs(g - ref).max() / np.abs(ref).max() < 2e-6
+
+
+# --------------------------------------------------------------------------
+# Stages with the oracle's basis: projection, arg-extrema, reconstruction.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def fitted():
+    cube = tissue()
+    p = oracle_params(cube)
+    return cube, p, wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p)
+
+
+def test_projection_and_subsampling(ctx, fitted):
+    say("project")
+    cube, p, res = fitted
+    b = ctx.basis_import(res["basis"])
+    z, qmax, qmin = ctx.project(b, dev(cube.i_cars))
+    zg = host(z)
+    zref = res["z"]
+    err = np.abs(zg - zref).max(axis=0) / np.abs(zref).max(axis=0)
+    assert err.max() < TOL
+    # the chosen rows hold the column extrema (ties within FP32 rounding)
+    for c in range(p.k):
+        scale = np.abs(zref[:, c]).max()
+        assert zref[qmax[c], c] >= zref[:, c].max() - 4 * TOL * scale
+        assert zref[qmin[c], c] <= zref[:, c].min() + 4 * TOL * scale
+
+
+@pytest.mark.parametrize("plane", [fk.OUT_IM, fk.OUT_RE, fk.OUT_ABS])
+def test_reconstruction_epilogue(ctx, fitted, plane):
+    say(f"reconstruct plane={plane}")
+    cube, p, res = fitted
+    b = ctx.basis_import(res["basis"])
+    z32 = res["z"].astype(np.float32)
+    out = host(ctx.reconstruct(b, dev(z32), plane))
+    ref = wf.reconstruct(z32.astype(np.float64), res["basis"])[{0: "im", 1: "re", 2: "abs"}[plane]]
+    assert spectrum_err(out, ref).max() < TOL
+
+
+@pytest.mark.parametrize("m", [1, 127, 129, 1000])
+def test_transform_with_oracle_basis(ctx, fitted, m):
+    say(f"transform m={m}")
+    cube, p, res = fitted
+    b = ctx.basis_import(res["basis"])
+    new = synth.tissue_cube(rows=1, cols=m, n=cube.shape[1], map_key=100 + m, noise_key=200 + m, blur=2.0)
+    out = host(ctx.transform(b, dev(new.i_cars)))
+    ref = wf.transform(new.i_cars.astype(np.float64), res["basis"])["im"]
+    assert spectrum_err(out, ref).max() < TOL
+
+
+def test_transform_with_ml_ridge(ctx, fitted):
+    say("transform ml_lambda")
+    cube, p, res = fitted
+    basis = dict(res["basis"], ml_lambda=float(res["basis"]["s"][3] ** 2))
+    b = ctx.basis_import(basis)
+    out = host(ctx.transform(b, dev(cube.i_cars)))
+    ref = wf.transform(cube.i_cars.astype(np.float64), basis)["im"]
+    assert spectrum_err(out, ref).max() < TOL
+
+
+# --------------------------------------------------------------------------
+# End to end.
+# --------------------------------------------------------------------------
+
+def _check_exported_basis_reproduces(cube, basis, out):
+    """Oracle evaluation of Eq. 23 with the GPU's basis: Z = A V (FP64)."""
+    e = basis.export()
+    ell, _ = wf.log_ratio(cube.i_cars.astype(np.float64), e["i_ref"], e["ratio_floor"])
+    z = (ell * e["f"]) @ e["v"]
+    ref = wf.reconstruct(z, e)["im"]
+    return spectrum_err(out, ref)
+
+
+@pytest.mark.parametrize("detrend", [op.DETREND_ALS, op.DETREND_WHITTAKER])
+def test_fit_lowrank_matches_independent_oracle(ctx, detrend):
+    # log ratio of exact rank 6 plus 1e-6 noise: a wide spectral gap at k = 6,
+    # so the FP32 Gram fixes the same subspace as the FP64 SVD.
+    say(f"fit low-rank detrend={detrend}")
+    cube = synth.lowrank_log_cube(4000, 300, rank=6, dtype=np.float32)
+    p = wf.Params(k=6, detrend=detrend)
+    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p))
+    out = host(out)
+    e = b.export()
+    np.testing.assert_allclose(e["s"], ref["basis"]["s"], rtol=1e-5)
+    assert np.linalg.norm(e["v"] @ e["v"].T - ref["basis"]["v"] @ ref["basis"]["v"].T, 2) < 1e-5
+    np.testing.assert_array_equal(np.sort(e["q"]), np.sort(ref["basis"]["q"]))
+    assert spectrum_err(out, ref["im"]).max() < TOL
+    assert rep["n_q"] == len(ref["basis"]["q"])
+
+
+def test_fit_tissue_with_oracle_subsample(ctx):
+    say("fit tissue q_override")
+    cube = tissue(rows=64, cols=64, n=256, key=5)
+    p = oracle_params(cube, k=10)
+    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p, q_override=ref["basis"]["q"]))
+    out = host(out)
+    assert _check_exported_basis_reproduces(cube, b, out).max() < TOL
+    e = b.export()
+    gap = (ref["basis"]["s"][-1] ** 2 - np.linalg.svd(
+        wf.log_ratio(cube.i_cars.astype(np.float64), cube.i_ref, 1e-6)[0] * ref["basis"]["f"],
+        compute_uv=False)[p.k] ** 2)
+    sin_angle = np.linalg.norm(e["v"] @ e["v"].T - ref["basis"]["v"] @ ref["basis"]["v"].T, 2)
+    # Davis-Kahan: sin <= ||dG|| / gap, with ||dG|| ~ 2e-6 ||G||
+    assert sin_angle <= max(1e-6, 4e-6 * ref["basis"]["s"][0] ** 2 / gap)
+
+
+def test_fit_default_subsample_reproduces_from_exported_basis(ctx):
+    say("fit tissue default")
+    cube = tissue(rows=50, cols=70, n=512, key=6)
+    p = oracle_params(cube, k=20)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p))
+    assert _check_exported_basis_reproduces(cube, b, host(out)).max() < TOL
+    assert rep["clamps"] == 0 and rep["n_q"] >= 20
+
+
+@pytest.mark.parametrize("sec", [op.SEC_SAVGOL, op.SEC_MEAN])
+def test_plain_path_whittaker_matches_oracle(ctx, sec):
+    say(f"plain whittaker sec={sec}")
+    cube = tissue(rows=20, cols=33, n=256, key=7)
+    p = wf.Params(k=5, detrend=op.DETREND_WHITTAKER, sec_mode=sec)
+    out = host(ctx.plain(dev(cube.i_cars), cube.i_ref, lib_params(p)))
+    ref = wf.plain(cube.i_cars.astype(np.float64), cube.i_ref, p)["im"]
+    assert spectrum_err(out, ref).max() < TOL
+
+
+def test_plain_path_als_matches_oracle(ctx):
+    say("plain als")
+    cube = synth.pixel_cube(side=24, n=512)
+    p = wf.Params(k=20)
+    out = host(ctx.plain(dev(cube.i_cars), cube.i_ref, lib_params(p)))
+    ref = wf.plain(cube.i_cars.astype(np.float32).astype(np.float64), cube.i_ref, p)["im"]
+    e = spectrum_err(out, ref)
+    assert np.mean(e < TOL) >= 0.999, (np.sort(e)[-5:])
+
+
+def test_plain_path_pad_zero_and_other_planes(ctx):
+    say("plain pad zero / planes")
+    cube = tissue(rows=9, cols=9, n=100, key=8)
+    p = wf.Params(k=5, detrend=op.DETREND_WHITTAKER, pad_mode=op.PAD_ZERO, fft_len=512, sg_window=31, sg_order=3)
+    ref = wf.plain(cube.i_cars.astype(np.float64), cube.i_ref, p)
+    for plane, key in ((fk.OUT_RE, "re"), (fk.OUT_ABS, "abs")):
+        out = host(ctx.plain(dev(cube.i_cars), cube.i_ref, lib_params(p, output=plane)))
+        assert spectrum_err(out, ref[key]).max() < TOL
+
+
+# --------------------------------------------------------------------------
+# Edge cases, errors, determinism.
+# --------------------------------------------------------------------------
+
+def test_nrb_only_input_gives_zero_raman(ctx):
+    say("nrb only")
+    w = synth.wavenumbers(128)
+    ref = synth.reference(w)
+    cube = np.tile(ref, (300, 1)).astype(np.float32)
+    b, out, rep = ctx.fit(dev(cube), ref.astype(np.float32).astype(np.float64), fk.params(k=4))
+    assert np.abs(host(out)).max() < 1e-6
+    assert np.abs(host(ctx.plain(dev(cube), ref.astype(np.float32).astype(np.float64), fk.params(k=4)))).max() < 1e-6
+
+
+def test_full_rank_and_minimum_sizes(ctx):
+    say("full rank / tiny")
+    cube = tissue(rows=10, cols=10, n=16, key=9)
+    p = wf.Params(k=16, detrend=op.DETREND_WHITTAKER, ridge_rel=0.0, sg_window=7)
+    b, out, _ = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p))
+    assert _check_exported_basis_reproduces(cube, b, host(out)).max() < TOL
+    one = dev(cube.i_cars[:1])
+    b1, out1, rep1 = ctx.fit(one, cube.i_ref, lib_params(wf.Params(k=1, sg_window=7)))
+    assert rep1["n_q"] == 1
+    assert np.isfinite(host(out1)).all()
+
+
+def test_invalid_arguments_fail_before_launch(ctx):
+    say("invalid args")
+    cube = tissue(rows=4, cols=4, n=64)
+    t = dev(cube.i_cars)
+    with pytest.raises(fk.FkkError):
+        ctx.fit(t, cube.i_ref, fk.params(k=65))
+    with pytest.raises(fk.FkkError):
+        ctx.fit(t, -cube.i_ref, fk.params(k=4))
+    b = ctx.basis_import(wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, wf.Params(k=4))["basis"])
+    with pytest.raises(fk.FkkError):
+        ctx.transform(b, dev(np.ones((3, 32))))
+    with pytest.raises(fk.FkkError):
+        ctx.fit(t, cube.i_ref, fk.params(k=4, strict=1, ratio_floor=10.0))
+
+
+def test_fit_is_deterministic_and_rows_independent(ctx):
+    say("determinism")
+    cube = tissue(rows=40, cols=40, n=256, key=10)
+    t = dev(cube.i_cars)
+    p = fk.params(k=10)
+    b1, o1, _ = ctx.fit(t, cube.i_ref, p)
+    b2, o2, _ = ctx.fit(t, cube.i_ref, p)
+    assert torch.equal(o1, o2)
+    new = dev(synth.tissue_cube(rows=7, cols=31, n=256, map_key=11, noise_key=11, blur=2.0).i_cars)
+    alone = ctx.transform(b1, new)
+    mixed = ctx.transform(b1, torch.cat([t[:333], new, t[333:700]]))
+    assert torch.equal(alone, mixed[333:333 + new.shape[0]])
+
+
+# --------------------------------------------------------------------------
+# Paper-scale cube (703,026 x 1,000, k = 50) in the benchmark's launch
+# configuration: the fit's output on sampled spectra against the oracle
+# evaluated with the exported basis, and the Gram against an FP64 Gram.
+# --------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_paper_scale_fit_sampled(ctx):
+    say("paper-scale fit")
+    cube = synth.tissue_703k()
+    t = dev(cube.i_cars)
+    p = fk.params(k=50, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    b, out, rep = ctx.fit(t, cube.i_ref, p)
+    rows = np.sort(synth.rng_for(703, 1).choice(cube.shape[0], 512, replace=False))
+    got = host(out[torch.from_numpy(rows).cuda()])
+    e = b.export()
+    ell, _ = wf.log_ratio(cube.i_cars[rows].astype(np.float64), e["i_ref"], e["ratio_floor"])
+    ref = wf.reconstruct((ell * e["f"]) @ e["v"], e)["im"]
+    assert spectrum_err(got, ref).max() < TOL
+    # f from the FP64 column means of the whole cube
+    mean = cube.i_cars.mean(axis=0, dtype=np.float64)
+    f_ref = 2 * mean / np.sqrt(cube.alpha * mean + cube.sigma_g ** 2)
+    np.testing.assert_allclose(e["f"], f_ref, rtol=1e-9)
+    # exported basis is the oracle's fKK/fPEC/fSEC of the exported factors
+    x = ((wf.log_ratio(cube.i_cars[e["q"]].astype(np.float64), e["i_ref"], 1e-6)[0] * e["f"]) @ e["v"])
+    ob = wf.basis_from_factors(e["f"], e["s"], e["v"], x, wf.Params(k=50), q=np.arange(len(e["q"])))
+    # X is taken from the device's FP32 Z on one side and FP64 on the other
+    assert np.abs(ob["b_im"] - e["b_im"]).max() / np.abs(ob["b_im"]).max() < 1e-3
+    del t, out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_paper_scale_gram_and_transform(ctx):
+    say("paper-scale gram / transform")
+    cube = synth.tissue_703k()
+    t = dev(cube.i_cars)
+    g, cs, clamps = ctx.gram(t, cube.i_ref)
+    ref = np.zeros_like(g)
+    for i0 in range(0, cube.shape[0], 65536):
+        ell, _ = wf.log_ratio(cube.i_cars[i0:i0 + 65536].astype(np.float64), cube.i_ref, 1e-6)
+        ref += ell.T @ ell
+    assert np.abs(g - ref).max() / np.abs(ref).max() < 2e-6
+    small = tissue(rows=128, cols=128, n=1000, key=12)
+    res = wf.fit(small.i_cars.astype(np.float64), small.i_ref, oracle_params(small, k=50))
+    b = ctx.basis_import(res["basis"])
+    out = ctx.transform(b, t)
+    rows = np.sort(synth.rng_for(703, 2).choice(cube.shape[0], 512, replace=False))
+    got = host(out[torch.from_numpy(rows).cuda()])
+    ref_t = wf.transform(cube.i_cars[rows].astype(np.float64), res["basis"])["im"]
+    assert spectrum_err(got, ref_t).max() < TOL
+    del t, out
+    torch.cuda.empty_cache()
