@@ -256,8 +256,7 @@ void basis_math(fkk_basis* b, const double* X, int n_q, const fkk_params* p) {
             double* dst = &raw[(size_t)r * N];
             for (int j = 0; j < N; ++j) dst[j] += x * hv[j];
         }
-    for (int r = 0; r < n_q; ++r)
-        fkk::detrend_row(&raw[(size_t)r * N], &err[(size_t)r * N], N, p->detrend, lam, p->als_p, p->als_iters);
+    fkk::detrend_rows(raw.data(), err.data(), n_q, N, p->detrend, lam, p->als_p, p->als_iters);
     b->phi_pec_t.assign((size_t)k * N, 0.0);
     b->ridge_lambda = fkk::ridge_rel_solve(X, err.data(), b->phi_pec_t.data(), n_q, k, N, p->ridge_rel);
     std::vector<double> h_phi((size_t)k * N), t((size_t)k * N);

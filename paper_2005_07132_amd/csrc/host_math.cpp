@@ -17,6 +17,101 @@ namespace fkk {
 
 using cplx = std::complex<double>;
 
+// ---------------------------------------------------------------------------
+// Host thread pool shared by all host stages.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Fork-join pool whose workers spin between back-to-back parallel regions
+// (the tridiagonalisation issues two regions per column) and sleep when the
+// pool is released.
+class Pool {
+  public:
+    explicit Pool(int n) : n_(std::max(1, n)) {
+        for (int t = 1; t < n_; ++t) th_.emplace_back([this, t] { worker(t); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    int size() const { return n_; }
+    // run fn(tid, nthreads) on every thread, return when all are done
+    void run(const std::function<void(int, int)>& fn) {
+        job_ = &fn;
+        done_.store(0);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        fn(0, n_);
+        while (done_.load(std::memory_order_acquire) != n_ - 1) std::this_thread::yield();
+    }
+
+  private:
+    void worker(int tid) {
+        int64_t seen = 0;
+        for (;;) {
+            int spins = 0;
+            while (gen_.load(std::memory_order_acquire) == seen) {
+                if (++spins > 20000) {
+                    std::unique_lock<std::mutex> lk(mu_);
+                    cv_.wait(lk, [&] { return gen_.load() != seen; });
+                    break;
+                }
+                std::this_thread::yield();
+            }
+            seen = gen_.load(std::memory_order_acquire);
+            if (stop_) return;
+            (*job_)(tid, n_);
+            done_.fetch_add(1, std::memory_order_release);
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::atomic<int64_t> gen_{0};
+    std::atomic<int> done_{0};
+    const std::function<void(int, int)>* job_ = nullptr;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    bool stop_ = false;
+};
+
+void split(int lo, int hi, int tid, int nt, int* a, int* b) {
+    const int len = hi - lo;
+    *a = lo + (int)((int64_t)len * tid / nt);
+    *b = lo + (int)((int64_t)len * (tid + 1) / nt);
+}
+
+Pool& host_pool() {
+    static Pool pool([] {
+        unsigned hw = std::thread::hardware_concurrency();
+        return (int)std::min(16u, hw == 0 ? 1u : hw);
+    }());
+    return pool;
+}
+
+// Rows [0, rows) split over the pool.
+void parallel_rows(int rows, const std::function<void(int, int)>& body) {
+    Pool& pool = host_pool();
+    if (rows <= 1 || pool.size() == 1) {
+        body(0, rows);
+        return;
+    }
+    pool.run([&](int tid, int nthr) {
+        int r0, r1;
+        split(0, rows, tid, nthr, &r0, &r1);
+        if (r0 < r1) body(r0, r1);
+    });
+}
+
+}  // namespace
+
 int default_fft_len(int n) {
     int len = 1;
     while (len < 3 * n) len *= 2;
@@ -58,23 +153,28 @@ struct FftPlan {
         }
     }
     void run(cplx* a, bool inverse) const {
+        double* z = reinterpret_cast<double*>(a);
         for (int i = 0; i < n; ++i)
             if (i < rev[i]) std::swap(a[i], a[rev[i]]);
+        const double sgn = inverse ? -1.0 : 1.0;
         for (int half = 1; half < n; half *= 2) {
             const int step = n / (2 * half);
             for (int s = 0; s < n; s += 2 * half) {
                 for (int j = 0; j < half; ++j) {
-                    cplx w = tw[j * step];
-                    if (inverse) w = std::conj(w);
-                    const cplx t = w * a[s + j + half];
-                    a[s + j + half] = a[s + j] - t;
-                    a[s + j] = a[s + j] + t;
+                    const double wr = tw[j * step].real(), wi = sgn * tw[j * step].imag();
+                    double* x = z + 2 * (s + j);
+                    double* y = z + 2 * (s + j + half);
+                    const double tr = wr * y[0] - wi * y[1], ti = wr * y[1] + wi * y[0];
+                    y[0] = x[0] - tr;
+                    y[1] = x[1] - ti;
+                    x[0] += tr;
+                    x[1] += ti;
                 }
             }
         }
         if (inverse) {
             const double inv = 1.0 / n;
-            for (int i = 0; i < n; ++i) a[i] *= inv;
+            for (int i = 0; i < 2 * n; ++i) z[i] *= inv;
         }
     }
 };
@@ -85,34 +185,36 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 void hilbert_rows(const double* x, double* y, int rows, int n, int len, int pad_mode) {
     if (!is_pow2(len) || len < n) return;
-    FftPlan plan(len);
+    const FftPlan plan(len);
     const int pl = (len - n) / 2;
-    std::vector<cplx> buf(len);
-    // -i sgn(nu): bins 1..len/2-1 positive, len/2+1..len-1 negative.
-    auto pad_value = [&](const double* row, int i) -> double {
-        const int src = i - pl;
-        if (src >= 0 && src < n) return row[src];
-        if (pad_mode == 1) return 0.0;
-        return src < 0 ? row[0] : row[n - 1];
-    };
     // Two real rows per complex transform: H is real and complex-linear, so
     // H{a + i b} = H{a} + i H{b}.
-    for (int r = 0; r < rows; r += 2) {
-        const double* ra = x + (size_t)r * n;
-        const double* rb = (r + 1 < rows) ? x + (size_t)(r + 1) * n : nullptr;
-        for (int i = 0; i < len; ++i)
-            buf[i] = cplx(pad_value(ra, i), rb ? pad_value(rb, i) : 0.0);
-        plan.run(buf.data(), false);
-        buf[0] = 0.0;
-        buf[len / 2] = 0.0;
-        for (int b = 1; b < len / 2; ++b) buf[b] *= cplx(0.0, -1.0);
-        for (int b = len / 2 + 1; b < len; ++b) buf[b] *= cplx(0.0, 1.0);
-        plan.run(buf.data(), true);
-        for (int i = 0; i < n; ++i) {
-            y[(size_t)r * n + i] = buf[pl + i].real();
-            if (rb) y[(size_t)(r + 1) * n + i] = buf[pl + i].imag();
+    const int pairs = (rows + 1) / 2;
+    parallel_rows(pairs, [&](int p0, int p1) {
+        std::vector<cplx> buf(len);
+        auto pad_value = [&](const double* row, int i) -> double {
+            const int src = i - pl;
+            if (src >= 0 && src < n) return row[src];
+            if (pad_mode == 1) return 0.0;
+            return src < 0 ? row[0] : row[n - 1];
+        };
+        for (int pr = p0; pr < p1; ++pr) {
+            const int r = 2 * pr;
+            const double* ra = x + (size_t)r * n;
+            const double* rb = (r + 1 < rows) ? x + (size_t)(r + 1) * n : nullptr;
+            for (int i = 0; i < len; ++i) buf[i] = cplx(pad_value(ra, i), rb ? pad_value(rb, i) : 0.0);
+            plan.run(buf.data(), false);
+            buf[0] = 0.0;
+            buf[len / 2] = 0.0;
+            for (int b = 1; b < len / 2; ++b) buf[b] = cplx(buf[b].imag(), -buf[b].real());        // * (-i)
+            for (int b = len / 2 + 1; b < len; ++b) buf[b] = cplx(-buf[b].imag(), buf[b].real());  // * (+i)
+            plan.run(buf.data(), true);
+            for (int i = 0; i < n; ++i) {
+                y[(size_t)r * n + i] = buf[pl + i].real();
+                if (rb) y[(size_t)(r + 1) * n + i] = buf[pl + i].imag();
+            }
         }
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -182,6 +284,12 @@ void detrend_row(const double* y, double* z, int n, int mode, double lam, double
     }
 }
 
+void detrend_rows(const double* y, double* z, int rows, int n, int mode, double lam, double p, int n_iter) {
+    parallel_rows(rows, [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r) detrend_row(y + (size_t)r * n, z + (size_t)r * n, n, mode, lam, p, n_iter);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Savitzky-Golay trendline.  The weights of output point i are those of the
 // least-squares polynomial of degree `order` through the window evaluated at
@@ -216,11 +324,10 @@ void small_solve(std::vector<double>& g, std::vector<double>& b, int m) {
 
 void sg_weights(int start, int window, int at, int order, double scale, double* out) {
     const int m = order + 1;
-    std::vector<double> g(m * m, 0.0), b(m, 0.0);
+    std::vector<double> g(m * m, 0.0), b(m, 0.0), pw(2 * m - 1);
     for (int j = 0; j < window; ++j) {
         const double x = (start + j - at) / scale;
         double pi = 1.0;
-        std::vector<double> pw(2 * m - 1);
         for (int e = 0; e < 2 * m - 1; ++e) { pw[e] = pi; pi *= x; }
         for (int r = 0; r < m; ++r)
             for (int c = 0; c < m; ++c) g[r * m + c] += pw[r + c];
@@ -248,38 +355,71 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
         return;
     }
     const int half = window / 2;
-    const double scale = std::max(1, half);
-    // weights for every output position (interior ones are all equal)
-    std::vector<double> wmid(window);
-    sg_weights(0, window, half, order, scale, wmid.data());
-    std::vector<double> wedge((size_t)2 * half * window);
-    std::vector<int> estart(2 * half), eat(2 * half);
-    for (int i = 0; i < half; ++i) {
-        sg_weights(0, window, i, order, scale, &wedge[(size_t)i * window]);
-        estart[i] = 0;
-        eat[i] = i;
-        const int at = n - half + i;
-        sg_weights(n - window, window, at, order, scale, &wedge[(size_t)(half + i) * window]);
-        estart[half + i] = n - window;
-        eat[half + i] = at;
+    // Weight tables depend only on (n, window, order): build once, reuse.
+    struct Tables {
+        int n = -1, window = -1, order = -1;
+        std::vector<double> wmid, wedge;
+        std::vector<int> estart, eat;
+    };
+    static std::mutex cache_mu;
+    static Tables cache;
+    Tables t;
+    {
+        std::lock_guard<std::mutex> g(cache_mu);
+        if (cache.n == n && cache.window == window && cache.order == order) t = cache;
     }
-    for (int r = 0; r < rows; ++r) {
-        const double* xr = x + (size_t)r * n;
-        double* yr = y + (size_t)r * n;
-        for (int i = half; i < n - half; ++i) {
-            double s = 0.0;
-            const double* src = xr + i - half;
-            for (int j = 0; j < window; ++j) s += wmid[j] * src[j];
-            yr[i] = s;
+    if (t.n != n || t.window != window || t.order != order) {
+        const double scale = std::max(1, half);
+        t.wmid.resize(window);
+        sg_weights(0, window, half, order, scale, t.wmid.data());
+        t.wedge.resize((size_t)2 * half * window);
+        t.estart.resize(2 * half);
+        t.eat.resize(2 * half);
+        for (int i = 0; i < half; ++i) {
+            sg_weights(0, window, i, order, scale, &t.wedge[(size_t)i * window]);
+            t.estart[i] = 0;
+            t.eat[i] = i;
+            const int at = n - half + i;
+            sg_weights(n - window, window, at, order, scale, &t.wedge[(size_t)(half + i) * window]);
+            t.estart[half + i] = n - window;
+            t.eat[half + i] = at;
         }
-        for (int e = 0; e < 2 * half; ++e) {
-            double s = 0.0;
-            const double* wts = &wedge[(size_t)e * window];
-            const double* src = xr + estart[e];
-            for (int j = 0; j < window; ++j) s += wts[j] * src[j];
-            yr[eat[e]] = s;
-        }
+        t.n = n;
+        t.window = window;
+        t.order = order;
+        std::lock_guard<std::mutex> g(cache_mu);
+        cache = t;
     }
+    const std::vector<double>& wmid = t.wmid;
+    const std::vector<double>& wedge = t.wedge;
+    const std::vector<int>& estart = t.estart;
+    const std::vector<int>& eat = t.eat;
+    parallel_rows(rows, [&](int ra, int rb) {
+        for (int r = ra; r < rb; ++r) {
+            const double* xr = x + (size_t)r * n;
+            double* yr = y + (size_t)r * n;
+            for (int i = half; i < n - half; ++i) {
+                const double* src = xr + i - half;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int j = 0;
+                for (; j + 3 < window; j += 4) {
+                    s0 += wmid[j] * src[j];
+                    s1 += wmid[j + 1] * src[j + 1];
+                    s2 += wmid[j + 2] * src[j + 2];
+                    s3 += wmid[j + 3] * src[j + 3];
+                }
+                for (; j < window; ++j) s0 += wmid[j] * src[j];
+                yr[i] = (s0 + s1) + (s2 + s3);
+            }
+            for (int e = 0; e < 2 * half; ++e) {
+                double s = 0.0;
+                const double* wts = &wedge[(size_t)e * window];
+                const double* src = xr + estart[e];
+                for (int j = 0; j < window; ++j) s += wts[j] * src[j];
+                yr[eat[e]] = s;
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -343,7 +483,7 @@ double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k
     const double cutoff = eps * std::max(m, k) * smax;
     std::vector<double> uty(n);
     for (int j = 0; j < k; ++j) {
-        if (lam == 0.0 && sig[j] <= cutoff) continue;
+        if (sig[j] == 0.0 || (lam == 0.0 && sig[j] <= cutoff)) continue;  // no contribution
         const double g = (lam == 0.0) ? 1.0 / sig[j] : sig[j] / (sig[j] * sig[j] + lam);
         // u_j^T Y with u_j = col_j / sigma_j
         std::fill(uty.begin(), uty.end(), 0.0);
@@ -366,72 +506,6 @@ double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k
 // Symmetric eigensolver for the top k eigenpairs.
 // ---------------------------------------------------------------------------
 namespace {
-
-// Fork-join pool whose workers spin between back-to-back parallel regions
-// (the tridiagonalisation issues two regions per column) and sleep when the
-// pool is released.
-class Pool {
-  public:
-    explicit Pool(int n) : n_(std::max(1, n)) {
-        for (int t = 1; t < n_; ++t) th_.emplace_back([this, t] { worker(t); });
-    }
-    ~Pool() {
-        {
-            std::lock_guard<std::mutex> g(mu_);
-            stop_ = true;
-            gen_.fetch_add(1);
-        }
-        cv_.notify_all();
-        for (auto& t : th_) t.join();
-    }
-    int size() const { return n_; }
-    // run fn(tid, nthreads) on every thread, return when all are done
-    void run(const std::function<void(int, int)>& fn) {
-        job_ = &fn;
-        done_.store(0);
-        {
-            std::lock_guard<std::mutex> g(mu_);
-            gen_.fetch_add(1);
-        }
-        cv_.notify_all();
-        fn(0, n_);
-        while (done_.load(std::memory_order_acquire) != n_ - 1) std::this_thread::yield();
-    }
-
-  private:
-    void worker(int tid) {
-        int64_t seen = 0;
-        for (;;) {
-            int spins = 0;
-            while (gen_.load(std::memory_order_acquire) == seen) {
-                if (++spins > 20000) {
-                    std::unique_lock<std::mutex> lk(mu_);
-                    cv_.wait(lk, [&] { return gen_.load() != seen; });
-                    break;
-                }
-                std::this_thread::yield();
-            }
-            seen = gen_.load(std::memory_order_acquire);
-            if (stop_) return;
-            (*job_)(tid, n_);
-            done_.fetch_add(1, std::memory_order_release);
-        }
-    }
-    int n_;
-    std::vector<std::thread> th_;
-    std::atomic<int64_t> gen_{0};
-    std::atomic<int> done_{0};
-    const std::function<void(int, int)>* job_ = nullptr;
-    std::mutex mu_;
-    std::condition_variable cv_;
-    bool stop_ = false;
-};
-
-inline void split(int lo, int hi, int tid, int nt, int* a, int* b) {
-    const int len = hi - lo;
-    *a = lo + (int)((int64_t)len * tid / nt);
-    *b = lo + (int)((int64_t)len * (tid + 1) / nt);
-}
 
 // Number of eigenvalues of the tridiagonal (d, e) that are smaller than x.
 int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
@@ -497,66 +571,96 @@ int eigh_topk(const double* a_in, int n, int k, double* vals, double* vecs, int 
     std::vector<double> vstore;          // Householder vectors, packed
     std::vector<size_t> voff(std::max(n - 2, 0));
     std::vector<double> beta(std::max(n - 2, 0), 0.0);
-    Pool pool(std::max(1, std::min(threads, n / 64 + 1)));
-    const int nt = pool.size();
-    std::vector<double> p(n), w(n), v(n);
-    std::vector<double> partial(nt);
+    Pool& pool = host_pool();
+    (void)threads;
+    std::vector<double> p(n), pn(n), w(n), v(n), vn(n);
 
     // ---- Householder reduction to tridiagonal form: A <- H A H ----
+    // H_i = I - beta_i v_i v_i^T zeroes row/column i below the subdiagonal.
+    // With p_i = beta_i B_i v_i (B_i the trailing block) and
+    // w_i = p_i - (beta_i/2)(p_i . v_i) v_i, the block becomes
+    // B_i - v_i w_i^T - w_i v_i^T.  The rank-2 update of column i is fused
+    // with the product B_{i+1} v_{i+1} of the next column: row i+1 is updated
+    // first (it defines v_{i+1}), then every further row is updated and
+    // immediately dotted with v_{i+1}, so the block is streamed once per column.
     size_t total = 0;
     for (int i = 0; i + 2 < n; ++i) { voff[i] = total; total += n - i - 1; }
     vstore.resize(std::max<size_t>(total, 1));
-    for (int i = 0; i + 2 < n; ++i) {
+    // reflector from row i (columns i+1..n-1); returns false if none is needed
+    auto reflector = [&](int i, double* vv, double* bb) {
         const int lo = i + 1, m = n - lo;
-        const double* x = &A[(size_t)i * n + lo];  // row i == column i
+        const double* x = &A[(size_t)i * n + lo];
         double sig2 = 0.0;
         for (int j = 1; j < m; ++j) sig2 += x[j] * x[j];
         const double x0 = x[0];
         d[i] = A[(size_t)i * n + i];
         if (sig2 == 0.0) {
             e[i] = x0;
-            beta[i] = 0.0;
-            double* vs = &vstore[voff[i]];
-            for (int j = 0; j < m; ++j) vs[j] = 0.0;
-            continue;
+            *bb = 0.0;
+            for (int j = 0; j < m; ++j) vv[j] = 0.0;
+        } else {
+            const double norm = std::sqrt(x0 * x0 + sig2);
+            const double alpha = (x0 >= 0) ? -norm : norm;
+            for (int j = 0; j < m; ++j) vv[j] = x[j];
+            vv[0] = x0 - alpha;
+            *bb = 2.0 / (vv[0] * vv[0] + sig2);
+            e[i] = alpha;
         }
-        const double norm = std::sqrt(x0 * x0 + sig2);
-        const double alpha = (x0 >= 0) ? -norm : norm;
-        for (int j = 0; j < m; ++j) v[j] = x[j];
-        v[0] = x0 - alpha;
-        const double vtv = v[0] * v[0] + sig2;
-        const double b = 2.0 / vtv;
-        e[i] = alpha;
-        beta[i] = b;
-        std::copy(v.begin(), v.begin() + m, vstore.begin() + voff[i]);
-        // p = b * B v, B the trailing block (rows/cols lo..n-1)
+        beta[i] = *bb;
+        std::copy(vv, vv + m, vstore.begin() + voff[i]);
+    };
+    auto dot = [](const double* a, const double* b, int m) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = 0;
+        for (; c + 3 < m; c += 4) {
+            s0 += a[c] * b[c];
+            s1 += a[c + 1] * b[c + 1];
+            s2 += a[c + 2] * b[c + 2];
+            s3 += a[c + 3] * b[c + 3];
+        }
+        for (; c < m; ++c) s0 += a[c] * b[c];
+        return (s0 + s1) + (s2 + s3);
+    };
+    if (n >= 3) {
+        double b0;
+        reflector(0, v.data(), &b0);
+        const int lo = 1, m = n - 1;
         pool.run([&](int tid, int nthr) {
             int r0, r1;
             split(lo, n, tid, nthr, &r0, &r1);
-            double dot = 0.0;
-            for (int r = r0; r < r1; ++r) {
-                const double* row = &A[(size_t)r * n + lo];
-                double s = 0.0;
-                for (int c = 0; c < m; ++c) s += row[c] * v[c];
-                p[r - lo] = b * s;
-                dot += p[r - lo] * v[r - lo];
-            }
-            partial[tid] = dot;
+            for (int r = r0; r < r1; ++r) p[r - lo] = b0 * dot(&A[(size_t)r * n + lo], v.data(), m);
         });
-        double ptv = 0.0;
-        for (int t = 0; t < nt; ++t) ptv += partial[t];
+    }
+    for (int i = 0; i + 2 < n; ++i) {
+        const int lo = i + 1, m = n - lo;
+        const double b = beta[i];
+        double ptv = dot(p.data(), v.data(), m);
         const double kk = 0.5 * b * ptv;
         for (int j = 0; j < m; ++j) w[j] = p[j] - kk * v[j];
-        // B <- B - v w^T - w v^T
+        // row lo first: it defines the next reflector
+        {
+            double* row = &A[(size_t)lo * n + lo];
+            const double vr = v[0], wr = w[0];
+            for (int c = 0; c < m; ++c) row[c] -= vr * w[c] + wr * v[c];
+        }
+        const bool next = (i + 3 < n);
+        double bn = 0.0;
+        if (next) reflector(lo, vn.data(), &bn);
+        const int lo2 = lo + 1, m2 = n - lo2;
         pool.run([&](int tid, int nthr) {
             int r0, r1;
-            split(lo, n, tid, nthr, &r0, &r1);
+            split(lo2, n, tid, nthr, &r0, &r1);
             for (int r = r0; r < r1; ++r) {
                 double* row = &A[(size_t)r * n + lo];
                 const double vr = v[r - lo], wr = w[r - lo];
                 for (int c = 0; c < m; ++c) row[c] -= vr * w[c] + wr * v[c];
+                if (next) pn[r - lo2] = bn * dot(row + 1, vn.data(), m2);
             }
         });
+        if (next) {
+            std::swap(v, vn);
+            std::swap(p, pn);
+        }
     }
     if (n >= 2) {
         d[n - 2] = A[(size_t)(n - 2) * n + (n - 2)];

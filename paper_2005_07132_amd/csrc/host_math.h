@@ -22,6 +22,7 @@ void hilbert_rows(const double* x, double* y, int rows, int n, int len, int pad_
 // elsewhere, starting from w = 1.  detrend == 1 (Whittaker) is one solve
 // with w = 1.
 void detrend_row(const double* y, double* z, int n, int mode, double lam, double p, int n_iter);
+void detrend_rows(const double* y, double* z, int rows, int n, int mode, double lam, double p, int n_iter);
 
 // Trendline of each row: Savitzky-Golay (window, order) with least-squares
 // polynomial fits on the first / last window near the ends, or the mean.
