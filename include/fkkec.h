@@ -108,6 +108,8 @@ typedef struct {
     double dev_ms_gram;    /* log ratio + Gram kernel                      */
     double dev_ms_project; /* projection + arg-extrema kernel              */
     double dev_ms_recon;   /* reconstruction + epilogue kernel             */
+    double dev_ms_tridiag; /* Householder tridiagonalisation (device)      */
+    double dev_ms_logratio;/* log-ratio pass (device)                      */
 } fkk_fit_report;
 
 /* Host description of a basis set (Sec. 2.6: f, S, V and the corrected

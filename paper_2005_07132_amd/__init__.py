@@ -48,6 +48,7 @@ class FitReport(ctypes.Structure):
         ("ms_gram", ctypes.c_double), ("ms_eig", ctypes.c_double), ("ms_project", ctypes.c_double),
         ("ms_basis", ctypes.c_double), ("ms_recon", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("dev_ms_gram", ctypes.c_double), ("dev_ms_project", ctypes.c_double), ("dev_ms_recon", ctypes.c_double),
+        ("dev_ms_tridiag", ctypes.c_double), ("dev_ms_logratio", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -17,6 +17,7 @@
 
 #include "fkkec.h"
 #include "host_math.h"
+#include "eig.h"
 #include "kernels.h"
 #include "plain.h"
 
@@ -88,8 +89,8 @@ struct fkk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    DevBuf<float> partial;
-    DevBuf<double> colsum_part, G, colsum;
+    DevBuf<float> partial, L;
+    DevBuf<double> colsum_part, G, colsum, fdev, tri;
     DevBuf<unsigned long long> clamps;
     DevBuf<int> tiles;
     DevBuf<float> rinv, Z, X;
@@ -97,7 +98,7 @@ struct fkk_ctx {
     DevBuf<long long> pmaxi, pmini, qext, qdev;
     PinnedBuf<double> hG;
     fkk::plain::Workspace plain_ws;
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[10] = {};
 
     hipError_t events() {
         for (auto& e : ev)
@@ -123,7 +124,8 @@ struct fkk_ctx {
         return s;
     }
     size_t bytes() const {
-        return partial.n * 4 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 + clamps.n * 8 + tiles.n * 4 +
+        return partial.n * 4 + L.n * 4 + fdev.n * 8 + tri.n * 8 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 +
+               clamps.n * 8 + tiles.n * 4 +
                rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
                qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
     }
@@ -288,45 +290,80 @@ fkk_basis* new_basis(int N, int k, const double* iref, const double* f, const do
     return b;
 }
 
-// Gram pass into ctx->G (device) and the column sums; copies G to h_gram.
-fkk_status run_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
-                    double floor, double* h_gram, double* h_colsum, int64_t* h_clamps, bool timed = false) {
+int npad_for(int N) { return round_up(N, fkk::dev::kGramTile); }
+
+// Log-ratio pass into ctx->L, Gram G_L = l^T l into ctx->G (device, FP64,
+// N x N), column sums into ctx->colsum and the clamp count into ctx->clamps.
+fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
+                       double floor, bool timed) {
+    const int npad = npad_for(N);
     const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64);
     std::vector<int> pairs(2 * plan.tiles);
     fkk::dev::gram_tile_list(plan.nb, pairs.data());
     std::vector<float> rinv(N);
     for (int j = 0; j < N; ++j) rinv[j] = (float)(1.0 / h_iref[j]);
+    const int64_t nlr = fkk::dev::logratio_blocks(M);
+    FKK_HIP(ctx, ctx->L.ensure((size_t)M * npad));
     FKK_HIP(ctx, ctx->partial.ensure(plan.partial_floats()));
-    FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)plan.chunks * N));
+    FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)nlr * npad));
     FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
     FKK_HIP(ctx, ctx->colsum.ensure(N));
     FKK_HIP(ctx, ctx->clamps.ensure(1));
     FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
     FKK_HIP(ctx, ctx->rinv.ensure(N));
-    FKK_HIP(ctx, ctx->hG.ensure((size_t)N * N + N + 1));
     hipStream_t s = ctx->stream;
     FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemcpyAsync(ctx->rinv.p, rinv.data(), N * sizeof(float), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemsetAsync(ctx->clamps.p, 0, sizeof(unsigned long long), s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
+    FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, ctx->rinv.p, (float)floor, ctx->L.p, npad, npad,
+                                           ctx->colsum_part.p, ctx->clamps.p, s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-    FKK_HIP(ctx, fkk::dev::launch_gram(d_I, M, N, ld, ctx->rinv.p, (float)floor, plan, ctx->tiles.p, ctx->partial.p,
-                                       ctx->colsum_part.p, ctx->clamps.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
-    FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, ctx->colsum_part.p, plan, ctx->tiles.p, N, ctx->G.p,
-                                              ctx->colsum.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, plan, ctx->tiles.p, N, ctx->G.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p, s));
+    return FKK_OK;
+}
+
+// Column sums and clamp count back to the host (synchronises the stream).
+fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) {
+    FKK_HIP(ctx, ctx->hG.ensure((size_t)N + 1));
+    hipStream_t s = ctx->stream;
     double* hg = ctx->hG.p;
-    FKK_HIP(ctx, hipMemcpyAsync(hg, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipMemcpyAsync(hg + (size_t)N * N, ctx->colsum.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipMemcpyAsync(hg + (size_t)N * N + N, ctx->clamps.p, sizeof(unsigned long long),
-                                hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg, ctx->colsum.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg + N, ctx->clamps.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
-    if (h_gram) std::memcpy(h_gram, hg, (size_t)N * N * sizeof(double));
-    if (h_colsum) std::memcpy(h_colsum, hg + (size_t)N * N, N * sizeof(double));
-    if (h_clamps) {
-        unsigned long long c;
-        std::memcpy(&c, hg + (size_t)N * N + N, sizeof c);
-        *h_clamps = (int64_t)c;
-    }
+    std::memcpy(h_colsum, hg, N * sizeof(double));
+    unsigned long long c;
+    std::memcpy(&c, hg + N, sizeof c);
+    *h_clamps = (int64_t)c;
+    return FKK_OK;
+}
+
+// Top-k eigenpairs of diag(f) G diag(f) with G = ctx->G: scaling and the
+// Householder reduction on the device, the tridiagonal eigenproblem and the
+// back-transformation on the host.  Overwrites ctx->G.
+fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed) {
+    const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
+    // layout of ctx->tri: p0 | p1 | beta | d | e | vstore
+    FKK_HIP(ctx, ctx->tri.ensure(5 * (size_t)N + nv));
+    FKK_HIP(ctx, ctx->fdev.ensure(N));
+    FKK_HIP(ctx, ctx->hG.ensure(3 * (size_t)N + nv));
+    hipStream_t s = ctx->stream;
+    double* t = ctx->tri.p;
+    double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, f, N * sizeof(double), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, fkk::dev::launch_scale_sym(ctx->G.p, ctx->fdev.p, N, s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
+    FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
+    if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+    double* h = ctx->hG.p;  // beta | d | e | vstore
+    FKK_HIP(ctx, hipMemcpyAsync(h, beta, (3 * (size_t)N + nv) * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipStreamSynchronize(s));
+    if (fkk::eig_tridiag_topk(h + N, h + 2 * N, h, h + 3 * N, N, k, vals, vecs) != 0)
+        return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
     return FKK_OK;
 }
 
@@ -396,6 +433,9 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     ctx->partial.release();
+    ctx->L.release();
+    ctx->fdev.release();
+    ctx->tri.release();
     ctx->colsum_part.release();
     ctx->G.release();
     ctx->colsum.release();
@@ -429,7 +469,15 @@ fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
     if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    return run_gram(ctx, d_I, M, N, ld, h_iref, ratio_floor, h_gram, h_colsum, h_clamps);
+    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, ratio_floor, false)) != FKK_OK) return st;
+    if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,
+                                            ctx->stream));
+    std::vector<double> cs(N);
+    int64_t cl = 0;
+    if ((st = fetch_sums(ctx, N, cs.data(), &cl)) != FKK_OK) return st;
+    if (h_colsum) std::memcpy(h_colsum, cs.data(), N * sizeof(double));
+    if (h_clamps) *h_clamps = cl;
+    return FKK_OK;
 }
 
 fkk_status fkk_eigh_topk(const double* h_a, int32_t N, int32_t k, double* h_evals, double* h_evecs) {
@@ -483,12 +531,13 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
 
     // 1. log ratio, Gram and column sums on the device (Eq. 2, 6, 9)
     auto t0 = std::chrono::steady_clock::now();
-    std::vector<double> G((size_t)N * N), colsum(N);
+    std::vector<double> colsum(N);
     int64_t clamps = 0;
     FKK_HIP(ctx, ctx->events());
-    if ((st = run_gram(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, G.data(), colsum.data(), &clamps, true)) != FKK_OK)
-        return st;
+    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, true)) != FKK_OK) return st;
+    if ((st = fetch_sums(ctx, N, colsum.data(), &clamps)) != FKK_OK) return st;
     r.dev_ms_gram = ctx->elapsed(0, 1);
+    r.dev_ms_logratio = ctx->elapsed(8, 9);
     r.clamps = clamps;
     r.ms_gram = ms_since(t0);
     if (p->strict && clamps > 0) return ctx->fail(FKK_EDOMAIN, "%lld intensity ratios clamped", (long long)clamps);
@@ -501,12 +550,10 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
             const double mean = colsum[j] / (double)M;
             f[j] = 2.0 * mean / std::sqrt(p->alpha * mean + p->sigma_g * p->sigma_g);
         }
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) G[(size_t)i * N + j] *= f[i] * f[j];
     std::vector<double> lam(k), V((size_t)N * k), sv(k);
-    if (fkk::eigh_topk(G.data(), N, k, lam.data(), V.data(), host_threads()) != 0)
-        return ctx->fail(FKK_EINTERNAL, "eigensolver failed");
+    if ((st = eig_device(ctx, N, k, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
     for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    r.dev_ms_tridiag = ctx->elapsed(6, 7);
     r.ms_eig = ms_since(t0);
 
     // 3. projection Z = A V_k and per-column arg-extrema (Eq. 13-15)
@@ -527,8 +574,8 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
         return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
     fkk::dev::ArgPart part{ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
     if (hipEventRecord(ctx->ev[2], s) != hipSuccess ||
-        fkk::dev::launch_project(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp, kp, ctx->Z.p,
-                                 kp, part, k, s) != hipSuccess ||
+        fkk::dev::launch_project(ctx->L.p, M, N, npad_for(N), ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp,
+                                 kp, ctx->Z.p, kp, part, k, s, true) != hipSuccess ||
         hipEventRecord(ctx->ev[3], s) != hipSuccess ||
         fkk::dev::launch_argext_reduce(part, nblk, kp, k, ctx->qext.p, ctx->qext.p + kp, s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));

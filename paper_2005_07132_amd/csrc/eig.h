@@ -1,0 +1,23 @@
+// Device Householder tridiagonalisation of a symmetric FP64 matrix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace fkk {
+namespace dev {
+
+// Packed reflector storage for an n x n reduction (column i: n - i - 1 values).
+size_t tridiag_vstore_doubles(int n);
+
+// A (n x n row-major FP64, symmetric, overwritten) -> tridiagonal (d: n,
+// e: n-1), reflectors (vstore, beta: n-2).  p0, p1: n doubles of scratch.
+hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vstore, double* beta, double* d, double* e,
+                          hipStream_t s);
+
+// G(r, c) *= f(r) f(c).
+hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s);
+
+}  // namespace dev
+}  // namespace fkk

@@ -1,0 +1,211 @@
+// Householder reduction of the symmetric N x N FP64 matrix G_A to
+// tridiagonal form on the device (the O(N^3) part of the eigensolve of
+// Eq. 6).  One launch per column i:
+//   every block rebuilds, in LDS, w_i = p_i - (beta_i/2)(p_i . v_i) v_i, the
+//   updated pivot row i+1 and from it the next reflector v_{i+1}; then the
+//   waves of all blocks apply B <- B - v_i w_i^T - w_i v_i^T to the rows
+//   below and dot each updated row with v_{i+1} (p_{i+1} = beta_{i+1} B v_{i+1}).
+// Rebuilding the O(N) pivot data in every block removes any grid-wide
+// synchronisation inside a step; the kernel boundary orders the steps.
+// Reflectors are stored packed (column i at i(N-1) - i(i-1)/2, length N-i-1)
+// with the same convention as the host reduction, so the host finishes with
+// bisection, inverse iteration and back-transformation.
+#include "eig.h"
+
+namespace fkk {
+namespace dev {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int64_t voff(int64_t i, int64_t n) { return i * (n - 1) - i * (i - 1) / 2; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Block-wide sum; every thread gets the result.  red: 4 doubles of LDS.
+__device__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+// Reflector of x (length m, in LDS): v = x - alpha e1, beta = 2 / v.v,
+// alpha = -sign(x0) |x|; zero reflector when x[1:] = 0.
+__device__ void make_reflector(const double* x, int m, double* v, double* beta, double* alpha, double* red) {
+    double part = 0.0;
+    for (int j = 1 + threadIdx.x; j < m; j += blockDim.x) part += x[j] * x[j];
+    const double sig2 = block_sum(part, red);
+    const double x0 = x[0];
+    if (sig2 == 0.0) {
+        for (int j = threadIdx.x; j < m; j += blockDim.x) v[j] = 0.0;
+        *beta = 0.0;
+        *alpha = x0;
+    } else {
+        const double norm = sqrt(x0 * x0 + sig2);
+        const double a = (x0 >= 0.0) ? -norm : norm;
+        for (int j = threadIdx.x; j < m; j += blockDim.x) v[j] = (j == 0) ? x0 - a : x[j];
+        *beta = 2.0 / ((x0 - a) * (x0 - a) + sig2);
+        *alpha = a;
+    }
+    __syncthreads();
+}
+
+// Step 0: reflector of row 0 and p_0 = beta_0 B_0 v_0.
+__global__ __launch_bounds__(kThreads) void tridiag_init(const double* __restrict__ A, int n,
+                                                         double* __restrict__ p_out, double* __restrict__ vstore,
+                                                         double* __restrict__ beta, double* __restrict__ d,
+                                                         double* __restrict__ e) {
+    extern __shared__ double sm[];
+    __shared__ double red[4];
+    const int m = n - 1;
+    double* x = sm;
+    double* v = sm + n;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) x[j] = A[1 + j];
+    __syncthreads();
+    double b, a;
+    make_reflector(x, m, v, &b, &a, red);
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < m; j += blockDim.x) vstore[j] = v[j];
+        if (threadIdx.x == 0) {
+            beta[0] = b;
+            d[0] = A[0];
+            e[0] = a;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tw = gridDim.x * (blockDim.x >> 6);
+    for (int r = 1 + gw; r < n; r += tw) {
+        const double* row = A + (size_t)r * n + 1;
+        double s = 0.0;
+        for (int c = lane; c < m; c += 64) s += row[c] * v[c];
+        s = wave_sum(s);
+        if (lane == 0) p_out[r - 1] = b * s;
+    }
+}
+
+// Step i (0 <= i <= n-3): rank-2 update of column i fused with p_{i+1}.
+__global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A, int n, int i,
+                                                         const double* __restrict__ p_in,
+                                                         double* __restrict__ p_out, double* __restrict__ vstore,
+                                                         double* __restrict__ beta, double* __restrict__ d,
+                                                         double* __restrict__ e) {
+    extern __shared__ double sm[];
+    __shared__ double red[4];
+    const int lo = i + 1, m = n - lo;
+    double* v = sm;          // v_i        (m)
+    double* w = sm + n;      // w_i        (m)
+    double* x = sm + 2 * n;  // updated row lo, columns lo..n-1 (m)
+    double* vn = sm + 3 * n; // v_{i+1}    (m-1)
+    const double* vs = vstore + voff(i, n);
+    const double bi = beta[i];
+    double part = 0.0;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        v[j] = vs[j];
+        w[j] = p_in[j];
+        part += p_in[j] * vs[j];
+    }
+    const double kk = 0.5 * bi * block_sum(part, red);
+    for (int j = threadIdx.x; j < m; j += blockDim.x) w[j] -= kk * v[j];
+    __syncthreads();
+    const double* rlo = A + (size_t)lo * n + lo;
+    for (int c = threadIdx.x; c < m; c += blockDim.x) x[c] = rlo[c] - (v[0] * w[c] + w[0] * v[c]);
+    __syncthreads();
+    const bool next = (i + 3 < n);
+    double bn = 0.0;
+    if (next) {
+        double a;
+        make_reflector(x + 1, m - 1, vn, &bn, &a, red);
+        if (blockIdx.x == 0) {
+            double* vso = vstore + voff(lo, n);
+            for (int j = threadIdx.x; j < m - 1; j += blockDim.x) vso[j] = vn[j];
+            if (threadIdx.x == 0) {
+                beta[lo] = bn;
+                d[lo] = x[0];
+                e[lo] = a;
+            }
+        }
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d[lo] = x[0];
+        e[lo] = x[1];
+    }
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tw = gridDim.x * (blockDim.x >> 6);
+    for (int r = lo + 1 + gw; r < n; r += tw) {
+        double* row = A + (size_t)r * n + lo;
+        const double vr = v[r - lo], wr = w[r - lo];
+        double s = 0.0;
+        for (int c = lane; c < m; c += 64) {
+            const double a = row[c] - (vr * w[c] + wr * v[c]);
+            row[c] = a;
+            if (next && c >= 1) s += a * vn[c - 1];
+            if (!next && r == n - 1 && c == m - 1) d[n - 1] = a;
+        }
+        if (next) {
+            s = wave_sum(s);
+            if (lane == 0) p_out[r - lo - 1] = bn * s;
+        }
+    }
+}
+
+__global__ void scale_sym_kernel(double* __restrict__ G, const double* __restrict__ f, int n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int r = (int)(idx / n), c = (int)(idx % n);
+    G[idx] *= f[r] * f[c];
+}
+
+}  // namespace
+
+size_t tridiag_vstore_doubles(int n) { return n >= 3 ? (size_t)(n - 2) * (n - 1) - (size_t)(n - 2) * (n - 3) / 2 : 1; }
+
+hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s) {
+    const int64_t total = (int64_t)n * n;
+    hipLaunchKernelGGL(scale_sym_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, f, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vstore, double* beta, double* d, double* e,
+                          hipStream_t s) {
+    if (n < 3) return hipErrorInvalidValue;
+    const size_t lds = (size_t)4 * n * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_init), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_step), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    auto blocks_for = [](int rows) {
+        int b = (rows + 7) / 8;  // at least two rows per wave
+        if (b < 1) b = 1;
+        if (b > 256) b = 256;
+        return b;
+    };
+    hipLaunchKernelGGL(tridiag_init, dim3(blocks_for(n - 1)), dim3(kThreads), lds, s, A, n, p0, vstore, beta, d, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    double* pin = p0;
+    double* pout = p1;
+    for (int i = 0; i + 2 < n; ++i) {
+        const int rows = n - (i + 2);
+        hipLaunchKernelGGL(tridiag_step, dim3(blocks_for(rows)), dim3(kThreads), lds, s, A, n, i, pin, pout, vstore,
+                           beta, d, e);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        double* t = pin;
+        pin = pout;
+        pout = t;
+    }
+    return hipSuccess;
+}
+
+}  // namespace dev
+}  // namespace fkk

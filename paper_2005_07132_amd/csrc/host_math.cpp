@@ -668,6 +668,18 @@ int eigh_topk(const double* a_in, int n, int k, double* vals, double* vecs, int 
     }
     d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
 
+    return eig_tridiag_topk(d.data(), e.data(), beta.data(), vstore.data(), n, k, vals, vecs);
+}
+
+int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta, const double* vstore, int n, int k,
+                     double* vals, double* vecs) {
+    if (n <= 0 || k <= 0 || k > n) return -1;
+    Pool& pool = host_pool();
+    std::vector<double> d(d_in, d_in + n), e(std::max(n - 1, 1), 0.0);
+    for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
+    std::vector<size_t> voff(std::max(n - 2, 0));
+    size_t total = 0;
+    for (int i = 0; i + 2 < n; ++i) { voff[i] = total; total += n - i - 1; }
     // ---- eigenvalues by bisection (Sturm counts) ----
     double tnorm = 0.0, lo = std::numeric_limits<double>::max(), hi = -lo;
     std::vector<double> e2(std::max(n - 1, 1), 0.0);

@@ -39,6 +39,13 @@ double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k
 // Returns 0 on success.
 int eigh_topk(const double* a, int n, int k, double* vals, double* vecs, int threads);
 
+// The same from an existing Householder tridiagonalisation: diagonal d (n),
+// off-diagonal e (n-1), reflectors beta (n-2) and vstore (column i packed at
+// sum_{j<i} (n-j-1), length n-i-1), with A = Q T Q^T, Q = H_0 ... H_{n-3},
+// H_i = I - beta_i v_i v_i^T acting on indices i+1..n-1.
+int eig_tridiag_topk(const double* d, const double* e, const double* beta, const double* vstore, int n, int k,
+                     double* vals, double* vecs);
+
 // Default readings of parameters the paper leaves open.
 int default_fft_len(int n);
 double default_als_lambda(int n);

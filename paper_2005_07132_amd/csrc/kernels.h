@@ -25,11 +25,17 @@ GramPlan gram_plan(int64_t M, int N, int target_chunks);
 // d_tiles: int2[tiles] (bi <= bj) written by the caller from gram_tile_list.
 void gram_tile_list(int nb, int* host_pairs /* 2 * tiles */);
 
-hipError_t launch_gram(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                       const GramPlan& plan, const int* d_tiles, float* partial, double* colsum_part,
-                       unsigned long long* clamps, hipStream_t s);
-hipError_t launch_gram_reduce(const float* partial, const double* colsum_part, const GramPlan& plan,
-                              const int* d_tiles, int N, double* G, double* colsum, hipStream_t s);
+// Log-ratio pass: L (M x ldl FP32, zero past column N up to npad) = l,
+// per-block FP64 column sums (logratio_blocks(M) x npad) and clamp count.
+int64_t logratio_blocks(int64_t M);
+hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, float* L,
+                           int64_t ldl, int npad, double* colsum_part, unsigned long long* clamps, hipStream_t s);
+// Gram partials of L (npad must cover plan.nb * 128 columns).
+hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
+                       float* partial, hipStream_t s);
+hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
+                              hipStream_t s);
+hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* out, hipStream_t s);
 
 // Projection Z = l W (W given transposed: Wt is kp x ldw, zero beyond k / N),
 // with per-block column arg-extrema partials when part != nullptr.
@@ -43,7 +49,7 @@ constexpr int kProjRows = 128;
 inline int64_t proj_blocks(int64_t M) { return (M + kProjRows - 1) / kProjRows; }
 hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                           const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z,
-                          ArgPart part, int k_arg, hipStream_t s);
+                          ArgPart part, int k_arg, hipStream_t s, bool logged = false);
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
                                 long long* qmin, hipStream_t s);
 

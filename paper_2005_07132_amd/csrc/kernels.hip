@@ -78,13 +78,66 @@ void gram_tile_list(int nb, int* pairs) {
         }
 }
 
+// ---------------------------------------------------------------------------
+// Log-ratio pass: l = 1/2 ln(I r) written once as FP32 (row stride ldl, zero
+// beyond column N), with FP64 column sums of I and the clamp count.
+// ---------------------------------------------------------------------------
+constexpr int LR_ROWS = 256;  // rows per block
+
 template <bool VEC>
-__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
-                                                   const float* __restrict__ rinv, float floor, int T,
+__global__ __launch_bounds__(256) void logratio_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                       const float* __restrict__ rinv, float floor,
+                                                       float* __restrict__ L, int64_t ldl, int npad,
+                                                       double* __restrict__ colsum_part,
+                                                       unsigned long long* __restrict__ clamps) {
+    const int64_t r0 = (int64_t)blockIdx.x * LR_ROWS;
+    const int64_t r1 = (r0 + LR_ROWS < M) ? r0 + LR_ROWS : M;
+    unsigned int cnt = 0;
+    for (int g0 = 0; g0 < npad; g0 += 1024) {
+        const int c = g0 + 4 * (int)threadIdx.x;
+        if (c >= npad) continue;
+        float r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = (c + q < N) ? rinv[c + q] : 0.f;
+        double cs[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t row0 = r0; row0 < r1; row0 += 4) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = (row0 + u < r1) ? load4_guarded(I + (row0 + u) * ld, c, N, VEC) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (row0 + u >= r1) break;
+                float l[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bool bad;
+                    const float xv = f4get(x[u], q);
+                    l[q] = log_ratio(xv, r[q], floor, bad);
+                    if (c + q < N) {
+                        cnt += bad ? 1u : 0u;
+                        cs[q] += (double)xv;
+                    } else {
+                        l[q] = 0.f;
+                    }
+                }
+                *reinterpret_cast<float4*>(L + (row0 + u) * ldl + c) = make_float4(l[0], l[1], l[2], l[3]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) colsum_part[(size_t)blockIdx.x * npad + c + q] = cs[q];
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(clamps, (unsigned long long)cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Gram of the log ratio from l (no bounds checks on columns: l is zero past
+// N up to the padded width).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, int64_t ldl, int64_t M, int T,
                                                    int64_t rpc, const int* __restrict__ tiles,
-                                                   float* __restrict__ partial,
-                                                   double* __restrict__ colsum_part,
-                                                   unsigned long long* __restrict__ clamps) {
+                                                   float* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) float sA[2][GKC][GLD];
     __shared__ __attribute__((aligned(16))) float sB[2][GKC][GLD];
 
@@ -104,14 +157,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, 
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = tid >> 5;
     const int lc = (tid & 31) * 4;
-    const int ca = bi * GT + lc, cb = bj * GT + lc;
-
-    float ra[4], rb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ra[q] = (ca + q < N) ? rinv[ca + q] : 0.f;
-        rb[q] = (cb + q < N) ? rinv[cb + q] : 0.f;
-    }
+    const float* La = L + bi * GT + lc;
+    const float* Lb = L + bj * GT + lc;
 
     floatx4 acc[4][4];
 #pragma unroll
@@ -120,62 +167,28 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, 
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     float4 xa[4], xb[4];
-    double cs[4] = {0.0, 0.0, 0.0, 0.0};
-    unsigned int cnt = 0;
-
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     auto load = [&](int64_t base) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int64_t row = base + lr + 8 * p;
-            if (row < m1) {
-                const float* src = I + row * ld;
-                xa[p] = load4_guarded(src, ca, N, VEC);
-                if (!diag) xb[p] = load4_guarded(src, cb, N, VEC);
-            } else {
-                xa[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-                xb[p] = xa[p];
-            }
+            const bool ok = row < m1;
+            xa[p] = ok ? *reinterpret_cast<const float4*>(La + row * ldl) : zero4;
+            if (!diag) xb[p] = ok ? *reinterpret_cast<const float4*>(Lb + row * ldl) : zero4;
         }
     };
-    auto store = [&](int buf, int64_t base) {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const int64_t row = base + lr + 8 * p;
-            const bool rv = row < m1;
-            float la[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                la[q] = 0.f;
-                if (rv && ca + q < N) {
-                    bool bad;
-                    const float x = f4get(xa[p], q);
-                    la[q] = log_ratio(x, ra[q], floor, bad);
-                    if (diag) {
-                        cnt += bad ? 1u : 0u;
-                        cs[q] += (double)x;
-                    }
-                }
-            }
-            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) = make_float4(la[0], la[1], la[2], la[3]);
-            if (!diag) {
-                float lb[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    lb[q] = 0.f;
-                    if (rv && cb + q < N) {
-                        bool bad;
-                        lb[q] = log_ratio(f4get(xb[p], q), rb[q], floor, bad);
-                    }
-                }
-                *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) = make_float4(lb[0], lb[1], lb[2], lb[3]);
-            }
+            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) = xa[p];
+            if (!diag) *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) = xb[p];
         }
     };
 
     const int64_t nst = (m1 > m0) ? (m1 - m0 + GKC - 1) / GKC : 0;
     if (nst > 0) {
         load(m0);
-        store(0, m0);
+        store(0);
     }
     __syncthreads();
     for (int64_t s = 0; s < nst; ++s) {
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(av[i], bv[j], acc[i][j]);
         }
-        if (s + 1 < nst) store(buf ^ 1, m0 + (s + 1) * GKC);
+        if (s + 1 < nst) store(buf ^ 1);
         __syncthreads();
     }
 
@@ -211,22 +224,6 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ I, 
                 const int c = wc * 64 + j * 16 + (lane & 15);
                 P[r * GT + c] = acc[i][j][v];
             }
-
-    if (diag) {
-        double* scs = reinterpret_cast<double*>(&sA[0][0][0]);  // 8 x GT doubles
-#pragma unroll
-        for (int q = 0; q < 4; ++q) scs[lr * GT + lc + q] = cs[q];
-        __syncthreads();
-        if (tid < GT) {
-            double t = 0.0;
-            for (int g = 0; g < 8; ++g) t += scs[g * GT + tid];
-            const int col = bi * GT + tid;
-            if (col < N) colsum_part[(size_t)chunk * N + col] = t;
-        }
-        unsigned int c = cnt;
-        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-        if (lane == 0 && c) atomicAdd(clamps, (unsigned long long)c);
-    }
 }
 
 __global__ void gram_reduce_kernel(const float* __restrict__ partial, int T, int C,
@@ -246,34 +243,47 @@ __global__ void gram_reduce_kernel(const float* __restrict__ partial, int T, int
     }
 }
 
-__global__ void colsum_reduce_kernel(const double* __restrict__ part, int C, int N, double* __restrict__ out) {
+__global__ void colsum_reduce_kernel(const double* __restrict__ part, int C, int stride, int N,
+                                     double* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     double s = 0.0;
-    for (int ch = 0; ch < C; ++ch) s += part[(size_t)ch * N + j];
+    for (int ch = 0; ch < C; ++ch) s += part[(size_t)ch * stride + j];
     out[j] = s;
 }
 
-hipError_t launch_gram(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                       const GramPlan& plan, const int* d_tiles, float* partial, double* colsum_part,
-                       unsigned long long* clamps, hipStream_t s) {
+int64_t logratio_blocks(int64_t M) { return (M + LR_ROWS - 1) / LR_ROWS; }
+
+hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, float* L,
+                           int64_t ldl, int npad, double* colsum_part, unsigned long long* clamps, hipStream_t s) {
     const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
-    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(256);
+    dim3 grid((unsigned)logratio_blocks(M)), block(256);
     if (vec)
-        hipLaunchKernelGGL(gram_kernel<true>, grid, block, 0, s, I, M, N, ld, rinv, floor, plan.tiles,
-                           plan.rows_per_chunk, d_tiles, partial, colsum_part, clamps);
+        hipLaunchKernelGGL(logratio_kernel<true>, grid, block, 0, s, I, M, N, ld, rinv, floor, L, ldl, npad,
+                           colsum_part, clamps);
     else
-        hipLaunchKernelGGL(gram_kernel<false>, grid, block, 0, s, I, M, N, ld, rinv, floor, plan.tiles,
-                           plan.rows_per_chunk, d_tiles, partial, colsum_part, clamps);
+        hipLaunchKernelGGL(logratio_kernel<false>, grid, block, 0, s, I, M, N, ld, rinv, floor, L, ldl, npad,
+                           colsum_part, clamps);
     return hipGetLastError();
 }
 
-hipError_t launch_gram_reduce(const float* partial, const double* colsum_part, const GramPlan& plan,
-                              const int* d_tiles, int N, double* G, double* colsum, hipStream_t s) {
+hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
+                       float* partial, hipStream_t s) {
+    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(256);
+    hipLaunchKernelGGL(gram_kernel, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
+                              hipStream_t s) {
     dim3 grid(GT * GT / 256, plan.tiles);
     hipLaunchKernelGGL(gram_reduce_kernel, grid, dim3(256), 0, s, partial, plan.tiles, plan.chunks, d_tiles, N, G);
-    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, colsum_part, plan.chunks, N,
-                       colsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, (int)nparts, stride, N,
+                       out);
     return hipGetLastError();
 }
 
@@ -313,6 +323,22 @@ __device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __
         }
         *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
     }
+}
+
+// Stage one 128 x 64 tile of a precomputed l (row stride ldl, zero past N).
+__device__ __forceinline__ void stage_loaded(float (*sL)[PLD], const float* __restrict__ L, int64_t r0, int64_t M,
+                                             int64_t ldl, int j0) {
+    const int tid = threadIdx.x;
+    const int lrow = tid >> 4;
+    const int lcol = (tid & 15) * 4;
+    float4 x[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int64_t row = r0 + lrow + 16 * p;
+        x[p] = (row < M) ? *reinterpret_cast<const float4*>(L + row * ldl + j0 + lcol) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = x[p];
 }
 
 template <int KB>
@@ -356,7 +382,7 @@ __device__ __forceinline__ void better_min(float& v, int& i, float ov, int oi) {
     if (ov < v || (ov == v && oi < i)) { v = ov; i = oi; }
 }
 
-template <int KB, bool VEC>
+template <int KB, bool VEC, bool LOGGED>
 __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                       const float* __restrict__ rinv, float floor,
                                                       const float* __restrict__ Wt, int ldw, int k_store,
@@ -376,7 +402,8 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
         for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     for (int j0 = 0; j0 < N; j0 += PNC) {
-        stage_logratio<VEC>(sL, I, r0, M, N, ld, j0, rinv, floor);
+        if (LOGGED) stage_loaded(sL, I, r0, M, ld, j0);
+        else stage_logratio<VEC>(sL, I, r0, M, N, ld, j0, rinv, floor);
         stage_weights<KB>(sW, Wt, ldw, j0);
         __syncthreads();
         project_stage<KB>(acc, sL, sW, wave, lane);
@@ -475,28 +502,32 @@ __global__ void argext_reduce_kernel(ArgPart part, int64_t nblocks, int kp, long
 }
 
 template <int KB>
-static hipError_t project_dispatch(bool vec, dim3 grid, hipStream_t s, const float* I, int64_t M, int N, int64_t ld,
+static hipError_t project_dispatch(int mode, dim3 grid, hipStream_t s, const float* I, int64_t M, int N, int64_t ld,
                                    const float* rinv, float floor, const float* Wt, int ldw, int k_store, float* Z,
                                    int64_t ld_z, ArgPart part, int k_arg) {
-    if (vec)
-        hipLaunchKernelGGL((project_kernel<KB, true>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,
-                           k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);
-    else
-        hipLaunchKernelGGL((project_kernel<KB, false>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,
-                           k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);
+#define FKK_PJ(a, b)                                                                                               \
+    hipLaunchKernelGGL((project_kernel<KB, a, b>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, \
+                       Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg)
+    if (mode == 2) FKK_PJ(true, true);
+    else if (mode == 1) FKK_PJ(true, false);
+    else FKK_PJ(false, false);
+#undef FKK_PJ
     return hipGetLastError();
 }
 
+// logged: I already holds l (row stride ld, 16-byte aligned, zero past N up
+// to a multiple of 64 columns).
 hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                           const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z, ArgPart part,
-                          int k_arg, hipStream_t s) {
+                          int k_arg, hipStream_t s, bool logged) {
     const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    const int mode = logged ? 2 : (vec ? 1 : 0);
     dim3 grid((unsigned)proj_blocks(M));
     switch (kp) {
-        case 16: return project_dispatch<1>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
-        case 32: return project_dispatch<2>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
-        case 64: return project_dispatch<4>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
-        case 128: return project_dispatch<8>(vec, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 16: return project_dispatch<1>(mode, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 32: return project_dispatch<2>(mode, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 64: return project_dispatch<4>(mode, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
+        case 128: return project_dispatch<8>(mode, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, k_store, Z, ld_z, part, k_arg);
         default: return hipErrorInvalidValue;
     }
 }
