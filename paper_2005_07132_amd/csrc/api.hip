@@ -307,7 +307,7 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
     FKK_HIP(ctx, ctx->partial.ensure(plan.partial_floats()));
     FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)nlr * npad));
     FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
-    FKK_HIP(ctx, ctx->colsum.ensure(N));
+    FKK_HIP(ctx, ctx->colsum.ensure(N + fkk::dev::colsum_scratch_doubles(N)));
     FKK_HIP(ctx, ctx->clamps.ensure(1));
     FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
     FKK_HIP(ctx, ctx->rinv.ensure(N));
@@ -323,7 +323,7 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
     FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
     FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, plan, ctx->tiles.p, N, ctx->G.p, s));
-    FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N, ctx->colsum.p, s));
     return FKK_OK;
 }
 

@@ -94,6 +94,8 @@ __global__ __launch_bounds__(kThreads) void tridiag_init(const double* __restric
 }
 
 // Step i (0 <= i <= n-3): rank-2 update of column i fused with p_{i+1}.
+// The pivot data are built with one round of global reads and two block
+// reductions: ptv = p_i . v_i, then |x_{1:}|^2 of the updated pivot row.
 __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A, int n, int i,
                                                          const double* __restrict__ p_in,
                                                          double* __restrict__ p_out, double* __restrict__ vstore,
@@ -107,24 +109,42 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
     double* x = sm + 2 * n;  // updated row lo, columns lo..n-1 (m)
     double* vn = sm + 3 * n; // v_{i+1}    (m-1)
     const double* vs = vstore + voff(i, n);
+    const double* rlo = A + (size_t)lo * n + lo;
     const double bi = beta[i];
+    // one round of independent global reads
     double part = 0.0;
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        v[j] = vs[j];
-        w[j] = p_in[j];
-        part += p_in[j] * vs[j];
+        const double vj = vs[j], pj = p_in[j];
+        v[j] = vj;
+        w[j] = pj;
+        x[j] = rlo[j];
+        part += pj * vj;
     }
-    const double kk = 0.5 * bi * block_sum(part, red);
-    for (int j = threadIdx.x; j < m; j += blockDim.x) w[j] -= kk * v[j];
-    __syncthreads();
-    const double* rlo = A + (size_t)lo * n + lo;
-    for (int c = threadIdx.x; c < m; c += blockDim.x) x[c] = rlo[c] - (v[0] * w[c] + w[0] * v[c]);
-    __syncthreads();
+    const double kk = 0.5 * bi * block_sum(part, red);  // barriers make v, w, x visible
+    const double v0 = vs[0], w0 = p_in[0] - kk * vs[0];   // from global: w[0] is rewritten below
     const bool next = (i + 3 < n);
+    double part2 = 0.0;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const double wj = w[j] - kk * v[j];
+        const double xj = x[j] - (v0 * wj + w0 * v[j]);
+        w[j] = wj;
+        x[j] = xj;
+        if (j >= 2) part2 += xj * xj;
+    }
     double bn = 0.0;
     if (next) {
+        const double sig2 = block_sum(part2, red);  // x, w complete after this
+        const double x0 = x[1];
         double a;
-        make_reflector(x + 1, m - 1, vn, &bn, &a, red);
+        if (sig2 == 0.0) {
+            a = x0;
+            for (int j = threadIdx.x; j < m - 1; j += blockDim.x) vn[j] = 0.0;
+        } else {
+            const double norm = sqrt(x0 * x0 + sig2);
+            a = (x0 >= 0.0) ? -norm : norm;
+            bn = 2.0 / ((x0 - a) * (x0 - a) + sig2);
+            for (int j = threadIdx.x; j < m - 1; j += blockDim.x) vn[j] = (j == 0) ? x0 - a : x[1 + j];
+        }
         if (blockIdx.x == 0) {
             double* vso = vstore + voff(lo, n);
             for (int j = threadIdx.x; j < m - 1; j += blockDim.x) vso[j] = vn[j];
@@ -134,7 +154,9 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
                 e[lo] = a;
             }
         }
-    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    }
+    __syncthreads();
+    if (!next && blockIdx.x == 0 && threadIdx.x == 0) {
         d[lo] = x[0];
         e[lo] = x[1];
     }
@@ -145,7 +167,23 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
         double* row = A + (size_t)r * n + lo;
         const double vr = v[r - lo], wr = w[r - lo];
         double s = 0.0;
-        for (int c = lane; c < m; c += 64) {
+        int c = lane;
+        for (; c + 192 < m; c += 256) {  // four independent loads in flight
+            const double a0 = row[c], a1 = row[c + 64], a2 = row[c + 128], a3 = row[c + 192];
+            const double u0 = a0 - (vr * w[c] + wr * v[c]);
+            const double u1 = a1 - (vr * w[c + 64] + wr * v[c + 64]);
+            const double u2 = a2 - (vr * w[c + 128] + wr * v[c + 128]);
+            const double u3 = a3 - (vr * w[c + 192] + wr * v[c + 192]);
+            row[c] = u0;
+            row[c + 64] = u1;
+            row[c + 128] = u2;
+            row[c + 192] = u3;
+            if (next) {
+                if (c >= 1) s += u0 * vn[c - 1];
+                s += u1 * vn[c + 63] + u2 * vn[c + 127] + u3 * vn[c + 191];
+            }
+        }
+        for (; c < m; c += 64) {
             const double a = row[c] - (vr * w[c] + wr * v[c]);
             row[c] = a;
             if (next && c >= 1) s += a * vn[c - 1];

@@ -35,7 +35,9 @@ hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& p
                        float* partial, hipStream_t s);
 hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
                               hipStream_t s);
-hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* out, hipStream_t s);
+size_t colsum_scratch_doubles(int N);
+hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* mid, double* out,
+                                hipStream_t s);
 
 // Projection Z = l W (W given transposed: Wt is kp x ldw, zero beyond k / N),
 // with per-block column arg-extrema partials when part != nullptr.

@@ -10,6 +10,7 @@
 // LDS load.
 #include "kernels.h"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -243,12 +244,31 @@ __global__ void gram_reduce_kernel(const float* __restrict__ partial, int T, int
     }
 }
 
-__global__ void colsum_reduce_kernel(const double* __restrict__ part, int C, int stride, int N,
-                                     double* __restrict__ out) {
+// Column sums over the partials in a fixed order: stage 1 sums groups of
+// partials (grid.y groups), stage 2 sums the groups.
+__global__ void colsum_stage1_kernel(const double* __restrict__ part, int64_t C, int stride, int N,
+                                     double* __restrict__ mid) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int64_t g = blockIdx.y, G = gridDim.y;
+    const int64_t c0 = C * g / G, c1 = C * (g + 1) / G;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t c = c0;
+    for (; c + 3 < c1; c += 4) {
+        s0 += part[(size_t)c * stride + j];
+        s1 += part[(size_t)(c + 1) * stride + j];
+        s2 += part[(size_t)(c + 2) * stride + j];
+        s3 += part[(size_t)(c + 3) * stride + j];
+    }
+    for (; c < c1; ++c) s0 += part[(size_t)c * stride + j];
+    mid[(size_t)g * N + j] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ void colsum_stage2_kernel(const double* __restrict__ mid, int G, int N, double* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     double s = 0.0;
-    for (int ch = 0; ch < C; ++ch) s += part[(size_t)ch * stride + j];
+    for (int g = 0; g < G; ++g) s += mid[(size_t)g * N + j];
     out[j] = s;
 }
 
@@ -281,9 +301,14 @@ hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const 
     return hipGetLastError();
 }
 
-hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, (int)nparts, stride, N,
-                       out);
+constexpr int kColsumGroups = 64;
+size_t colsum_scratch_doubles(int N) { return (size_t)kColsumGroups * N; }
+
+hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* mid, double* out,
+                                hipStream_t s) {
+    const int G = (int)std::min<int64_t>(kColsumGroups, nparts);
+    hipLaunchKernelGGL(colsum_stage1_kernel, dim3((N + 255) / 256, G), dim3(256), 0, s, part, nparts, stride, N, mid);
+    hipLaunchKernelGGL(colsum_stage2_kernel, dim3((N + 255) / 256), dim3(256), 0, s, mid, G, N, out);
     return hipGetLastError();
 }
 
