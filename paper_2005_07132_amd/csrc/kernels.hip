@@ -168,21 +168,29 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, 
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     float4 xa[4], xb[4];
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float keep[4];
+    // Rows past the chunk are loaded from the chunk's last row (always valid)
+    // and zeroed when written to LDS, so the loads are unconditional and the
+    // loaded registers are first used after the MFMA block.
     auto load = [&](int64_t base) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int64_t row = base + lr + 8 * p;
-            const bool ok = row < m1;
-            xa[p] = ok ? *reinterpret_cast<const float4*>(La + row * ldl) : zero4;
-            if (!diag) xb[p] = ok ? *reinterpret_cast<const float4*>(Lb + row * ldl) : zero4;
+            const int64_t rc = row < m1 ? row : m1 - 1;
+            keep[p] = row < m1 ? 1.f : 0.f;
+            xa[p] = *reinterpret_cast<const float4*>(La + rc * ldl);
+            xb[p] = *reinterpret_cast<const float4*>(Lb + rc * ldl);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) = xa[p];
-            if (!diag) *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) = xb[p];
+            const float k = keep[p];
+            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) =
+                make_float4(xa[p].x * k, xa[p].y * k, xa[p].z * k, xa[p].w * k);
+            if (!diag)
+                *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) =
+                    make_float4(xb[p].x * k, xb[p].y * k, xb[p].z * k, xb[p].w * k);
         }
     };
 
@@ -360,10 +368,14 @@ __device__ __forceinline__ void stage_loaded(float (*sL)[PLD], const float* __re
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
         const int64_t row = r0 + lrow + 16 * p;
-        x[p] = (row < M) ? *reinterpret_cast<const float4*>(L + row * ldl + j0 + lcol) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int64_t rc = row < M ? row : M - 1;
+        x[p] = *reinterpret_cast<const float4*>(L + rc * ldl + j0 + lcol);
     }
 #pragma unroll
-    for (int p = 0; p < 8; ++p) *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = x[p];
+    for (int p = 0; p < 8; ++p) {
+        const float k = (r0 + lrow + 16 * p < M) ? 1.f : 0.f;
+        *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(x[p].x * k, x[p].y * k, x[p].z * k, x[p].w * k);
+    }
 }
 
 template <int KB>
