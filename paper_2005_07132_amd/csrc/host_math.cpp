@@ -717,41 +717,74 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
         }
     });
 
-    // ---- eigenvectors of T by inverse iteration, re-orthogonalised within
-    //      clusters of close eigenvalues ----
+    // ---- eigenvectors of T by inverse iteration ----
+    // Each vector is iterated with its own shift (independently, in
+    // parallel).  Eigenvalues closer than ortol (numerically equal) form a
+    // group that is iterated together with re-orthogonalisation; a final
+    // modified Gram-Schmidt pass removes the remaining O(eps |T| / gap)
+    // overlaps between computed vectors.
     std::vector<double> Y((size_t)k * n);  // vector j at j*n
-    {
-        std::vector<double> dl, dd, du, du2, b(n);
-        std::vector<char> sw;
-        const double ortol = 1e-3 * tnorm;
-        int cluster_start = 0;
-        for (int j = 0; j < k; ++j) {
-            if (j > 0 && std::fabs(vals[j - 1] - vals[j]) > ortol) cluster_start = j;
-            // deterministic start vector
-            uint64_t state = 0x9E3779B97F4A7C15ull + (uint64_t)j;
-            for (int i = 0; i < n; ++i) {
-                state = state * 6364136223846793005ull + 1442695040888963407ull;
-                b[i] = 0.5 + (double)(state >> 11) * (1.0 / 9007199254740992.0);
-            }
-            // a tiny shift separates equal eigenvalues of a cluster
-            double lam = vals[j];
-            const int iters = (j > cluster_start) ? 5 : 3;
-            for (int it = 0; it < iters; ++it) {
-                tri_shift_solve(d.data(), e.data(), n, lam, pivmin + eps * tnorm, b.data(), dl, dd, du, du2, sw);
-                for (int c = cluster_start; c < j; ++c) {
-                    const double* yc = &Y[(size_t)c * n];
-                    double s = 0.0;
-                    for (int i = 0; i < n; ++i) s += yc[i] * b[i];
-                    for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
-                }
-                double nrm = 0.0;
-                for (int i = 0; i < n; ++i) nrm += b[i] * b[i];
-                nrm = std::sqrt(nrm);
-                if (!(nrm > 0.0) || !std::isfinite(nrm)) return -2;
-                for (int i = 0; i < n; ++i) b[i] /= nrm;
-            }
-            std::copy(b.begin(), b.end(), Y.begin() + (size_t)j * n);
+    const double ortol = 1e-10 * tnorm;
+    std::vector<int> group_start;
+    for (int j = 0; j < k; ++j)
+        if (j == 0 || std::fabs(vals[j - 1] - vals[j]) > ortol) group_start.push_back(j);
+    const int ngroups = (int)group_start.size();
+    group_start.push_back(k);
+    auto dotn = [n](const double* a, const double* b) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int i = 0;
+        for (; i + 3 < n; i += 4) {
+            s0 += a[i] * b[i];
+            s1 += a[i + 1] * b[i + 1];
+            s2 += a[i + 2] * b[i + 2];
+            s3 += a[i + 3] * b[i + 3];
         }
+        for (; i < n; ++i) s0 += a[i] * b[i];
+        return (s0 + s1) + (s2 + s3);
+    };
+    std::atomic<int> failed{0};
+    pool.run([&](int tid, int nthr) {
+        std::vector<double> dl, dd, du, du2;
+        std::vector<char> sw;
+        for (int g = tid; g < ngroups; g += nthr) {
+            const int c0 = group_start[g], c1 = group_start[g + 1];
+            for (int j = c0; j < c1; ++j) {
+                double* b = &Y[(size_t)j * n];
+                uint64_t state = 0x9E3779B97F4A7C15ull + (uint64_t)j;  // deterministic start
+                for (int i = 0; i < n; ++i) {
+                    state = state * 6364136223846793005ull + 1442695040888963407ull;
+                    b[i] = 0.5 + (double)(state >> 11) * (1.0 / 9007199254740992.0);
+                }
+                const int iters = (j > c0) ? 5 : 3;
+                for (int it = 0; it < iters; ++it) {
+                    tri_shift_solve(d.data(), e.data(), n, vals[j], pivmin + eps * tnorm, b, dl, dd, du, du2, sw);
+                    for (int c = c0; c < j; ++c) {
+                        const double* yc = &Y[(size_t)c * n];
+                        const double s = dotn(yc, b);
+                        for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
+                    }
+                    const double nrm = std::sqrt(dotn(b, b));
+                    if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+                        failed.store(1);
+                        return;
+                    }
+                    const double inv = 1.0 / nrm;
+                    for (int i = 0; i < n; ++i) b[i] *= inv;
+                }
+            }
+        }
+    });
+    if (failed.load()) return -2;
+    for (int j = 1; j < k; ++j) {
+        double* b = &Y[(size_t)j * n];
+        for (int c = 0; c < j; ++c) {
+            const double* yc = &Y[(size_t)c * n];
+            const double s = dotn(yc, b);
+            for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
+        }
+        const double nrm = std::sqrt(dotn(b, b));
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return -2;
+        for (int i = 0; i < n; ++i) b[i] /= nrm;
     }
 
     // ---- back-transformation x = H_0 H_1 ... H_{n-3} y ----

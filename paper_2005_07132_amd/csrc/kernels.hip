@@ -598,11 +598,40 @@ hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long lo
 constexpr int RR = 128;  // rows per block (4 waves x 32)
 constexpr int RCN = 64;  // wavenumbers per chunk
 
+// exp(x) = 2^(x log2 e) on the hardware exp2 (relative error a few ulp for
+// the exponent range of log-ratio spectra).
+__device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// sin and cos by reduction to r in [-pi/4, pi/4] (three-part Cody-Waite
+// split of pi/2; n * 1.5703125 is exact for |n| < 2^16) and Taylor
+// polynomials through r^9 (sin) and r^10 (cos), truncation error below
+// 2e-9 and 2e-11.
+__device__ __forceinline__ void sincos_fast(float x, float* sn, float* cs) {
+    const float n = rintf(x * 0.636619772367581343f);
+    float r = fmaf(-n, 1.5703125f, x);
+    r = fmaf(-n, 4.83826794896619231e-4f, r);
+    r = fmaf(-n, 2.56328311e-12f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);
+    ps = fmaf(r2, ps, 8.33333333e-3f);
+    ps = fmaf(r2, ps, -1.66666667e-1f);
+    const float s = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -2.75573192e-7f, 2.48015873e-5f);
+    pc = fmaf(r2, pc, -1.38888889e-3f);
+    pc = fmaf(r2, pc, 4.16666667e-2f);
+    pc = fmaf(r2, pc, -0.5f);
+    const float c = fmaf(r2, pc, 1.0f);
+    const int q = ((int)n) & 3;
+    *sn = (q == 0) ? s : (q == 1) ? c : (q == 2) ? -s : -c;
+    *cs = (q == 0) ? c : (q == 1) ? -s : (q == 2) ? -c : s;
+}
+
 __device__ __forceinline__ float epilogue(float re, float im, int plane) {
-    const float mag = expf(re);
-    if (plane == 0) return mag * sinf(im);
-    if (plane == 1) return mag * cosf(im);
-    return mag;
+    const float mag = exp_fast(re);
+    if (plane == 2) return mag;
+    float sn, cs;
+    sincos_fast(im, &sn, &cs);
+    return mag * (plane == 0 ? sn : cs);
 }
 
 template <int KB>

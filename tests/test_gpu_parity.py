@@ -144,6 +144,28 @@ def test_reconstruction_epilogue(ctx, fitted, plane):
     assert spectrum_err(out, ref).max() < TOL
 
 
+def test_reconstruction_epilogue_wide_phase_range(ctx):
+    # the device epilogue reduces the phase by multiples of pi/2: check it
+    # over several periods (|phase| up to ~8 rad) against FP64 sin/cos/exp
+    say("reconstruct wide phase")
+    rng = synth.rng_for(77, 1)
+    n, k, m = 200, 10, 3000
+    v = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    basis = {"i_ref": np.ones(n), "f": np.ones(n), "s": np.ones(k), "v": v,
+             "b_re": 0.05 * rng.standard_normal((k, n)), "b_im": rng.standard_normal((k, n)),
+             "ml_lambda": 0.0, "ratio_floor": 1e-6}
+    z = (2.0 * rng.standard_normal((m, k)) / np.sqrt(k)).astype(np.float32)
+    b = ctx.basis_import(basis)
+    bas32 = dict(basis, b_re=basis["b_re"].astype(np.float32).astype(np.float64),
+                 b_im=basis["b_im"].astype(np.float32).astype(np.float64))
+    phase = z.astype(np.float64) @ bas32["b_im"]
+    assert np.abs(phase).max() > 6.0
+    for plane, key in ((fk.OUT_IM, "im"), (fk.OUT_RE, "re"), (fk.OUT_ABS, "abs")):
+        out = host(ctx.reconstruct(b, dev(z), plane))
+        ref = wf.reconstruct(z.astype(np.float64), bas32)[key]
+        assert spectrum_err(out, ref).max() < TOL, key
+
+
 @pytest.mark.parametrize("m", [1, 127, 129, 1000])
 def test_transform_with_oracle_basis(ctx, fitted, m):
     say(f"transform m={m}")
