@@ -725,12 +725,44 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z,
         }
 
     floatx4 are[4][2], aim[4][2];
+    constexpr int PER_ROW = KP / 4;
+    floatx4 nre[KB], nim[KB];  // native vectors stay in registers
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        const int idx = threadIdx.x + 256 * p;
+        const size_t src = (size_t)(idx / PER_ROW) * KP + (idx % PER_ROW) * 4;
+        nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
+        nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
+    }
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        const int idx = threadIdx.x + 256 * p;
+        const int dst = (idx / PER_ROW) * BLD + (idx % PER_ROW) * 4;
+        *reinterpret_cast<floatx4*>(sRe + dst) = nre[p];
+        *reinterpret_cast<floatx4*>(sIm + dst) = nim[p];
+    }
+    __syncthreads();
     for (int j0 = 0; j0 < N; j0 += RCN) {
-        stage_basis_chunk<KB>(sRe, sIm, BLD, BreT, BimT, j0);
-        __syncthreads();
+        // the last chunk reloads itself (harmless) so loads stay unconditional
+        const int jn = (j0 + RCN < N) ? j0 + RCN : j0;
+#pragma unroll
+        for (int p = 0; p < KB; ++p) {
+            const int idx = threadIdx.x + 256 * p;
+            const size_t src = (size_t)(jn + idx / PER_ROW) * KP + (idx % PER_ROW) * 4;
+            nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
+            nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
+        }
         recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
         __syncthreads();
+#pragma unroll
+        for (int p = 0; p < KB; ++p) {
+            const int idx = threadIdx.x + 256 * p;
+            const int dst = (idx / PER_ROW) * BLD + (idx % PER_ROW) * 4;
+            *reinterpret_cast<floatx4*>(sRe + dst) = nre[p];
+            *reinterpret_cast<floatx4*>(sIm + dst) = nim[p];
+        }
         store_out<VEC_OUT>(out, ld_out, M, N, r0, wave, lane, j0, are, aim, plane);
+        __syncthreads();
     }
 }
 
@@ -818,12 +850,44 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
                                                           4 * (lane >> 4));
     // sRe / sIm live beyond sZ, so no barrier is needed before staging them.
     floatx4 are[4][2], aim[4][2];
+    constexpr int PER_ROW = KP / 4;
+    floatx4 nre[KB], nim[KB];  // native vectors stay in registers
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        const int idx = threadIdx.x + 256 * p;
+        const size_t src = (size_t)(idx / PER_ROW) * KP + (idx % PER_ROW) * 4;
+        nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
+        nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
+    }
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        const int idx = threadIdx.x + 256 * p;
+        const int dst = (idx / PER_ROW) * BLD + (idx % PER_ROW) * 4;
+        *reinterpret_cast<floatx4*>(sRe + dst) = nre[p];
+        *reinterpret_cast<floatx4*>(sIm + dst) = nim[p];
+    }
+    __syncthreads();
     for (int j0 = 0; j0 < N; j0 += RCN) {
-        stage_basis_chunk<KB>(sRe, sIm, BLD, BreT, BimT, j0);
-        __syncthreads();
+        // the last chunk reloads itself (harmless) so loads stay unconditional
+        const int jn = (j0 + RCN < N) ? j0 + RCN : j0;
+#pragma unroll
+        for (int p = 0; p < KB; ++p) {
+            const int idx = threadIdx.x + 256 * p;
+            const size_t src = (size_t)(jn + idx / PER_ROW) * KP + (idx % PER_ROW) * 4;
+            nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
+            nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
+        }
         recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
         __syncthreads();
+#pragma unroll
+        for (int p = 0; p < KB; ++p) {
+            const int idx = threadIdx.x + 256 * p;
+            const int dst = (idx / PER_ROW) * BLD + (idx % PER_ROW) * 4;
+            *reinterpret_cast<floatx4*>(sRe + dst) = nre[p];
+            *reinterpret_cast<floatx4*>(sIm + dst) = nim[p];
+        }
         store_out<VEC_OUT>(out, ld_out, M, N, r0, wave, lane, j0, are, aim, plane);
+        __syncthreads();
     }
 }
 
