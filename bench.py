@@ -51,6 +51,114 @@ def cpu_baseline(cube, k, seconds_target=20.0):
             "sample": f"first {m} spectra of the cube, full fKK-EC fit (gesdd SVD, k={k}), {dt:.1f} s"}
 
 
+def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
+    """Poisson arrivals of square tiles (side 2^U(5,9), log-uniform) from two
+    instruments with resident bases (N = 1,000 and N = 1,600, k = 50),
+    offered load rising to saturation; fKK-EC through the continuous-batching
+    server and the conventional method on the same arrival trace."""
+    import threading
+    import queue as queue_mod
+    log("serving: second instrument (512 x 512 x 1,600 cube) and its basis")
+    cube2 = synth.tissue_cube(rows=512, cols=512, n=1600, map_key=3, noise_key=3)
+    I2 = torch.from_numpy(cube2.i_cars).cuda()
+    b1600, _, _ = ctx.fit(I2, cube2.i_ref, fk.params(k=50, f_mode=fk.F_NOISE, alpha=cube2.alpha,
+                                                       sigma_g=cube2.sigma_g), want_out=False)
+    del I2
+    frames = []
+    for n, key in ((1000, 700), (1600, 701)):
+        fr = synth.tissue_cube(rows=512, cols=512, n=n, map_key=key, noise_key=key)
+        t = torch.empty(fr.i_cars.shape, dtype=torch.float32, pin_memory=True)
+        t.copy_(torch.from_numpy(fr.i_cars))
+        frames.append((t, fr.i_ref))
+    del cube2
+    out_pool = [torch.empty((2 * 512 * 512, n), dtype=torch.float32, pin_memory=True) for n in (1000, 1600)]
+    srv = fk.Server(0, hbm_budget_bytes=16 << 30, max_inflight=64, max_batch_rows=1 << 20)
+    ids = [srv.add_basis(basis1000), srv.add_basis(b1600)]
+    rng = np.random.default_rng(20200514)
+    mean_spectra = float(np.mean([round(2 ** rng.uniform(5, 9)) ** 2 for _ in range(200000)]))
+    levels = []
+    pctx = fk.Context(0, stream=torch.cuda.default_stream(0))
+    pparams = [fk.params(k=50), fk.params(k=50)]
+
+    def trace(rate_spectra, seed):
+        r = np.random.default_rng(seed)
+        rate_tiles = rate_spectra / mean_spectra
+        n_tiles = int(max(5, min(max_tiles, rate_tiles * seconds)))
+        gaps = r.exponential(1.0 / rate_tiles, n_tiles)
+        sides = np.round(2 ** r.uniform(5, 9, n_tiles)).astype(int)
+        which = r.integers(0, 2, n_tiles)
+        return np.cumsum(gaps), sides, which
+
+    for rate in (5e4, 1e6, 1e7, 3e7, 1e8):
+        arr, sides, which = trace(rate, int(rate))
+        # fKK-EC through the server
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        offs = [0, 0]
+        tickets = []
+        for t_arr, side, w in zip(arr, sides, which):
+            now = time.perf_counter() - t0
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            rows = int(side) * int(side)
+            o = offs[w]
+            if o + rows > out_pool[w].shape[0]:
+                o = 0
+            offs[w] = o + rows
+            tickets.append(srv.submit(ids[w], frames[w][0][:rows], out_pool[w][o:o + rows]))
+        srv.drain()
+        st = srv.stats()
+        # conventional method: one tile after another on the same trace
+        q = queue_mod.Queue()
+        lat = []
+
+        def worker():
+            # the plain context runs on the default stream, like these copies
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                t_sub, w, rows = item
+                d = frames[w][0][:rows].to("cuda", non_blocking=True)
+                o = pctx.plain(d, frames[w][1], pparams[w])
+                o.to("cpu")
+                torch.cuda.synchronize()
+                lat.append((time.perf_counter() - t_sub) * 1e3)
+
+        pctx_stream_thread = threading.Thread(target=worker)
+        pctx_stream_thread.start()
+        t0 = time.perf_counter()
+        deadline = t0 + 3 * seconds
+        n_plain = 0
+        for t_arr, side, w in zip(arr, sides, which):
+            now = time.perf_counter() - t0
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            if time.perf_counter() > deadline:
+                break
+            q.put((time.perf_counter(), w, int(side) * int(side)))
+            n_plain += 1
+        q.put(None)
+        pctx_stream_thread.join()
+        plain_spectra = int(sum(int(s) ** 2 for s in sides[:n_plain]))
+        plain_wall = (time.perf_counter() - t0)
+        level = {"offered_spectra_per_s": rate, "tiles": int(len(arr)),
+                 "fkkec": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                           "spectra_per_s": st["spectra"] / max(st["busy_s"], 1e-9),
+                           "mean_tiles_per_launch": st["mean_batch_tiles"]},
+                 "plain": {"tiles": n_plain, "p50_ms": float(np.percentile(lat, 50)) if lat else None,
+                           "p99_ms": float(np.percentile(lat, 99)) if lat else None,
+                           "spectra_per_s": plain_spectra / plain_wall}}
+        log(f"serving offered {rate:.0e}/s: fkk p50 {st['p50_ms']:.2f} p99 {st['p99_ms']:.2f} ms, "
+            f"{level['fkkec']['spectra_per_s']:.3e}/s; plain p50 {level['plain']['p50_ms']} ms")
+        levels.append(level)
+    srv.close()
+    pctx.close()
+    return {"mean_tile_spectra": mean_spectra, "levels": levels,
+            "note": "latency = submit from host memory -> result in host memory (pinned buffers); "
+                    "fKK-EC through the continuous-batching server, conventional method tile by tile"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +168,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--frames", type=int, default=20)
+    ap.add_argument("--skip-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path is data-parallel over spectra and this build runs on a "
@@ -156,6 +265,10 @@ def main():
         plain = {"spectra": mp, "ms": pl_ms, "spectra_per_s": mp / (pl_ms * 1e-3)}
         del pout
 
+    serving = None
+    if not args.skip_serving:
+        serving = serving_bench(ctx, fk, torch, synth, b)
+
     cpu = None
     if not args.skip_cpu:
         log("oracle on the host")
@@ -179,6 +292,7 @@ def main():
         "logratio_pass": logratio,
         "transform": transform,
         "plain": plain,
+        "serving": serving,
         "speedup_vs_plain_same_gpu": (value / plain["spectra_per_s"]) if plain else None,
         "paper_context": {"fkk_ec_cpu_s_per_spectrum": 99e-6, "conventional_cpu_s_per_spectrum": 7.0e-3,
                           "hardware": "6-core i7-8850H laptop, NumPy/SciPy"},

@@ -44,7 +44,8 @@ typedef enum {
     FKK_EDOMAIN = -4,    /* invalid intensities while strict mode is on      */
     FKK_EMISMATCH = -5,  /* basis and data disagree (N, device)              */
     FKK_ERANK = -7,      /* the requested rank is not available              */
-    FKK_EINTERNAL = -8   /* numerical failure inside the library             */
+    FKK_EINTERNAL = -8,  /* numerical failure inside the library             */
+    FKK_EBUSY = -9       /* not finished within the requested time           */
 } fkk_status;
 
 /* Detrending operator D of PEC (Sec. 2.1, Eq. 12, 16). */
@@ -231,6 +232,59 @@ fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double
                             double* v, double* b_re, double* b_im, double* phi_pec_t,
                             double* v_sec_t, double* h_v, int64_t* q, double* scalars3);
 void fkk_basis_free(fkk_basis* b);
+
+/* ---- serving: stored-basis transforms of image tiles as they arrive ------
+ *
+ * ML:fKK-EC applies a trained basis to new data as it is acquired (Sec. 2.6,
+ * "applied to new data as it is acquired").  A server keeps bases resident
+ * on one device and processes tiles (any number of spectra) submitted from
+ * host memory.  A scheduler thread admits queued tiles while their device
+ * bytes fit the HBM budget and an in-flight slot is free, concatenates the
+ * admitted tiles of one basis into a single launch (continuous batching:
+ * tiles that arrive while others run join the next launch), and overlaps
+ * host-to-device copies, the transform and device-to-host copies on separate
+ * streams.  Each output row depends only on its input row and the basis, so
+ * a tile's result is the same alone or batched with others.
+ */
+typedef struct fkk_server fkk_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device bytes for in-flight tiles (in + out) */
+    int32_t max_inflight;      /* tiles in flight at once                     */
+    int64_t max_batch_rows;    /* spectra per launch                          */
+} fkk_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t spectra;           /* spectra completed                           */
+    int64_t launches;          /* transform launches (batches)                */
+    double p50_ms, p99_ms, max_ms, mean_ms;  /* submit -> result in host memory */
+    double busy_s;             /* wall time from first submit to last completion */
+    double mean_batch_tiles;   /* tiles per launch                            */
+} fkk_server_stats;
+
+/* Creates a server on `device` (own streams, own workspace of
+ * hbm_budget_bytes, allocated here). */
+fkk_status fkk_server_create(int device, const fkk_server_config* cfg, fkk_server** out);
+/* Makes a basis resident for this server; *basis_id identifies it in
+ * fkk_server_submit.  The basis must stay alive until the server is destroyed. */
+fkk_status fkk_server_add_basis(fkk_server* srv, const fkk_basis* basis, int32_t* basis_id);
+/* Queues one tile: h_in (rows x N FP32, stride ld) -> h_out (rows x N FP32,
+ * stride ld_out), both host memory (page-locked memory overlaps best) that
+ * must stay valid until the tile completes.  Returns immediately with a
+ * ticket.  Fails with FKK_ENOMEM if the tile alone exceeds the budget. */
+fkk_status fkk_server_submit(fkk_server* srv, int32_t basis_id, const float* h_in, int64_t rows, int64_t ld,
+                             float* h_out, int64_t ld_out, int64_t* ticket);
+/* Waits until the tile has completed (timeout_ms < 0: no limit).  Returns
+ * FKK_OK when done, FKK_EBUSY on timeout.  *latency_ms (nullable) receives
+ * submit-to-completion time. */
+fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, double* latency_ms);
+/* Blocks until every submitted tile has completed. */
+fkk_status fkk_server_drain(fkk_server* srv);
+fkk_status fkk_server_stats_get(fkk_server* srv, fkk_server_stats* st);
+/* Clears the latency record and counters (bases stay resident). */
+fkk_status fkk_server_reset_stats(fkk_server* srv);
+void fkk_server_destroy(fkk_server* srv);
 
 #ifdef __cplusplus
 }

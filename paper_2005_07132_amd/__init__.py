@@ -63,13 +63,30 @@ class BasisDesc(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch_rows", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("spectra", ctypes.c_int64), ("launches", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("mean_batch_tiles", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _LIB = None
 
 SYMBOLS = [
     "fkk_version", "fkk_status_string", "fkk_params_default", "fkk_ctx_create", "fkk_ctx_destroy",
     "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram",
     "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
-    "fkk_basis_info", "fkk_basis_export", "fkk_basis_free",
+    "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_server_create", "fkk_server_add_basis",
+    "fkk_server_submit", "fkk_server_wait", "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats",
+    "fkk_server_destroy",
 ]
 
 
@@ -106,6 +123,17 @@ def lib() -> ctypes.CDLL:
     L.fkk_basis_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.fkk_basis_export.argtypes = [vp] + [_c_double_p] * 9 + [_c_int64_p, _c_double_p]
     L.fkk_basis_free.argtypes = [vp]
+    L.fkk_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    L.fkk_server_add_basis.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.fkk_server_submit.argtypes = [vp, i32, vp, i64, i64, vp, i64, ctypes.POINTER(i64)]
+    L.fkk_server_wait.argtypes = [vp, i64, dbl, ctypes.POINTER(dbl)]
+    L.fkk_server_drain.argtypes = [vp]
+    L.fkk_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.fkk_server_reset_stats.argtypes = [vp]
+    L.fkk_server_destroy.argtypes = [vp]
+    for name in ("fkk_server_create", "fkk_server_add_basis", "fkk_server_submit", "fkk_server_wait",
+                 "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram", "fkk_eigh_topk",
                  "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
                  "fkk_basis_info", "fkk_basis_export"):
@@ -362,5 +390,73 @@ class Context:
         return Basis(out.value)
 
 
-__all__ = ["Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
+class Server:
+    """Continuous-batching server of stored-basis transforms (host tiles)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 64,
+                 max_batch_rows: int = 1 << 20):
+        cfg = ServerConfig(hbm_budget_bytes, max_inflight, max_batch_rows)
+        h = ctypes.c_void_p()
+        st = lib().fkk_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
+        if st != FKK_OK:
+            raise FkkError(st, "server creation")
+        self._h = h
+        self._bases = []
+
+    def add_basis(self, basis: Basis) -> int:
+        bid = ctypes.c_int32()
+        st = lib().fkk_server_add_basis(self._h, basis.handle, ctypes.byref(bid))
+        if st != FKK_OK:
+            raise FkkError(st, "add_basis")
+        self._bases.append(basis)  # keep it alive as long as the server
+        return bid.value
+
+    def submit(self, basis_id: int, tile, out) -> int:
+        """tile, out: host (preferably pinned) float32 2-D tensors or arrays."""
+        def ptr(a):
+            return a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data
+        def stride(a):
+            return a.stride(0) if hasattr(a, "data_ptr") else a.strides[0] // 4
+        t = ctypes.c_int64()
+        st = lib().fkk_server_submit(self._h, basis_id, ptr(tile), tile.shape[0], stride(tile), ptr(out),
+                                     stride(out), ctypes.byref(t))
+        if st != FKK_OK:
+            raise FkkError(st, "submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        lat = ctypes.c_double()
+        st = lib().fkk_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat))
+        if st != FKK_OK:
+            raise FkkError(st, "wait")
+        return lat.value
+
+    def drain(self):
+        st = lib().fkk_server_drain(self._h)
+        if st != FKK_OK:
+            raise FkkError(st, "drain")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = lib().fkk_server_stats_get(self._h, ctypes.byref(s))
+        if st != FKK_OK:
+            raise FkkError(st, "stats")
+        return s.as_dict()
+
+    def reset_stats(self):
+        lib().fkk_server_reset_stats(self._h)
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().fkk_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
            "SYMBOLS", "LIB_PATH"]

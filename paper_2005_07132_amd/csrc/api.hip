@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fkkec.h"
+#include "internal.h"
 #include "host_math.h"
 #include "eig.h"
 #include "kernels.h"
@@ -128,24 +129,6 @@ struct fkk_ctx {
                clamps.n * 8 + tiles.n * 4 +
                rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
                qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
-    }
-};
-
-struct fkk_basis {
-    int device = -1;
-    int N = 0, k = 0, kp = 0, npad = 0;
-    std::vector<double> i_ref, f, s, v, b_re, b_im, phi_pec_t, v_sec_t, h_v;
-    std::vector<int64_t> q;
-    double ml_lambda = 0.0, ratio_floor = 1e-6, ridge_lambda = 0.0;
-    float* d_rinv = nullptr;
-    float* d_wt = nullptr;      // kp x npad: f(j) V(j,c) shrink(c)
-    float* d_bre_t = nullptr;   // npad x kp
-    float* d_bim_t = nullptr;   // npad x kp
-    ~fkk_basis() {
-        if (d_rinv) hipFree(d_rinv);
-        if (d_wt) hipFree(d_wt);
-        if (d_bre_t) hipFree(d_bre_t);
-        if (d_bim_t) hipFree(d_bim_t);
     }
 };
 
