@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
+#include <vector>
 
 namespace fkk {
 namespace plain {
@@ -30,9 +32,11 @@ struct Workspace {
     double* phi = nullptr;     // batch x N   KK phase, later H{phi_err}
     double* err = nullptr;     // batch x N   phase error phi_err
     double* scratch = nullptr; // 4 x N x batch, interleaved ALS state
-    double* twiddle = nullptr; // len / 2 complex
+    double* twiddle = nullptr; // len / 2 complex (table of the current length)
+    std::vector<std::pair<int, double*>> tw_tables;  // one table per FFT length used
     double* sg = nullptr;      // trendline coefficient tables
     int64_t batch = 0;
+    size_t cap_row = 0;        // doubles per batch-sized array (batch x N)
     int n = 0, len = 0, tw_len = 0;
     size_t sg_doubles = 0;
     size_t bytes() const;

@@ -16,17 +16,19 @@
 namespace fkk {
 namespace plain {
 
-size_t Workspace::bytes() const {
-    return (size_t)batch * n * 8 * 3 + (size_t)batch * n * 8 * 4 + (size_t)tw_len * 8 + sg_doubles * 8;
-}
+size_t Workspace::bytes() const { return cap_row * 8 * 7 + (size_t)tw_len * 8 + sg_doubles * 8; }
 
 void Workspace::release() {
-    for (double** p : {&ell, &phi, &err, &scratch, &twiddle, &sg})
+    for (double** p : {&ell, &phi, &err, &scratch, &sg})
         if (*p) {
             hipFree(*p);
             *p = nullptr;
         }
+    for (auto& t : tw_tables) hipFree(t.second);
+    tw_tables.clear();
+    twiddle = nullptr;
     batch = 0;
+    cap_row = 0;
     n = len = tw_len = 0;
     sg_doubles = 0;
 }
@@ -419,29 +421,43 @@ hipError_t run(Workspace& ws, const Config& cfg, const float* d_I, int64_t M, in
     }
     const int64_t batch = std::min<int64_t>(((M + kThreads - 1) / kThreads) * kThreads, 131072);
     hipError_t e;
-    if (ws.batch < batch || ws.n != N) {
-        ws.release();
-        const size_t row = (size_t)batch * N * sizeof(double);
+    // arrays are sized batch x N doubles; grow only, so alternating spectral
+    // lengths and tile sizes reuse the same buffers
+    const size_t need = (size_t)batch * N;
+    if (ws.cap_row < need) {
+        for (double** p : {&ws.ell, &ws.phi, &ws.err, &ws.scratch})
+            if (*p) {
+                hipFree(*p);
+                *p = nullptr;
+            }
+        ws.cap_row = 0;
+        const size_t row = need * sizeof(double);
         if ((e = hipMalloc(&ws.ell, row)) != hipSuccess) return e;
         if ((e = hipMalloc(&ws.phi, row)) != hipSuccess) return e;
         if ((e = hipMalloc(&ws.err, row)) != hipSuccess) return e;
         if ((e = hipMalloc(&ws.scratch, 4 * row)) != hipSuccess) return e;
-        ws.batch = batch;
-        ws.n = N;
+        ws.cap_row = need;
     }
-    if (ws.len != L) {
-        if (ws.twiddle) hipFree(ws.twiddle);
+    ws.batch = batch;
+    ws.n = N;
+    ws.twiddle = nullptr;
+    for (auto& t : ws.tw_tables)
+        if (t.first == L) ws.twiddle = t.second;
+    if (!ws.twiddle) {
         std::vector<double> tw(L);
         for (int j = 0; j < L / 2; ++j) {
             const double a = -2.0 * M_PI * (double)j / (double)L;
             tw[2 * j] = std::cos(a);
             tw[2 * j + 1] = std::sin(a);
         }
-        if ((e = hipMalloc(&ws.twiddle, L * sizeof(double))) != hipSuccess) return e;
-        if ((e = hipMemcpy(ws.twiddle, tw.data(), L * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return e;
-        ws.len = L;
-        ws.tw_len = L;
+        double* dtw = nullptr;
+        if ((e = hipMalloc(&dtw, L * sizeof(double))) != hipSuccess) return e;
+        if ((e = hipMemcpy(dtw, tw.data(), L * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return e;
+        ws.tw_tables.emplace_back(L, dtw);
+        ws.twiddle = dtw;
+        ws.tw_len += L;
     }
+    ws.len = L;
     // (V^T V)^-1 of the scaled Vandermonde of the window and I_ref
     const int half = cfg.window / 2, m = cfg.order + 1;
     std::vector<double> host((size_t)N + 16, 0.0);

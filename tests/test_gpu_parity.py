@@ -244,6 +244,42 @@ def test_fit_default_subsample_reproduces_from_exported_basis(ctx):
     assert rep["clamps"] == 0 and rep["n_q"] >= 20
 
 
+@pytest.mark.parametrize("k,n,m,ld_pad", [(100, 400, 3000, 0), (20, 250, 2000, 3), (8, 1600, 1500, 0),
+                                           (64, 300, 700, 1), (16, 200, 129, 0)])
+def test_fit_shapes_and_strides(ctx, k, n, m, ld_pad):
+    # every matrix-core tile width (k padded to 16/32/64/128), spectral
+    # lengths that are not multiples of the tiles, unaligned row strides
+    say(f"fit k={k} n={n} m={m} ld_pad={ld_pad}")
+    cube = synth.tissue_cube(rows=1, cols=m, n=n, map_key=40 + k, noise_key=40 + k, blur=1.0)
+    data = cube.i_cars
+    if ld_pad:
+        full = np.zeros((m, n + ld_pad), dtype=np.float32)
+        full[:, :n] = data
+        t = dev(full)[:, :n]
+    else:
+        t = dev(data)
+    p = oracle_params(cube, k=k)
+    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p))
+    assert _check_exported_basis_reproduces(cube, b, host(out)).max() < TOL
+    # the stored basis applied to new data matches the oracle's transform
+    e = b.export()
+    new = synth.tissue_cube(rows=1, cols=257, n=n, map_key=50 + k, noise_key=50 + k, blur=1.0)
+    got = host(ctx.transform(b, dev(new.i_cars)))
+    ref = wf.transform(new.i_cars.astype(np.float64), e)["im"]
+    assert spectrum_err(got, ref).max() < TOL
+
+
+def test_plain_path_long_spectra_and_strides(ctx):
+    say("plain n=1600 / strided")
+    cube = synth.tissue_cube(rows=6, cols=7, n=1600, map_key=60, noise_key=60, blur=1.0)
+    p = wf.Params(k=5, detrend=op.DETREND_WHITTAKER)
+    full = np.zeros((42, 1603), dtype=np.float32)
+    full[:, :1600] = cube.i_cars
+    out = host(ctx.plain(dev(full)[:, :1600], cube.i_ref, lib_params(p)))
+    ref = wf.plain(cube.i_cars.astype(np.float64), cube.i_ref, p)["im"]
+    assert spectrum_err(out, ref).max() < TOL
+
+
 @pytest.mark.parametrize("sec", [op.SEC_SAVGOL, op.SEC_MEAN])
 def test_plain_path_whittaker_matches_oracle(ctx, sec):
     say(f"plain whittaker sec={sec}")
