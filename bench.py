@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix peak, flop/s
+PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix peak, flop/s
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 
 
@@ -62,7 +63,8 @@ def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
     cube2 = synth.tissue_cube(rows=512, cols=512, n=1600, map_key=3, noise_key=3)
     I2 = torch.from_numpy(cube2.i_cars).cuda()
     b1600, _, _ = ctx.fit(I2, cube2.i_ref, fk.params(k=50, f_mode=fk.F_NOISE, alpha=cube2.alpha,
-                                                       sigma_g=cube2.sigma_g), want_out=False)
+                                                       sigma_g=cube2.sigma_g, recon_prec=fk.PREC_BF16),
+                          want_out=False)
     del I2
     frames = []
     for n, key in ((1000, 700), (1600, 701)):
@@ -74,6 +76,8 @@ def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
     out_pool = [torch.empty((2 * 512 * 512, n), dtype=torch.float32, pin_memory=True) for n in (1000, 1600)]
     plain_out = [torch.empty((512 * 512, n), dtype=torch.float32, pin_memory=True) for n in (1000, 1600)]
     srv = fk.Server(0, hbm_budget_bytes=16 << 30, max_inflight=64, max_batch_rows=1 << 20)
+    # both resident bases serve in BF16 (matrix-core operands; FP32 accumulation)
+    basis1000.precision = fk.PREC_BF16
     ids = [srv.add_basis(basis1000), srv.add_basis(b1600)]
     rng = np.random.default_rng(20200514)
     mean_spectra = float(np.mean([round(2 ** rng.uniform(5, 9)) ** 2 for _ in range(200000)]))
@@ -157,7 +161,55 @@ def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
     pctx.close()
     return {"mean_tile_spectra": mean_spectra, "levels": levels,
             "note": "latency = submit from host memory -> result in host memory (pinned buffers); "
-                    "fKK-EC through the continuous-batching server, conventional method tile by tile"}
+                    "fKK-EC through the continuous-batching server (BF16 transforms, k=50), conventional "
+                    "method tile by tile"}
+
+
+def fit_steps(ctx, I, i_ref, p, steps, warmup, out, torch, tag):
+    """Times `steps` back-to-back fits (after `warmup`); returns ms/step and
+    the per-fit reports."""
+    for i in range(warmup):
+        b, _, rep = ctx.fit(I, i_ref, p, out=out)
+        b.free()
+        log(f"{tag} warmup {i}: {rep['ms_total']:.1f} ms")
+    reps = []
+    b = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if b is not None:
+            b.free()
+        b, _, rep = ctx.fit(I, i_ref, p, out=out)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / steps
+    stage = {key: float(np.mean([r[key] for r in reps])) for key in reps[0] if key.startswith(("ms_", "dev_ms_"))}
+    return ms_step, stage, b
+
+
+def time_transform(ctx, b, frames, fout, I, out, n_frames, torch):
+    for _ in range(3):
+        ctx.transform(b, frames[0], out=fout)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(n_frames):
+        ctx.transform(b, frames[i % len(frames)], out=fout)
+    stop.record()
+    torch.cuda.synchronize()
+    fr_ms = start.elapsed_time(stop) / n_frames
+    ctx.transform(b, I, out=out)
+    torch.cuda.synchronize()
+    start.record()
+    ctx.transform(b, I, out=out)
+    stop.record()
+    torch.cuda.synchronize()
+    full_ms = start.elapsed_time(stop)
+    m, n = I.shape
+    return {"frame_ms": fr_ms, "frames_per_s": 1e3 / fr_ms, "spectra_per_s_frames": frames[0].shape[0] / (fr_ms * 1e-3),
+            "full_cube_ms": full_ms, "spectra_per_s_full_cube": m / (full_ms * 1e-3),
+            "HBM_GB/s_full_cube": 8.0 * m * n / (full_ms * 1e-3) / 1e9,
+            "HBM_frac_full_cube": 8.0 * m * n / (full_ms * 1e-3) / PEAK_HBM}
 
 
 def main():
@@ -191,25 +243,9 @@ def main():
     ctx = fk.Context(0)
     p = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
 
-    for i in range(args.warmup):
-        b, _, rep = ctx.fit(I, cube.i_ref, p, out=out)
-        b.free()
-        log(f"warmup {i}: {rep['ms_total']:.1f} ms")
-    reps = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        b, _, rep = ctx.fit(I, cube.i_ref, p, out=out)
-        reps.append(rep)
-        if i + 1 < args.steps:
-            b.free()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = 1e3 * elapsed / args.steps
-    value = m / (elapsed / args.steps)
+    ms_step, stage, b = fit_steps(ctx, I, cube.i_ref, p, args.steps, args.warmup, out, torch, "fp32")
+    value = m / (ms_step * 1e-3)
     log(f"fit: {ms_step:.2f} ms/step, {value:.3e} spectra/s")
-
-    stage = {key: float(np.mean([r[key] for r in reps])) for key in reps[0] if key.startswith(("ms_", "dev_ms_"))}
     gram_ms = stage["dev_ms_gram"]
     gram_flop = float(m) * n * (n + 1)  # symmetric Gram: N(N+1)/2 entries x 2M flop
     roofline = {"bound": "mfma", "kernel": "gram_kernel (FP32 MFMA Gram of the log ratio)",
@@ -219,36 +255,42 @@ def main():
     npad = (n + 127) // 128 * 128
     logratio = {"ms": stage["dev_ms_logratio"],
                 "GB/s": (4.0 * m * n + 4.0 * m * npad) / (stage["dev_ms_logratio"] * 1e-3) / 1e9}
-    recon_bytes = 4.0 * m * n + 4.0 * m * 64 + 8.0 * n * 64
-    recon = {"ms": stage["dev_ms_recon"], "GB/s": recon_bytes / (stage["dev_ms_recon"] * 1e-3) / 1e9,
-             "flop": 4.0 * m * n * args.k,
-             "TFLOP/s": 4.0 * m * n * args.k / (stage["dev_ms_recon"] * 1e-3) / 1e12}
+    kp = 16 if args.k <= 16 else 32 if args.k <= 32 else 64 if args.k <= 64 else 128
+    kq = max(kp, 32)
+
+    def recon_stats(ms, kcols, bytes_per_basis_elem):
+        nbytes = 4.0 * m * n + 4.0 * m * kp + 2.0 * n * kcols * bytes_per_basis_elem
+        return {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9, "HBM_frac": nbytes / (ms * 1e-3) / PEAK_HBM,
+                "bytes": nbytes, "flop": 4.0 * m * n * args.k,
+                "TFLOP/s": 4.0 * m * n * args.k / (ms * 1e-3) / 1e12}
+
+    recon = recon_stats(stage["dev_ms_recon"], kp, 4)
 
     # stored-basis transform on 256 x 256 x 1000 frames (new maps and noise)
     log("stored-basis transform frames")
     frames = [torch.from_numpy(synth.frame(i).i_cars).to(dev) for i in range(2)]
     fout = torch.empty_like(frames[0])
-    for _ in range(3):
-        ctx.transform(b, frames[0], out=fout)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for i in range(args.frames):
-        ctx.transform(b, frames[i % 2], out=fout)
-    stop.record()
-    torch.cuda.synchronize()
-    fr_ms = start.elapsed_time(stop) / args.frames
-    ctx.transform(b, I, out=out)
-    torch.cuda.synchronize()
-    start.record()
-    ctx.transform(b, I, out=out)
-    stop.record()
-    torch.cuda.synchronize()
-    tr_full_ms = start.elapsed_time(stop)
-    transform = {"frame_ms": fr_ms, "frames_per_s": 1e3 / fr_ms, "spectra_per_s_frames": 65536 / (fr_ms * 1e-3),
-                 "full_cube_ms": tr_full_ms, "spectra_per_s_full_cube": m / (tr_full_ms * 1e-3),
-                 "HBM_GB/s_full_cube": 8.0 * m * n / (tr_full_ms * 1e-3) / 1e9}
+    transform = time_transform(ctx, b, frames, fout, I, out, args.frames, torch)
+
+    # the same fit and transforms with BF16 matrix-core operands
+    log("BF16 fit and transforms")
+    p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
+                    gram_prec=fk.PREC_BF16, recon_prec=fk.PREC_BF16)
+    ms16, stage16, b16 = fit_steps(ctx, I, cube.i_ref, p16, args.steps, 1, out, torch, "bf16")
+    gram16_ms = stage16["dev_ms_gram"]
+    bf16 = {"fit_ms_per_step": ms16, "fit_spectra_per_s": m / (ms16 * 1e-3), "stages_ms": stage16,
+            "gram": {"ms": gram16_ms, "TFLOP/s": gram_flop / (gram16_ms * 1e-3) / 1e12,
+                     "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA,
+                     "bytes_read": 2.0 * m * npad,
+                     "GB/s_algorithmic": 2.0 * m * npad / (gram16_ms * 1e-3) / 1e9},
+            "logratio_pass": {"ms": stage16["dev_ms_logratio"],
+                              "GB/s": (4.0 * m * n + 2.0 * m * npad) / (stage16["dev_ms_logratio"] * 1e-3) / 1e9},
+            "reconstruction": recon_stats(stage16["dev_ms_recon"], kq, 2),
+            "transform": time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)}
+    log(f"bf16 fit: {ms16:.2f} ms/step; transform {bf16['transform']['spectra_per_s_full_cube']:.3e}/s")
+    b16.free()
     del frames, fout
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     plain = None
     if not args.skip_plain:
@@ -292,6 +334,7 @@ def main():
         "reconstruction": recon,
         "logratio_pass": logratio,
         "transform": transform,
+        "bf16": bf16,
         "plain": plain,
         "serving": serving,
         "speedup_vs_plain_same_gpu": (value / plain["spectra_per_s"]) if plain else None,

@@ -58,8 +58,11 @@ enum { FKK_PAD_EDGE = 0, FKK_PAD_ZERO = 1 };
 enum { FKK_F_ONE = 0, FKK_F_NOISE = 1 };
 /* Which plane of K_CARS (Eq. 23) the output holds. */
 enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
-/* Input precision of the matrix-core contractions (FP32 accumulation). */
-enum { FKK_PREC_FP32 = 0 };
+/* Input precision of the matrix-core contractions, always with FP32
+ * accumulation.  BF16 rounds the operands (log ratio, projection weights,
+ * Z and the corrected bases) to BF16, nearest even, as they are staged;
+ * the eigensolve and the basis-vector KK / PEC / SEC stay FP64 either way. */
+enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1 };
 
 /*
  * Method parameters.  Fill with fkk_params_default() and override fields.
@@ -86,8 +89,10 @@ typedef struct {
     double ml_lambda;      /* Eq. 25 ridge weight of the stored basis      */
     double ratio_floor;    /* ratios I/I_ref not above it are clamped      */
     int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
-    int32_t gram_prec;     /* FKK_PREC_*                                   */
-    int32_t recon_prec;    /* FKK_PREC_*                                   */
+    int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6)               */
+    int32_t recon_prec;    /* FKK_PREC_* of the projection (Eq. 13) and the
+                              reconstruction (Eq. 23); stored in the basis
+                              and used by its later transforms             */
     int32_t output;        /* FKK_OUT_*                                    */
     const int64_t* q_override; /* host, optional: rows used as U_ss       */
     int32_t n_q_override;  /* length of q_override (0 = use Eq. 13-15)    */
@@ -174,11 +179,13 @@ fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64
 
 /*
  * Log ratio and Gram (Eq. 2, Eq. 6): G = l^T l (N x N, FP64, row-major,
- * symmetric) with l = 1/2 ln(I / I_ref) computed in FP32 on load, plus the
- * column sums of I (FP64, N) and the number of clamped ratios.  Synchronous.
+ * symmetric) with l = 1/2 ln(I / I_ref) computed in FP32 (rounded to BF16
+ * when prec is FKK_PREC_BF16) and products accumulated in FP32 over chunks
+ * of rows, the chunks summed in FP64; plus the column sums of I (FP64, N)
+ * and the number of clamped ratios.  Synchronous.
  */
 fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
-                    const double* h_iref, double ratio_floor, double* h_gram,
+                    const double* h_iref, double ratio_floor, int32_t prec, double* h_gram,
                     double* h_colsum, int64_t* h_clamps);
 
 /*
@@ -232,6 +239,13 @@ fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double
                             double* v, double* b_re, double* b_im, double* phi_pec_t,
                             double* v_sec_t, double* h_v, int64_t* q, double* scalars3);
 void fkk_basis_free(fkk_basis* b);
+/* Matrix-core precision (FKK_PREC_*) of the projection and reconstruction
+ * that fkk_transform, fkk_project, fkk_reconstruct and the server run with
+ * this basis (both copies are kept on the device).  Imported bases start in
+ * FP32; fitted ones and those made from factors in the params' recon_prec.  Not thread-safe against
+ * concurrent transforms with the same basis. */
+fkk_status fkk_basis_set_precision(fkk_basis* b, int32_t prec);
+fkk_status fkk_basis_get_precision(const fkk_basis* b, int32_t* prec);
 
 /* ---- serving: stored-basis transforms of image tiles as they arrive ------
  *
@@ -267,7 +281,8 @@ typedef struct {
  * hbm_budget_bytes, allocated here). */
 fkk_status fkk_server_create(int device, const fkk_server_config* cfg, fkk_server** out);
 /* Makes a basis resident for this server; *basis_id identifies it in
- * fkk_server_submit.  The basis must stay alive until the server is destroyed. */
+ * fkk_server_submit.  Its tiles run in the basis's precision at the time of
+ * this call.  The basis must stay alive until the server is destroyed. */
 fkk_status fkk_server_add_basis(fkk_server* srv, const fkk_basis* basis, int32_t* basis_id);
 /* Queues one tile: h_in (rows x N FP32, stride ld) -> h_out (rows x N FP32,
  * stride ld_out), both host memory (page-locked memory overlaps best) that

@@ -24,6 +24,7 @@ SEC_SAVGOL, SEC_MEAN = 0, 1
 PAD_EDGE, PAD_ZERO = 0, 1
 F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
+PREC_FP32, PREC_BF16 = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
@@ -84,7 +85,8 @@ SYMBOLS = [
     "fkk_version", "fkk_status_string", "fkk_params_default", "fkk_ctx_create", "fkk_ctx_destroy",
     "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram",
     "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
-    "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_server_create", "fkk_server_add_basis",
+    "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
+    "fkk_basis_get_precision", "fkk_server_create", "fkk_server_add_basis",
     "fkk_server_submit", "fkk_server_wait", "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats",
     "fkk_server_destroy",
 ]
@@ -113,7 +115,7 @@ def lib() -> ctypes.CDLL:
                           ctypes.POINTER(FitReport)]
     L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64]
     L.fkk_plain.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64]
-    L.fkk_gram.argtypes = [vp, vp, i64, i32, i64, _c_double_p, dbl, _c_double_p, _c_double_p, _c_int64_p]
+    L.fkk_gram.argtypes = [vp, vp, i64, i32, i64, _c_double_p, dbl, i32, _c_double_p, _c_double_p, _c_int64_p]
     L.fkk_eigh_topk.argtypes = [_c_double_p, i32, i32, _c_double_p, _c_double_p]
     L.fkk_basis_from_factors.argtypes = [vp, i32, i32, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                          _c_double_p, i32, ctypes.POINTER(Params), ctypes.POINTER(vp)]
@@ -123,6 +125,8 @@ def lib() -> ctypes.CDLL:
     L.fkk_basis_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.fkk_basis_export.argtypes = [vp] + [_c_double_p] * 9 + [_c_int64_p, _c_double_p]
     L.fkk_basis_free.argtypes = [vp]
+    L.fkk_basis_set_precision.argtypes = [vp, i32]
+    L.fkk_basis_get_precision.argtypes = [vp, ctypes.POINTER(i32)]
     L.fkk_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     L.fkk_server_add_basis.argtypes = [vp, vp, ctypes.POINTER(i32)]
     L.fkk_server_submit.argtypes = [vp, i32, vp, i64, i64, vp, i64, ctypes.POINTER(i64)]
@@ -136,7 +140,7 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = ctypes.c_int
     for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram", "fkk_eigh_topk",
                  "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
-                 "fkk_basis_info", "fkk_basis_export"):
+                 "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision", "fkk_basis_get_precision"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -212,6 +216,21 @@ class Basis:
         n, k, nq = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         lib().fkk_basis_info(self._h, ctypes.byref(n), ctypes.byref(k), ctypes.byref(nq))
         return n.value, k.value, nq.value
+
+    @property
+    def precision(self) -> int:
+        """PREC_FP32 or PREC_BF16: precision of transforms with this basis."""
+        p = ctypes.c_int32()
+        st = lib().fkk_basis_get_precision(self._h, ctypes.byref(p))
+        if st != FKK_OK:
+            raise FkkError(st, "get_precision")
+        return p.value
+
+    @precision.setter
+    def precision(self, prec: int):
+        st = lib().fkk_basis_set_precision(self._h, int(prec))
+        if st != FKK_OK:
+            raise FkkError(st, "set_precision")
 
     def export(self) -> dict:
         n, k, nq = self.info()
@@ -338,15 +357,15 @@ class Context:
         return out
 
     # -- stages -------------------------------------------------------------
-    def gram(self, I, i_ref, ratio_floor: float = 1e-6):
+    def gram(self, I, i_ref, ratio_floor: float = 1e-6, prec: int = PREC_FP32):
         _check_tensor(I, "I")
         m, n = I.shape
         i_ref = _f64(i_ref, (n,))
         g = np.empty((n, n))
         cs = np.empty(n)
         cl = np.zeros(1, dtype=np.int64)
-        st = lib().fkk_gram(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ratio_floor, _dptr(g), _dptr(cs),
-                            cl.ctypes.data_as(_c_int64_p))
+        st = lib().fkk_gram(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ratio_floor, int(prec), _dptr(g),
+                            _dptr(cs), cl.ctypes.data_as(_c_int64_p))
         self._ok(st, "gram")
         return g, cs, int(cl[0])
 
@@ -459,4 +478,4 @@ class Server:
 
 
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
-           "SYMBOLS", "LIB_PATH"]
+           "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16"]

@@ -71,6 +71,25 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// 1/I_ref as two floats per wavenumber: hi in out[0..N), lo in out[N..2N).
+void split_reciprocal(const double* iref, int N, float* out) {
+    for (int j = 0; j < N; ++j) {
+        const double r = 1.0 / iref[j];
+        out[j] = (float)r;
+        out[N + j] = (float)(r - (double)out[j]);
+    }
+}
+
+bool valid_prec(int p) { return p == FKK_PREC_FP32 || p == FKK_PREC_BF16; }
+
+// Nearest-even BF16 bit pattern of a finite float.
+uint16_t to_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, sizeof u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 int kp_for(int k) {
     if (k <= 16) return 16;
     if (k <= 32) return 32;
@@ -90,7 +109,8 @@ struct fkk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    DevBuf<float> partial, L;
+    DevBuf<double> partial;
+    DevBuf<float> L;
     DevBuf<double> colsum_part, G, colsum, fdev, tri;
     DevBuf<unsigned long long> clamps;
     DevBuf<int> tiles;
@@ -163,8 +183,9 @@ fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N) {
     }
     if (!(p->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
     if (p->output < FKK_OUT_IM || p->output > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad output plane");
-    if (p->gram_prec != FKK_PREC_FP32 || p->recon_prec != FKK_PREC_FP32)
-        return ctx->fail(FKK_EINVAL, "only FP32 matrix-core precision is built");
+    if (!valid_prec(p->gram_prec) || !valid_prec(p->recon_prec))
+        return ctx->fail(FKK_EINVAL, "bad matrix-core precision (gram_prec=%d, recon_prec=%d)", p->gram_prec,
+                         p->recon_prec);
     if (p->f_mode == FKK_F_NOISE && !(p->alpha >= 0.0 && p->sigma_g >= 0.0 && (p->alpha > 0.0 || p->sigma_g > 0.0)))
         return ctx->fail(FKK_EINVAL, "f_mode=noise needs alpha >= 0, sigma_g >= 0, not both 0");
     return FKK_OK;
@@ -190,8 +211,9 @@ fkk_status check_iref(fkk_ctx* ctx, const double* h_iref, int N) {
 // corrected bases (transposed, zero padded to kp columns and npad rows).
 fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     const int N = b->N, k = b->k, kp = b->kp, np = b->npad;
-    std::vector<float> rinv(N), wt((size_t)kp * np, 0.f), bre((size_t)np * kp, 0.f), bim((size_t)np * kp, 0.f);
-    for (int j = 0; j < N; ++j) rinv[j] = (float)(1.0 / b->i_ref[j]);
+    std::vector<float> rinv(2 * (size_t)N), wt((size_t)kp * np, 0.f), bre((size_t)np * kp, 0.f),
+        bim((size_t)np * kp, 0.f);
+    split_reciprocal(b->i_ref.data(), N, rinv.data());
     double smax = 0.0;
     for (int c = 0; c < k; ++c) smax = std::max(smax, b->s[c]);
     for (int c = 0; c < k; ++c) {
@@ -217,6 +239,26 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     FKK_HIP(ctx, alloc_copy(&b->d_wt, wt));
     FKK_HIP(ctx, alloc_copy(&b->d_bre_t, bre));
     FKK_HIP(ctx, alloc_copy(&b->d_bim_t, bim));
+    // BF16 copies, k padded to kq columns (rows of W^T)
+    const int kq = b->kq;
+    std::vector<uint16_t> wt16((size_t)kq * np, 0), bre16((size_t)np * kq, 0), bim16((size_t)np * kq, 0);
+    for (int c = 0; c < kp; ++c)
+        for (int j = 0; j < np; ++j) wt16[(size_t)c * np + j] = to_bf16(wt[(size_t)c * np + j]);
+    for (int j = 0; j < np; ++j)
+        for (int c = 0; c < kp; ++c) {
+            bre16[(size_t)j * kq + c] = to_bf16(bre[(size_t)j * kp + c]);
+            bim16[(size_t)j * kq + c] = to_bf16(bim[(size_t)j * kp + c]);
+        }
+    auto alloc_copy16 = [&](uint16_t** dst, const std::vector<uint16_t>& src) -> hipError_t {
+        if (!*dst) {
+            hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(uint16_t));
+            if (e != hipSuccess) return e;
+        }
+        return hipMemcpy(*dst, src.data(), src.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    };
+    FKK_HIP(ctx, alloc_copy16(&b->d_wt16, wt16));
+    FKK_HIP(ctx, alloc_copy16(&b->d_bre16, bre16));
+    FKK_HIP(ctx, alloc_copy16(&b->d_bim16, bim16));
     b->device = ctx->device;
     return FKK_OK;
 }
@@ -263,6 +305,7 @@ fkk_basis* new_basis(int N, int k, const double* iref, const double* f, const do
     b->N = N;
     b->k = k;
     b->kp = kp_for(k);
+    b->kq = std::max(b->kp, 32);
     b->npad = round_up(N, 64);
     b->i_ref.assign(iref, iref + N);
     b->f.assign(f, f + N);
@@ -278,32 +321,42 @@ int npad_for(int N) { return round_up(N, fkk::dev::kGramTile); }
 // Log-ratio pass into ctx->L, Gram G_L = l^T l into ctx->G (device, FP64,
 // N x N), column sums into ctx->colsum and the clamp count into ctx->clamps.
 fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
-                       double floor, bool timed) {
+                       double floor, int prec, bool timed) {
     const int npad = npad_for(N);
-    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64);
+    const bool bf16 = (prec == FKK_PREC_BF16);
+    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
     std::vector<int> pairs(2 * plan.tiles);
     fkk::dev::gram_tile_list(plan.nb, pairs.data());
-    std::vector<float> rinv(N);
-    for (int j = 0; j < N; ++j) rinv[j] = (float)(1.0 / h_iref[j]);
+    std::vector<float> rinv(2 * (size_t)N);
+    split_reciprocal(h_iref, N, rinv.data());
     const int64_t nlr = fkk::dev::logratio_blocks(M);
-    FKK_HIP(ctx, ctx->L.ensure((size_t)M * npad));
-    FKK_HIP(ctx, ctx->partial.ensure(plan.partial_floats()));
+    // FP32 l (M x npad) or the packed BF16 l, which needs at most half of it
+    FKK_HIP(ctx, ctx->L.ensure(bf16 ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4 : (size_t)M * npad));
+    FKK_HIP(ctx, ctx->partial.ensure(plan.partial_doubles()));
     FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)nlr * npad));
     FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
     FKK_HIP(ctx, ctx->colsum.ensure(N + fkk::dev::colsum_scratch_doubles(N)));
     FKK_HIP(ctx, ctx->clamps.ensure(1));
     FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
-    FKK_HIP(ctx, ctx->rinv.ensure(N));
+    FKK_HIP(ctx, ctx->rinv.ensure(2 * (size_t)N));
     hipStream_t s = ctx->stream;
     FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->rinv.p, rinv.data(), N * sizeof(float), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->rinv.p, rinv.data(), rinv.size() * sizeof(float), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemsetAsync(ctx->clamps.p, 0, sizeof(unsigned long long), s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
-    FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, ctx->rinv.p, (float)floor, ctx->L.p, npad, npad,
-                                           ctx->colsum_part.p, ctx->clamps.p, s));
+    uint16_t* lp16 = reinterpret_cast<uint16_t*>(ctx->L.p);
+    if (bf16)
+        FKK_HIP(ctx, fkk::dev::launch_logratio16(d_I, M, N, ld, ctx->rinv.p, (float)floor, lp16, npad,
+                                                 ctx->colsum_part.p, ctx->clamps.p, s));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, ctx->rinv.p, (float)floor, ctx->L.p, npad, npad,
+                                               ctx->colsum_part.p, ctx->clamps.p, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-    FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
+    if (bf16)
+        FKK_HIP(ctx, fkk::dev::launch_gram16(lp16, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
     FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, plan, ctx->tiles.p, N, ctx->G.p, s));
     FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N, ctx->colsum.p, s));
@@ -445,14 +498,15 @@ const char* fkk_ctx_last_error(const fkk_ctx* ctx) { return ctx ? ctx->err.c_str
 size_t fkk_ctx_workspace_bytes(const fkk_ctx* ctx) { return ctx ? ctx->bytes() : 0; }
 
 fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                    double ratio_floor, double* h_gram, double* h_colsum, int64_t* h_clamps) {
+                    double ratio_floor, int32_t prec, double* h_gram, double* h_colsum, int64_t* h_clamps) {
     if (!ctx) return FKK_EINVAL;
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
     if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
+    if (!valid_prec(prec)) return ctx->fail(FKK_EINVAL, "bad precision %d", prec);
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, ratio_floor, false)) != FKK_OK) return st;
+    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, ratio_floor, prec, false)) != FKK_OK) return st;
     if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,
                                             ctx->stream));
     std::vector<double> cs(N);
@@ -480,6 +534,7 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
     if ((st = check_params(c, p, N)) != FKK_OK) return st;
     if (p->k != k) return c->fail(FKK_EINVAL, "params.k != k");
     fkk_basis* b = new_basis(N, k, h_iref, h_f, h_s, h_v, p->ml_lambda, p->ratio_floor);
+    b->prec = p->recon_prec;
     basis_math(b, h_x, n_q, p);
     if (ctx) {
         if ((st = upload_basis(ctx, b, p->ml_lambda)) != FKK_OK) {
@@ -517,7 +572,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     std::vector<double> colsum(N);
     int64_t clamps = 0;
     FKK_HIP(ctx, ctx->events());
-    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, true)) != FKK_OK) return st;
+    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, p->gram_prec, true)) != FKK_OK) return st;
     if ((st = fetch_sums(ctx, N, colsum.data(), &clamps)) != FKK_OK) return st;
     r.dev_ms_gram = ctx->elapsed(0, 1);
     r.dev_ms_logratio = ctx->elapsed(8, 9);
@@ -542,27 +597,49 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     // 3. projection Z = A V_k and per-column arg-extrema (Eq. 13-15)
     t0 = std::chrono::steady_clock::now();
     fkk_basis* b = new_basis(N, k, h_iref, f.data(), sv.data(), V.data(), p->ml_lambda, p->ratio_floor);
+    b->prec = p->recon_prec;
+    const bool pbf16 = (p->recon_prec == FKK_PREC_BF16);
+    const int kq = b->kq;
+    const int ka = pbf16 ? kq : kp;  // column blocks of the arg-extrema partials
     std::vector<float> wt((size_t)kp * b->npad, 0.f);
     for (int c = 0; c < k; ++c)
         for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(f[j] * V[(size_t)j * k + c]);
+    std::vector<uint16_t> wt16;
+    if (pbf16) {
+        wt16.assign((size_t)kq * b->npad, 0);
+        for (size_t i = 0; i < wt.size(); ++i) wt16[i] = to_bf16(wt[i]);
+    }
     auto cleanup = [&](fkk_status e) { delete b; return e; };
     const int64_t nblk = fkk::dev::proj_blocks(M);
+    // ctx->X holds the weights: kp x npad FP32, or kq x npad BF16 (kq <= 2 kp)
     if (ctx->Z.ensure((size_t)M * kp) != hipSuccess || ctx->X.ensure((size_t)kp * b->npad) != hipSuccess ||
-        ctx->pmaxv.ensure((size_t)nblk * kp) != hipSuccess || ctx->pminv.ensure((size_t)nblk * kp) != hipSuccess ||
-        ctx->pmaxi.ensure((size_t)nblk * kp) != hipSuccess || ctx->pmini.ensure((size_t)nblk * kp) != hipSuccess ||
-        ctx->qext.ensure(2 * (size_t)kp) != hipSuccess)
+        ctx->pmaxv.ensure((size_t)nblk * ka) != hipSuccess || ctx->pminv.ensure((size_t)nblk * ka) != hipSuccess ||
+        ctx->pmaxi.ensure((size_t)nblk * ka) != hipSuccess || ctx->pmini.ensure((size_t)nblk * ka) != hipSuccess ||
+        ctx->qext.ensure(2 * (size_t)ka) != hipSuccess)
         return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
     float* d_wt = ctx->X.p;  // the fit's projection weights (no ML shrink)
-    if (hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess)
-        return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
+    uint16_t* d_wt16 = reinterpret_cast<uint16_t*>(ctx->X.p);
+    const hipError_t wcopy =
+        pbf16 ? hipMemcpyAsync(d_wt16, wt16.data(), wt16.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s)
+              : hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s);
+    if (wcopy != hipSuccess) return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
     fkk::dev::ArgPart part{ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
-    if (hipEventRecord(ctx->ev[2], s) != hipSuccess ||
-        fkk::dev::launch_project(ctx->L.p, M, N, npad_for(N), ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp,
-                                 kp, ctx->Z.p, kp, part, k, s, true) != hipSuccess ||
-        hipEventRecord(ctx->ev[3], s) != hipSuccess ||
-        fkk::dev::launch_argext_reduce(part, nblk, kp, k, ctx->qext.p, ctx->qext.p + kp, s) != hipSuccess)
+    hipError_t perr = hipEventRecord(ctx->ev[2], s);
+    if (perr == hipSuccess) {
+        if (pbf16)  // log ratio recomputed from I
+            perr = fkk::dev::launch_project16(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt16, b->npad, kq,
+                                              kp, ctx->Z.p, kp, part, k, s);
+        else if (p->gram_prec == FKK_PREC_BF16)  // ctx->L holds the packed BF16 l: start from I
+            perr = fkk::dev::launch_project(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
+                                            ctx->Z.p, kp, part, k, s, false);
+        else  // the FP32 l of the Gram pass
+            perr = fkk::dev::launch_project(ctx->L.p, M, N, npad_for(N), ctx->rinv.p, (float)p->ratio_floor, d_wt,
+                                            b->npad, kp, kp, ctx->Z.p, kp, part, k, s, true);
+    }
+    if (perr != hipSuccess || hipEventRecord(ctx->ev[3], s) != hipSuccess ||
+        fkk::dev::launch_argext_reduce(part, nblk, ka, k, ctx->qext.p, ctx->qext.p + ka, s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));
-    std::vector<long long> qe(2 * (size_t)kp);
+    std::vector<long long> qe(2 * (size_t)ka);
     if (hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection failed"));
@@ -573,32 +650,51 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     } else {
         for (int c = 0; c < k; ++c) {
             if (qe[c] >= 0) q.push_back(qe[c]);
-            if (qe[kp + c] >= 0) q.push_back(qe[kp + c]);
+            if (qe[ka + c] >= 0) q.push_back(qe[ka + c]);
         }
         std::sort(q.begin(), q.end());
         q.erase(std::unique(q.begin(), q.end()), q.end());
     }
     const int n_q = (int)q.size();
-    std::vector<float> xf((size_t)n_q * k);
+    // U_ss S = A[q] V_k (Eq. 13-15) in FP64 from the FP32 input rows q: the
+    // device Z only selects q.  fPEC's ridge solve amplifies errors of X
+    // along its weak directions, so X is not taken from the FP32 projection.
+    std::vector<float> rows((size_t)n_q * N);
     if (ctx->qdev.ensure(std::max(n_q, 1)) != hipSuccess)
         return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
-    float* d_x = ctx->pmaxv.p;  // reuse: n_q * k <= nblk * kp is not guaranteed, checked below
-    DevBuf<float> xtmp;
-    if ((size_t)n_q * k > ctx->pmaxv.n) {
-        if (xtmp.ensure((size_t)n_q * k) != hipSuccess) return cleanup(ctx->fail(FKK_ENOMEM, "allocation failed"));
-        d_x = xtmp.p;
+    DevBuf<float> rtmp;
+    float* d_rows = ctx->pmaxv.p;  // reused when large enough
+    if ((size_t)n_q * N > ctx->pmaxv.n) {
+        if (rtmp.ensure((size_t)n_q * N) != hipSuccess) return cleanup(ctx->fail(FKK_ENOMEM, "allocation failed"));
+        d_rows = rtmp.p;
     }
     if (hipMemcpyAsync(ctx->qdev.p, q.data(), n_q * sizeof(long long), hipMemcpyHostToDevice, s) != hipSuccess ||
-        fkk::dev::launch_gather_rows(ctx->Z.p, kp, k, ctx->qdev.p, n_q, d_x, s) != hipSuccess ||
-        hipMemcpyAsync(xf.data(), d_x, xf.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        fkk::dev::launch_gather_rows(d_I, ld, N, ctx->qdev.p, n_q, d_rows, s) != hipSuccess ||
+        hipMemcpyAsync(rows.data(), d_rows, rows.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "gather of sub-sampled rows failed"));
-    xtmp.release();
+    rtmp.release();
     r.ms_project = ms_since(t0);
 
     // 4. fKK, fPEC, fSEC on the basis vectors (host FP64)
     t0 = std::chrono::steady_clock::now();
-    std::vector<double> X(xf.begin(), xf.end());
+    std::vector<double> X((size_t)n_q * k, 0.0);
+    fkk::parallel_rows(n_q, [&](int q0, int q1) {
+        std::vector<double> a(N);
+        for (int rq = q0; rq < q1; ++rq) {
+            for (int j = 0; j < N; ++j) {
+                double ratio = (double)rows[(size_t)rq * N + j] / h_iref[j];
+                if (!(ratio > p->ratio_floor) || !std::isfinite(ratio)) ratio = p->ratio_floor;
+                a[j] = 0.5 * std::log(ratio) * f[j];
+            }
+            double* xr = &X[(size_t)rq * k];
+            for (int j = 0; j < N; ++j) {
+                const double aj = a[j];
+                const double* vr = &V[(size_t)j * k];
+                for (int c = 0; c < k; ++c) xr[c] += aj * vr[c];
+            }
+        }
+    });
     b->q.assign(q.begin(), q.end());
     basis_math(b, X.data(), n_q, p);
     if ((st = upload_basis(ctx, b, p->ml_lambda)) != FKK_OK) return cleanup(st);
@@ -610,8 +706,10 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     t0 = std::chrono::steady_clock::now();
     if (d_out) {
         if (hipEventRecord(ctx->ev[4], s) != hipSuccess ||
-            fkk::dev::launch_reconstruct(ctx->Z.p, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out, p->output,
-                                         s) != hipSuccess ||
+            (pbf16 ? fkk::dev::launch_reconstruct16(ctx->Z.p, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
+                                                    p->output, s)
+                   : fkk::dev::launch_reconstruct(ctx->Z.p, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
+                                                  p->output, s)) != hipSuccess ||
             hipEventRecord(ctx->ev[5], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return cleanup(ctx->fail(FKK_EDEVICE, "reconstruction failed"));
         r.dev_ms_recon = ctx->elapsed(4, 5);
@@ -633,8 +731,13 @@ fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int
     if (!d_out || ld_out < b->N) return ctx->fail(FKK_EINVAL, "bad output");
     if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
-                                            b->kp, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM, ctx->stream));
+    if (b->prec == FKK_PREC_BF16)
+        FKK_HIP(ctx, fkk::dev::launch_transform16(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt16,
+                                                  b->npad, b->kq, b->d_bre16, b->d_bim16, d_out, ld_out, FKK_OUT_IM,
+                                                  ctx->stream));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
+                                                b->kp, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM, ctx->stream));
     return FKK_OK;
 }
 
@@ -649,26 +752,32 @@ fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int64_t nblk = fkk::dev::proj_blocks(M);
+    const bool bf16 = (b->prec == FKK_PREC_BF16);
+    const int ka = bf16 ? b->kq : b->kp;
     fkk::dev::ArgPart part{nullptr, nullptr, nullptr, nullptr};
     const bool want = h_qmax || h_qmin;
     if (want) {
-        FKK_HIP(ctx, ctx->pmaxv.ensure((size_t)nblk * b->kp));
-        FKK_HIP(ctx, ctx->pminv.ensure((size_t)nblk * b->kp));
-        FKK_HIP(ctx, ctx->pmaxi.ensure((size_t)nblk * b->kp));
-        FKK_HIP(ctx, ctx->pmini.ensure((size_t)nblk * b->kp));
-        FKK_HIP(ctx, ctx->qext.ensure(2 * (size_t)b->kp));
+        FKK_HIP(ctx, ctx->pmaxv.ensure((size_t)nblk * ka));
+        FKK_HIP(ctx, ctx->pminv.ensure((size_t)nblk * ka));
+        FKK_HIP(ctx, ctx->pmaxi.ensure((size_t)nblk * ka));
+        FKK_HIP(ctx, ctx->pmini.ensure((size_t)nblk * ka));
+        FKK_HIP(ctx, ctx->qext.ensure(2 * (size_t)ka));
         part = {ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
     }
-    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
-                                          b->k, d_z, ld_z, part, b->k, s));
+    if (bf16)
+        FKK_HIP(ctx, fkk::dev::launch_project16(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt16, b->npad,
+                                                b->kq, b->k, d_z, ld_z, part, b->k, s));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
+                                              b->kp, b->k, d_z, ld_z, part, b->k, s));
     if (!want) return FKK_OK;
-    FKK_HIP(ctx, fkk::dev::launch_argext_reduce(part, nblk, b->kp, b->k, ctx->qext.p, ctx->qext.p + b->kp, s));
-    std::vector<long long> qe(2 * (size_t)b->kp);
+    FKK_HIP(ctx, fkk::dev::launch_argext_reduce(part, nblk, ka, b->k, ctx->qext.p, ctx->qext.p + ka, s));
+    std::vector<long long> qe(2 * (size_t)ka);
     FKK_HIP(ctx, hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     for (int c = 0; c < b->k; ++c) {
         if (h_qmax) h_qmax[c] = qe[c];
-        if (h_qmin) h_qmin[c] = qe[b->kp + c];
+        if (h_qmin) h_qmin[c] = qe[ka + c];
     }
     return FKK_OK;
 }
@@ -682,8 +791,12 @@ fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, i
     if (plane < FKK_OUT_IM || plane > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad plane");
     if (b->device != ctx->device || !b->d_bre_t) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    FKK_HIP(ctx, fkk::dev::launch_reconstruct(d_z, M, ld_z, b->k, b->d_bre_t, b->d_bim_t, b->kp, b->N, d_out, ld_out,
-                                              plane, ctx->stream));
+    if (b->prec == FKK_PREC_BF16)
+        FKK_HIP(ctx, fkk::dev::launch_reconstruct16(d_z, M, ld_z, b->k, b->d_bre16, b->d_bim16, b->kq, b->N, d_out,
+                                                    ld_out, plane, ctx->stream));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_reconstruct(d_z, M, ld_z, b->k, b->d_bre_t, b->d_bim_t, b->kp, b->N, d_out,
+                                                  ld_out, plane, ctx->stream));
     return FKK_OK;
 }
 
@@ -704,6 +817,18 @@ fkk_status fkk_basis_import(fkk_ctx* ctx, const fkk_basis_desc* d, fkk_basis** o
         return st;
     }
     *out = b;
+    return FKK_OK;
+}
+
+fkk_status fkk_basis_set_precision(fkk_basis* b, int32_t prec) {
+    if (!b || !valid_prec(prec)) return FKK_EINVAL;
+    b->prec = prec;
+    return FKK_OK;
+}
+
+fkk_status fkk_basis_get_precision(const fkk_basis* b, int32_t* prec) {
+    if (!b || !prec) return FKK_EINVAL;
+    *prec = b->prec;
     return FKK_OK;
 }
 

@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
+#include <cstdint>
 
 namespace fkk {
 namespace dev {
@@ -14,10 +16,13 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// l = 1/2 ln(x r); ratios that are not finite or not above the floor are
-// replaced by the floor.
-__device__ __forceinline__ float log_ratio(float x, float r, float floor, bool& bad) {
-    float q = x * r;
+// l = 1/2 ln(x r) with r = 1/I_ref given as rh + rl (two floats): one
+// rounding of the product x (rh + rl).  A single-float r would shift every
+// l of a column by the same ~3e-8 and that offset adds up coherently over
+// all rows of the Gram.  Ratios that are not finite or not above the floor
+// are replaced by the floor.
+__device__ __forceinline__ float log_ratio(float x, float rh, float rl, float floor, bool& bad) {
+    float q = fmaf(x, rh, x * rl);
     bad = !(q > floor && q < INFINITY);
     q = bad ? floor : q;
     return 0.5f * logf(q);
@@ -63,6 +68,134 @@ __device__ __forceinline__ void sincos_fast(float x, float* sn, float* cs) {
     const int q = ((int)n) & 3;
     *sn = (q == 0) ? s : (q == 1) ? c : (q == 2) ? -s : -c;
     *cs = (q == 0) ? c : (q == 1) ? -s : (q == 2) ? -c : s;
+}
+
+
+// Output plane of K = exp(re) exp(i im) (Eq. 23): Im, Re or |K|.
+__device__ __forceinline__ float epilogue(float re, float im, int plane) {
+    const float mag = exp_fast(re);
+    if (plane == 2) return mag;
+    float sn, cs;
+    sincos_fast(im, &sn, &cs);
+    return mag * (plane == 0 ? sn : cs);
+}
+
+// Same with the hardware sine / cosine (v_sin_f32 / v_cos_f32 take the
+// angle in revolutions; the fraction of a revolution keeps the argument in
+// [-1/2, 1/2]).  Absolute error of order 1e-6: used where the operands are
+// BF16 and contribute far more.
+__device__ __forceinline__ float epilogue_hw(float re, float im, int plane) {
+    const float mag = exp_fast(re);
+    if (plane == 2) return mag;
+    float t = im * 0.159154943091895336f;
+    t -= rintf(t);
+    return mag * (plane == 0 ? __builtin_amdgcn_sinf(t) : __builtin_amdgcn_cosf(t));
+}
+
+// Epilogue of a 128-spectrum reconstruction tile: lane l of wave w holds,
+// in acc[ib][jb][v], wavenumber j0 + 16 ib + 4 (l/16) + v of spectrum
+// r0 + 32 w + 16 jb + l%16.
+template <bool VEC_OUT, bool HW_SIN = false>
+__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
+                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
+                                          const floatx4 (&aim)[4][2], int plane) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
+            const int col = j0 + ib * 16 + 4 * (lane >> 4);
+            if (row >= M) continue;
+            float o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = HW_SIN ? epilogue_hw(are[ib][jb][v], aim[ib][jb][v], plane)
+                              : epilogue(are[ib][jb][v], aim[ib][jb][v], plane);
+            float* dst = out + row * ld_out + col;
+            if (VEC_OUT && col + 3 < N) {
+                *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (col + v < N) dst[v] = o[v];
+            }
+        }
+}
+
+
+__device__ __forceinline__ void better_max(float& v, int& i, float ov, int oi) {
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+__device__ __forceinline__ void better_min(float& v, int& i, float ov, int oi) {
+    if (ov < v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+// End of a projection block of 128 spectra: lane l of wave w holds, in
+// acc[rb][cb][v], Z[r0 + 32 w + 16 rb + 4 (l/16) + v][16 cb + l%16].  Stores
+// the first k_store columns of Z and, when pmaxv != nullptr, the block's
+// per-column arg-extrema (first row on ties) for the first k_arg columns.
+template <int KB>
+__device__ __forceinline__ void project_finish(const floatx4 (&acc)[2][KB], int64_t r0, int64_t M,
+                                               float* __restrict__ Z, int64_t ld_z, int k_store, float* pmaxv,
+                                               float* pminv, long long* pmaxi, long long* pmini, int k_arg) {
+    constexpr int KP = KB * 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // Z[row][c]: acc[rb][cb][v], row = wave*32 + rb*16 + 4*(lane/16) + v, c = cb*16 + lane%16
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+                const int c = cb * 16 + (lane & 15);
+                if (row < M && c < k_store) Z[row * ld_z + c] = acc[rb][cb][v];
+            }
+
+    if (pmaxv == nullptr) return;
+    __shared__ float smx[4][KP], smn[4][KP];
+    __shared__ int smxi[4][KP], smni[4][KP];
+#pragma unroll
+    for (int cb = 0; cb < KB; ++cb) {
+        float mx = -INFINITY, mn = INFINITY;
+        int ix = INT_MAX, in = INT_MAX;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+                if (r0 + rl < M) {
+                    better_max(mx, ix, acc[rb][cb][v], rl);
+                    better_min(mn, in, acc[rb][cb][v], rl);
+                }
+            }
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+            const float omx = __shfl_xor(mx, off), omn = __shfl_xor(mn, off);
+            const int oix = __shfl_xor(ix, off), oin = __shfl_xor(in, off);
+            better_max(mx, ix, omx, oix);
+            better_min(mn, in, omn, oin);
+        }
+        if (lane < 16) {
+            smx[wave][cb * 16 + lane] = mx;
+            smxi[wave][cb * 16 + lane] = ix;
+            smn[wave][cb * 16 + lane] = mn;
+            smni[wave][cb * 16 + lane] = in;
+        }
+    }
+    __syncthreads();
+    if (tid < KP && tid < k_arg) {
+        float mx = smx[0][tid], mn = smn[0][tid];
+        int ix = smxi[0][tid], in = smni[0][tid];
+        for (int w = 1; w < 4; ++w) {
+            better_max(mx, ix, smx[w][tid], smxi[w][tid]);
+            better_min(mn, in, smn[w][tid], smni[w][tid]);
+        }
+        const size_t o = (size_t)blockIdx.x * KP + tid;
+        pmaxv[o] = mx;
+        pminv[o] = mn;
+        pmaxi[o] = (ix == INT_MAX) ? -1 : (long long)(r0 + ix);
+        pmini[o] = (in == INT_MAX) ? -1 : (long long)(r0 + in);
+    }
 }
 
 }  // namespace dev

@@ -96,6 +96,8 @@ Pool& host_pool() {
     return pool;
 }
 
+}  // namespace
+
 // Rows [0, rows) split over the pool.
 void parallel_rows(int rows, const std::function<void(int, int)>& body) {
     Pool& pool = host_pool();
@@ -110,7 +112,6 @@ void parallel_rows(int rows, const std::function<void(int, int)>& body) {
     });
 }
 
-}  // namespace
 
 int default_fft_len(int n) {
     int len = 1;

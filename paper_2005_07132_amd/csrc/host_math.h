@@ -7,9 +7,14 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace fkk {
+
+// Runs body(r0, r1) over a split of the rows [0, rows) on the library's
+// host thread pool (one call on the caller's thread when there is one).
+void parallel_rows(int rows, const std::function<void(int, int)>& body);
 
 // Discrete Hilbert transform of each of `rows` rows of x (rows x n,
 // row-major) into y: centred padding to `len` points (edge replication or

@@ -13,6 +13,8 @@
 struct fkk_basis {
     int device = -1;
     int N = 0, k = 0, kp = 0, npad = 0;
+    int kq = 0;                 // k padded for the BF16 copies: 32, 64 or 128
+    int prec = FKK_PREC_FP32;   // precision of transforms with this basis
     std::vector<double> i_ref, f, s, v, b_re, b_im, phi_pec_t, v_sec_t, h_v;
     std::vector<int64_t> q;
     double ml_lambda = 0.0, ratio_floor = 1e-6, ridge_lambda = 0.0;
@@ -20,7 +22,13 @@ struct fkk_basis {
     float* d_wt = nullptr;      // kp x npad: f(j) V(j,c) shrink(c)
     float* d_bre_t = nullptr;   // npad x kp
     float* d_bim_t = nullptr;   // npad x kp
+    uint16_t* d_wt16 = nullptr;  // kq x npad, BF16 of d_wt
+    uint16_t* d_bre16 = nullptr; // npad x kq, BF16 of d_bre_t
+    uint16_t* d_bim16 = nullptr; // npad x kq
     ~fkk_basis() {
+        if (d_wt16) hipFree(d_wt16);
+        if (d_bre16) hipFree(d_bre16);
+        if (d_bim16) hipFree(d_bim16);
         if (d_rinv) hipFree(d_rinv);
         if (d_wt) hipFree(d_wt);
         if (d_bre_t) hipFree(d_bre_t);

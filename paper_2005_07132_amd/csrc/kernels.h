@@ -1,4 +1,7 @@
 // Launch interface of the gfx950 kernels of the fKK-EC hot path.
+//
+// rinv arguments hold 1/I_ref as two floats per wavenumber: the nearest
+// float in rinv[0..N) and the remainder in rinv[N..2N).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,9 +21,11 @@ struct GramPlan {
     int tiles = 0;     // upper-triangle tiles nb(nb+1)/2
     int chunks = 0;    // row chunks (multiple of 8)
     int64_t rows_per_chunk = 0;
-    size_t partial_floats() const { return (size_t)chunks * tiles * kGramTile * kGramTile; }
+    size_t partial_doubles() const { return (size_t)chunks * tiles * kGramTile * kGramTile; }
 };
-GramPlan gram_plan(int64_t M, int N, int target_chunks);
+// rows_per_chunk is a multiple of row_quantum (32 for the FP32 kernel, 64
+// for the BF16 kernel).
+GramPlan gram_plan(int64_t M, int N, int target_chunks, int row_quantum = 32);
 
 // d_tiles: int2[tiles] (bi <= bj) written by the caller from gram_tile_list.
 void gram_tile_list(int nb, int* host_pairs /* 2 * tiles */);
@@ -30,10 +35,11 @@ void gram_tile_list(int nb, int* host_pairs /* 2 * tiles */);
 int64_t logratio_blocks(int64_t M);
 hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, float* L,
                            int64_t ldl, int npad, double* colsum_part, unsigned long long* clamps, hipStream_t s);
-// Gram partials of L (npad must cover plan.nb * 128 columns).
+// FP64 Gram partials of L per chunk of rows (npad must cover plan.nb * 128
+// columns), and their sum in chunk order into G (N x N FP64, both triangles).
 hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
-                       float* partial, hipStream_t s);
-hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
+                       double* partial, hipStream_t s);
+hipError_t launch_gram_reduce(const double* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
                               hipStream_t s);
 size_t colsum_scratch_doubles(int N);
 hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* mid, double* out,
@@ -66,7 +72,34 @@ hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const 
                             const float* Wt, int ldw, int kp, const float* BreT, const float* BimT,
                             float* out, int64_t ld_out, int plane, hipStream_t s);
 
-// Gather rows q of Z (k columns) into X (n_q x k, FP32).
+// ---- BF16 operands, FP32 accumulation -------------------------------------
+// BF16 arrays are passed as uint16_t (bit patterns).  kq = padded k of the
+// BF16 basis copies: 32, 64 or 128.
+
+// Log ratio rounded to BF16 in row-group-packed order (8 rows of one column
+// per 16-byte unit, logratio16_bytes(M, npad) bytes), with the column-sum
+// partials and clamp count of launch_logratio.
+size_t logratio16_bytes(int64_t M, int npad);
+hipError_t launch_logratio16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                             uint16_t* Lp, int npad, double* colsum_part, unsigned long long* clamps,
+                             hipStream_t s);
+// Gram partials from the packed log ratio (plan from gram_plan(.., 64)).
+hipError_t launch_gram16(const uint16_t* Lp, int npad, int64_t M, const GramPlan& plan, const int* d_tiles,
+                         double* partial, hipStream_t s);
+// Projection from I (log ratio on load), Wt: kq x ldw BF16.
+hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                            const uint16_t* Wt, int ldw, int kq, int k_store, float* Z, int64_t ld_z,
+                            ArgPart part, int k_arg, hipStream_t s);
+// Reconstruction from FP32 Z; BreT / BimT: (rows >= roundup(N, 64)) x kq BF16.
+hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
+                                const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
+                                hipStream_t s);
+hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                              const uint16_t* Wt, int ldw, int kq, const uint16_t* BreT, const uint16_t* BimT,
+                              float* out, int64_t ld_out, int plane, hipStream_t s);
+
+// Gather rows q of a row-major FP32 matrix Z (k columns, row stride ld_z)
+// into X (n_q x k).
 hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long long* q, int n_q, float* X,
                               hipStream_t s);
 

@@ -25,14 +25,14 @@ constexpr int GT = kGramTile;  // output tile
 constexpr int GKC = 32;        // rows per LDS stage
 constexpr int GLD = GT + 16;   // LDS row stride: rows 0/1 of a wave read hit disjoint banks
 
-GramPlan gram_plan(int64_t M, int N, int target_chunks) {
+GramPlan gram_plan(int64_t M, int N, int target_chunks, int row_quantum) {
     GramPlan p;
     p.nb = (N + GT - 1) / GT;
     p.tiles = p.nb * (p.nb + 1) / 2;
     int64_t want = target_chunks > 0 ? target_chunks : 64;
     int64_t rpc = (M + want - 1) / want;
-    rpc = ((rpc + GKC - 1) / GKC) * GKC;
-    if (rpc < GKC) rpc = GKC;
+    rpc = ((rpc + row_quantum - 1) / row_quantum) * row_quantum;
+    if (rpc < row_quantum) rpc = row_quantum;
     int64_t chunks = (M + rpc - 1) / rpc;
     if (chunks < 1) chunks = 1;
     chunks = ((chunks + 7) / 8) * 8;
@@ -69,9 +69,12 @@ __global__ __launch_bounds__(256) void logratio_kernel(const float* __restrict__
     for (int g0 = 0; g0 < npad; g0 += 1024) {
         const int c = g0 + 4 * (int)threadIdx.x;
         if (c >= npad) continue;
-        float r[4];
+        float r[4], rl[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r[q] = (c + q < N) ? rinv[c + q] : 0.f;
+        for (int q = 0; q < 4; ++q) {
+            r[q] = (c + q < N) ? rinv[c + q] : 0.f;
+            rl[q] = (c + q < N) ? rinv[N + c + q] : 0.f;
+        }
         double cs[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t row0 = r0; row0 < r1; row0 += 4) {
             float4 x[4];
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) void logratio_kernel(const float* __restrict__
                 for (int q = 0; q < 4; ++q) {
                     bool bad;
                     const float xv = f4get(x[u], q);
-                    l[q] = log_ratio(xv, r[q], floor, bad);
+                    l[q] = log_ratio(xv, r[q], rl[q], floor, bad);
                     if (c + q < N) {
                         cnt += bad ? 1u : 0u;
                         cs[q] += (double)xv;
@@ -106,11 +109,17 @@ __global__ __launch_bounds__(256) void logratio_kernel(const float* __restrict__
 
 // ---------------------------------------------------------------------------
 // Gram of the log ratio from l (no bounds checks on columns: l is zero past
-// N up to the padded width).
+// N up to the padded width).  Each 32-row LDS stage is accumulated by the
+// matrix cores in FP32 and then added into FP64 registers: the tail of the
+// spectrum of G (eigenvalue gaps near 1e-8 of the largest) is resolved only
+// if the accumulation error stays far below that, which FP32 sums over
+// thousands of rows do not achieve.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, int64_t ldl, int64_t M, int T,
-                                                   int64_t rpc, const int* __restrict__ tiles,
-                                                   float* __restrict__ partial) {
+constexpr int kGramThreads = 512;  // 8 waves, each 32 x 64 of the 128 x 128 tile
+
+__global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restrict__ L, int64_t ldl, int64_t M,
+                                                            int T, int64_t rpc, const int* __restrict__ tiles,
+                                                            double* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) float sA[2][GKC][GLD];
     __shared__ __attribute__((aligned(16))) float sB[2][GKC][GLD];
 
@@ -127,27 +136,29 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, 
     const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int lr = tid >> 5;
+    const int wr = wave >> 1, wc = wave & 1;  // rows 32 wr.., columns 64 wc..
+    const int lr = tid >> 5;                  // 0..15
     const int lc = (tid & 31) * 4;
     const float* La = L + bi * GT + lc;
     const float* Lb = L + bj * GT + lc;
 
-    floatx4 acc[4][4];
+    double acc64[2][4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
 
-    float4 xa[4], xb[4];
-    float keep[4];
+    float4 xa[2], xb[2];
+    float keep[2];
     // Rows past the chunk are loaded from the chunk's last row (always valid)
     // and zeroed when written to LDS, so the loads are unconditional and the
     // loaded registers are first used after the MFMA block.
     auto load = [&](int64_t base) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int64_t row = base + lr + 8 * p;
+        for (int p = 0; p < 2; ++p) {
+            const int64_t row = base + lr + 16 * p;
             const int64_t rc = row < m1 ? row : m1 - 1;
             keep[p] = row < m1 ? 1.f : 0.f;
             xa[p] = *reinterpret_cast<const float4*>(La + rc * ldl);
@@ -156,12 +167,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, 
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < 2; ++p) {
             const float k = keep[p];
-            *reinterpret_cast<float4*>(&sA[buf][lr + 8 * p][lc]) =
+            *reinterpret_cast<float4*>(&sA[buf][lr + 16 * p][lc]) =
                 make_float4(xa[p].x * k, xa[p].y * k, xa[p].z * k, xa[p].w * k);
             if (!diag)
-                *reinterpret_cast<float4*>(&sB[buf][lr + 8 * p][lc]) =
+                *reinterpret_cast<float4*>(&sB[buf][lr + 16 * p][lc]) =
                     make_float4(xb[p].x * k, xb[p].y * k, xb[p].z * k, xb[p].w * k);
         }
     };
@@ -177,44 +188,52 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ L, 
         if (s + 1 < nst) load(m0 + (s + 1) * GKC);
         const float(*A)[GLD] = sA[buf];
         const float(*B)[GLD] = diag ? sA[buf] : sB[buf];
+        floatx4 acc[2][4];
 #pragma unroll
         for (int ks = 0; ks < GKC / 4; ++ks) {
             const int row = ks * 4 + (lane >> 4);
-            float av[4], bv[4];
+            float av[2], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = A[row][wr * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < 2; ++i) av[i] = A[row][wr * 32 + i * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = B[row][wc * 64 + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = mfma4(av[i], bv[j], ks == 0 ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[i][j]);
         }
         if (s + 1 < nst) store(buf ^ 1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
         __syncthreads();
     }
 
-    float* P = partial + ((size_t)chunk * T + tile) * (size_t)(GT * GT);
+    double* P = partial + ((size_t)chunk * T + tile) * (size_t)(GT * GT);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = wr * 64 + i * 16 + 4 * (lane >> 4) + v;
+                const int r = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
                 const int c = wc * 64 + j * 16 + (lane & 15);
-                P[r * GT + c] = acc[i][j][v];
+                P[r * GT + c] = acc64[i][j][v];
             }
 }
 
-__global__ void gram_reduce_kernel(const float* __restrict__ partial, int T, int C,
+__global__ void gram_reduce_kernel(const double* __restrict__ partial, int T, int C,
                                    const int* __restrict__ tiles, int N, double* __restrict__ G) {
     const int tile = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= GT * GT) return;
     const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
     double s = 0.0;
-    for (int ch = 0; ch < C; ++ch) s += (double)partial[((size_t)ch * T + tile) * (size_t)(GT * GT) + e];
+    for (int ch = 0; ch < C; ++ch) s += partial[((size_t)ch * T + tile) * (size_t)(GT * GT) + e];
     const int r = e / GT, c = e % GT;
     const int gi = bi * GT + r, gj = bj * GT + c;
     if (gi >= N || gj >= N) return;
@@ -268,13 +287,13 @@ hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const f
 }
 
 hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
-                       float* partial, hipStream_t s) {
-    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(256);
+                       double* partial, hipStream_t s) {
+    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(kGramThreads);
     hipLaunchKernelGGL(gram_kernel, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles, partial);
     return hipGetLastError();
 }
 
-hipError_t launch_gram_reduce(const float* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
+hipError_t launch_gram_reduce(const double* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
                               hipStream_t s) {
     dim3 grid(GT * GT / 256, plan.tiles);
     hipLaunchKernelGGL(gram_reduce_kernel, grid, dim3(256), 0, s, partial, plan.tiles, plan.chunks, d_tiles, N, G);
@@ -308,9 +327,12 @@ __device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __
     const int lrow = tid >> 4;
     const int lcol = (tid & 15) * 4;
     const int col = j0 + lcol;
-    float r[4];
+    float r[4], rl[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = (col + q < N) ? rinv[col + q] : 0.f;
+    for (int q = 0; q < 4; ++q) {
+        r[q] = (col + q < N) ? rinv[col + q] : 0.f;
+        rl[q] = (col + q < N) ? rinv[N + col + q] : 0.f;
+    }
     float4 x[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -324,7 +346,7 @@ __device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             bool bad;
-            l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], floor, bad) : 0.f;
+            l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], rl[q], floor, bad) : 0.f;
         }
         *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
     }
@@ -384,13 +406,6 @@ __device__ __forceinline__ void project_stage(floatx4 (&acc)[2][KB], const float
     }
 }
 
-__device__ __forceinline__ void better_max(float& v, int& i, float ov, int oi) {
-    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
-}
-__device__ __forceinline__ void better_min(float& v, int& i, float ov, int oi) {
-    if (ov < v || (ov == v && oi < i)) { v = ov; i = oi; }
-}
-
 template <int KB, bool VEC, bool LOGGED>
 __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                       const float* __restrict__ rinv, float floor,
@@ -419,63 +434,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
         __syncthreads();
     }
 
-    // Z[row][c]: acc[rb][cb][v], row = wave*32 + rb*16 + 4*(lane/16) + v, c = cb*16 + lane%16
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < KB; ++cb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = r0 + wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
-                const int c = cb * 16 + (lane & 15);
-                if (row < M && c < k_store) Z[row * ld_z + c] = acc[rb][cb][v];
-            }
-
-    if (pmaxv == nullptr) return;
-    __shared__ float smx[4][KP], smn[4][KP];
-    __shared__ int smxi[4][KP], smni[4][KP];
-#pragma unroll
-    for (int cb = 0; cb < KB; ++cb) {
-        float mx = -INFINITY, mn = INFINITY;
-        int ix = INT_MAX, in = INT_MAX;
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rl = wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
-                if (r0 + rl < M) {
-                    better_max(mx, ix, acc[rb][cb][v], rl);
-                    better_min(mn, in, acc[rb][cb][v], rl);
-                }
-            }
-#pragma unroll
-        for (int off = 16; off <= 32; off <<= 1) {
-            const float omx = __shfl_xor(mx, off), omn = __shfl_xor(mn, off);
-            const int oix = __shfl_xor(ix, off), oin = __shfl_xor(in, off);
-            better_max(mx, ix, omx, oix);
-            better_min(mn, in, omn, oin);
-        }
-        if (lane < 16) {
-            smx[wave][cb * 16 + lane] = mx;
-            smxi[wave][cb * 16 + lane] = ix;
-            smn[wave][cb * 16 + lane] = mn;
-            smni[wave][cb * 16 + lane] = in;
-        }
-    }
-    __syncthreads();
-    if (tid < KP && tid < k_arg) {
-        float mx = smx[0][tid], mn = smn[0][tid];
-        int ix = smxi[0][tid], in = smni[0][tid];
-        for (int w = 1; w < 4; ++w) {
-            better_max(mx, ix, smx[w][tid], smxi[w][tid]);
-            better_min(mn, in, smn[w][tid], smni[w][tid]);
-        }
-        const size_t o = (size_t)blockIdx.x * KP + tid;
-        pmaxv[o] = mx;
-        pminv[o] = mn;
-        pmaxi[o] = (ix == INT_MAX) ? -1 : (long long)(r0 + ix);
-        pmini[o] = (in == INT_MAX) ? -1 : (long long)(r0 + in);
-    }
+    project_finish<KB>(acc, r0, M, Z, ld_z, k_store, pmaxv, pminv, pmaxi, pmini, k_arg);
 }
 
 __global__ void argext_reduce_kernel(ArgPart part, int64_t nblocks, int kp, long long* qmax, long long* qmin) {
@@ -570,14 +529,6 @@ hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long lo
 constexpr int RR = 128;  // rows per block (4 waves x 32)
 constexpr int RCN = 64;  // wavenumbers per chunk
 
-__device__ __forceinline__ float epilogue(float re, float im, int plane) {
-    const float mag = exp_fast(re);
-    if (plane == 2) return mag;
-    float sn, cs;
-    sincos_fast(im, &sn, &cs);
-    return mag * (plane == 0 ? sn : cs);
-}
-
 template <int KB>
 __device__ __forceinline__ void recon_chunk(const float4 (&zf)[2][KB], const float* sRe, const float* sIm, int bld,
                                             int lane, floatx4 (&are)[4][2], floatx4 (&aim)[4][2]) {
@@ -617,31 +568,6 @@ __device__ __forceinline__ void stage_basis_chunk(float* sRe, float* sIm, int bl
         *reinterpret_cast<float4*>(sRe + jr * bld + c4) = *reinterpret_cast<const float4*>(BreT + src);
         *reinterpret_cast<float4*>(sIm + jr * bld + c4) = *reinterpret_cast<const float4*>(BimT + src);
     }
-}
-
-template <bool VEC_OUT>
-__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
-                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
-                                          const floatx4 (&aim)[4][2], int plane) {
-#pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb) {
-            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
-            const int col = j0 + ib * 16 + 4 * (lane >> 4);
-            if (row >= M) continue;
-            float o[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = epilogue(are[ib][jb][v], aim[ib][jb][v], plane);
-            float* dst = out + row * ld_out + col;
-            if (VEC_OUT && col + 3 < N) {
-                *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (col + v < N) dst[v] = o[v];
-            }
-        }
 }
 
 template <int KB, bool VEC_OUT>

@@ -107,6 +107,7 @@ struct fkk_server {
     char* arena_base = nullptr;
     Arena arena;
     std::vector<const fkk_basis*> bases;
+    std::vector<int> base_prec;  // precision captured when the basis was added
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -126,7 +127,9 @@ struct fkk_server {
 };
 
 bool fkk_server::issue(std::vector<Request>& reqs) {
-    const fkk_basis* b = bases[reqs[0].basis];
+    const int bid = reqs[0].basis;  // reqs is moved from below
+    const fkk_basis* b = bases[bid];
+    const int prec = base_prec[bid];
     const int n = b->N;
     int64_t rows = 0;
     size_t bytes = 0;
@@ -156,8 +159,12 @@ bool fkk_server::issue(std::vector<Request>& reqs) {
     }
     chk(hipEventRecord(bt.copied, s_in));
     chk(hipStreamWaitEvent(s_comp, bt.copied, 0));
-    chk(fkk::dev::launch_transform(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
-                                   b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp));
+    if (prec == FKK_PREC_BF16)
+        chk(fkk::dev::launch_transform16(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt16, b->npad, b->kq,
+                                         b->d_bre16, b->d_bim16, dout, n, FKK_OUT_IM, s_comp));
+    else
+        chk(fkk::dev::launch_transform(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
+                                       b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp));
     chk(hipEventRecord(bt.computed, s_comp));
     chk(hipStreamWaitEvent(s_out, bt.computed, 0));
     r0 = 0;
@@ -280,6 +287,7 @@ fkk_status fkk_server_add_basis(fkk_server* srv, const fkk_basis* basis, int32_t
     if (basis->device != srv->device || !basis->d_wt) return FKK_EMISMATCH;
     std::lock_guard<std::mutex> g(srv->mu);
     srv->bases.push_back(basis);
+    srv->base_prec.push_back(basis->prec);
     *basis_id = (int32_t)srv->bases.size() - 1;
     return FKK_OK;
 }
