@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix peak, flop/s
 PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix peak, flop/s
+PEAK_FP64_MFMA = 78.6e12    # MI355X dense FP64 matrix peak, flop/s
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 
 
@@ -272,6 +273,16 @@ def main():
     fout = torch.empty_like(frames[0])
     transform = time_transform(ctx, b, frames, fout, I, out, args.frames, torch)
 
+    # the same fit with the FP64 Gram (products and sums in FP64)
+    log("fit with the FP64 Gram")
+    p64 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g, gram_prec=fk.PREC_FP64)
+    ms64, stage64, b64 = fit_steps(ctx, I, cube.i_ref, p64, args.steps, 1, out, torch, "fp64-gram")
+    b64.free()
+    fp64_gram = {"fit_ms_per_step": ms64, "fit_spectra_per_s": m / (ms64 * 1e-3), "stages_ms": stage64,
+                 "gram": {"ms": stage64["dev_ms_gram"], "TFLOP/s": gram_flop / (stage64["dev_ms_gram"] * 1e-3) / 1e12,
+                          "frac_of_fp64_peak": gram_flop / (stage64["dev_ms_gram"] * 1e-3) / PEAK_FP64_MFMA}}
+    log(f"fp64-gram fit: {ms64:.2f} ms/step")
+
     # the same fit and transforms with BF16 matrix-core operands
     log("BF16 fit and transforms")
     p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
@@ -334,6 +345,7 @@ def main():
         "reconstruction": recon,
         "logratio_pass": logratio,
         "transform": transform,
+        "fp64_gram": fp64_gram,
         "bf16": bf16,
         "plain": plain,
         "serving": serving,

@@ -58,11 +58,16 @@ enum { FKK_PAD_EDGE = 0, FKK_PAD_ZERO = 1 };
 enum { FKK_F_ONE = 0, FKK_F_NOISE = 1 };
 /* Which plane of K_CARS (Eq. 23) the output holds. */
 enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
-/* Input precision of the matrix-core contractions, always with FP32
- * accumulation.  BF16 rounds the operands (log ratio, projection weights,
- * Z and the corrected bases) to BF16, nearest even, as they are staged;
- * the eigensolve and the basis-vector KK / PEC / SEC stay FP64 either way. */
-enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1 };
+/* Precision of the matrix-core contractions.  FP32 and BF16 accumulate in
+ * FP32 (the Gram sums its 32- or 64-row stages in FP64); BF16 rounds the
+ * operands (log ratio, projection weights, Z and the corrected bases) to
+ * BF16, nearest even, as they are staged.  FP64 (Gram only) promotes the
+ * FP32 log ratio to FP64 and accumulates in FP64 on the FP64 matrix cores:
+ * the tail of the Gram's spectrum (eigenvalue gaps of ~1e-9 of the largest
+ * on tissue cubes) then moves the retained subspace, and with it the
+ * sub-sampled rows of Eq. 13-15, only by the FP32 rounding of the log ratio.
+ * The eigensolve and the basis-vector KK / PEC / SEC are FP64 always. */
+enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2 };
 
 /*
  * Method parameters.  Fill with fkk_params_default() and override fields.
@@ -89,10 +94,11 @@ typedef struct {
     double ml_lambda;      /* Eq. 25 ridge weight of the stored basis      */
     double ratio_floor;    /* ratios I/I_ref not above it are clamped      */
     int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
-    int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6)               */
-    int32_t recon_prec;    /* FKK_PREC_* of the projection (Eq. 13) and the
-                              reconstruction (Eq. 23); stored in the basis
-                              and used by its later transforms             */
+    int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6), FP64 allowed */
+    int32_t recon_prec;    /* FKK_PREC_FP32 / _BF16 of the projection
+                              (Eq. 13) and the reconstruction (Eq. 23);
+                              stored in the basis and used by its later
+                              transforms                                   */
     int32_t output;        /* FKK_OUT_*                                    */
     const int64_t* q_override; /* host, optional: rows used as U_ss       */
     int32_t n_q_override;  /* length of q_override (0 = use Eq. 13-15)    */
@@ -180,9 +186,9 @@ fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64
 /*
  * Log ratio and Gram (Eq. 2, Eq. 6): G = l^T l (N x N, FP64, row-major,
  * symmetric) with l = 1/2 ln(I / I_ref) computed in FP32 (rounded to BF16
- * when prec is FKK_PREC_BF16) and products accumulated in FP32 over chunks
- * of rows, the chunks summed in FP64; plus the column sums of I (FP64, N)
- * and the number of clamped ratios.  Synchronous.
+ * when prec is FKK_PREC_BF16), products summed as FKK_PREC_* describes;
+ * plus the column sums of I (FP64, N) and the number of clamped ratios.
+ * Synchronous.
  */
 fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
                     const double* h_iref, double ratio_floor, int32_t prec, double* h_gram,

@@ -24,7 +24,7 @@ SEC_SAVGOL, SEC_MEAN = 0, 1
 PAD_EDGE, PAD_ZERO = 0, 1
 F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
@@ -478,4 +478,5 @@ class Server:
 
 
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
-           "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16"]
+           "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16",
+           "PREC_FP64"]

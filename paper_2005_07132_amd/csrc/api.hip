@@ -81,6 +81,7 @@ void split_reciprocal(const double* iref, int N, float* out) {
 }
 
 bool valid_prec(int p) { return p == FKK_PREC_FP32 || p == FKK_PREC_BF16; }
+bool valid_gram_prec(int p) { return valid_prec(p) || p == FKK_PREC_FP64; }
 
 // Nearest-even BF16 bit pattern of a finite float.
 uint16_t to_bf16(float x) {
@@ -183,7 +184,7 @@ fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N) {
     }
     if (!(p->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
     if (p->output < FKK_OUT_IM || p->output > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad output plane");
-    if (!valid_prec(p->gram_prec) || !valid_prec(p->recon_prec))
+    if (!valid_gram_prec(p->gram_prec) || !valid_prec(p->recon_prec))
         return ctx->fail(FKK_EINVAL, "bad matrix-core precision (gram_prec=%d, recon_prec=%d)", p->gram_prec,
                          p->recon_prec);
     if (p->f_mode == FKK_F_NOISE && !(p->alpha >= 0.0 && p->sigma_g >= 0.0 && (p->alpha > 0.0 || p->sigma_g > 0.0)))
@@ -356,7 +357,8 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
     if (bf16)
         FKK_HIP(ctx, fkk::dev::launch_gram16(lp16, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
     else
-        FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
+        FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s,
+                                           prec == FKK_PREC_FP64));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
     FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, plan, ctx->tiles.p, N, ctx->G.p, s));
     FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N, ctx->colsum.p, s));
@@ -504,7 +506,7 @@ fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
     if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
-    if (!valid_prec(prec)) return ctx->fail(FKK_EINVAL, "bad precision %d", prec);
+    if (!valid_gram_prec(prec)) return ctx->fail(FKK_EINVAL, "bad precision %d", prec);
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, ratio_floor, prec, false)) != FKK_OK) return st;
     if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,

@@ -37,8 +37,9 @@ hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const f
                            int64_t ldl, int npad, double* colsum_part, unsigned long long* clamps, hipStream_t s);
 // FP64 Gram partials of L per chunk of rows (npad must cover plan.nb * 128
 // columns), and their sum in chunk order into G (N x N FP64, both triangles).
+// fp64: products and sums in FP64 (v_mfma_f64_16x16x4f64).
 hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
-                       double* partial, hipStream_t s);
+                       double* partial, hipStream_t s, bool fp64 = false);
 hipError_t launch_gram_reduce(const double* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
                               hipStream_t s);
 size_t colsum_scratch_doubles(int N);

@@ -109,14 +109,20 @@ __global__ __launch_bounds__(256) void logratio_kernel(const float* __restrict__
 
 // ---------------------------------------------------------------------------
 // Gram of the log ratio from l (no bounds checks on columns: l is zero past
-// N up to the padded width).  Each 32-row LDS stage is accumulated by the
-// matrix cores in FP32 and then added into FP64 registers: the tail of the
-// spectrum of G (eigenvalue gaps near 1e-8 of the largest) is resolved only
-// if the accumulation error stays far below that, which FP32 sums over
-// thousands of rows do not achieve.
+// N up to the padded width).  FP32: each 32-row LDS stage is accumulated by
+// the matrix cores in FP32 and then added into FP64 registers, so the error
+// does not grow with the rows of a chunk.
 // ---------------------------------------------------------------------------
 constexpr int kGramThreads = 512;  // 8 waves, each 32 x 64 of the 128 x 128 tile
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// F64: the FP32 l is promoted to FP64 (products exact) and accumulated by
+// v_mfma_f64_16x16x4f64 (operands laid out as for the FP32 instruction; the
+// result rows are interleaved differently, see the store).  Needed
+// where the Gram must resolve eigenvalue gaps below the rounding of the
+// FP32 matrix cores, which do not round each sum correctly.
+template <bool F64>
 __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restrict__ L, int64_t ldl, int64_t M,
                                                             int T, int64_t rpc, const int* __restrict__ tiles,
                                                             double* __restrict__ partial) {
@@ -142,13 +148,11 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
     const float* La = L + bi * GT + lc;
     const float* Lb = L + bj * GT + lc;
 
-    double acc64[2][4][4];
+    doublex4 acc64[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+        for (int j = 0; j < 4; ++j) acc64[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
 
     float4 xa[2], xb[2];
     float keep[2];
@@ -188,28 +192,46 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
         if (s + 1 < nst) load(m0 + (s + 1) * GKC);
         const float(*A)[GLD] = sA[buf];
         const float(*B)[GLD] = diag ? sA[buf] : sB[buf];
-        floatx4 acc[2][4];
+        if constexpr (F64) {
 #pragma unroll
-        for (int ks = 0; ks < GKC / 4; ++ks) {
-            const int row = ks * 4 + (lane >> 4);
-            float av[2], bv[4];
+            for (int ks = 0; ks < GKC / 4; ++ks) {
+                const int row = ks * 4 + (lane >> 4);
+                double av[2], bv[4];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = A[row][wr * 32 + i * 16 + (lane & 15)];
+                for (int i = 0; i < 2; ++i) av[i] = (double)A[row][wr * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = B[row][wc * 64 + j * 16 + (lane & 15)];
+                for (int j = 0; j < 4; ++j) bv[j] = (double)B[row][wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc64[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc64[i][j], 0, 0, 0);
+            }
+            if (s + 1 < nst) store(buf ^ 1);
+        } else {
+            floatx4 acc[2][4];
+#pragma unroll
+            for (int ks = 0; ks < GKC / 4; ++ks) {
+                const int row = ks * 4 + (lane >> 4);
+                float av[2], bv[4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) av[i] = A[row][wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[j] = B[row][wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = mfma4(av[i], bv[j], ks == 0 ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[i][j]);
+            }
+            if (s + 1 < nst) store(buf ^ 1);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = mfma4(av[i], bv[j], ks == 0 ? floatx4{0.f, 0.f, 0.f, 0.f} : acc[i][j]);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
         }
-        if (s + 1 < nst) store(buf ^ 1);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
         __syncthreads();
     }
 
@@ -220,7 +242,9 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+                // element v of lane l: row 4 (l/16) + v (FP32 instruction),
+                // row l/16 + 4 v (FP64 instruction); column l % 16 in both
+                const int r = wr * 32 + i * 16 + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
                 const int c = wc * 64 + j * 16 + (lane & 15);
                 P[r * GT + c] = acc64[i][j][v];
             }
@@ -287,9 +311,14 @@ hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const f
 }
 
 hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
-                       double* partial, hipStream_t s) {
+                       double* partial, hipStream_t s, bool fp64) {
     dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(kGramThreads);
-    hipLaunchKernelGGL(gram_kernel, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles, partial);
+    if (fp64)
+        hipLaunchKernelGGL(gram_kernel<true>, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles,
+                           partial);
+    else
+        hipLaunchKernelGGL(gram_kernel<false>, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles,
+                           partial);
     return hipGetLastError();
 }
 

@@ -92,6 +92,49 @@ def test_gram_matches_oracle(ctx, m, n, ld_pad):
     assert clamps == bad == 0
 
 
+@pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3)])
+def test_gram_fp64_matches_oracle(ctx, m, n, ld_pad):
+    # FP64 matrix cores: the only difference left is the FP32 log ratio
+    # (relative rounding ~6e-8 per entry, which averages over the rows)
+    say(f"gram fp64 m={m} n={n} ld_pad={ld_pad}")
+    cube = synth.tissue_cube(rows=1, cols=m, n=n, blur=1.0)
+    data = cube.i_cars
+    if ld_pad:
+        full = np.zeros((m, n + ld_pad), dtype=np.float32)
+        full[:, :n] = data
+        t = dev(full)[:, :n]
+    else:
+        t = dev(data)
+    g, cs, clamps = ctx.gram(t, cube.i_ref, prec=fk.PREC_FP64)
+    ell, bad = wf.log_ratio(data.astype(np.float64), cube.i_ref, 1e-6)
+    ref = ell.T @ ell
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    say(f"gram fp64 rel err {err:.2e}")
+    # element-wise bound from the FP32 log ratio alone: |dl| <= 2^-22 |l| +
+    # 2^-24 (ratio rounded once, logarithm within two ulp; the second term
+    # is the absolute error of ln near ratio 1); FP64 sums add nothing visible
+    e = 2.0 ** -22 * np.abs(ell) + 2.0 ** -24
+    bound = e.T @ np.abs(ell) + np.abs(ell).T @ e
+    assert np.all(np.abs(g - ref) <= bound)
+    np.testing.assert_array_equal(g, g.T)
+    assert clamps == bad == 0
+
+
+def test_fit_fp64_gram_matches_oracle_directly(ctx):
+    # with the FP64 Gram the fit (eigenvectors, sub-sampled rows, fPEC, fSEC)
+    # follows the FP64 oracle itself, not only its own exported basis
+    say("fit fp64 gram vs oracle")
+    cube = tissue(rows=96, cols=96, n=500, key=9)
+    p = oracle_params(cube, k=20)
+    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p, gram_prec=fk.PREC_FP64))
+    e = b.export()
+    np.testing.assert_array_equal(np.sort(e["q"]), np.sort(ref["basis"]["q"]))
+    err = spectrum_err(host(out), ref["im"])
+    say(f"fit fp64 gram: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    assert err.max() < TOL
+
+
 def test_gram_counts_and_clamps_invalid_ratios(ctx):
     say("gram clamps")
     cube = tissue(rows=20, cols=20, n=64)
@@ -394,6 +437,27 @@ def test_paper_scale_fit_sampled(ctx):
     ob = wf.basis_from_factors(e["f"], e["s"], e["v"], x, wf.Params(k=50), q=np.arange(len(e["q"])))
     # X is taken from the device's FP32 Z on one side and FP64 on the other
     assert np.abs(ob["b_im"] - e["b_im"]).max() / np.abs(ob["b_im"]).max() < 1e-3
+    del t, out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_paper_scale_fit_fp64_gram_matches_oracle(ctx):
+    # the 703,026 x 1,000 cube, k = 50: every output spectrum against the
+    # FP64 oracle's own fit of the same FP32 input
+    say("paper-scale fit, FP64 Gram, vs oracle")
+    cube = synth.tissue_703k()
+    p = oracle_params(cube, k=50)
+    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p, svd="gram")
+    t = dev(cube.i_cars)
+    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=fk.PREC_FP64))
+    got = out.cpu().numpy()
+    e = b.export()
+    np.testing.assert_array_equal(np.sort(e["q"]), np.sort(ref["basis"]["q"]))
+    err = np.concatenate([spectrum_err(got[i:i + 65536].astype(np.float64), ref["im"][i:i + 65536])
+                          for i in range(0, cube.shape[0], 65536)])
+    say(f"paper-scale fp64-gram fit: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    assert err.max() < TOL
     del t, out
     torch.cuda.empty_cache()
 

@@ -2,8 +2,9 @@
 
 The 703,026 x 1,000 cube and a 262,144 x 1,600 cube (512 x 512 pixels) are
 fitted on the device with the Gram and the projection / reconstruction
-contractions in FP32 and in BF16 (always FP32 accumulation; FP64 eigensolve
-and basis-vector KK / PEC / SEC), k in {20, 50, 100}.  For each fit the
+contractions in FP32 and in BF16 (FP32 accumulation), and with an FP64 Gram
+and FP32 projection / reconstruction; FP64 eigensolve and basis-vector
+KK / PEC / SEC always; k in {20, 50, 100}.  For each fit the
 per-spectrum relative error of the retrieved Raman spectrum (Im K_CARS),
 max_j |y - y*| / max_j |y*|, is taken against the FP64 oracle's fit of the
 same FP32 input, and its maximum and RMS over all spectra are reported.
@@ -73,9 +74,11 @@ def test_precision_sweep():
             ref = wf.fit(i64, cube.i_ref, wf.Params(k=k, f_mode=wf.F_NOISE, alpha=cube.alpha,
                                                     sigma_g=cube.sigma_g), svd="gram")["im"]
             say(f"sweep {name} k={k}: oracle fit {time.perf_counter() - t0:.1f} s")
-            for label, prec in (("fp32", fk.PREC_FP32), ("bf16", fk.PREC_BF16)):
+            for label, gprec, rprec in (("fp64 gram + fp32", fk.PREC_FP64, fk.PREC_FP32),
+                                        ("fp32", fk.PREC_FP32, fk.PREC_FP32),
+                                        ("bf16", fk.PREC_BF16, fk.PREC_BF16)):
                 p = fk.params(k=k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
-                              gram_prec=prec, recon_prec=prec)
+                              gram_prec=gprec, recon_prec=rprec)
                 b, _, rep = ctx.fit(I, cube.i_ref, p, out=out)
                 b.free()
                 torch.cuda.synchronize()
