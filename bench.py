@@ -11,6 +11,7 @@ host's cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +26,23 @@ PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix peak, flop/s
 PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix peak, flop/s
 PEAK_FP64_MFMA = 78.6e12    # MI355X dense FP64 matrix peak, flop/s
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
+
+
+def profiled_traffic(key):
+    """HBM bytes per launch of a Gram kernel from the committed counter
+    summary, or None once the profiled kernel source has changed."""
+    path = os.path.join(ROOT, "profiles", "gram_kernel_tissue703k_traffic.txt")
+    try:
+        text = open(path).read()
+        src = open(os.path.join(ROOT, "paper_2005_07132_amd", "csrc", "kernels.hip")).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_", "source_sha256")))
+    region = src[src.index("constexpr int GT = kGramTile;"):src.index("__global__ void gram_reduce_kernel(")]
+    if hashlib.sha256(region.encode()).hexdigest() != vals.get("source_sha256", "").strip():
+        return None
+    return int(vals[key])
 
 
 def log(msg):
@@ -213,6 +231,27 @@ def time_transform(ctx, b, frames, fout, I, out, n_frames, torch):
             "HBM_frac_full_cube": 8.0 * m * n / (full_ms * 1e-3) / PEAK_HBM}
 
 
+def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, args, m, n, npad, kq, gram_flop, recon_stats):
+    """The fit and the transforms with BF16 matrix-core operands."""
+    log("BF16 fit and transforms")
+    p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
+                    gram_prec=fk.PREC_BF16, recon_prec=fk.PREC_BF16)
+    ms16, stage16, b16 = fit_steps(ctx, I, cube.i_ref, p16, args.steps, 1, out, torch, "bf16")
+    gram16_ms = stage16["dev_ms_gram"]
+    bf16 = {"fit_ms_per_step": ms16, "fit_spectra_per_s": m / (ms16 * 1e-3), "stages_ms": stage16,
+            "gram": {"ms": gram16_ms, "TFLOP/s": gram_flop / (gram16_ms * 1e-3) / 1e12,
+                     "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA,
+                     "bytes_read": 2.0 * m * npad,
+                     "GB/s_algorithmic": 2.0 * m * npad / (gram16_ms * 1e-3) / 1e9},
+            "logratio_pass": {"ms": stage16["dev_ms_logratio"],
+                              "GB/s": (4.0 * m * n + 2.0 * m * npad) / (stage16["dev_ms_logratio"] * 1e-3) / 1e9},
+            "reconstruction": recon_stats(stage16["dev_ms_recon"], kq, 2),
+            "transform": time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)}
+    log(f"bf16 fit: {ms16:.2f} ms/step; transform {bf16['transform']['spectra_per_s_full_cube']:.3e}/s")
+    b16.free()
+    return bf16
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +262,10 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--frames", type=int, default=20)
     ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--skip-bf16", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one 1 GiB device-to-device copy: the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a --pmc run to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path is data-parallel over spectra and this build runs on a "
@@ -251,7 +294,12 @@ def main():
     gram_flop = float(m) * n * (n + 1)  # symmetric Gram: N(N+1)/2 entries x 2M flop
     roofline = {"bound": "mfma", "kernel": "gram_kernel (FP32 MFMA Gram of the log ratio)",
                 "achieved": gram_flop / (gram_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                "unit": "TFLOP/s", "frac": gram_flop / (gram_ms * 1e-3) / PEAK_FP32_MFMA, "traffic": None,
+                "unit": "TFLOP/s", "frac": gram_flop / (gram_ms * 1e-3) / PEAK_FP32_MFMA,
+                "traffic": profiled_traffic("traffic_bytes_gram_kernel_fp32"),
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                "profiles/gram_kernel_tissue703k_traffic.txt)",
+                "algorithmic_bytes_per_launch": 4.0 * m * ((n + 127) // 128 * 128) + 8.0 * 64 * 128 * 128 *
+                ((n + 127) // 128) * ((n + 127) // 128 + 1) / 2,
                 "flop_per_launch": gram_flop, "ms_per_launch": gram_ms}
     npad = (n + 127) // 128 * 128
     logratio = {"ms": stage["dev_ms_logratio"],
@@ -284,24 +332,12 @@ def main():
     log(f"fp64-gram fit: {ms64:.2f} ms/step")
 
     # the same fit and transforms with BF16 matrix-core operands
-    log("BF16 fit and transforms")
-    p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
-                    gram_prec=fk.PREC_BF16, recon_prec=fk.PREC_BF16)
-    ms16, stage16, b16 = fit_steps(ctx, I, cube.i_ref, p16, args.steps, 1, out, torch, "bf16")
-    gram16_ms = stage16["dev_ms_gram"]
-    bf16 = {"fit_ms_per_step": ms16, "fit_spectra_per_s": m / (ms16 * 1e-3), "stages_ms": stage16,
-            "gram": {"ms": gram16_ms, "TFLOP/s": gram_flop / (gram16_ms * 1e-3) / 1e12,
-                     "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA,
-                     "bytes_read": 2.0 * m * npad,
-                     "GB/s_algorithmic": 2.0 * m * npad / (gram16_ms * 1e-3) / 1e9},
-            "logratio_pass": {"ms": stage16["dev_ms_logratio"],
-                              "GB/s": (4.0 * m * n + 2.0 * m * npad) / (stage16["dev_ms_logratio"] * 1e-3) / 1e9},
-            "reconstruction": recon_stats(stage16["dev_ms_recon"], kq, 2),
-            "transform": time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)}
-    log(f"bf16 fit: {ms16:.2f} ms/step; transform {bf16['transform']['spectra_per_s_full_cube']:.3e}/s")
-    b16.free()
+    bf16 = None
+    if not args.skip_bf16:
+        bf16 = bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, args, m, n, npad, kq, gram_flop, recon_stats)
     del frames, fout
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
 
     plain = None
     if not args.skip_plain:
@@ -354,6 +390,14 @@ def main():
                           "hardware": "6-core i7-8850H laptop, NumPy/SciPy"},
     }
     print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
 
 
 if __name__ == "__main__":

@@ -142,7 +142,11 @@ int fkk_version(void);
 const char* fkk_status_string(fkk_status s);
 void fkk_params_default(fkk_params* p);
 
-/* Context: one device and one HIP stream (NULL = the default stream). */
+/* Context: one device and one HIP stream (NULL = the default stream).  The
+ * context records the launch sequence of the Householder tridiagonalisation
+ * into a HIP graph (kernel nodes only) the first time it meets an order N
+ * and replays it on its stream; FKK_NO_GRAPHS=1 in the environment when the
+ * context is created launches the same kernels one by one instead. */
 fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out);
 void fkk_ctx_destroy(fkk_ctx* ctx);
 const char* fkk_ctx_last_error(const fkk_ctx* ctx);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -121,6 +122,13 @@ struct fkk_ctx {
     PinnedBuf<double> hG;
     fkk::plain::Workspace plain_ws;
     hipEvent_t ev[10] = {};
+    // The n - 1 launches of the tridiagonalisation, recorded once per order
+    // and buffer set on a private stream and replayed on `stream`.
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t tri_exec = nullptr;
+    int tri_n = 0;
+    const double* tri_key[2] = {nullptr, nullptr};
 
     hipError_t events() {
         for (auto& e : ev)
@@ -146,7 +154,7 @@ struct fkk_ctx {
         return s;
     }
     size_t bytes() const {
-        return partial.n * 4 + L.n * 4 + fdev.n * 8 + tri.n * 8 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 +
+        return partial.n * 8 + L.n * 4 + fdev.n * 8 + tri.n * 8 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 +
                clamps.n * 8 + tiles.n * 4 +
                rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
                qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
@@ -394,8 +402,34 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
     FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, f, N * sizeof(double), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, fkk::dev::launch_scale_sym(ctx->G.p, ctx->fdev.p, N, s));
+    FKK_HIP(ctx, fkk::dev::tridiag_prepare(N));
+    if (ctx->graphs && !(ctx->tri_exec && ctx->tri_n == N && ctx->tri_key[0] == ctx->G.p && ctx->tri_key[1] == t)) {
+        if (ctx->tri_exec) {
+            hipGraphExecDestroy(ctx->tri_exec);
+            ctx->tri_exec = nullptr;
+        }
+        if (!ctx->cap_stream) FKK_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        FKK_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+        hipError_t ie = hipSuccess;
+        if (le == hipSuccess && ce == hipSuccess) ie = hipGraphInstantiate(&ctx->tri_exec, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        if (le != hipSuccess || ce != hipSuccess || ie != hipSuccess) {
+            ctx->tri_exec = nullptr;
+            return ctx->fail(FKK_EDEVICE, "recording the tridiagonalisation failed: %s",
+                             hipGetErrorString(le != hipSuccess ? le : ce != hipSuccess ? ce : ie));
+        }
+        ctx->tri_n = N;
+        ctx->tri_key[0] = ctx->G.p;
+        ctx->tri_key[1] = t;
+    }
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
-    FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
+    if (ctx->graphs)
+        FKK_HIP(ctx, hipGraphLaunch(ctx->tri_exec, s));
+    else
+        FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     double* h = ctx->hG.p;  // beta | d | e | vstore
     FKK_HIP(ctx, hipMemcpyAsync(h, beta, (3 * (size_t)N + nv) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -462,6 +496,8 @@ fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
     fkk_ctx* c = new fkk_ctx;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const char* ng = std::getenv("FKK_NO_GRAPHS");
+    c->graphs = !(ng && ng[0] == '1');
     *out = c;
     return FKK_OK;
 }
@@ -470,6 +506,8 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
+    if (ctx->tri_exec) hipGraphExecDestroy(ctx->tri_exec);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     ctx->partial.release();
     ctx->L.release();
     ctx->fdev.release();

@@ -11,8 +11,14 @@ namespace dev {
 // Packed reflector storage for an n x n reduction (column i: n - i - 1 values).
 size_t tridiag_vstore_doubles(int n);
 
+// Sets the kernels' dynamic LDS size for order n (call before
+// launch_tridiag, outside any stream capture).
+hipError_t tridiag_prepare(int n);
+
 // A (n x n row-major FP64, symmetric, overwritten) -> tridiagonal (d: n,
 // e: n-1), reflectors (vstore, beta: n-2).  p0, p1: n doubles of scratch.
+// Kernel launches only (n - 1 of them), so the sequence can be recorded
+// into a graph.
 hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vstore, double* beta, double* d, double* e,
                           hipStream_t s);
 

@@ -18,6 +18,8 @@ namespace dev {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kPrefetch = 16;  // row doubles per lane held in registers (trailing width <= 1024)
+static_assert(64 * kPrefetch <= 4 * kThreads, "pivot loads of a prefetching step assume m <= 4 * kThreads");
 
 __device__ __forceinline__ int64_t voff(int64_t i, int64_t n) { return i * (n - 1) - i * (i - 1) / 2; }
 
@@ -96,6 +98,10 @@ __global__ __launch_bounds__(kThreads) void tridiag_init(const double* __restric
 // Step i (0 <= i <= n-3): rank-2 update of column i fused with p_{i+1}.
 // The pivot data are built with one round of global reads and two block
 // reductions: ptv = p_i . v_i, then |x_{1:}|^2 of the updated pivot row.
+// Each wave's first two rows do not depend on the pivot data: with PF > 0
+// (trailing width m <= 64 PF) they are loaded into registers before it, so
+// their round trip overlaps the reductions; further rows stream as before.
+template <int PF>
 __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A, int n, int i,
                                                          const double* __restrict__ p_in,
                                                          double* __restrict__ p_out, double* __restrict__ vstore,
@@ -111,17 +117,53 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
     const double* vs = vstore + voff(i, n);
     const double* rlo = A + (size_t)lo * n + lo;
     const double bi = beta[i];
-    // one round of independent global reads
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tw = gridDim.x * (blockDim.x >> 6);
+    const int r0 = lo + 1 + gw, r1 = r0 + tw;
+    constexpr int PFN = PF > 0 ? PF : 1;
+    double ra[PFN], rb[PFN];
+    if (PF > 0) {
+#pragma unroll
+        for (int t = 0; t < PFN; ++t) {
+            const int c = lane + 64 * t;
+            ra[t] = (r0 < n && c < m) ? A[(size_t)r0 * n + lo + c] : 0.0;
+            rb[t] = (r1 < n && c < m) ? A[(size_t)r1 * n + lo + c] : 0.0;
+        }
+    }
+    // one round of independent global reads (issued together with the rows)
+    const double v0 = vs[0], p0 = p_in[0];  // w[0] in LDS is rewritten below
     double part = 0.0;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const double vj = vs[j], pj = p_in[j];
-        v[j] = vj;
-        w[j] = pj;
-        x[j] = rlo[j];
-        part += pj * vj;
+    if (PF > 0) {  // m <= 4 * kThreads: all loads in flight at once
+        double tv[4], tp[4], tx[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = threadIdx.x + kThreads * u;
+            tv[u] = j < m ? vs[j] : 0.0;
+            tp[u] = j < m ? p_in[j] : 0.0;
+            tx[u] = j < m ? rlo[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = threadIdx.x + kThreads * u;
+            if (j < m) {
+                v[j] = tv[u];
+                w[j] = tp[u];
+                x[j] = tx[u];
+                part += tp[u] * tv[u];
+            }
+        }
+    } else {
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            const double vj = vs[j], pj = p_in[j];
+            v[j] = vj;
+            w[j] = pj;
+            x[j] = rlo[j];
+            part += pj * vj;
+        }
     }
     const double kk = 0.5 * bi * block_sum(part, red);  // barriers make v, w, x visible
-    const double v0 = vs[0], w0 = p_in[0] - kk * vs[0];   // from global: w[0] is rewritten below
+    const double w0 = p0 - kk * v0;
     const bool next = (i + 3 < n);
     double part2 = 0.0;
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
@@ -160,13 +202,37 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
         d[lo] = x[0];
         e[lo] = x[1];
     }
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int tw = gridDim.x * (blockDim.x >> 6);
-    for (int r = lo + 1 + gw; r < n; r += tw) {
+    // rows held in registers
+    int rstart = r0;
+    if (PF > 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = h == 0 ? r0 : r1;
+            if (r >= n) break;
+            double* row = A + (size_t)r * n + lo;
+            const double vr = v[r - lo], wr = w[r - lo];
+            double sacc = 0.0;
+#pragma unroll
+            for (int t = 0; t < PFN; ++t) {
+                const int c = lane + 64 * t;
+                if (c < m) {
+                    const double u = (h == 0 ? ra[t] : rb[t]) - (vr * w[c] + wr * v[c]);
+                    row[c] = u;
+                    if (next && c >= 1) sacc += u * vn[c - 1];
+                    if (!next && r == n - 1 && c == m - 1) d[n - 1] = u;
+                }
+            }
+            if (next) {
+                sacc = wave_sum(sacc);
+                if (lane == 0) p_out[r - lo - 1] = bn * sacc;
+            }
+        }
+        rstart = r1 + tw;
+    }
+    for (int r = rstart; r < n; r += tw) {
         double* row = A + (size_t)r * n + lo;
         const double vr = v[r - lo], wr = w[r - lo];
-        double s = 0.0;
+        double sacc = 0.0;
         int c = lane;
         for (; c + 192 < m; c += 256) {  // four independent loads in flight
             const double a0 = row[c], a1 = row[c + 64], a2 = row[c + 128], a3 = row[c + 192];
@@ -179,19 +245,19 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
             row[c + 128] = u2;
             row[c + 192] = u3;
             if (next) {
-                if (c >= 1) s += u0 * vn[c - 1];
-                s += u1 * vn[c + 63] + u2 * vn[c + 127] + u3 * vn[c + 191];
+                if (c >= 1) sacc += u0 * vn[c - 1];
+                sacc += u1 * vn[c + 63] + u2 * vn[c + 127] + u3 * vn[c + 191];
             }
         }
         for (; c < m; c += 64) {
             const double a = row[c] - (vr * w[c] + wr * v[c]);
             row[c] = a;
-            if (next && c >= 1) s += a * vn[c - 1];
+            if (next && c >= 1) sacc += a * vn[c - 1];
             if (!next && r == n - 1 && c == m - 1) d[n - 1] = a;
         }
         if (next) {
-            s = wave_sum(s);
-            if (lane == 0) p_out[r - lo - 1] = bn * s;
+            sacc = wave_sum(sacc);
+            if (lane == 0) p_out[r - lo - 1] = bn * sacc;
         }
     }
 }
@@ -213,15 +279,25 @@ hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t tridiag_prepare(int n) {
+    if (n < 3) return hipErrorInvalidValue;
+    const size_t lds = (size_t)4 * n * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_init),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_step<kPrefetch>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_step<0>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vstore, double* beta, double* d, double* e,
                           hipStream_t s) {
     if (n < 3) return hipErrorInvalidValue;
     const size_t lds = (size_t)4 * n * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_init), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_step), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
     auto blocks_for = [](int rows) {
         int b = (rows + 7) / 8;  // at least two rows per wave
         if (b < 1) b = 1;
@@ -235,8 +311,12 @@ hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vsto
     double* pout = p1;
     for (int i = 0; i + 2 < n; ++i) {
         const int rows = n - (i + 2);
-        hipLaunchKernelGGL(tridiag_step, dim3(blocks_for(rows)), dim3(kThreads), lds, s, A, n, i, pin, pout, vstore,
-                           beta, d, e);
+        if (n - (i + 1) <= 64 * kPrefetch)
+            hipLaunchKernelGGL(tridiag_step<kPrefetch>, dim3(blocks_for(rows)), dim3(kThreads), lds, s, A, n, i, pin,
+                               pout, vstore, beta, d, e);
+        else
+            hipLaunchKernelGGL(tridiag_step<0>, dim3(blocks_for(rows)), dim3(kThreads), lds, s, A, n, i, pin, pout,
+                               vstore, beta, d, e);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         double* t = pin;
         pin = pout;

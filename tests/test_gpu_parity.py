@@ -6,6 +6,7 @@ Stage checks use the oracle's FP64 evaluation of the same stage on the same
 inputs; the Gram is held to 2e-6 of its largest entry (FP32 log ratio; the
 matrix cores accumulate 32-row stages in FP32, summed in FP64).
 """
+import os
 import sys
 
 import numpy as np
@@ -378,6 +379,36 @@ def test_full_rank_and_minimum_sizes(ctx):
     b1, out1, rep1 = ctx.fit(one, cube.i_ref, lib_params(wf.Params(k=1, sg_window=7)))
     assert rep1["n_q"] == 1
     assert np.isfinite(host(out1)).all()
+
+
+def test_tridiag_graph_replays_match_eager_launches(ctx):
+    # the tridiagonalisation runs from a recorded graph; every replay, with
+    # other device work and synchronisations in between and a re-record for
+    # another order, equals the kernels launched one by one, bit for bit
+    say("tridiag graph replays vs eager")
+    cube = tissue(rows=40, cols=40, n=300, key=21)
+    other = tissue(rows=20, cols=20, n=257, key=22)
+    p = lib_params(oracle_params(cube, k=12))
+    po = lib_params(oracle_params(other, k=8))
+    os.environ["FKK_NO_GRAPHS"] = "1"
+    try:
+        eager = fk.Context(0)
+    finally:
+        del os.environ["FKK_NO_GRAPHS"]
+    t = dev(cube.i_cars)
+    b0, out0, _ = eager.fit(t, cube.i_ref, p)
+    ref_out, ref_v = host(out0), b0.export()["v"]
+    bo0, outo0, _ = eager.fit(dev(other.i_cars), other.i_ref, po)
+    ref_other = host(outo0)
+    for rep in range(3):
+        b, out, _ = ctx.fit(t, cube.i_ref, p)
+        np.testing.assert_array_equal(host(out), ref_out)
+        np.testing.assert_array_equal(b.export()["v"], ref_v)
+        ctx.transform(b, t)  # eager device work between replays
+        torch.cuda.synchronize()
+        bo, outo, _ = ctx.fit(dev(other.i_cars), other.i_ref, po)  # another order: re-recorded
+        np.testing.assert_array_equal(host(outo), ref_other)
+    eager.close()
 
 
 def test_invalid_arguments_fail_before_launch(ctx):
