@@ -285,13 +285,15 @@ void basis_math(fkk_basis* b, const double* X, int n_q, const fkk_params* p) {
     fkk::hilbert_rows(vt_f.data(), b->h_v.data(), k, N, len, p->pad_mode);
     // Phi_raw = X H{V^T/f}; Phi_err = D{Phi_raw} row by row
     std::vector<double> raw((size_t)n_q * N, 0.0), err((size_t)n_q * N);
-    for (int r = 0; r < n_q; ++r)
-        for (int c = 0; c < k; ++c) {
-            const double x = X[(size_t)r * k + c];
-            const double* hv = &b->h_v[(size_t)c * N];
-            double* dst = &raw[(size_t)r * N];
-            for (int j = 0; j < N; ++j) dst[j] += x * hv[j];
-        }
+    fkk::parallel_rows(n_q, [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r)
+            for (int c = 0; c < k; ++c) {
+                const double x = X[(size_t)r * k + c];
+                const double* hv = &b->h_v[(size_t)c * N];
+                double* dst = &raw[(size_t)r * N];
+                for (int j = 0; j < N; ++j) dst[j] += x * hv[j];
+            }
+    });
     fkk::detrend_rows(raw.data(), err.data(), n_q, N, p->detrend, lam, p->als_p, p->als_iters);
     b->phi_pec_t.assign((size_t)k * N, 0.0);
     b->ridge_lambda = fkk::ridge_rel_solve(X, err.data(), b->phi_pec_t.data(), n_q, k, N, p->ridge_rel);

@@ -285,9 +285,89 @@ void detrend_row(const double* y, double* z, int n, int mode, double lam, double
     }
 }
 
+namespace {
+
+// detrend_row on four rows at once: the same operations per row, with the
+// four factorisation and substitution chains interleaved (their divisions
+// and dependent updates overlap).  Rows are independent, so the results
+// equal four calls of detrend_row.
+void detrend_row4(const double* const* y, double* const* z, int n, int mode, double lam, double p, int n_iter) {
+    constexpr int R = 4;
+    std::vector<double> w((size_t)R * n, 1.0), dd((size_t)R * n), l1((size_t)R * (n + 1)), l2((size_t)R * (n + 2));
+    const int iters = (mode == 1) ? 1 : n_iter;
+    const double a2 = lam;
+    for (int it = 0; it < iters; ++it) {
+        std::fill(l1.begin(), l1.end(), 0.0);
+        std::fill(l2.begin(), l2.end(), 0.0);
+        for (int i = 0; i < n; ++i) {
+            double c0 = 6.0;
+            if (i == 0 || i == n - 1) c0 = 1.0;
+            else if (i == 1 || i == n - 2) c0 = 5.0;
+            double c1 = -4.0;
+            if (i == 0 || i == n - 2) c1 = -2.0;
+            for (int r = 0; r < R; ++r) {
+                double* D = &dd[(size_t)r * n];
+                double* L1 = &l1[(size_t)r * (n + 1)];
+                double* L2 = &l2[(size_t)r * (n + 2)];
+                double d = w[(size_t)r * n + i] + lam * c0;
+                if (i >= 1) d -= L1[i] * L1[i] * D[i - 1];
+                if (i >= 2) d -= L2[i] * L2[i] * D[i - 2];
+                D[i] = d;
+                if (i + 1 < n) {
+                    double v = lam * c1;
+                    if (i >= 1) v -= L2[i + 1] * L1[i] * D[i - 1];
+                    L1[i + 1] = v / d;
+                }
+                if (i + 2 < n) L2[i + 2] = a2 / d;
+            }
+        }
+        for (int i = 0; i < n; ++i)
+            for (int r = 0; r < R; ++r) {
+                const double* L1 = &l1[(size_t)r * (n + 1)];
+                const double* L2 = &l2[(size_t)r * (n + 2)];
+                double* zr = z[r];
+                double u = w[(size_t)r * n + i] * y[r][i];
+                if (i >= 1) u -= L1[i] * zr[i - 1];
+                if (i >= 2) u -= L2[i] * zr[i - 2];
+                zr[i] = u;
+            }
+        for (int r = 0; r < R; ++r)
+            for (int i = 0; i < n; ++i) z[r][i] /= dd[(size_t)r * n + i];
+        for (int i = n - 1; i >= 0; --i)
+            for (int r = 0; r < R; ++r) {
+                const double* L1 = &l1[(size_t)r * (n + 1)];
+                const double* L2 = &l2[(size_t)r * (n + 2)];
+                double* zr = z[r];
+                double v = zr[i];
+                if (i + 1 < n) v -= L1[i + 1] * zr[i + 1];
+                if (i + 2 < n) v -= L2[i + 2] * zr[i + 2];
+                zr[i] = v;
+            }
+        for (int r = 0; r < R; ++r)
+            for (int i = 0; i < n; ++i) w[(size_t)r * n + i] = (y[r][i] > z[r][i]) ? p : 1.0 - p;
+    }
+}
+
+}  // namespace
+
 void detrend_rows(const double* y, double* z, int rows, int n, int mode, double lam, double p, int n_iter) {
-    parallel_rows(rows, [&](int r0, int r1) {
-        for (int r = r0; r < r1; ++r) detrend_row(y + (size_t)r * n, z + (size_t)r * n, n, mode, lam, p, n_iter);
+    // rows 4g..4g+3 go through detrend_row4, the rows - rows % 4 .. rows-1
+    // tail through detrend_row: fixed by the row count, not by the threads
+    const int groups = (n >= 4) ? rows / 4 : 0;
+    parallel_rows(groups + (rows - 4 * groups), [&](int t0, int t1) {
+        for (int t = t0; t < t1; ++t) {
+            if (t < groups) {
+                const int r = 4 * t;
+                const double* ys[4] = {y + (size_t)r * n, y + (size_t)(r + 1) * n, y + (size_t)(r + 2) * n,
+                                       y + (size_t)(r + 3) * n};
+                double* zs[4] = {z + (size_t)r * n, z + (size_t)(r + 1) * n, z + (size_t)(r + 2) * n,
+                                 z + (size_t)(r + 3) * n};
+                detrend_row4(ys, zs, n, mode, lam, p, n_iter);
+            } else {
+                const int r = 4 * groups + (t - groups);
+                detrend_row(y + (size_t)r * n, z + (size_t)r * n, n, mode, lam, p, n_iter);
+            }
+        }
     });
 }
 
@@ -429,7 +509,85 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
 // with singular values below eps * max(m, k) * sigma_max dropped when
 // lam = 0 (the minimum-norm least-squares solution).
 // ---------------------------------------------------------------------------
+// lam > 0: the normal equations (X^T X + lam I) B = X^T Y by Cholesky
+// (condition number at most lam_max / lam); false if the factorisation
+// breaks down (non-finite input), so the caller can take the SVD route.
+static bool ridge_normal_equations(const double* X, const double* Y, double* B, int m, int k, int n, double rel,
+                                   double* lam_out) {
+    std::vector<double> G((size_t)k * k, 0.0);
+    for (int i = 0; i < m; ++i) {
+        const double* xr = X + (size_t)i * k;
+        for (int a = 0; a < k; ++a)
+            for (int b = a; b < k; ++b) G[(size_t)a * k + b] += xr[a] * xr[b];
+    }
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < a; ++b) G[(size_t)a * k + b] = G[(size_t)b * k + a];
+    double lmax = 0.0;
+    std::vector<double> vec(k);
+    if (eigh_topk(G.data(), k, 1, &lmax, vec.data(), 1) != 0 || !std::isfinite(lmax)) return false;
+    std::fill(B, B + (size_t)k * n, 0.0);
+    *lam_out = 0.0;
+    if (!(lmax > 0.0)) return true;  // X = 0
+    const double lam = rel * lmax;
+    for (int a = 0; a < k; ++a) G[(size_t)a * k + a] += lam;
+    // G = L L^T, L in the lower triangle
+    for (int j = 0; j < k; ++j) {
+        double dj = G[(size_t)j * k + j];
+        for (int c = 0; c < j; ++c) dj -= G[(size_t)j * k + c] * G[(size_t)j * k + c];
+        if (!(dj > 0.0) || !std::isfinite(dj)) return false;
+        const double ljj = std::sqrt(dj);
+        G[(size_t)j * k + j] = ljj;
+        for (int r = j + 1; r < k; ++r) {
+            double v = G[(size_t)r * k + j];
+            for (int c = 0; c < j; ++c) v -= G[(size_t)r * k + c] * G[(size_t)j * k + c];
+            G[(size_t)r * k + j] = v / ljj;
+        }
+    }
+    // X^T Y and the two triangular solves, split over columns of Y
+    parallel_rows(n, [&](int c0, int c1) {
+        const int w = c1 - c0;
+        std::vector<double> R((size_t)k * w, 0.0);
+        for (int i = 0; i < m; ++i) {
+            const double* xr = X + (size_t)i * k;
+            const double* yr = Y + (size_t)i * n + c0;
+            for (int a = 0; a < k; ++a) {
+                const double xa = xr[a];
+                double* ra = &R[(size_t)a * w];
+                for (int c = 0; c < w; ++c) ra[c] += xa * yr[c];
+            }
+        }
+        for (int a = 0; a < k; ++a) {  // L z = R
+            double* ra = &R[(size_t)a * w];
+            for (int b = 0; b < a; ++b) {
+                const double l = G[(size_t)a * k + b];
+                const double* rb = &R[(size_t)b * w];
+                for (int c = 0; c < w; ++c) ra[c] -= l * rb[c];
+            }
+            const double inv = 1.0 / G[(size_t)a * k + a];
+            for (int c = 0; c < w; ++c) ra[c] *= inv;
+        }
+        for (int a = k - 1; a >= 0; --a) {  // L^T b = z
+            double* ra = &R[(size_t)a * w];
+            for (int b = a + 1; b < k; ++b) {
+                const double l = G[(size_t)b * k + a];
+                const double* rb = &R[(size_t)b * w];
+                for (int c = 0; c < w; ++c) ra[c] -= l * rb[c];
+            }
+            const double inv = 1.0 / G[(size_t)a * k + a];
+            for (int c = 0; c < w; ++c) ra[c] *= inv;
+            std::copy(ra, ra + w, B + (size_t)a * n + c0);
+        }
+    });
+    *lam_out = lam;
+    return true;
+}
+
 double ridge_rel_solve(const double* X, const double* Y, double* B, int m, int k, int n, double rel) {
+    if (rel > 0.0) {
+        double lam = 0.0;
+        if (ridge_normal_equations(X, Y, B, m, k, n, rel, &lam)) return lam;
+    }
+    // lam = 0 (minimum-norm least squares): one-sided Jacobi SVD of X
     // columns of X as contiguous vectors
     std::vector<double> cols((size_t)k * m), W((size_t)k * k, 0.0);
     for (int j = 0; j < k; ++j) {
@@ -520,6 +678,28 @@ int sturm_count(const double* d, const double* e2, int n, double x, double pivmi
         if (q < 0) ++count;
     }
     return count;
+}
+
+// Four Sturm counts at once (independent recurrences interleaved, so the
+// division chains overlap); each lane computes exactly what sturm_count does.
+void sturm_count4(const double* d, const double* e2, int n, const double* x, double pivmin, int* count) {
+    double q[4];
+    int c[4];
+    for (int l = 0; l < 4; ++l) {
+        q[l] = d[0] - x[l];
+        if (std::fabs(q[l]) < pivmin) q[l] = -pivmin;
+        c[l] = q[l] < 0 ? 1 : 0;
+    }
+    for (int i = 1; i < n; ++i) {
+        const double di = d[i], ei = e2[i - 1];
+        for (int l = 0; l < 4; ++l) {
+            double t = di - x[l] - ei / q[l];
+            if (std::fabs(t) < pivmin) t = -pivmin;
+            c[l] += t < 0 ? 1 : 0;
+            q[l] = t;
+        }
+    }
+    for (int l = 0; l < 4; ++l) count[l] = c[l];
 }
 
 // Solve (T - lam I) x = b for tridiagonal T by Gaussian elimination with
@@ -704,17 +884,36 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
     pool.run([&](int tid, int nthr) {
         int j0, j1;
         split(0, k, tid, nthr, &j0, &j1);
-        for (int j = j0; j < j1; ++j) {
-            const int idx = n - 1 - j;  // ascending index of the j-th largest
-            double a = lo, b = hi;
-            for (int it = 0; it < 200; ++it) {
-                const double mid = 0.5 * (a + b);
-                if (b - a <= 2 * eps * std::max(std::fabs(a), std::fabs(b)) + pivmin) break;
-                if (mid <= a || mid >= b) break;
-                if (sturm_count(d.data(), e2.data(), n, mid, pivmin) > idx) b = mid;
-                else a = mid;
+        // four eigenvalues bisected together; a lane stops moving its
+        // interval once converged, exactly as the one-at-a-time loop would
+        for (int jb = j0; jb < j1; jb += 4) {
+            double a[4], b[4], mid[4];
+            bool live[4];
+            int cnt[4];
+            for (int l = 0; l < 4; ++l) {
+                a[l] = lo;
+                b[l] = hi;
+                live[l] = (jb + l < j1);
             }
-            vals[j] = 0.5 * (a + b);
+            for (int it = 0; it < 200; ++it) {
+                bool any = false;
+                for (int l = 0; l < 4; ++l) {
+                    mid[l] = 0.5 * (a[l] + b[l]);
+                    if (live[l] && (b[l] - a[l] <= 2 * eps * std::max(std::fabs(a[l]), std::fabs(b[l])) + pivmin ||
+                                    mid[l] <= a[l] || mid[l] >= b[l]))
+                        live[l] = false;
+                    any = any || live[l];
+                }
+                if (!any) break;
+                sturm_count4(d.data(), e2.data(), n, mid, pivmin, cnt);
+                for (int l = 0; l < 4; ++l) {
+                    if (!live[l]) continue;
+                    const int idx = n - 1 - (jb + l);  // ascending index of the j-th largest
+                    if (cnt[l] > idx) b[l] = mid[l];
+                    else a[l] = mid[l];
+                }
+            }
+            for (int l = 0; l < 4 && jb + l < j1; ++l) vals[jb + l] = 0.5 * (a[l] + b[l]);
         }
     });
 
@@ -789,20 +988,53 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
     }
 
     // ---- back-transformation x = H_0 H_1 ... H_{n-3} y ----
+    // Each thread applies every reflector to all of its vectors while the
+    // reflector is in cache (the packed reflectors are read once per thread).
     pool.run([&](int tid, int nthr) {
         int j0, j1;
         split(0, k, tid, nthr, &j0, &j1);
-        for (int j = j0; j < j1; ++j) {
-            double* y = &Y[(size_t)j * n];
-            for (int i = n - 3; i >= 0; --i) {
-                if (beta[i] == 0.0) continue;
-                const int lo2 = i + 1, m = n - lo2;
-                const double* vs = &vstore[voff[i]];
+        for (int i = n - 3; i >= 0; --i) {
+            if (beta[i] == 0.0) continue;
+            const int lo2 = i + 1, m = n - lo2;
+            const double* vs = &vstore[voff[i]];
+            int j = j0;
+            // four vectors at a time: four independent accumulation chains,
+            // each summed in the same order as the one-vector loop below
+            for (; j + 4 <= j1; j += 4) {
+                double* y0 = &Y[(size_t)j * n + lo2];
+                double* y1 = y0 + n;
+                double* y2 = y1 + n;
+                double* y3 = y2 + n;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                for (int c = 0; c < m; ++c) {
+                    const double vc = vs[c];
+                    s0 += vc * y0[c];
+                    s1 += vc * y1[c];
+                    s2 += vc * y2[c];
+                    s3 += vc * y3[c];
+                }
+                s0 *= beta[i];
+                s1 *= beta[i];
+                s2 *= beta[i];
+                s3 *= beta[i];
+                for (int c = 0; c < m; ++c) {
+                    const double vc = vs[c];
+                    y0[c] -= s0 * vc;
+                    y1[c] -= s1 * vc;
+                    y2[c] -= s2 * vc;
+                    y3[c] -= s3 * vc;
+                }
+            }
+            for (; j < j1; ++j) {
+                double* y = &Y[(size_t)j * n];
                 double s = 0.0;
                 for (int c = 0; c < m; ++c) s += vs[c] * y[lo2 + c];
                 s *= beta[i];
                 for (int c = 0; c < m; ++c) y[lo2 + c] -= s * vs[c];
             }
+        }
+        for (int j = j0; j < j1; ++j) {
+            double* y = &Y[(size_t)j * n];
             // sign: largest-magnitude entry positive (first on ties)
             int imax = 0;
             for (int r = 1; r < n; ++r)
