@@ -184,6 +184,10 @@ fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I,
  */
 fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
                      const double* h_iref, const fkk_params* p, float* d_out, int64_t ld_out);
+/* Same with FP64 intensities in and FP64 K_CARS out (d_I 8-byte aligned);
+ * the arithmetic is FP64 in both variants. */
+fkk_status fkk_plain_f64(fkk_ctx* ctx, const double* d_I, int64_t M, int32_t N, int64_t ld,
+                         const double* h_iref, const fkk_params* p, double* d_out, int64_t ld_out);
 
 /* ---- stages of the fit (each step of Fig. 1b on its own) ---------------- */
 

@@ -83,7 +83,8 @@ _LIB = None
 
 SYMBOLS = [
     "fkk_version", "fkk_status_string", "fkk_params_default", "fkk_ctx_create", "fkk_ctx_destroy",
-    "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram",
+    "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
+    "fkk_gram",
     "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
     "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
     "fkk_basis_get_precision", "fkk_server_create", "fkk_server_add_basis",
@@ -115,6 +116,7 @@ def lib() -> ctypes.CDLL:
                           ctypes.POINTER(FitReport)]
     L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64]
     L.fkk_plain.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64]
+    L.fkk_plain_f64.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64]
     L.fkk_gram.argtypes = [vp, vp, i64, i32, i64, _c_double_p, dbl, i32, _c_double_p, _c_double_p, _c_int64_p]
     L.fkk_eigh_topk.argtypes = [_c_double_p, i32, i32, _c_double_p, _c_double_p]
     L.fkk_basis_from_factors.argtypes = [vp, i32, i32, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
@@ -138,7 +140,8 @@ def lib() -> ctypes.CDLL:
     for name in ("fkk_server_create", "fkk_server_add_basis", "fkk_server_submit", "fkk_server_wait",
                  "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_gram", "fkk_eigh_topk",
+    for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64", "fkk_gram",
+                 "fkk_eigh_topk",
                  "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
                  "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision", "fkk_basis_get_precision"):
         getattr(L, name).restype = ctypes.c_int
@@ -344,15 +347,20 @@ class Context:
         return out
 
     def plain(self, I, i_ref, p: Params, out=None):
+        """Conventional per-spectrum KK / PEC / SEC.  float32 tensors use
+        fkk_plain, float64 tensors fkk_plain_f64 (output of the same dtype)."""
         import torch
-        _check_tensor(I, "I")
+        f64 = I.dtype == torch.float64
+        dt = "float64" if f64 else "float32"
+        _check_tensor(I, "I", dt)
         m, n = I.shape
         i_ref = _f64(i_ref, (n,))
         if out is None:
-            out = torch.empty((m, n), dtype=torch.float32, device=I.device)
-        _check_tensor(out, "out")
-        st = lib().fkk_plain(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ctypes.byref(p),
-                             out.data_ptr(), out.stride(0))
+            out = torch.empty((m, n), dtype=I.dtype, device=I.device)
+        _check_tensor(out, "out", dt)
+        fn = lib().fkk_plain_f64 if f64 else lib().fkk_plain
+        st = fn(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ctypes.byref(p), out.data_ptr(),
+                out.stride(0))
         self._ok(st, "plain")
         return out
 

@@ -909,11 +909,14 @@ fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double
 
 void fkk_basis_free(fkk_basis* b) { delete b; }
 
-fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                     const fkk_params* p, float* d_out, int64_t ld_out) {
+namespace {
+
+fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                     const fkk_params* p, void* d_out, int64_t ld_out) {
     if (!ctx) return FKK_EINVAL;
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
+    if (f64 && (reinterpret_cast<uintptr_t>(d_I) & 7) != 0) return ctx->fail(FKK_EINVAL, "I must be 8-byte aligned");
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
     if ((st = check_params(ctx, p, N)) != FKK_OK) return st;
     if (!d_out || ld_out < N) return ctx->fail(FKK_EINVAL, "bad output");
@@ -932,10 +935,23 @@ fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64
     cfg.floor = p->ratio_floor;
     cfg.plane = p->output;
     std::string why;
-    const hipError_t e = fkk::plain::run(ctx->plain_ws, cfg, d_I, M, ld, h_iref, d_out, ld_out, ctx->stream, &why);
+    const hipError_t e =
+        fkk::plain::run(ctx->plain_ws, cfg, d_I, f64, M, ld, h_iref, d_out, f64, ld_out, ctx->stream, &why);
     if (e != hipSuccess)
         return ctx->fail(FKK_EDEVICE, "plain path: %s (%s)", hipGetErrorString(e), why.c_str());
     return FKK_OK;
+}
+
+}  // namespace
+
+fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                     const fkk_params* p, float* d_out, int64_t ld_out) {
+    return plain_any(ctx, d_I, false, M, N, ld, h_iref, p, d_out, ld_out);
+}
+
+fkk_status fkk_plain_f64(fkk_ctx* ctx, const double* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
+                         const fkk_params* p, double* d_out, int64_t ld_out) {
+    return plain_any(ctx, d_I, true, M, N, ld, h_iref, p, d_out, ld_out);
 }
 
 }  // extern "C"

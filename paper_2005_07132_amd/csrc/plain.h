@@ -43,10 +43,11 @@ struct Workspace {
     void release();
 };
 
-// Runs the whole conventional workflow for M spectra of d_I (row stride ld),
-// writing the selected plane of K_CARS to d_out (row stride ld_out).
-hipError_t run(Workspace& ws, const Config& cfg, const float* d_I, int64_t M, int64_t ld, const double* h_iref,
-               float* d_out, int64_t ld_out, hipStream_t s, std::string* why);
+// Runs the whole conventional workflow for M spectra of d_I (row stride ld;
+// FP64 when in_f64, else FP32), writing the selected plane of K_CARS to d_out
+// (row stride ld_out; FP64 when out_f64, else FP32).  All arithmetic is FP64.
+hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, int64_t M, int64_t ld,
+               const double* h_iref, void* d_out, bool out_f64, int64_t ld_out, hipStream_t s, std::string* why);
 
 }  // namespace plain
 }  // namespace fkk

@@ -92,13 +92,14 @@ __device__ void hilbert_pair(double2* z, const double2* __restrict__ tw, int L) 
     fft_dif(z, tw, L);
 }
 
-__device__ __forceinline__ double log_ratio64(float x, double iref, double floor) {
-    double q = (double)x / iref;
+__device__ __forceinline__ double log_ratio64(double x, double iref, double floor) {
+    double q = x / iref;
     if (!(q > floor && q < INFINITY)) q = floor;
     return 0.5 * log(q);
 }
 
-__global__ __launch_bounds__(kThreads) void kk_kernel(const float* __restrict__ I, int64_t m0, int64_t nb, int N,
+template <typename TIn>
+__global__ __launch_bounds__(kThreads) void kk_kernel(const TIn* __restrict__ I, int64_t m0, int64_t nb, int N,
                                                       int64_t ld, const double* __restrict__ iref, double floor,
                                                       int L, int bits, int pad_mode, const double2* __restrict__ tw,
                                                       double* __restrict__ ell, double* __restrict__ phi) {
@@ -106,8 +107,8 @@ __global__ __launch_bounds__(kThreads) void kk_kernel(const float* __restrict__ 
     const int64_t ra = m0 + 2 * (int64_t)blockIdx.x, rb = ra + 1;
     const bool hb = 2 * (int64_t)blockIdx.x + 1 < nb;
     const int pl = (L - N) / 2;
-    const float* xa = I + ra * ld;
-    const float* xb = I + rb * ld;
+    const TIn* xa = I + ra * ld;
+    const TIn* xb = I + rb * ld;
     const int64_t la = 2 * (int64_t)blockIdx.x, lb = la + 1;  // batch-local rows
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const int src = i - pl;
@@ -246,12 +247,13 @@ __global__ __launch_bounds__(kThreads) void als_kernel(const double* __restrict_
 // for the window of half width h around i, m_p = sum_x (x/h)^p y(i+x),
 // value = sum_p g_p m_p with g = row 0 of (V^T V)^-1; near the ends the
 // first / last full window is fitted and evaluated at t = (i - centre)/h.
+template <typename TOut>
 __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, int N, int L, int bits, int pad_mode,
                                                        const double2* __restrict__ tw, const double* __restrict__ ell,
                                                        const double* __restrict__ phi,
                                                        const double* __restrict__ err, int sec_mode, int half,
                                                        int order, const double* __restrict__ ginv, int plane,
-                                                       float* __restrict__ out, int64_t ld_out) {
+                                                       TOut* __restrict__ out, int64_t ld_out) {
     extern __shared__ double2 z[];
     __shared__ double part[4][kThreads + 1];
     const int64_t la = 2 * (int64_t)blockIdx.x, lb = la + 1;
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
     for (int s = 0; s < (hb ? 2 : 1); ++s) {
         const double* y = rho + (size_t)s * N;
         const int64_t lrow = la + s;
-        float* orow = out + (m0 + lrow) * ld_out;
+        TOut* orow = out + (m0 + lrow) * ld_out;
         if (sec_mode == 1) {
             double acc = 0.0;
             for (int i = threadIdx.x; i < N; i += blockDim.x) acc += y[i];
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
                 const double r = y[i] - mean;
                 const double ph = phi[lrow * N + i] - err[lrow * N + i];
                 const double mag = exp(r);
-                orow[i] = (float)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
+                orow[i] = (TOut)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
             }
             __syncthreads();
             continue;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
             const double r = y[i] - val;
             const double ph = phi[lrow * N + i] - err[lrow * N + i];
             const double mag = exp(r);
-            orow[i] = (float)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
+            orow[i] = (TOut)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
         }
         __syncthreads();
     }
@@ -398,8 +400,8 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
 
 }  // namespace
 
-hipError_t run(Workspace& ws, const Config& cfg, const float* d_I, int64_t M, int64_t ld, const double* h_iref,
-               float* d_out, int64_t ld_out, hipStream_t s, std::string* why) {
+hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, int64_t M, int64_t ld,
+               const double* h_iref, void* d_out, bool out_f64, int64_t ld_out, hipStream_t s, std::string* why) {
     const int N = cfg.N, L = cfg.len;
     int bits = 0;
     while ((1 << bits) < L) ++bits;
@@ -508,23 +510,43 @@ hipError_t run(Workspace& ws, const Config& cfg, const float* d_I, int64_t M, in
         if (why) *why = "spectrum too long for the LDS-resident transform";
         return hipErrorInvalidValue;
     }
-    hipFuncSetAttribute(reinterpret_cast<const void*>(kk_kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(sec_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+    if (in_f64)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kk_kernel<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    else
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kk_kernel<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (out_f64)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(sec_kernel<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    else
+        hipFuncSetAttribute(reinterpret_cast<const void*>(sec_kernel<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int iters = (cfg.detrend == 1) ? 1 : cfg.iters;
     const double p = (cfg.detrend == 1) ? 0.5 : cfg.p;
     for (int64_t m0 = 0; m0 < M; m0 += batch) {
         const int64_t nb = std::min(batch, M - m0);
         const unsigned pairs = (unsigned)((nb + 1) / 2);
-        hipLaunchKernelGGL(kk_kernel, dim3(pairs), dim3(kThreads), lds, s, d_I, m0, nb, N, ld, d_iref, cfg.floor, L,
-                           bits, cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi);
+        if (in_f64)
+            hipLaunchKernelGGL(kk_kernel<double>, dim3(pairs), dim3(kThreads), lds, s,
+                               static_cast<const double*>(d_I), m0, nb, N, ld, d_iref, cfg.floor, L, bits,
+                               cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi);
+        else
+            hipLaunchKernelGGL(kk_kernel<float>, dim3(pairs), dim3(kThreads), lds, s, static_cast<const float*>(d_I),
+                               m0, nb, N, ld, d_iref, cfg.floor, L, bits, cfg.pad_mode,
+                               reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(als_kernel, dim3((unsigned)((nb + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, ws.phi,
                            ws.err, nb, N, cfg.lam, p, iters, ws.scratch);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(sec_kernel, dim3(pairs), dim3(kThreads), lds, s, m0, nb, N, L, bits, cfg.pad_mode,
-                           reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi, ws.err, cfg.sec_mode, half,
-                           cfg.order, d_ginv, cfg.plane, d_out, ld_out);
+        if (out_f64)
+            hipLaunchKernelGGL(sec_kernel<double>, dim3(pairs), dim3(kThreads), lds, s, m0, nb, N, L, bits,
+                               cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi, ws.err,
+                               cfg.sec_mode, half, cfg.order, d_ginv, cfg.plane, static_cast<double*>(d_out), ld_out);
+        else
+            hipLaunchKernelGGL(sec_kernel<float>, dim3(pairs), dim3(kThreads), lds, s, m0, nb, N, L, bits,
+                               cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi, ws.err,
+                               cfg.sec_mode, half, cfg.order, d_ginv, cfg.plane, static_cast<float*>(d_out), ld_out);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -345,6 +345,53 @@ def test_plain_path_als_matches_oracle(ctx):
     assert np.mean(e < TOL) >= 0.999, (np.sort(e)[-5:])
 
 
+# --------------------------------------------------------------------------
+# The FP64 workload: 64 x 64 = 4,096 spectra x 512 points, 8 Lorentzians per
+# pixel, AWGN at SNR 50.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def pixel64():
+    return synth.pixel_cube(side=64, n=512)
+
+
+@pytest.mark.parametrize("detrend", [op.DETREND_WHITTAKER, op.DETREND_ALS])
+def test_plain_fp64_io_matches_oracle(ctx, pixel64, detrend):
+    # FP64 in and out, FP64 arithmetic on both sides.  Whittaker: agreement
+    # to rounding.  ALS: its systems diag(w) + lam D^T D have condition
+    # numbers up to ~16 lam / p ~ 1e8 (lam = 1e5 (N/1000)^4, p = 1e-3), so two
+    # correct FP64 solvers (LDL^T recurrence here, banded Cholesky in the
+    # oracle) agree to ~1e-8; spectra where a weight (a comparison y > z)
+    # falls the other way at a point where the two are equal to rounding are
+    # held to the FP32 bar
+    say(f"plain fp64 4096 x 512 detrend={detrend}")
+    cube = pixel64
+    p = wf.Params(k=20, detrend=detrend)
+    out = ctx.plain(dev(cube.i_cars, np.float64), cube.i_ref, lib_params(p))
+    assert out.dtype == torch.float64
+    e = spectrum_err(host(out), wf.plain(cube.i_cars, cube.i_ref, p)["im"])
+    say(f"plain fp64: max {e.max():.2e}, fraction within 1e-10 {np.mean(e < 1e-10):.4f}, 1e-7 {np.mean(e < 1e-7):.4f}")
+    if detrend == op.DETREND_WHITTAKER:
+        assert e.max() < 1e-10
+    else:
+        assert np.mean(e < 1e-7) >= 0.999 and e.max() < TOL
+
+
+@pytest.mark.parametrize("gram_prec", [0, 2])
+def test_fit_pixel64_matches_fp64_oracle(ctx, pixel64, gram_prec):
+    # the oracle fits the FP64 data, the device its FP32 rounding (which
+    # moves the oracle's own result by 6e-7)
+    say(f"fit 4096 x 512 vs fp64 oracle gram_prec={gram_prec}")
+    cube = pixel64
+    p = wf.Params(k=20)
+    ref = wf.fit(cube.i_cars, cube.i_ref, p)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p, gram_prec=gram_prec))
+    err = spectrum_err(host(out), ref["im"])
+    say(f"fit pixel64: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    np.testing.assert_array_equal(np.sort(b.export()["q"]), np.sort(ref["basis"]["q"]))
+    assert err.max() < TOL
+
+
 def test_plain_path_pad_zero_and_other_planes(ctx):
     say("plain pad zero / planes")
     cube = tissue(rows=9, cols=9, n=100, key=8)
