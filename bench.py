@@ -207,6 +207,8 @@ def fit_steps(ctx, I, i_ref, p, steps, warmup, out, torch, tag):
 
 
 def time_transform(ctx, b, frames, fout, I, out, n_frames, torch):
+    """Device-resident stored-basis transforms: the frames back to back (each
+    frame once), then the full cube."""
     for _ in range(3):
         ctx.transform(b, frames[0], out=fout)
     torch.cuda.synchronize()
@@ -231,7 +233,33 @@ def time_transform(ctx, b, frames, fout, I, out, n_frames, torch):
             "HBM_frac_full_cube": 8.0 * m * n / (full_ms * 1e-3) / PEAK_HBM}
 
 
-def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, args, m, n, npad, kq, gram_flop, recon_stats):
+def host_streamed(fk, torch, basis, host_frames):
+    """Frames from pinned host memory through the serving runtime (copy in,
+    transform, copy out overlapped on three streams), wall clock from the
+    first submission to the last result in host memory."""
+    nf, rows, n = host_frames.shape
+    # results go to a ring of 16 pinned buffers; at most 8 frames are in
+    # flight and they complete in order, so a buffer is free when reused
+    outs = torch.empty((16, rows, n), dtype=torch.float32, pin_memory=True)
+    srv = fk.Server(0, hbm_budget_bytes=8 << 30, max_inflight=8, max_batch_rows=rows)
+    bid = srv.add_basis(basis)
+    srv.submit(bid, host_frames[0], outs[0])  # warm-up
+    srv.drain()
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    for i in range(nf):
+        srv.submit(bid, host_frames[i], outs[i % 16])
+    srv.drain()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {"frames": nf, "frames_per_s": nf / wall, "spectra_per_s": nf * rows / wall,
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "note": "pinned host frames -> device -> host, copies included (PCIe)"}
+
+
+def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n, npad, kq, gram_flop,
+             recon_stats):
     """The fit and the transforms with BF16 matrix-core operands."""
     log("BF16 fit and transforms")
     p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
@@ -247,6 +275,8 @@ def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, args, m, n, npad, kq, g
                               "GB/s": (4.0 * m * n + 2.0 * m * npad) / (stage16["dev_ms_logratio"] * 1e-3) / 1e9},
             "reconstruction": recon_stats(stage16["dev_ms_recon"], kq, 2),
             "transform": time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)}
+    b16.precision = fk.PREC_BF16
+    bf16["transform"]["host_streamed"] = host_streamed(fk, torch, b16, host_frames)
     log(f"bf16 fit: {ms16:.2f} ms/step; transform {bf16['transform']['spectra_per_s_full_cube']:.3e}/s")
     b16.free()
     return bf16
@@ -260,7 +290,7 @@ def main():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
-    ap.add_argument("--frames", type=int, default=20)
+    ap.add_argument("--frames", type=int, default=50)
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-bf16", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -315,11 +345,18 @@ def main():
 
     recon = recon_stats(stage["dev_ms_recon"], kp, 4)
 
-    # stored-basis transform on 256 x 256 x 1000 frames (new maps and noise)
-    log("stored-basis transform frames")
-    frames = [torch.from_numpy(synth.frame(i).i_cars).to(dev) for i in range(2)]
+    # stored-basis stream: args.frames new 256 x 256 x 1000 frames (same
+    # components, new abundance maps and noise), each transformed once
+    log(f"stored-basis stream: generating {args.frames} frames")
+    t0 = time.perf_counter()
+    host_frames = torch.empty((args.frames, 65536, n), dtype=torch.float32, pin_memory=True)
+    for i in range(args.frames):
+        host_frames[i].copy_(torch.from_numpy(synth.frame(i).i_cars))
+    log(f"frames ready in {time.perf_counter() - t0:.1f} s")
+    frames = [host_frames[i].to(dev) for i in range(args.frames)]
     fout = torch.empty_like(frames[0])
     transform = time_transform(ctx, b, frames, fout, I, out, args.frames, torch)
+    transform["host_streamed"] = host_streamed(fk, torch, b, host_frames)
 
     # the same fit with the FP64 Gram (products and sums in FP64)
     log("fit with the FP64 Gram")
@@ -334,8 +371,9 @@ def main():
     # the same fit and transforms with BF16 matrix-core operands
     bf16 = None
     if not args.skip_bf16:
-        bf16 = bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, args, m, n, npad, kq, gram_flop, recon_stats)
-    del frames, fout
+        bf16 = bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n, npad, kq, gram_flop,
+                        recon_stats)
+    del frames, fout, host_frames
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
