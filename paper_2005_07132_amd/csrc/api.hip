@@ -231,10 +231,16 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
         else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
         for (int j = 0; j < N; ++j) wt[(size_t)c * np + j] = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
     }
+    // FP32 B^T in the kernels' group order; the BF16 copies below keep the
+    // natural order
+    std::vector<float> bre_nat((size_t)np * kp, 0.f), bim_nat((size_t)np * kp, 0.f);
     for (int j = 0; j < N; ++j)
         for (int c = 0; c < k; ++c) {
-            bre[(size_t)j * kp + c] = (float)b->b_re[(size_t)c * N + j];
-            bim[(size_t)j * kp + c] = (float)b->b_im[(size_t)c * N + j];
+            const float re = (float)b->b_re[(size_t)c * N + j], im = (float)b->b_im[(size_t)c * N + j];
+            bre[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = re;
+            bim[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = im;
+            bre_nat[(size_t)j * kp + c] = re;
+            bim_nat[(size_t)j * kp + c] = im;
         }
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     auto alloc_copy = [&](float** dst, const std::vector<float>& src) -> hipError_t {
@@ -255,8 +261,8 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
         for (int j = 0; j < np; ++j) wt16[(size_t)c * np + j] = to_bf16(wt[(size_t)c * np + j]);
     for (int j = 0; j < np; ++j)
         for (int c = 0; c < kp; ++c) {
-            bre16[(size_t)j * kq + c] = to_bf16(bre[(size_t)j * kp + c]);
-            bim16[(size_t)j * kq + c] = to_bf16(bim[(size_t)j * kp + c]);
+            bre16[(size_t)j * kq + c] = to_bf16(bre_nat[(size_t)j * kp + c]);
+            bim16[(size_t)j * kq + c] = to_bf16(bim_nat[(size_t)j * kp + c]);
         }
     auto alloc_copy16 = [&](uint16_t** dst, const std::vector<uint16_t>& src) -> hipError_t {
         if (!*dst) {
@@ -779,7 +785,8 @@ fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int
                                                   ctx->stream));
     else
         FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
-                                                b->kp, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM, ctx->stream));
+                                                b->kp, b->k, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM,
+                                                ctx->stream));
     return FKK_OK;
 }
 

@@ -62,15 +62,18 @@ hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const fl
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
                                 long long* qmin, hipStream_t s);
 
-// Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im); BT holds
-// [B_re^T | B_im^T] as two (ldb_rows x kp) blocks (rows = wavenumbers).
+// Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im); BreT / BimT are
+// (rows = wavenumbers) x kp with the vectors in kgroup_pos order.
 hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, const float* BreT,
                               const float* BimT, int kp, int N, float* out, int64_t ld_out, int plane,
                               hipStream_t s);
 
 // Fused stored-basis transform: projection onto Wt then reconstruction.
+// B^T (FP32) holds the basis vectors of each group of 16 in the order
+// 0,4,8,12,1,5,9,13,2,... (kgroup_pos); Z and W keep the natural order.
+inline int kgroup_pos(int c) { return (c & ~15) + 4 * (c & 3) + ((c & 15) >> 2); }
 hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                            const float* Wt, int ldw, int kp, const float* BreT, const float* BimT,
+                            const float* Wt, int ldw, int kp, int k, const float* BreT, const float* BimT,
                             float* out, int64_t ld_out, int plane, hipStream_t s);
 
 // ---- BF16 operands, FP32 accumulation -------------------------------------

@@ -554,11 +554,35 @@ hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long lo
 // Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im).
 // The product is formed transposed (A = B^T, B = Z^T) so that every lane
 // ends with four consecutive wavenumbers of one spectrum: one 128-bit store.
+// Within each group of 16 basis vectors, lane group g = lane/16 holds the
+// values of vectors 4q + g (q = 0..3) contiguously (B^T is stored with the
+// 4 x 4 transposed order, see kgroup_pos), so matrix-core step q covers the
+// consecutive vectors 4q..4q+3 and the steps past k are skipped.
 // ===========================================================================
 constexpr int RR = 128;  // rows per block (4 waves x 32)
 constexpr int RCN = 64;  // wavenumbers per chunk
 
-template <int KB>
+// Matrix-core steps q < Q of basis group kg (vectors 16 kg + 4q .. +3).
+template <int KB, int Q>
+__device__ __forceinline__ void recon_group(const float4 (&zf)[2][KB], const float* sRe, const float* sIm, int bld,
+                                            int lane, int kg, floatx4 (&are)[4][2], floatx4 (&aim)[4][2]) {
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+        const int off = (ib * 16 + (lane & 15)) * bld + kg * 16 + 4 * (lane >> 4);
+        const float4 bre = *reinterpret_cast<const float4*>(sRe + off);
+        const float4 bim = *reinterpret_cast<const float4*>(sIm + off);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                are[ib][jb] = mfma4(f4get(bre, q), f4get(zf[jb][kg], q), are[ib][jb]);
+                aim[ib][jb] = mfma4(f4get(bim, q), f4get(zf[jb][kg], q), aim[ib][jb]);
+            }
+    }
+}
+
+// QL: steps of the last group that hold vectors below k (1..4).
+template <int KB, int QL>
 __device__ __forceinline__ void recon_chunk(const float4 (&zf)[2][KB], const float* sRe, const float* sIm, int bld,
                                             int lane, floatx4 (&are)[4][2], floatx4 (&aim)[4][2]) {
 #pragma unroll
@@ -569,37 +593,11 @@ __device__ __forceinline__ void recon_chunk(const float4 (&zf)[2][KB], const flo
             aim[ib][jb] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-    for (int kg = 0; kg < KB; ++kg)
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            const int off = (ib * 16 + (lane & 15)) * bld + kg * 16 + 4 * (lane >> 4);
-            const float4 bre = *reinterpret_cast<const float4*>(sRe + off);
-            const float4 bim = *reinterpret_cast<const float4*>(sIm + off);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int jb = 0; jb < 2; ++jb) {
-                    are[ib][jb] = mfma4(f4get(bre, q), f4get(zf[jb][kg], q), are[ib][jb]);
-                    aim[ib][jb] = mfma4(f4get(bim, q), f4get(zf[jb][kg], q), aim[ib][jb]);
-                }
-        }
+    for (int kg = 0; kg + 1 < KB; ++kg) recon_group<KB, 4>(zf, sRe, sIm, bld, lane, kg, are, aim);
+    recon_group<KB, QL>(zf, sRe, sIm, bld, lane, KB - 1, are, aim);
 }
 
-template <int KB>
-__device__ __forceinline__ void stage_basis_chunk(float* sRe, float* sIm, int bld, const float* __restrict__ BreT,
-                                                  const float* __restrict__ BimT, int j0) {
-    constexpr int KP = KB * 16;
-    constexpr int PER_ROW = KP / 4;  // float4 per row
-    constexpr int TOTAL = RCN * PER_ROW;
-    for (int idx = threadIdx.x; idx < TOTAL; idx += 256) {
-        const int jr = idx / PER_ROW, c4 = (idx % PER_ROW) * 4;
-        const size_t src = (size_t)(j0 + jr) * KP + c4;
-        *reinterpret_cast<float4*>(sRe + jr * bld + c4) = *reinterpret_cast<const float4*>(BreT + src);
-        *reinterpret_cast<float4*>(sIm + jr * bld + c4) = *reinterpret_cast<const float4*>(BimT + src);
-    }
-}
-
-template <int KB, bool VEC_OUT>
+template <int KB, int QL, bool VEC_OUT>
 __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
                                                     const float* __restrict__ BreT, const float* __restrict__ BimT,
                                                     int N, float* __restrict__ out, int64_t ld_out, int plane) {
@@ -616,10 +614,10 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z,
 #pragma unroll
         for (int kg = 0; kg < KB; ++kg) {
             const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
-            const int c = kg * 16 + 4 * (lane >> 4);
+            const int c = kg * 16 + (lane >> 4);  // vectors c + 4q
             float v[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (row < M && c + q < k) ? Z[row * ld_z + c + q] : 0.f;
+            for (int q = 0; q < 4; ++q) v[q] = (row < M && c + 4 * q < k) ? Z[row * ld_z + c + 4 * q] : 0.f;
             zf[jb][kg] = make_float4(v[0], v[1], v[2], v[3]);
         }
 
@@ -651,7 +649,7 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z,
             nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
             nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
         }
-        recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
+        recon_chunk<KB, QL>(zf, sRe, sIm, BLD, lane, are, aim);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < KB; ++p) {
@@ -668,12 +666,17 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z,
 template <int KB>
 static hipError_t recon_dispatch(bool vec, dim3 grid, hipStream_t s, const float* Z, int64_t M, int64_t ld_z, int k,
                                  const float* BreT, const float* BimT, int N, float* out, int64_t ld_out, int plane) {
-    if (vec)
-        hipLaunchKernelGGL((recon_kernel<KB, true>), grid, dim3(256), 0, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out,
-                           plane);
-    else
-        hipLaunchKernelGGL((recon_kernel<KB, false>), grid, dim3(256), 0, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out,
-                           plane);
+    // steps of the last basis group below k; the unaligned-output variant
+    // runs all four (the padded vectors are zero)
+    const int ql = ((k - 1 - 16 * (KB - 1)) >> 2) + 1;
+#define FKK_RC(Q, V) \
+    hipLaunchKernelGGL((recon_kernel<KB, Q, V>), grid, dim3(256), 0, s, Z, M, ld_z, k, BreT, BimT, N, out, ld_out, plane)
+    if (!vec) FKK_RC(4, false);
+    else if (ql == 1) FKK_RC(1, true);
+    else if (ql == 2) FKK_RC(2, true);
+    else if (ql == 3) FKK_RC(3, true);
+    else FKK_RC(4, true);
+#undef FKK_RC
     return hipGetLastError();
 }
 
@@ -695,13 +698,13 @@ hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, co
 // (Z tile kept in LDS) and reconstructs them; I is read once, out written
 // once.
 // ===========================================================================
-template <int KB, bool VEC_IN, bool VEC_OUT>
+template <int KB, int QL, bool VEC_IN, bool VEC_OUT>
 __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                         const float* __restrict__ rinv, float floor,
                                                         const float* __restrict__ Wt, int ldw,
                                                         const float* __restrict__ BreT,
-                                                        const float* __restrict__ BimT, float* __restrict__ out,
-                                                        int64_t ld_out, int plane) {
+                                                        const float* __restrict__ BimT, int k,
+                                                        float* __restrict__ out, int64_t ld_out, int plane) {
     constexpr int KP = KB * 16;
     constexpr int BLD = KP + 4;
     constexpr int P1 = PR * PLD + KP * PLD;             // projection phase
@@ -737,7 +740,8 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
-                sZ[row * BLD + cb * 16 + (lane & 15)] = acc[rb][cb][v];
+                const int kk = lane & 15;  // vector 16 cb + kk at position 4 (kk % 4) + kk / 4
+                sZ[row * BLD + cb * 16 + 4 * (kk & 3) + (kk >> 2)] = acc[rb][cb][v];
             }
     __syncthreads();
     float4 zf[2][KB];
@@ -776,7 +780,7 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
             nre[p] = *reinterpret_cast<const floatx4*>(BreT + src);
             nim[p] = *reinterpret_cast<const floatx4*>(BimT + src);
         }
-        recon_chunk<KB>(zf, sRe, sIm, BLD, lane, are, aim);
+        recon_chunk<KB, QL>(zf, sRe, sIm, BLD, lane, are, aim);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < KB; ++p) {
@@ -793,29 +797,35 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
 template <int KB>
 static hipError_t transform_dispatch(bool vin, bool vout, dim3 grid, hipStream_t s, const float* I, int64_t M, int N,
                                      int64_t ld, const float* rinv, float floor, const float* Wt, int ldw,
-                                     const float* BreT, const float* BimT, float* out, int64_t ld_out, int plane) {
-#define FKK_TR(a, b)                                                                                              \
-    hipLaunchKernelGGL((transform_kernel<KB, a, b>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, \
-                       BimT, out, ld_out, plane)
-    if (vin && vout) FKK_TR(true, true);
-    else if (vin) FKK_TR(true, false);
-    else if (vout) FKK_TR(false, true);
-    else FKK_TR(false, false);
+                                     const float* BreT, const float* BimT, int k, float* out, int64_t ld_out,
+                                     int plane) {
+    const int ql = ((k - 1 - 16 * (KB - 1)) >> 2) + 1;  // as in recon_dispatch
+#define FKK_TR(Q, a, b)                                                                                              \
+    hipLaunchKernelGGL((transform_kernel<KB, Q, a, b>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,   \
+                       BreT, BimT, k, out, ld_out, plane)
+    if (vin && vout) {
+        if (ql == 1) FKK_TR(1, true, true);
+        else if (ql == 2) FKK_TR(2, true, true);
+        else if (ql == 3) FKK_TR(3, true, true);
+        else FKK_TR(4, true, true);
+    } else if (vin) FKK_TR(4, true, false);
+    else if (vout) FKK_TR(4, false, true);
+    else FKK_TR(4, false, false);
 #undef FKK_TR
     return hipGetLastError();
 }
 
 hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                            const float* Wt, int ldw, int kp, const float* BreT, const float* BimT, float* out,
+                            const float* Wt, int ldw, int kp, int k, const float* BreT, const float* BimT, float* out,
                             int64_t ld_out, int plane, hipStream_t s) {
     const bool vin = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
     const bool vout = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
     dim3 grid((unsigned)proj_blocks(M));
     switch (kp) {
-        case 16: return transform_dispatch<1>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
-        case 32: return transform_dispatch<2>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
-        case 64: return transform_dispatch<4>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
-        case 128: return transform_dispatch<8>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, out, ld_out, plane);
+        case 16: return transform_dispatch<1>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
+        case 32: return transform_dispatch<2>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
+        case 64: return transform_dispatch<4>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
+        case 128: return transform_dispatch<8>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
         default: return hipErrorInvalidValue;
     }
 }

@@ -164,7 +164,7 @@ bool fkk_server::issue(std::vector<Request>& reqs) {
                                          b->d_bre16, b->d_bim16, dout, n, FKK_OUT_IM, s_comp));
     else
         chk(fkk::dev::launch_transform(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
-                                       b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp));
+                                       b->k, b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp));
     chk(hipEventRecord(bt.computed, s_comp));
     chk(hipStreamWaitEvent(s_out, bt.computed, 0));
     r0 = 0;
