@@ -120,6 +120,7 @@ struct fkk_ctx {
     DevBuf<float> pmaxv, pminv;
     DevBuf<long long> pmaxi, pmini, qext, qdev;
     PinnedBuf<double> hG;
+    PinnedBuf<double> hstage;  // basis uploads
     fkk::plain::Workspace plain_ws;
     hipEvent_t ev[10] = {};
     // The n - 1 launches of the tridiagonalisation, recorded once per order
@@ -216,69 +217,82 @@ fkk_status check_iref(fkk_ctx* ctx, const double* h_iref, int N) {
     return FKK_OK;
 }
 
-// Device copies of a basis: 1/I_ref, the projection weights and the
-// corrected bases (transposed, zero padded to kp columns and npad rows).
+// Device copies of a basis: 1/I_ref (two floats per wavenumber), the
+// projection weights W^T (kp x npad), B_re^T and B_im^T (npad x kp, vectors
+// in the kernels' group order) and BF16 copies of the three (natural order,
+// k padded to kq).  All live in one device allocation, assembled in the
+// context's pinned staging buffer and sent with one copy.
 fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
-    const int N = b->N, k = b->k, kp = b->kp, np = b->npad;
-    std::vector<float> rinv(2 * (size_t)N), wt((size_t)kp * np, 0.f), bre((size_t)np * kp, 0.f),
-        bim((size_t)np * kp, 0.f);
-    split_reciprocal(b->i_ref.data(), N, rinv.data());
+    const int N = b->N, k = b->k, kp = b->kp, np = b->npad, kq = b->kq;
+    auto al = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
+    const size_t o_rinv = 0;
+    const size_t o_wt = o_rinv + al(2 * (size_t)N * 4);
+    const size_t o_bre = o_wt + al((size_t)kp * np * 4);
+    const size_t o_bim = o_bre + al((size_t)np * kp * 4);
+    const size_t o_wt16 = o_bim + al((size_t)np * kp * 4);
+    const size_t o_bre16 = o_wt16 + al((size_t)kq * np * 2);
+    const size_t o_bim16 = o_bre16 + al((size_t)np * kq * 2);
+    const size_t total = o_bim16 + al((size_t)np * kq * 2);
+    FKK_HIP(ctx, ctx->hstage.ensure((total + 7) / 8));  // doubles
+    unsigned char* h = reinterpret_cast<unsigned char*>(ctx->hstage.p);
+    std::memset(h, 0, total);
+    float* rinv = reinterpret_cast<float*>(h + o_rinv);
+    float* wt = reinterpret_cast<float*>(h + o_wt);
+    float* bre = reinterpret_cast<float*>(h + o_bre);
+    float* bim = reinterpret_cast<float*>(h + o_bim);
+    uint16_t* wt16 = reinterpret_cast<uint16_t*>(h + o_wt16);
+    uint16_t* bre16 = reinterpret_cast<uint16_t*>(h + o_bre16);
+    uint16_t* bim16 = reinterpret_cast<uint16_t*>(h + o_bim16);
+    split_reciprocal(b->i_ref.data(), N, rinv);
     double smax = 0.0;
     for (int c = 0; c < k; ++c) smax = std::max(smax, b->s[c]);
     for (int c = 0; c < k; ++c) {
         double shrink;
         if (shrink_lambda > 0.0) shrink = b->s[c] * b->s[c] / (b->s[c] * b->s[c] + shrink_lambda);
         else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
-        for (int j = 0; j < N; ++j) wt[(size_t)c * np + j] = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
+        for (int j = 0; j < N; ++j) {
+            const float w = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
+            wt[(size_t)c * np + j] = w;
+            wt16[(size_t)c * np + j] = to_bf16(w);
+        }
     }
-    // FP32 B^T in the kernels' group order; the BF16 copies below keep the
-    // natural order
-    std::vector<float> bre_nat((size_t)np * kp, 0.f), bim_nat((size_t)np * kp, 0.f);
     for (int j = 0; j < N; ++j)
         for (int c = 0; c < k; ++c) {
             const float re = (float)b->b_re[(size_t)c * N + j], im = (float)b->b_im[(size_t)c * N + j];
             bre[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = re;
             bim[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = im;
-            bre_nat[(size_t)j * kp + c] = re;
-            bim_nat[(size_t)j * kp + c] = im;
+            bre16[(size_t)j * kq + c] = to_bf16(re);
+            bim16[(size_t)j * kq + c] = to_bf16(im);
         }
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    auto alloc_copy = [&](float** dst, const std::vector<float>& src) -> hipError_t {
-        if (!*dst) {
-            hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(float));
-            if (e != hipSuccess) return e;
-        }
-        return hipMemcpy(*dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice);
-    };
-    FKK_HIP(ctx, alloc_copy(&b->d_rinv, rinv));
-    FKK_HIP(ctx, alloc_copy(&b->d_wt, wt));
-    FKK_HIP(ctx, alloc_copy(&b->d_bre_t, bre));
-    FKK_HIP(ctx, alloc_copy(&b->d_bim_t, bim));
-    // BF16 copies, k padded to kq columns (rows of W^T)
-    const int kq = b->kq;
-    std::vector<uint16_t> wt16((size_t)kq * np, 0), bre16((size_t)np * kq, 0), bim16((size_t)np * kq, 0);
-    for (int c = 0; c < kp; ++c)
-        for (int j = 0; j < np; ++j) wt16[(size_t)c * np + j] = to_bf16(wt[(size_t)c * np + j]);
-    for (int j = 0; j < np; ++j)
-        for (int c = 0; c < kp; ++c) {
-            bre16[(size_t)j * kq + c] = to_bf16(bre_nat[(size_t)j * kp + c]);
-            bim16[(size_t)j * kq + c] = to_bf16(bim_nat[(size_t)j * kp + c]);
-        }
-    auto alloc_copy16 = [&](uint16_t** dst, const std::vector<uint16_t>& src) -> hipError_t {
-        if (!*dst) {
-            hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(uint16_t));
-            if (e != hipSuccess) return e;
-        }
-        return hipMemcpy(*dst, src.data(), src.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
-    };
-    FKK_HIP(ctx, alloc_copy16(&b->d_wt16, wt16));
-    FKK_HIP(ctx, alloc_copy16(&b->d_bre16, bre16));
-    FKK_HIP(ctx, alloc_copy16(&b->d_bim16, bim16));
+    if (!b->d_arena) FKK_HIP(ctx, hipMalloc(&b->d_arena, total));
+    unsigned char* d = reinterpret_cast<unsigned char*>(b->d_arena);
+    FKK_HIP(ctx, hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, ctx->stream));
+    FKK_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer is reused
+    b->d_rinv = reinterpret_cast<float*>(d + o_rinv);
+    b->d_wt = reinterpret_cast<float*>(d + o_wt);
+    b->d_bre_t = reinterpret_cast<float*>(d + o_bre);
+    b->d_bim_t = reinterpret_cast<float*>(d + o_bim);
+    b->d_wt16 = reinterpret_cast<uint16_t*>(d + o_wt16);
+    b->d_bre16 = reinterpret_cast<uint16_t*>(d + o_bre16);
+    b->d_bim16 = reinterpret_cast<uint16_t*>(d + o_bim16);
     b->device = ctx->device;
     return FKK_OK;
 }
 
-// fKK, fPEC and fSEC on the basis vectors (Eq. 7, 11, 16-18, 21-23), FP64.
+// fKK on the basis vectors (Eq. 7, 11): H_V = H{V^T / f}, FP64.  Needs only
+// V and f, so the fit runs it while the projection is on the device.
+void basis_fkk(fkk_basis* b, const fkk_params* p) {
+    const int N = b->N, k = b->k;
+    const int len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
+    std::vector<double> vt_f((size_t)k * N);
+    for (int c = 0; c < k; ++c)
+        for (int j = 0; j < N; ++j) vt_f[(size_t)c * N + j] = b->v[(size_t)j * k + c] / b->f[j];
+    b->h_v.assign((size_t)k * N, 0.0);
+    fkk::hilbert_rows(vt_f.data(), b->h_v.data(), k, N, len, p->pad_mode);
+}
+
+// fPEC and fSEC on the basis vectors (Eq. 16-18, 21-23), FP64, after basis_fkk.
 void basis_math(fkk_basis* b, const double* X, int n_q, const fkk_params* p) {
     const int N = b->N, k = b->k;
     const int len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
@@ -287,8 +301,6 @@ void basis_math(fkk_basis* b, const double* X, int n_q, const fkk_params* p) {
     std::vector<double> vt_f((size_t)k * N);
     for (int c = 0; c < k; ++c)
         for (int j = 0; j < N; ++j) vt_f[(size_t)c * N + j] = b->v[(size_t)j * k + c] / b->f[j];
-    b->h_v.assign((size_t)k * N, 0.0);
-    fkk::hilbert_rows(vt_f.data(), b->h_v.data(), k, N, len, p->pad_mode);
     // Phi_raw = X H{V^T/f}; Phi_err = D{Phi_raw} row by row
     std::vector<double> raw((size_t)n_q * N, 0.0), err((size_t)n_q * N);
     fkk::parallel_rows(n_q, [&](int r0, int r1) {
@@ -535,6 +547,7 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     ctx->qext.release();
     ctx->qdev.release();
     ctx->hG.release();
+    ctx->hstage.release();
     ctx->plain_ws.release();
     for (auto& e : ctx->ev)
         if (e) hipEventDestroy(e);
@@ -583,6 +596,7 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
     if (p->k != k) return c->fail(FKK_EINVAL, "params.k != k");
     fkk_basis* b = new_basis(N, k, h_iref, h_f, h_s, h_v, p->ml_lambda, p->ratio_floor);
     b->prec = p->recon_prec;
+    basis_fkk(b, p);
     basis_math(b, h_x, n_q, p);
     if (ctx) {
         if ((st = upload_basis(ctx, b, p->ml_lambda)) != FKK_OK) {
@@ -687,6 +701,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     if (perr != hipSuccess || hipEventRecord(ctx->ev[3], s) != hipSuccess ||
         fkk::dev::launch_argext_reduce(part, nblk, ka, k, ctx->qext.p, ctx->qext.p + ka, s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));
+    basis_fkk(b, p);  // host FP64 while the projection runs
     std::vector<long long> qe(2 * (size_t)ka);
     if (hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

@@ -18,21 +18,16 @@ struct fkk_basis {
     std::vector<double> i_ref, f, s, v, b_re, b_im, phi_pec_t, v_sec_t, h_v;
     std::vector<int64_t> q;
     double ml_lambda = 0.0, ratio_floor = 1e-6, ridge_lambda = 0.0;
-    float* d_rinv = nullptr;
-    float* d_wt = nullptr;      // kp x npad: f(j) V(j,c) shrink(c)
-    float* d_bre_t = nullptr;   // npad x kp
-    float* d_bim_t = nullptr;   // npad x kp
+    void* d_arena = nullptr;     // one allocation holding the arrays below
+    float* d_rinv = nullptr;     // 2N: 1/I_ref as hi, lo floats
+    float* d_wt = nullptr;       // kp x npad: f(j) V(j,c) shrink(c)
+    float* d_bre_t = nullptr;    // npad x kp, vectors in group order
+    float* d_bim_t = nullptr;    // npad x kp
     uint16_t* d_wt16 = nullptr;  // kq x npad, BF16 of d_wt
-    uint16_t* d_bre16 = nullptr; // npad x kq, BF16 of d_bre_t
+    uint16_t* d_bre16 = nullptr; // npad x kq, BF16, natural order
     uint16_t* d_bim16 = nullptr; // npad x kq
     ~fkk_basis() {
-        if (d_wt16) hipFree(d_wt16);
-        if (d_bre16) hipFree(d_bre16);
-        if (d_bim16) hipFree(d_bim16);
-        if (d_rinv) hipFree(d_rinv);
-        if (d_wt) hipFree(d_wt);
-        if (d_bre_t) hipFree(d_bre_t);
-        if (d_bim_t) hipFree(d_bim_t);
+        if (d_arena) hipFree(d_arena);
     }
 };
 
