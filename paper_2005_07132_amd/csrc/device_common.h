@@ -71,54 +71,84 @@ __device__ __forceinline__ void sincos_fast(float x, float* sn, float* cs) {
 }
 
 
-// Output plane of K = exp(re) exp(i im) (Eq. 23): Im, Re or |K|.
-__device__ __forceinline__ float epilogue(float re, float im, int plane) {
+// Output plane PLANE of K = exp(re) exp(i im) (Eq. 23): 0 Im, 1 Re, 2 |K|.
+template <int PLANE>
+__device__ __forceinline__ float epilogue(float re, float im) {
     const float mag = exp_fast(re);
-    if (plane == 2) return mag;
+    if (PLANE == 2) return mag;
     float sn, cs;
     sincos_fast(im, &sn, &cs);
-    return mag * (plane == 0 ? sn : cs);
+    return mag * (PLANE == 0 ? sn : cs);
 }
 
 // Same with the hardware sine / cosine (v_sin_f32 / v_cos_f32 take the
 // angle in revolutions; the fraction of a revolution keeps the argument in
 // [-1/2, 1/2]).  Absolute error of order 1e-6: used where the operands are
 // BF16 and contribute far more.
-__device__ __forceinline__ float epilogue_hw(float re, float im, int plane) {
+template <int PLANE>
+__device__ __forceinline__ float epilogue_hw(float re, float im) {
     const float mag = exp_fast(re);
-    if (plane == 2) return mag;
+    if (PLANE == 2) return mag;
     float t = im * 0.159154943091895336f;
     t -= rintf(t);
-    return mag * (plane == 0 ? __builtin_amdgcn_sinf(t) : __builtin_amdgcn_cosf(t));
+    return mag * (PLANE == 0 ? __builtin_amdgcn_sinf(t) : __builtin_amdgcn_cosf(t));
 }
 
 // Epilogue of a 128-spectrum reconstruction tile: lane l of wave w holds,
 // in acc[ib][jb][v], wavenumber j0 + 16 ib + 4 (l/16) + v of spectrum
-// r0 + 32 w + 16 jb + l%16.
-template <bool VEC_OUT, bool HW_SIN = false>
-__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
-                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
-                                          const floatx4 (&aim)[4][2], int plane) {
+// r0 + 32 w + 16 jb + l%16.  All 32 values of a lane are evaluated in one
+// straight-line block before any store; only the stores are guarded, and
+// a tile that lies inside the matrix takes an unguarded path.
+template <int PLANE, bool VEC_OUT, bool HW_SIN>
+__device__ __forceinline__ void store_plane(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
+                                            int wave, int lane, int j0, const floatx4 (&are)[4][2],
+                                            const floatx4 (&aim)[4][2]) {
+    float o[4][2][4];
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                o[ib][jb][v] = HW_SIN ? epilogue_hw<PLANE>(are[ib][jb][v], aim[ib][jb][v])
+                                      : epilogue<PLANE>(are[ib][jb][v], aim[ib][jb][v]);
+    const int64_t row0 = r0 + wave * 32 + (lane & 15);
+    const int col0 = j0 + 4 * (lane >> 4);
+    if (VEC_OUT && j0 + 64 <= N && r0 + 128 <= M) {  // uniform: whole tile inside
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+                *reinterpret_cast<float4*>(out + (row0 + jb * 16) * ld_out + col0 + ib * 16) =
+                    make_float4(o[ib][jb][0], o[ib][jb][1], o[ib][jb][2], o[ib][jb][3]);
+        return;
+    }
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb) {
-            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
-            const int col = j0 + ib * 16 + 4 * (lane >> 4);
+            const int64_t row = row0 + jb * 16;
+            const int col = col0 + ib * 16;
             if (row >= M) continue;
-            float o[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = HW_SIN ? epilogue_hw(are[ib][jb][v], aim[ib][jb][v], plane)
-                              : epilogue(are[ib][jb][v], aim[ib][jb][v], plane);
             float* dst = out + row * ld_out + col;
             if (VEC_OUT && col + 3 < N) {
-                *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+                *reinterpret_cast<float4*>(dst) = make_float4(o[ib][jb][0], o[ib][jb][1], o[ib][jb][2], o[ib][jb][3]);
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (col + v < N) dst[v] = o[v];
+                    if (col + v < N) dst[v] = o[ib][jb][v];
             }
         }
+}
+
+// The plane is chosen once per tile, outside the per-value code.
+template <bool VEC_OUT, bool HW_SIN = false>
+__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
+                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
+                                          const floatx4 (&aim)[4][2], int plane) {
+    if (plane == 0) store_plane<0, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
+    else if (plane == 1) store_plane<1, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
+    else store_plane<2, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
 }
 
 

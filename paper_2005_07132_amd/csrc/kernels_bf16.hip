@@ -411,9 +411,13 @@ __global__ __launch_bounds__(256) void recon16_kernel(const float* __restrict__ 
         for (int kg = 0; kg < KB2; ++kg) {
             const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
             const int c = kg * 32 + 8 * (lane >> 4);
+            // unconditional loads from clamped (in-bounds) addresses, masked
+            // by a multiply: guarded loads each wait for the previous one
+            const float* zr = Z + (row < M ? row : M - 1) * ld_z;
             float v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = (row < M && c + q < k) ? Z[row * ld_z + c + q] : 0.f;
+            for (int q = 0; q < 8; ++q)
+                v[q] = zr[c + q < k ? c + q : k - 1] * ((row < M && c + q < k) ? 1.f : 0.f);
             zb[jb][kg] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
         }
     recon16_loop<KB2, VEC_OUT>(zb, BreT, BimT, sRe, sIm, N, out, ld_out, M, r0, plane);
@@ -539,6 +543,8 @@ hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const 
 hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
                                 const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
                                 hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    if (k < 1 || k > ld_z) return hipErrorInvalidValue;
     const bool vec = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
     dim3 grid((unsigned)((M + PR - 1) / PR));
     const u32x4* bre = reinterpret_cast<const u32x4*>(BreT);
