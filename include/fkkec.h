@@ -143,10 +143,16 @@ const char* fkk_status_string(fkk_status s);
 void fkk_params_default(fkk_params* p);
 
 /* Context: one device and one HIP stream (NULL = the default stream).  The
- * context records the launch sequence of the Householder tridiagonalisation
- * into a HIP graph (kernel nodes only) the first time it meets an order N
- * and replays it on its stream; FKK_NO_GRAPHS=1 in the environment when the
- * context is created launches the same kernels one by one instead. */
+ * Householder tridiagonalisation of the eigensolve runs as one cooperative
+ * launch whose blocks keep the matrix rows in LDS, when the device supports
+ * cooperative launches and the rows fit (N up to about 1,700 on 256 CUs).
+ * Its waits for data exchanged between blocks give up after
+ * FKK_TRIDIAG_SPIN_LIMIT polls (default 2^22); the context then, and for N
+ * beyond that size, uses one launch per
+ * column, which it records into a HIP graph (kernel nodes only) the first
+ * time it meets an order N and replays on its stream.  Environment, read
+ * when the context is created: FKK_NO_RESIDENT_TRIDIAG=1 selects the
+ * per-column launches, FKK_NO_GRAPHS=1 launches them one by one. */
 fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out);
 void fkk_ctx_destroy(fkk_ctx* ctx);
 const char* fkk_ctx_last_error(const fkk_ctx* ctx);

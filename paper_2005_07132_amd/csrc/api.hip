@@ -126,6 +126,11 @@ struct fkk_ctx {
     // The n - 1 launches of the tridiagonalisation, recorded once per order
     // and buffer set on a private stream and replayed on `stream`.
     bool graphs = true;
+    // The whole reduction as one cooperative launch when the device and the
+    // order allow it (FKK_NO_RESIDENT_TRIDIAG=1 forces the per-column
+    // launches); a wait that gives up falls back to the per-column launches.
+    bool resident_tri = true;
+    int tri_spin_limit = 1 << 22;  // polls of a wait before giving up (FKK_TRIDIAG_SPIN_LIMIT)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t tri_exec = nullptr;
     int tri_n = 0;
@@ -413,15 +418,42 @@ fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) 
 // back-transformation on the host.  Overwrites ctx->G.
 fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed) {
     const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
-    // layout of ctx->tri: p0 | p1 | beta | d | e | vstore
-    FKK_HIP(ctx, ctx->tri.ensure(5 * (size_t)N + nv));
+    const size_t nx = fkk::dev::tridiag_resident_xch_doubles(N);
+    // layout of ctx->tri: p0 | p1 | beta | d | e | vstore | flags (2) | exchange (nx)
+    FKK_HIP(ctx, ctx->tri.ensure(5 * (size_t)N + nv + 2 + nx));
     FKK_HIP(ctx, ctx->fdev.ensure(N));
-    FKK_HIP(ctx, ctx->hG.ensure(3 * (size_t)N + nv));
+    FKK_HIP(ctx, ctx->hG.ensure(3 * (size_t)N + nv + 1));
     hipStream_t s = ctx->stream;
     double* t = ctx->tri.p;
     double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
+    double* flags = vs + nv;  // [0]: exchange error (int), [1]: unused
+    double* xch = flags + 2;
+    double* h = ctx->hG.p;  // beta | d | e | vstore | flags[0]
+    const size_t hcount = 3 * (size_t)N + nv + 1;
     FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, f, N * sizeof(double), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, fkk::dev::launch_scale_sym(ctx->G.p, ctx->fdev.p, N, s));
+    const int rg = ctx->resident_tri ? fkk::dev::tridiag_resident_grid(N, ctx->device) : 0;
+    if (rg > 0) {
+        // G is read only, so a failed exchange leaves it for the per-column path
+        if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
+        FKK_HIP(ctx, hipMemsetAsync(flags, 0, (2 + nx) * sizeof(double), s));
+        int berr = 1;
+        if (fkk::dev::launch_tridiag_resident(ctx->G.p, N, rg, xch, reinterpret_cast<int*>(flags), vs, beta, d, e,
+                                              ctx->tri_spin_limit, s) == hipSuccess) {
+            if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+            FKK_HIP(ctx, hipMemcpyAsync(h, beta, hcount * sizeof(double), hipMemcpyDeviceToHost, s));
+            FKK_HIP(ctx, hipStreamSynchronize(s));
+            std::memcpy(&berr, h + hcount - 1, sizeof berr);
+        } else {
+            (void)hipGetLastError();  // launch refused (e.g. the grid cannot be co-resident)
+        }
+        if (berr == 0) {
+            if (fkk::eig_tridiag_topk(h + N, h + 2 * N, h, h + 3 * N, N, k, vals, vecs) != 0)
+                return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
+            return FKK_OK;
+        }
+        ctx->resident_tri = false;
+    }
     FKK_HIP(ctx, fkk::dev::tridiag_prepare(N));
     if (ctx->graphs && !(ctx->tri_exec && ctx->tri_n == N && ctx->tri_key[0] == ctx->G.p && ctx->tri_key[1] == t)) {
         if (ctx->tri_exec) {
@@ -451,7 +483,6 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     else
         FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
-    double* h = ctx->hG.p;  // beta | d | e | vstore
     FKK_HIP(ctx, hipMemcpyAsync(h, beta, (3 * (size_t)N + nv) * sizeof(double), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     if (fkk::eig_tridiag_topk(h + N, h + 2 * N, h, h + 3 * N, N, k, vals, vecs) != 0)
@@ -518,6 +549,12 @@ fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     const char* ng = std::getenv("FKK_NO_GRAPHS");
     c->graphs = !(ng && ng[0] == '1');
+    const char* nr = std::getenv("FKK_NO_RESIDENT_TRIDIAG");
+    c->resident_tri = !(nr && nr[0] == '1');
+    if (const char* sl = std::getenv("FKK_TRIDIAG_SPIN_LIMIT")) {
+        const long v = std::strtol(sl, nullptr, 10);
+        if (v >= 0 && v <= (1L << 30)) c->tri_spin_limit = (int)v;
+    }
     *out = c;
     return FKK_OK;
 }

@@ -22,6 +22,18 @@ hipError_t tridiag_prepare(int n);
 hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vstore, double* beta, double* d, double* e,
                           hipStream_t s);
 
+// Whole reduction in one cooperative launch of G blocks (each keeps its rows
+// in LDS).  tridiag_resident_grid returns G for order n on `device`, or 0
+// when the device cannot run it (no cooperative launch, rows do not fit).
+// A is read only.  xch: tridiag_resident_xch_doubles(n) doubles of scratch
+// and *err, all zero before the launch; *err != 0 afterwards means a wait
+// for exchanged data gave up after spin_limit polls (0: at the first wait)
+// and the outputs are invalid.
+int tridiag_resident_grid(int n, int device);
+size_t tridiag_resident_xch_doubles(int n);
+hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, int* err, double* vstore,
+                                   double* beta, double* d, double* e, int spin_limit, hipStream_t s);
+
 // G(r, c) *= f(r) f(c).
 hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s);
 

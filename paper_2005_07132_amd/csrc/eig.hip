@@ -262,6 +262,222 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Whole reduction in one cooperative launch.  Block b keeps rows b, b+G,
+// b+2G, ... of the matrix in LDS for the whole reduction, so the rank-2
+// updates never leave the CU.  Per column the blocks exchange only p (one
+// entry per row) and the next pivot row.  Each exchanged double travels as
+// two 64-bit words that carry one half of it and the number of the column
+// it belongs to; a reader polls its words until all of them carry the
+// expected number, so no separate grid barrier is needed.  Two buffers
+// alternate between columns: a block writes the words of column i+1 only
+// after it has read all words of column i, and every block wrote those
+// only after reading all of column i-1, the previous content of the buffer.
+// The arithmetic of a column is that of tridiag_step.
+// ---------------------------------------------------------------------------
+constexpr int kMaxOwnedRows = 16;
+constexpr int kXchPerThread = 8;  // exchange entries per thread and column: n - 1 <= 8 * kThreads
+constexpr size_t kResidentLdsMax = 160 * 1024 - 512;  // dynamic part; the static part is < 200 bytes
+
+typedef unsigned long long u64;
+
+// Agent-coherent (relaxed atomic) accesses: they miss in the per-XCD caches.
+__device__ __forceinline__ void xch_put(u64* slot, double v, unsigned tag) {
+    const u64 bits = (u64)__double_as_longlong(v);
+    const u64 t = (u64)tag << 32;
+    __hip_atomic_store(slot, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 xch_word(const u64* p) {
+    return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool xch_tagged(u64 lo, u64 hi, unsigned tag) {
+    return (unsigned)(lo >> 32) == tag && (unsigned)(hi >> 32) == tag;
+}
+__device__ __forceinline__ double xch_value(u64 lo, u64 hi) {
+    return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+}
+
+// Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
+// (LDS), with part += p . v over this thread's entries.  Gives up after
+// spin_limit polls (spin_limit 0: at once), or when *err is set.
+__device__ bool xch_fetch(const u64* pw, const u64* xw, int m, unsigned tag, int spin_limit, const int* err,
+                          double* w, double* x, const double* v, double& part) {
+    u64 a[kXchPerThread][2], c[kXchPerThread][2];
+    int spins = 0;
+    for (;;) {
+        if (spins >= spin_limit) return false;
+        if ((spins & 63) == 63 && __hip_atomic_load(const_cast<int*>(err), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        ++spins;
+#pragma unroll
+        for (int u = 0; u < kXchPerThread; ++u) {  // clamped: every load in bounds, none waits for another
+            const int j = min((int)threadIdx.x + kThreads * u, m - 1);
+            a[u][0] = xch_word(pw + 2 * j);
+            a[u][1] = xch_word(pw + 2 * j + 1);
+            c[u][0] = xch_word(xw + 2 * j);
+            c[u][1] = xch_word(xw + 2 * j + 1);
+        }
+        bool all = true;
+#pragma unroll
+        for (int u = 0; u < kXchPerThread; ++u) {
+            const int j = threadIdx.x + kThreads * u;
+            if (j < m) all = all && xch_tagged(a[u][0], a[u][1], tag) && xch_tagged(c[u][0], c[u][1], tag);
+        }
+        if (all) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int u = 0; u < kXchPerThread; ++u) {
+        const int j = threadIdx.x + kThreads * u;
+        if (j < m) {
+            const double pj = xch_value(a[u][0], a[u][1]);
+            w[j] = pj;
+            x[j] = xch_value(c[u][0], c[u][1]);
+            part += pj * v[j];
+        }
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __restrict__ A, int n, int R, u64* xch,
+                                                             double* __restrict__ vstore, double* __restrict__ beta,
+                                                             double* __restrict__ d, double* __restrict__ e,
+                                                             int* err, int spin_limit) {
+    extern __shared__ double sm[];
+    __shared__ double red[4];
+    __shared__ double sp0;
+    __shared__ int sbad;
+    const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* rows = sm;                   // local row t = matrix row b + t G, all n columns
+    double* va = sm + (size_t)R * n;     // v_i
+    double* vb = va + n;                 // v_{i+1}
+    double* w = vb + n;                  // p_i, then w_i
+    double* x = w + n;                   // pivot row
+    if (tid == 0) sbad = 0;
+    for (int t = 0; t < R; ++t) {
+        const int r = b + t * G;
+        if (r >= n) break;
+        for (int c = tid; c < n; c += kThreads) rows[(size_t)t * n + c] = A[(size_t)r * n + c];
+    }
+    // column 0: reflector of row 0 and p_0 = beta_0 B_0 v_0, from A itself
+    const int m0 = n - 1;
+    for (int j = tid; j < m0; j += kThreads) x[j] = A[1 + j];
+    __syncthreads();
+    double bcur, a0;
+    make_reflector(x, m0, va, &bcur, &a0, red);
+    if (b == 0) {
+        for (int j = tid; j < m0; j += kThreads) vstore[j] = va[j];
+        if (tid == 0) {
+            beta[0] = bcur;
+            d[0] = A[0];
+            e[0] = a0;
+        }
+    }
+    for (int t = wave; t < R; t += kThreads / 64) {
+        const int r = b + t * G;
+        if (r < 1 || r >= n) continue;
+        const double* row = rows + (size_t)t * n + 1;
+        double sacc = 0.0;
+        for (int c = lane; c < m0; c += 64) {
+            sacc += row[c] * va[c];
+            if (r == 1) xch_put(xch + 4 * (size_t)n + 2 * c, row[c], 1u);  // pivot row of column 0
+        }
+        sacc = wave_sum(sacc);
+        if (lane == 0) xch_put(xch + 2 * (r - 1), bcur * sacc, 1u);
+    }
+
+    for (int i = 0; i + 2 < n; ++i) {
+        const int lo = i + 1, m = n - lo;
+        const unsigned tag = (unsigned)i + 1u;  // words of column i
+        const double v0 = va[0];
+        double part = 0.0;
+        __syncthreads();  // LDS of the previous column no longer read
+        // words of column i: p at xch + 2n (i & 1), pivot row at xch + 4n + 2n (i & 1)
+        const size_t half = (i & 1) ? 2 * (size_t)n : 0;
+        if (!xch_fetch(xch + half, xch + 4 * (size_t)n + half, m, tag, spin_limit, err, w, x, va, part)) sbad = 1;
+        if (tid == 0) sp0 = w[0];  // w[0] is this thread's own entry
+        __syncthreads();
+        if (sbad) {
+            if (tid == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        const double p0 = sp0;
+        const double kk = 0.5 * bcur * block_sum(part, red);
+        const double w0 = p0 - kk * v0;
+        const bool next = (i + 3 < n);
+        double part2 = 0.0;
+        for (int j = tid; j < m; j += kThreads) {
+            const double wj = w[j] - kk * va[j];
+            const double xj = x[j] - (v0 * wj + w0 * va[j]);
+            w[j] = wj;
+            x[j] = xj;
+            if (j >= 2) part2 += xj * xj;
+        }
+        double bn = 0.0;
+        if (next) {
+            const double sig2 = block_sum(part2, red);  // x, w complete after this
+            const double x0 = x[1];
+            double a;
+            if (sig2 == 0.0) {
+                a = x0;
+                for (int j = tid; j < m - 1; j += kThreads) vb[j] = 0.0;
+            } else {
+                const double norm = sqrt(x0 * x0 + sig2);
+                a = (x0 >= 0.0) ? -norm : norm;
+                bn = 2.0 / ((x0 - a) * (x0 - a) + sig2);
+                for (int j = tid; j < m - 1; j += kThreads) vb[j] = (j == 0) ? x0 - a : x[1 + j];
+            }
+            if (b == 0) {
+                double* vso = vstore + voff(lo, n);
+                for (int j = tid; j < m - 1; j += kThreads) vso[j] = vb[j];
+                if (tid == 0) {
+                    beta[lo] = bn;
+                    d[lo] = x[0];
+                    e[lo] = a;
+                }
+            }
+        } else {
+            __syncthreads();
+            if (b == 0 && tid == 0) {
+                d[lo] = x[0];
+                e[lo] = x[1];
+            }
+        }
+        __syncthreads();  // vb, w, x complete
+        const unsigned ntag = tag + 1u;
+        u64* pout = xch + (half ? 0 : 2 * (size_t)n);
+        u64* xout = xch + 4 * (size_t)n + (half ? 0 : 2 * (size_t)n);
+        for (int t = wave; t < R; t += kThreads / 64) {
+            const int r = b + t * G;
+            if (r <= lo || r >= n) continue;
+            double* row = rows + (size_t)t * n + lo;
+            const double vr = va[r - lo], wr = w[r - lo];
+            const bool pivot = next && r == lo + 1;  // pivot row of the next column
+            double sacc = 0.0;
+            for (int c = lane; c < m; c += 64) {
+                const double u = row[c] - (vr * w[c] + wr * va[c]);
+                row[c] = u;
+                if (next && c >= 1) {
+                    sacc += u * vb[c - 1];
+                    if (pivot) xch_put(xout + 2 * (c - 1), u, ntag);
+                }
+                if (!next && r == n - 1 && c == m - 1) d[n - 1] = u;
+            }
+            if (next) {
+                sacc = wave_sum(sacc);
+                if (lane == 0) xch_put(pout + 2 * (r - lo - 1), bn * sacc, ntag);
+            }
+        }
+        if (!next) break;
+        double* tv = va;
+        va = vb;
+        vb = tv;
+        bcur = bn;
+    }
+}
+
 __global__ void scale_sym_kernel(double* __restrict__ G, const double* __restrict__ f, int n) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n * n) return;
@@ -277,6 +493,43 @@ hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s) {
     const int64_t total = (int64_t)n * n;
     hipLaunchKernelGGL(scale_sym_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, f, n);
     return hipGetLastError();
+}
+
+
+size_t tridiag_resident_lds(int n, int G) {
+    const int R = (n + G - 1) / G;
+    return ((size_t)R * n + 4 * (size_t)n) * sizeof(double);
+}
+
+int tridiag_resident_grid(int n, int device) {
+    if (n < 3 || n - 1 > kXchPerThread * kThreads) return 0;
+    int coop = 0, cus = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) return 0;
+    const int G = cus < n ? cus : n;
+    if ((n + G - 1) / G > kMaxOwnedRows) return 0;
+    if (tridiag_resident_lds(n, G) > kResidentLdsMax) return 0;
+    return G;
+}
+
+size_t tridiag_resident_xch_doubles(int n) { return 8 * (size_t)n; }
+
+hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, int* err, double* vstore,
+                                   double* beta, double* d, double* e, int spin_limit, hipStream_t s) {
+    if (n < 3 || n - 1 > kXchPerThread * kThreads || G < 1 || G > n || spin_limit < 0) return hipErrorInvalidValue;
+    const int R = (n + G - 1) / G;
+    if (R > kMaxOwnedRows) return hipErrorInvalidValue;
+    const size_t lds = tridiag_resident_lds(n, G);
+    if (lds > kResidentLdsMax) return hipErrorInvalidValue;
+    hipError_t er = hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_resident),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (er != hipSuccess) return er;
+    u64* words = reinterpret_cast<u64*>(xch);
+    int nn = n, rr = R;
+    void* args[] = {(void*)&A,    (void*)&nn,   (void*)&rr, (void*)&words, (void*)&vstore,
+                    (void*)&beta, (void*)&d,    (void*)&e,  (void*)&err,   (void*)&spin_limit};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_resident), dim3(G), dim3(kThreads), args,
+                                      (unsigned)lds, s);
 }
 
 hipError_t tridiag_prepare(int n) {

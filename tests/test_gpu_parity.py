@@ -428,20 +428,31 @@ def test_full_rank_and_minimum_sizes(ctx):
     assert np.isfinite(host(out1)).all()
 
 
-def test_tridiag_graph_replays_match_eager_launches(ctx):
-    # the tridiagonalisation runs from a recorded graph; every replay, with
-    # other device work and synchronisations in between and a re-record for
-    # another order, equals the kernels launched one by one, bit for bit
+def context_with(**env):
+    old = {key: os.environ.get(key) for key in env}
+    os.environ.update({key: str(v) for key, v in env.items()})
+    try:
+        return fk.Context(0)
+    finally:
+        for key, v in old.items():
+            if v is None:
+                del os.environ[key]
+            else:
+                os.environ[key] = v
+
+
+def test_tridiag_graph_replays_match_eager_launches():
+    # the per-column tridiagonalisation runs from a recorded graph; every
+    # replay, with other device work and synchronisations in between and a
+    # re-record for another order, equals the kernels launched one by one,
+    # bit for bit
     say("tridiag graph replays vs eager")
     cube = tissue(rows=40, cols=40, n=300, key=21)
     other = tissue(rows=20, cols=20, n=257, key=22)
     p = lib_params(oracle_params(cube, k=12))
     po = lib_params(oracle_params(other, k=8))
-    os.environ["FKK_NO_GRAPHS"] = "1"
-    try:
-        eager = fk.Context(0)
-    finally:
-        del os.environ["FKK_NO_GRAPHS"]
+    eager = context_with(FKK_NO_GRAPHS=1, FKK_NO_RESIDENT_TRIDIAG=1)
+    ctx = context_with(FKK_NO_RESIDENT_TRIDIAG=1)
     t = dev(cube.i_cars)
     b0, out0, _ = eager.fit(t, cube.i_ref, p)
     ref_out, ref_v = host(out0), b0.export()["v"]
@@ -456,6 +467,57 @@ def test_tridiag_graph_replays_match_eager_launches(ctx):
         bo, outo, _ = ctx.fit(dev(other.i_cars), other.i_ref, po)  # another order: re-recorded
         np.testing.assert_array_equal(host(outo), ref_other)
     eager.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,k", [(300, 12), (1000, 50), (1025, 20), (1600, 50), (8, 2)])
+def test_resident_tridiag_matches_per_column_launches(n, k):
+    # one cooperative launch (rows resident in LDS) against one launch per
+    # column: the same arithmetic up to the summation order of the p dot
+    # products past 1,024 columns.  Singular values and V agree to
+    # rounding, twice in a row; up to 1,024 columns the outputs too
+    say(f"resident tridiag vs per-column n={n} k={k}")
+    if n > 8:
+        cube = tissue(rows=24, cols=24, n=n, key=23)
+        t, ref_i = dev(cube.i_cars), cube.i_ref
+        p = lib_params(oracle_params(cube, k=k))
+    else:
+        rng = np.random.default_rng(5)
+        ref_i = np.full(n, 2.0)
+        t = dev((ref_i * np.exp(0.3 * rng.standard_normal((50, n)))).astype(np.float32))
+        p = fk.params(k=k, sg_window=3)
+    percol = context_with(FKK_NO_RESIDENT_TRIDIAG=1)
+    res = fk.Context(0)
+    b0, out0, _ = percol.fit(t, ref_i, p)
+    e0, o0 = b0.export(), host(out0).astype(np.float64)
+    for _ in range(2):
+        b1, out1, _ = res.fit(t, ref_i, p)
+        e1 = b1.export()
+        assert np.abs(e1["s"] - e0["s"]).max() <= 1e-12 * e0["s"].max()
+        assert np.abs(e1["v"] - e0["v"]).max() < 1e-9
+        if n <= 1024:
+            assert spectrum_err(host(out1), o0).max() < 1e-5
+    percol.close()
+    res.close()
+
+
+def test_resident_tridiag_wait_timeout_falls_back():
+    # a spin limit of 0 makes every wait for exchanged data give up at
+    # once: the kernel exits, flags the failure, and the context redoes the
+    # reduction with one launch per column, with the same result
+    say("resident tridiag wait give-up -> per-column fallback")
+    cube = tissue(rows=24, cols=24, n=300, key=24)
+    p = lib_params(oracle_params(cube, k=10))
+    t = dev(cube.i_cars)
+    percol = context_with(FKK_NO_RESIDENT_TRIDIAG=1)
+    quick = context_with(FKK_TRIDIAG_SPIN_LIMIT=0)
+    b0, out0, _ = percol.fit(t, cube.i_ref, p)
+    for _ in range(2):
+        b1, out1, _ = quick.fit(t, cube.i_ref, p)
+        np.testing.assert_array_equal(host(out1), host(out0))
+        np.testing.assert_array_equal(b1.export()["v"], b0.export()["v"])
+    percol.close()
+    quick.close()
 
 
 def test_invalid_arguments_fail_before_launch(ctx):
