@@ -45,6 +45,28 @@ def profiled_traffic(key):
     return int(vals[key])
 
 
+def stream_bandwidth(torch, dev, out):
+    """What plain streaming kernels sustain on this GPU, as a reference for
+    the memory-bound kernels: torch's device copy of 1 GiB (read + write)
+    and torch's fill of the 2.8 GB output buffer (write only)."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    c = torch.empty_like(a)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn, nbytes in (("copy_GB/s", lambda: c.copy_(a), 2.0 * a.numel() * 4),
+                             ("fill_GB/s", lambda: out.fill_(0.5), 4.0 * out.numel())):
+        fn()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(5):
+            fn()
+        stop.record()
+        torch.cuda.synchronize()
+        res[name] = nbytes * 5 / (start.elapsed_time(stop) * 1e-3) / 1e9
+    del a, c
+    return res
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -344,6 +366,10 @@ def main():
                 "TFLOP/s": 4.0 * m * n * args.k / (ms * 1e-3) / 1e12}
 
     recon = recon_stats(stage["dev_ms_recon"], kp, 4)
+    recon["frac_of_fp32_mfma_peak"] = recon["TFLOP/s"] * 1e12 / PEAK_FP32_MFMA
+    stream_ref = stream_bandwidth(torch, dev, out)
+    for r in (recon, logratio):
+        r["frac_of_measured_copy"] = r["GB/s"] / stream_ref["copy_GB/s"]
 
     # stored-basis stream: args.frames new 256 x 256 x 1000 frames (same
     # components, new abundance maps and noise), each transformed once
@@ -374,6 +400,11 @@ def main():
         bf16 = bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n, npad, kq, gram_flop,
                         recon_stats)
     del frames, fout, host_frames
+    copy_gbps = stream_ref["copy_GB/s"]
+    transform["frac_of_measured_copy_full_cube"] = transform["HBM_GB/s_full_cube"] / copy_gbps
+    if bf16 is not None:
+        bf16["reconstruction"]["frac_of_measured_copy"] = bf16["reconstruction"]["GB/s"] / copy_gbps
+        bf16["transform"]["frac_of_measured_copy_full_cube"] = bf16["transform"]["HBM_GB/s_full_cube"] / copy_gbps
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
@@ -418,6 +449,7 @@ def main():
         "stages_ms": stage,
         "reconstruction": recon,
         "logratio_pass": logratio,
+        "streaming_reference": stream_ref,
         "transform": transform,
         "fp64_gram": fp64_gram,
         "bf16": bf16,

@@ -122,7 +122,7 @@ struct fkk_ctx {
     PinnedBuf<double> hG;
     PinnedBuf<double> hstage;  // basis uploads
     fkk::plain::Workspace plain_ws;
-    hipEvent_t ev[10] = {};
+    hipEvent_t ev[12] = {};  // 0-9 stage timing, 10-11 eigensolve copies
     // The n - 1 launches of the tridiagonalisation, recorded once per order
     // and buffer set on a private stream and replayed on `stream`.
     bool graphs = true;
@@ -416,6 +416,39 @@ fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) 
 // Top-k eigenpairs of diag(f) G diag(f) with G = ctx->G: scaling and the
 // Householder reduction on the device, the tridiagonal eigenproblem and the
 // back-transformation on the host.  Overwrites ctx->G.
+// Host end of the eigensolve once the reduction is queued on s: the small
+// arrays (beta | d | e, and the exchange error flag when flag != nullptr)
+// come first; the packed reflectors follow asynchronously while the host
+// finds the eigenpairs of T, and are waited for only by the back-
+// transformation.  *failed reports a set flag (outputs then unused).
+fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta, const double* flag, double* vals,
+                      double* vecs, bool* failed) {
+    hipStream_t s = ctx->stream;
+    double* h = ctx->hG.p;  // beta | d | e | vstore | flag
+    *failed = false;
+    FKK_HIP(ctx, hipMemcpyAsync(h, beta, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (flag) FKK_HIP(ctx, hipMemcpyAsync(h + 3 * N + nv, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipEventRecord(ctx->ev[10], s));
+    FKK_HIP(ctx, hipMemcpyAsync(h + 3 * N, beta + 3 * N, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipEventRecord(ctx->ev[11], s));
+    FKK_HIP(ctx, hipEventSynchronize(ctx->ev[10]));
+    if (flag) {
+        int berr = 0;
+        std::memcpy(&berr, h + 3 * N + nv, sizeof berr);
+        if (berr != 0) {
+            *failed = true;
+            FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
+            return FKK_OK;
+        }
+    }
+    std::vector<double> Y((size_t)(k + 3) / 4 * 4 * N, 0.0);
+    const int rc = fkk::tridiag_eigvecs(h + N, h + 2 * N, N, k, vals, Y.data());
+    FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
+    if (rc != 0) return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
+    fkk::tridiag_back_transform(h, h + 3 * N, N, k, Y.data(), vecs);
+    return FKK_OK;
+}
+
 fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed) {
     const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
     const size_t nx = fkk::dev::tridiag_resident_xch_doubles(N);
@@ -428,8 +461,6 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
     double* flags = vs + nv;  // [0]: exchange error (int), [1]: unused
     double* xch = flags + 2;
-    double* h = ctx->hG.p;  // beta | d | e | vstore | flags[0]
-    const size_t hcount = 3 * (size_t)N + nv + 1;
     FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, f, N * sizeof(double), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, fkk::dev::launch_scale_sym(ctx->G.p, ctx->fdev.p, N, s));
     const int rg = ctx->resident_tri ? fkk::dev::tridiag_resident_grid(N, ctx->device) : 0;
@@ -437,20 +468,14 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
         // G is read only, so a failed exchange leaves it for the per-column path
         if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
         FKK_HIP(ctx, hipMemsetAsync(flags, 0, (2 + nx) * sizeof(double), s));
-        int berr = 1;
         if (fkk::dev::launch_tridiag_resident(ctx->G.p, N, rg, xch, reinterpret_cast<int*>(flags), vs, beta, d, e,
                                               ctx->tri_spin_limit, s) == hipSuccess) {
             if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
-            FKK_HIP(ctx, hipMemcpyAsync(h, beta, hcount * sizeof(double), hipMemcpyDeviceToHost, s));
-            FKK_HIP(ctx, hipStreamSynchronize(s));
-            std::memcpy(&berr, h + hcount - 1, sizeof berr);
+            bool failed = false;
+            const fkk_status st = eig_finish(ctx, N, k, nv, beta, flags, vals, vecs, &failed);
+            if (st != FKK_OK || !failed) return st;
         } else {
             (void)hipGetLastError();  // launch refused (e.g. the grid cannot be co-resident)
-        }
-        if (berr == 0) {
-            if (fkk::eig_tridiag_topk(h + N, h + 2 * N, h, h + 3 * N, N, k, vals, vecs) != 0)
-                return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
-            return FKK_OK;
         }
         ctx->resident_tri = false;
     }
@@ -483,11 +508,8 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     else
         FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
-    FKK_HIP(ctx, hipMemcpyAsync(h, beta, (3 * (size_t)N + nv) * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipStreamSynchronize(s));
-    if (fkk::eig_tridiag_topk(h + N, h + 2 * N, h, h + 3 * N, N, k, vals, vecs) != 0)
-        return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
-    return FKK_OK;
+    bool failed = false;
+    return eig_finish(ctx, N, k, nv, beta, nullptr, vals, vecs, &failed);
 }
 
 }  // namespace

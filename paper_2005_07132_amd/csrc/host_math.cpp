@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <memory>
 #include <mutex>
 #include <thread>
 
@@ -443,13 +444,14 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
         std::vector<int> estart, eat;
     };
     static std::mutex cache_mu;
-    static Tables cache;
-    Tables t;
+    static std::shared_ptr<const Tables> cache;
+    std::shared_ptr<const Tables> tp;
     {
         std::lock_guard<std::mutex> g(cache_mu);
-        if (cache.n == n && cache.window == window && cache.order == order) t = cache;
+        if (cache && cache->n == n && cache->window == window && cache->order == order) tp = cache;
     }
-    if (t.n != n || t.window != window || t.order != order) {
+    if (!tp) {
+        Tables t;
         const double scale = std::max(1, half);
         t.wmid.resize(window);
         sg_weights(0, window, half, order, scale, t.wmid.data());
@@ -468,18 +470,39 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
         t.n = n;
         t.window = window;
         t.order = order;
+        tp = std::make_shared<const Tables>(std::move(t));
         std::lock_guard<std::mutex> g(cache_mu);
-        cache = t;
+        cache = tp;
     }
-    const std::vector<double>& wmid = t.wmid;
-    const std::vector<double>& wedge = t.wedge;
-    const std::vector<int>& estart = t.estart;
-    const std::vector<int>& eat = t.eat;
+    const std::vector<double>& wmid = tp->wmid;
+    const std::vector<double>& wedge = tp->wedge;
+    const std::vector<int>& estart = tp->estart;
+    const std::vector<int>& eat = tp->eat;
     parallel_rows(rows, [&](int ra, int rb) {
         for (int r = ra; r < rb; ++r) {
             const double* xr = x + (size_t)r * n;
             double* yr = y + (size_t)r * n;
-            for (int i = half; i < n - half; ++i) {
+            int i = half;
+            // four outputs at once (one 4-wide vector FMA per weight), each
+            // summed in the order of the one-output loop below
+            for (; i + 4 <= n - half; i += 4) {
+                const double* src = xr + i - half;
+                double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0}, s3[4] = {0, 0, 0, 0};
+                int j = 0;
+                for (; j + 3 < window; j += 4) {
+                    const double w0 = wmid[j], w1 = wmid[j + 1], w2 = wmid[j + 2], w3 = wmid[j + 3];
+                    for (int o = 0; o < 4; ++o) {
+                        s0[o] += w0 * src[j + o];
+                        s1[o] += w1 * src[j + 1 + o];
+                        s2[o] += w2 * src[j + 2 + o];
+                        s3[o] += w3 * src[j + 3 + o];
+                    }
+                }
+                for (; j < window; ++j)
+                    for (int o = 0; o < 4; ++o) s0[o] += wmid[j] * src[j + o];
+                for (int o = 0; o < 4; ++o) yr[i + o] = (s0[o] + s1[o]) + (s2[o] + s3[o]);
+            }
+            for (; i < n - half; ++i) {
                 const double* src = xr + i - half;
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
                 int j = 0;
@@ -852,15 +875,11 @@ int eigh_topk(const double* a_in, int n, int k, double* vals, double* vecs, int 
     return eig_tridiag_topk(d.data(), e.data(), beta.data(), vstore.data(), n, k, vals, vecs);
 }
 
-int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta, const double* vstore, int n, int k,
-                     double* vals, double* vecs) {
+int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double* vals, double* Y) {
     if (n <= 0 || k <= 0 || k > n) return -1;
     Pool& pool = host_pool();
     std::vector<double> d(d_in, d_in + n), e(std::max(n - 1, 1), 0.0);
     for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
-    std::vector<size_t> voff(std::max(n - 2, 0));
-    size_t total = 0;
-    for (int i = 0; i + 2 < n; ++i) { voff[i] = total; total += n - i - 1; }
     // ---- eigenvalues by bisection (Sturm counts) ----
     double tnorm = 0.0, lo = std::numeric_limits<double>::max(), hi = -lo;
     std::vector<double> e2(std::max(n - 1, 1), 0.0);
@@ -875,8 +894,8 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
     const double pivmin = std::max(std::numeric_limits<double>::min(), tnorm * eps * eps);
     if (tnorm == 0.0) {  // zero matrix: eigenvalues 0, unit vectors
         for (int j = 0; j < k; ++j) vals[j] = 0.0;
-        for (int r = 0; r < n; ++r)
-            for (int j = 0; j < k; ++j) vecs[(size_t)r * k + j] = (r == j) ? 1.0 : 0.0;
+        for (int j = 0; j < k; ++j)
+            for (int r = 0; r < n; ++r) Y[(size_t)j * n + r] = (r == j) ? 1.0 : 0.0;
         return 0;
     }
     lo -= 2 * eps * tnorm;
@@ -923,7 +942,6 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
     // group that is iterated together with re-orthogonalisation; a final
     // modified Gram-Schmidt pass removes the remaining O(eps |T| / gap)
     // overlaps between computed vectors.
-    std::vector<double> Y((size_t)k * n);  // vector j at j*n
     const double ortol = 1e-10 * tnorm;
     std::vector<int> group_start;
     for (int j = 0; j < k; ++j)
@@ -986,63 +1004,88 @@ int eig_tridiag_topk(const double* d_in, const double* e_in, const double* beta,
         if (!(nrm > 0.0) || !std::isfinite(nrm)) return -2;
         for (int i = 0; i < n; ++i) b[i] /= nrm;
     }
+    return 0;
+}
 
+void tridiag_back_transform(const double* beta, const double* vstore, int n, int k, double* Y, double* vecs) {
+    Pool& pool = host_pool();
+    std::vector<size_t> voff(std::max(n - 2, 0));
+    size_t total = 0;
+    for (int i = 0; i + 2 < n; ++i) {
+        voff[i] = total;
+        total += n - i - 1;
+    }
     // ---- back-transformation x = H_0 H_1 ... H_{n-3} y ----
-    // Each thread applies every reflector to all of its vectors while the
-    // reflector is in cache (the packed reflectors are read once per thread).
+    // Y holds k4 = k rounded up to 4 vectors (the extra ones zero).  Each
+    // thread takes whole groups of four vectors and applies every reflector
+    // to them while the reflector is in cache; the dot products keep four
+    // partial sums per vector (c mod 4) so they run on 4-wide vector FMAs.
+    const int groups = (k + 3) / 4;
     pool.run([&](int tid, int nthr) {
-        int j0, j1;
-        split(0, k, tid, nthr, &j0, &j1);
-        for (int i = n - 3; i >= 0; --i) {
-            if (beta[i] == 0.0) continue;
-            const int lo2 = i + 1, m = n - lo2;
-            const double* vs = &vstore[voff[i]];
-            int j = j0;
-            // four vectors at a time: four independent accumulation chains,
-            // each summed in the same order as the one-vector loop below
-            for (; j + 4 <= j1; j += 4) {
-                double* y0 = &Y[(size_t)j * n + lo2];
-                double* y1 = y0 + n;
-                double* y2 = y1 + n;
-                double* y3 = y2 + n;
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                for (int c = 0; c < m; ++c) {
+        int g0, g1;
+        split(0, groups, tid, nthr, &g0, &g1);
+        for (int gi = g0; gi < g1; ++gi) {
+            double* y0 = Y + (size_t)(4 * gi) * n;
+            double* y1 = y0 + n;
+            double* y2 = y1 + n;
+            double* y3 = y2 + n;
+            for (int i = n - 3; i >= 0; --i) {
+                if (beta[i] == 0.0) continue;
+                const int lo2 = i + 1, m = n - lo2;
+                const double* vs = &vstore[voff[i]];
+                double* a0 = y0 + lo2;
+                double* a1 = y1 + lo2;
+                double* a2 = y2 + lo2;
+                double* a3 = y3 + lo2;
+                double p0[4] = {0, 0, 0, 0}, p1[4] = {0, 0, 0, 0}, p2[4] = {0, 0, 0, 0}, p3[4] = {0, 0, 0, 0};
+                int c = 0;
+                for (; c + 4 <= m; c += 4)
+                    for (int l = 0; l < 4; ++l) {
+                        const double vc = vs[c + l];
+                        p0[l] += vc * a0[c + l];
+                        p1[l] += vc * a1[c + l];
+                        p2[l] += vc * a2[c + l];
+                        p3[l] += vc * a3[c + l];
+                    }
+                for (; c < m; ++c) {
                     const double vc = vs[c];
-                    s0 += vc * y0[c];
-                    s1 += vc * y1[c];
-                    s2 += vc * y2[c];
-                    s3 += vc * y3[c];
+                    p0[0] += vc * a0[c];
+                    p1[0] += vc * a1[c];
+                    p2[0] += vc * a2[c];
+                    p3[0] += vc * a3[c];
                 }
-                s0 *= beta[i];
-                s1 *= beta[i];
-                s2 *= beta[i];
-                s3 *= beta[i];
-                for (int c = 0; c < m; ++c) {
-                    const double vc = vs[c];
-                    y0[c] -= s0 * vc;
-                    y1[c] -= s1 * vc;
-                    y2[c] -= s2 * vc;
-                    y3[c] -= s3 * vc;
+                const double s0 = ((p0[0] + p0[1]) + (p0[2] + p0[3])) * beta[i];
+                const double s1 = ((p1[0] + p1[1]) + (p1[2] + p1[3])) * beta[i];
+                const double s2 = ((p2[0] + p2[1]) + (p2[2] + p2[3])) * beta[i];
+                const double s3 = ((p3[0] + p3[1]) + (p3[2] + p3[3])) * beta[i];
+                for (int cc = 0; cc < m; ++cc) {
+                    const double vc = vs[cc];
+                    a0[cc] -= s0 * vc;
+                    a1[cc] -= s1 * vc;
+                    a2[cc] -= s2 * vc;
+                    a3[cc] -= s3 * vc;
                 }
             }
-            for (; j < j1; ++j) {
-                double* y = &Y[(size_t)j * n];
-                double s = 0.0;
-                for (int c = 0; c < m; ++c) s += vs[c] * y[lo2 + c];
-                s *= beta[i];
-                for (int c = 0; c < m; ++c) y[lo2 + c] -= s * vs[c];
+            for (int j = 4 * gi; j < 4 * gi + 4 && j < k; ++j) {
+                const double* y = Y + (size_t)j * n;
+                // sign: largest-magnitude entry positive (first on ties)
+                int imax = 0;
+                for (int r = 1; r < n; ++r)
+                    if (std::fabs(y[r]) > std::fabs(y[imax])) imax = r;
+                const double sg = (y[imax] < 0) ? -1.0 : 1.0;
+                for (int r = 0; r < n; ++r) vecs[(size_t)r * k + j] = sg * y[r];
             }
-        }
-        for (int j = j0; j < j1; ++j) {
-            double* y = &Y[(size_t)j * n];
-            // sign: largest-magnitude entry positive (first on ties)
-            int imax = 0;
-            for (int r = 1; r < n; ++r)
-                if (std::fabs(y[r]) > std::fabs(y[imax])) imax = r;
-            const double sg = (y[imax] < 0) ? -1.0 : 1.0;
-            for (int r = 0; r < n; ++r) vecs[(size_t)r * k + j] = sg * y[r];
         }
     });
+}
+
+int eig_tridiag_topk(const double* d, const double* e, const double* beta, const double* vstore, int n, int k,
+                     double* vals, double* vecs) {
+    if (n <= 0 || k <= 0 || k > n) return -1;
+    std::vector<double> Y((size_t)(k + 3) / 4 * 4 * n, 0.0);
+    const int rc = tridiag_eigvecs(d, e, n, k, vals, Y.data());
+    if (rc != 0) return rc;
+    tridiag_back_transform(beta, vstore, n, k, Y.data(), vecs);
     return 0;
 }
 

@@ -50,6 +50,12 @@ int eigh_topk(const double* a, int n, int k, double* vals, double* vecs, int thr
 // H_i = I - beta_i v_i v_i^T acting on indices i+1..n-1.
 int eig_tridiag_topk(const double* d, const double* e, const double* beta, const double* vstore, int n, int k,
                      double* vals, double* vecs);
+// Its two halves: the top-k eigenpairs of T (values descending, vector j of
+// T at Y + j n), which need only d and e; then x = Q y for each vector, the
+// sign rule, and the transpose into vecs (n x k).  Y has room for k rounded
+// up to a multiple of 4 vectors, the ones past k zero.
+int tridiag_eigvecs(const double* d, const double* e, int n, int k, double* vals, double* Y);
+void tridiag_back_transform(const double* beta, const double* vstore, int n, int k, double* Y, double* vecs);
 
 // Default readings of parameters the paper leaves open.
 int default_fft_len(int n);
