@@ -97,7 +97,9 @@ def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
     """Poisson arrivals of square tiles (side 2^U(5,9), log-uniform) from two
     instruments with resident bases (N = 1,000 and N = 1,600, k = 50),
     offered load rising to saturation; fKK-EC through the continuous-batching
-    server and the conventional method on the same arrival trace."""
+    server and the conventional method on the same arrival trace.  A level
+    offers min(max_tiles, rate x seconds) tiles (at least 5): with
+    seconds = 30 and max_tiles = 1,000 every level runs 30 s or 1,000 tiles."""
     import threading
     import queue as queue_mod
     log("serving: second instrument (512 x 512 x 1,600 cube) and its basis")
@@ -129,7 +131,7 @@ def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
     def trace(rate_spectra, seed):
         r = np.random.default_rng(seed)
         rate_tiles = rate_spectra / mean_spectra
-        n_tiles = int(max(5, min(max_tiles, rate_tiles * seconds)))
+        n_tiles = int(max(5, min(max_tiles, np.ceil(rate_tiles * seconds))))
         gaps = r.exponential(1.0 / rate_tiles, n_tiles)
         sides = np.round(2 ** r.uniform(5, 9, n_tiles)).astype(int)
         which = r.integers(0, 2, n_tiles)
@@ -314,6 +316,10 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--frames", type=int, default=50)
     ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="seconds of arrivals per serving level (30 for the full serving workload)")
+    ap.add_argument("--serving-tiles", type=int, default=400,
+                    help="most tiles per serving level (1000 for the full serving workload)")
     ap.add_argument("--skip-bf16", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device-to-device copy: the reference kernel that scales the "
@@ -426,7 +432,8 @@ def main():
 
     serving = None
     if not args.skip_serving:
-        serving = serving_bench(ctx, fk, torch, synth, b)
+        serving = serving_bench(ctx, fk, torch, synth, b, seconds=args.serving_seconds,
+                                max_tiles=args.serving_tiles)
 
     cpu = None
     if not args.skip_cpu:
