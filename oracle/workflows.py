@@ -51,6 +51,7 @@ class Params:
     sg_order: int = 2
     ml_lambda: float = 0.0
     ratio_floor: float = 1.0e-6
+    k_max: int = 128        # k = 0: at most this many vectors from the rank rule
     q_override: np.ndarray | None = field(default=None, repr=False)
 
     def with_(self, **kw) -> "Params":
@@ -116,6 +117,16 @@ def truncated_svd(a: np.ndarray, k: int, method: str = "gesdd"):
         raise ValueError(method)
     v, u = fix_signs(v, u)
     return u, s, v
+
+
+def rank_cutoff(s: np.ndarray, m: int, n: int, eps: float) -> int:
+    """Number of singular values larger than s_max * max(M, N) * eps, eps
+    the machine epsilon of the data type of the SVD input (Sec. 4.1: the
+    cut-off of NumPy's and MATLAB's rank estimate)."""
+    s = np.asarray(s, dtype=np.float64)
+    if s.size == 0 or not s.max() > 0.0:
+        return 0
+    return int(np.count_nonzero(s > s.max() * max(m, n) * eps))
 
 
 def subsample_rows(z: np.ndarray) -> np.ndarray:
@@ -217,12 +228,23 @@ def reconstruct(z, basis) -> dict:
 
 
 def fit(i_cars, i_ref, p: Params, svd: str = "gesdd") -> dict:
-    """Full fKK-EC on I_CARS (M x N).  Returns basis, Z and outputs."""
+    """Full fKK-EC on I_CARS (M x N).  Returns basis, Z and outputs.
+
+    k = 0 keeps the singular vectors the rank rule of Sec. 4.1 selects
+    (rank_cutoff with the machine epsilon of I_CARS's data type), at least
+    one and at most p.k_max."""
+    in_type = np.asarray(i_cars).dtype
+    eps = float(np.finfo(in_type).eps) if np.issubdtype(in_type, np.floating) else float(np.finfo(np.float64).eps)
     i_cars = np.asarray(i_cars, dtype=np.float64)
     ell, clamps = log_ratio(i_cars, i_ref, p.ratio_floor)
     f = scaling_f(i_cars, p)
     a = ell * f                                       # Eq. 10
-    u, s, v = truncated_svd(a, p.k, svd)
+    if p.k == 0:
+        u, s, v = truncated_svd(a, min(a.shape), svd)
+        k = min(max(rank_cutoff(s, a.shape[0], a.shape[1], eps), 1), p.k_max)
+        u, s, v = u[:, :k], s[:k], v[:, :k]
+    else:
+        u, s, v = truncated_svd(a, p.k, svd)
     z = u * s                                         # U_k S_k
     basis = basis_from_factors(f, s, v, z, p)
     basis["i_ref"] = np.asarray(i_ref, dtype=np.float64)

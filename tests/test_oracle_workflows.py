@@ -236,3 +236,40 @@ def test_q_is_union_of_column_extrema():
     z = np.array([[0.0, 5.0], [3.0, -1.0], [3.0, 2.0], [-2.0, -1.0]])
     # col 0: max first at row 1, min at row 3; col 1: max row 0, min first at row 1
     np.testing.assert_array_equal(wf.subsample_rows(z), [0, 1, 3])
+
+
+# --------------------------------------------------------------------------
+# Rank rule of Sec. 4.1 (k = 0)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,m,n", [(np.float32, 300, 120), (np.float64, 200, 90), (np.float32, 80, 150)])
+def test_rank_rule_matches_numpy_matrix_rank(dtype, m, n):
+    # singular values built around the cut-off s_max max(M, N) eps: seven
+    # well above it, the rest well below; NumPy's own rank estimate on the
+    # same matrix in its own data type must agree
+    rng = np.random.default_rng(3)
+    r = min(m, n)
+    u, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    v, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    tol = max(m, n) * float(np.finfo(dtype).eps)
+    s = np.concatenate([np.geomspace(1.0, 30 * tol, 7), np.geomspace(tol / 30, tol / 3000, r - 7)])
+    a = ((u * s) @ v.T).astype(dtype)
+    expected = int(np.linalg.matrix_rank(a))
+    assert expected == 7
+    sv = np.linalg.svd(a.astype(np.float64), compute_uv=False)
+    assert wf.rank_cutoff(sv, m, n, float(np.finfo(dtype).eps)) == expected
+    # "larger than": a value exactly at the cut-off is not counted
+    assert wf.rank_cutoff(np.array([2.0, 2.0 * 10 * 1e-3]), 10, 4, 1e-3) == 1
+
+
+def test_fit_with_rank_rule_equals_fit_at_that_rank():
+    cube = synth.lowrank_log_cube(1500, 256, rank=4, noise=1e-6, dtype=np.float32)
+    p = wf.Params(k=0, sg_window=101)
+    auto = wf.fit(cube.i_cars, cube.i_ref, p)
+    assert auto["basis"]["s"].shape == (4,)
+    fixed = wf.fit(cube.i_cars, cube.i_ref, p.with_(k=4))
+    np.testing.assert_array_equal(auto["im"], fixed["im"])
+    # the same data in FP64 has a smaller epsilon: the noise floor is kept
+    # too, up to k_max
+    auto64 = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p.with_(k_max=12))
+    assert auto64["basis"]["s"].shape == (12,)
