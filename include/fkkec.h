@@ -77,7 +77,10 @@ enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2 };
  *   sg_window 0   -> largest odd number <= N/2
  */
 typedef struct {
-    int32_t k;             /* retained singular vectors, 1..N (Sec. 2.2)   */
+    int32_t k;             /* retained singular vectors, 1..N (Sec. 2.2);
+                              0 in fkk_fit: those above s_max max(M, N) eps
+                              (eps of FP32; Sec. 4.1), at least 1, at most
+                              min(N, 128); the basis reports the count    */
     int32_t f_mode;        /* FKK_F_ONE or FKK_F_NOISE (Eq. 9)             */
     double alpha;          /* Poisson multiplier of Eq. 9                  */
     double sigma_g;        /* Gaussian noise std of Eq. 9                  */

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cfloat>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -176,9 +177,11 @@ struct fkk_ctx {
 
 namespace {
 
-fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N) {
+// auto_k: k = 0 (the rank rule of Sec. 4.1) is allowed.
+fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = false) {
     if (!p) return ctx->fail(FKK_EINVAL, "params is NULL");
-    if (p->k < 1 || p->k > N) return ctx->fail(FKK_EINVAL, "k=%d outside 1..N=%d", p->k, N);
+    if (!(auto_k && p->k == 0) && (p->k < 1 || p->k > N))
+        return ctx->fail(FKK_EINVAL, "k=%d outside 1..N=%d", p->k, N);
     if (p->k > 128) return ctx->fail(FKK_ERANK, "k=%d above the supported 128", p->k);
     if (p->f_mode != FKK_F_ONE && p->f_mode != FKK_F_NOISE) return ctx->fail(FKK_EINVAL, "bad f_mode");
     if (p->pad_mode != FKK_PAD_EDGE && p->pad_mode != FKK_PAD_ZERO) return ctx->fail(FKK_EINVAL, "bad pad_mode");
@@ -674,7 +677,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
-    if ((st = check_params(ctx, p, N)) != FKK_OK) return st;
+    if ((st = check_params(ctx, p, N, true)) != FKK_OK) return st;
     if (d_out && ld_out < N) return ctx->fail(FKK_EINVAL, "ld_out=%lld < N", (long long)ld_out);
     if (p->n_q_override > 0) {
         if (!p->q_override) return ctx->fail(FKK_EINVAL, "q_override is NULL");
@@ -685,7 +688,9 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     if (out_basis) *out_basis = nullptr;
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int k = p->k, kp = kp_for(k);
+    // k = 0: the top min(N, 128) pairs are computed and the rank rule keeps
+    // those above the cut-off (Sec. 4.1)
+    const int kcap = p->k > 0 ? p->k : std::min(N, 128);
     fkk_fit_report r{};
 
     // 1. log ratio, Gram and column sums on the device (Eq. 2, 6, 9)
@@ -709,9 +714,26 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
             const double mean = colsum[j] / (double)M;
             f[j] = 2.0 * mean / std::sqrt(p->alpha * mean + p->sigma_g * p->sigma_g);
         }
-    std::vector<double> lam(k), V((size_t)N * k), sv(k);
-    if ((st = eig_device(ctx, N, k, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
-    for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    std::vector<double> lam(kcap), V((size_t)N * kcap), sv(kcap);
+    if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
+    for (int c = 0; c < kcap; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    int k = kcap;
+    if (p->k == 0) {
+        // singular values above s_max max(M, N) eps, eps of the FP32 input
+        const double cut = sv[0] * (double)std::max<int64_t>(M, N) * (double)FLT_EPSILON;
+        int cnt = 0;
+        for (int c = 0; c < kcap; ++c) cnt += sv[c] > cut ? 1 : 0;
+        k = std::max(cnt, 1);
+        if (k < kcap) {
+            std::vector<double> Vk((size_t)N * k);
+            for (int j = 0; j < N; ++j)
+                for (int c = 0; c < k; ++c) Vk[(size_t)j * k + c] = V[(size_t)j * kcap + c];
+            V.swap(Vk);
+            lam.resize(k);
+            sv.resize(k);
+        }
+    }
+    const int kp = kp_for(k);
     r.dev_ms_tridiag = ctx->elapsed(6, 7);
     r.ms_eig = ms_since(t0);
 

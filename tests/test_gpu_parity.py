@@ -263,6 +263,26 @@ def test_fit_lowrank_matches_independent_oracle(ctx, detrend):
     assert rep["n_q"] == len(ref["basis"]["q"])
 
 
+def test_fit_rank_rule_matches_oracle(ctx):
+    # k = 0: the rank rule of Sec. 4.1 with the FP32 epsilon of the input
+    # keeps the 6 components of an exact rank-6 log ratio (noise 1e-6 lies
+    # far below the cut-off); then the fit is the k = 6 fit
+    say("fit k=0 rank rule")
+    cube = synth.lowrank_log_cube(4000, 300, rank=6, dtype=np.float32)
+    p = wf.Params(k=0)
+    ref = wf.fit(cube.i_cars, cube.i_ref, p)  # FP32 input: the oracle takes FP32's epsilon
+    assert ref["basis"]["s"].shape == (6,)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p))
+    n, k, nq = b.info()
+    assert (n, k) == (300, 6)
+    np.testing.assert_allclose(b.export()["s"], ref["basis"]["s"], rtol=1e-5)
+    assert spectrum_err(host(out), ref["im"]).max() < TOL
+    # k = 0 is a fit-only setting
+    with pytest.raises(fk.FkkError):
+        ctx.basis_import(dict(ref["basis"], v=ref["basis"]["v"][:, :0], s=ref["basis"]["s"][:0],
+                              b_re=ref["basis"]["b_re"][:0], b_im=ref["basis"]["b_im"][:0]))
+
+
 def test_fit_tissue_with_oracle_subsample(ctx):
     say("fit tissue q_override")
     cube = tissue(rows=64, cols=64, n=256, key=5)
