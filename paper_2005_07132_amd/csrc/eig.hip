@@ -299,46 +299,80 @@ __device__ __forceinline__ double xch_value(u64 lo, u64 hi) {
 }
 
 // Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
-// (LDS), with part += p . v over this thread's entries.  Gives up after
-// spin_limit polls (spin_limit 0: at once), or when *err is set.
-__device__ bool xch_fetch(const u64* pw, const u64* xw, int m, unsigned tag, int spin_limit, const int* err,
-                          double* w, double* x, const double* v, double& part) {
-    u64 a[kXchPerThread][2], c[kXchPerThread][2];
-    int spins = 0;
-    for (;;) {
-        if (spins >= spin_limit) return false;
-        if ((spins & 63) == 63 && __hip_atomic_load(const_cast<int*>(err), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT) != 0)
-            return false;
-        ++spins;
+// (LDS), with part += p . v over this thread's entries; NU = ceil(m /
+// kThreads) entries per thread, so a poll loads only live entries.  Gives
+// up after spin_limit polls (spin_limit 0: at once), or when *err is set.
+template <int NU>
+struct XchPoll {
+    u64 a[NU][2], c[NU][2];
+    __device__ __forceinline__ void issue(const u64* pw, const u64* xw, int m) {
 #pragma unroll
-        for (int u = 0; u < kXchPerThread; ++u) {  // clamped: every load in bounds, none waits for another
+        for (int u = 0; u < NU; ++u) {  // clamped: every load in bounds, none waits for another
             const int j = min((int)threadIdx.x + kThreads * u, m - 1);
             a[u][0] = xch_word(pw + 2 * j);
             a[u][1] = xch_word(pw + 2 * j + 1);
             c[u][0] = xch_word(xw + 2 * j);
             c[u][1] = xch_word(xw + 2 * j + 1);
         }
+    }
+    __device__ __forceinline__ bool complete(int m, unsigned tag) const {
         bool all = true;
 #pragma unroll
-        for (int u = 0; u < kXchPerThread; ++u) {
+        for (int u = 0; u < NU; ++u) {
             const int j = threadIdx.x + kThreads * u;
             if (j < m) all = all && xch_tagged(a[u][0], a[u][1], tag) && xch_tagged(c[u][0], c[u][1], tag);
         }
-        if (all) break;
-        __builtin_amdgcn_s_sleep(1);
+        return all;
     }
+    __device__ __forceinline__ void use(int m, double* w, double* x, const double* v, double& part) const {
 #pragma unroll
-    for (int u = 0; u < kXchPerThread; ++u) {
-        const int j = threadIdx.x + kThreads * u;
-        if (j < m) {
-            const double pj = xch_value(a[u][0], a[u][1]);
-            w[j] = pj;
-            x[j] = xch_value(c[u][0], c[u][1]);
-            part += pj * v[j];
+        for (int u = 0; u < NU; ++u) {
+            const int j = threadIdx.x + kThreads * u;
+            if (j < m) {
+                const double pj = xch_value(a[u][0], a[u][1]);
+                w[j] = pj;
+                x[j] = xch_value(c[u][0], c[u][1]);
+                part += pj * v[j];
+            }
         }
     }
+};
+
+// Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
+// (LDS), with part += p . v over this thread's entries; NU = ceil(m /
+// kThreads) entries per thread, so a poll loads only live entries.  (Two
+// polls in flight at a time measured slower: the extra traffic to the
+// coherence point costs more than the earlier detection gains.)  Gives up
+// after spin_limit polls (spin_limit 0: at once), or when *err is set.
+template <int NU>
+__device__ bool xch_fetch_n(const u64* pw, const u64* xw, int m, unsigned tag, int spin_limit, const int* err,
+                            double* w, double* x, const double* v, double& part) {
+    XchPoll<NU> p0;
+    for (int spins = 0;; ++spins) {
+        if (spins >= spin_limit) return false;
+        if ((spins & 63) == 63 &&
+            __hip_atomic_load(const_cast<int*>(err), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        p0.issue(pw, xw, m);
+        if (p0.complete(m, tag)) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    p0.use(m, w, x, v, part);
     return true;
+}
+
+__device__ bool xch_fetch(const u64* pw, const u64* xw, int m, unsigned tag, int spin_limit, const int* err,
+                          double* w, double* x, const double* v, double& part) {
+    switch ((m + kThreads - 1) / kThreads) {  // uniform over the block
+        case 1: return xch_fetch_n<1>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 2: return xch_fetch_n<2>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 3: return xch_fetch_n<3>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 4: return xch_fetch_n<4>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 5: return xch_fetch_n<5>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 6: return xch_fetch_n<6>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        case 7: return xch_fetch_n<7>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+        default: return xch_fetch_n<kXchPerThread>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __restrict__ A, int n, int R, u64* xch,
