@@ -97,13 +97,31 @@ def fix_signs(v: np.ndarray, u: np.ndarray | None = None):
     return v, u
 
 
-def truncated_svd(a: np.ndarray, k: int, method: str = "gesdd"):
+def randomized_svd(a: np.ndarray, k: int, omega: np.ndarray, power_iters: int = 1):
+    """Rank-k SVD of A from a randomized range finder (the alternative the
+    paper names for very large data, Sec. 5): Halko, Martinsson & Tropp
+    (2011), randomized subspace iteration (their Algorithm 4.4) on the test
+    matrix omega (N x l, l >= k), then the SVD of B = Q^T A (Algorithm 5.1).
+    Returns (U_k, s_k, V_k) before the sign rule."""
+    q, _ = np.linalg.qr(a @ omega)                    # range of A Omega
+    for _ in range(power_iters):
+        z, _ = np.linalg.qr(a.T @ q)                  # re-orthonormalised each half step
+        q, _ = np.linalg.qr(a @ z)
+    b = q.T @ a                                       # l x N
+    ub, s, vt = np.linalg.svd(b, full_matrices=False)
+    return (q @ ub)[:, :k], s[:k], vt[:k].T
+
+
+def truncated_svd(a: np.ndarray, k: int, method: str = "gesdd", omega=None, power_iters: int = 1):
     """Rank-k SVD of A (Eq. 6): returns (U_k, s_k, V_k), descending s.
 
     method 'gesdd' is LAPACK's SVD of A itself; 'gram' is the symmetric
-    eigendecomposition of A^T A with s = sqrt(eigenvalue) and U = A V / s.
+    eigendecomposition of A^T A with s = sqrt(eigenvalue) and U = A V / s;
+    'randomized' is randomized_svd with the test matrix omega.
     """
-    if method == "gesdd":
+    if method == "randomized":
+        u, s, v = randomized_svd(a, k, omega, power_iters)
+    elif method == "gesdd":
         u, s, vt = np.linalg.svd(a, full_matrices=False)
         u, s, v = u[:, :k], s[:k], vt[:k].T
     elif method == "gram":
@@ -227,7 +245,7 @@ def reconstruct(z, basis) -> dict:
     return retrieve(z @ basis["b_re"], z @ basis["b_im"])
 
 
-def fit(i_cars, i_ref, p: Params, svd: str = "gesdd") -> dict:
+def fit(i_cars, i_ref, p: Params, svd: str = "gesdd", omega=None, power_iters: int = 1) -> dict:
     """Full fKK-EC on I_CARS (M x N).  Returns basis, Z and outputs.
 
     k = 0 keeps the singular vectors the rank rule of Sec. 4.1 selects
@@ -240,11 +258,11 @@ def fit(i_cars, i_ref, p: Params, svd: str = "gesdd") -> dict:
     f = scaling_f(i_cars, p)
     a = ell * f                                       # Eq. 10
     if p.k == 0:
-        u, s, v = truncated_svd(a, min(a.shape), svd)
+        u, s, v = truncated_svd(a, min(a.shape), svd, omega, power_iters)
         k = min(max(rank_cutoff(s, a.shape[0], a.shape[1], eps), 1), p.k_max)
         u, s, v = u[:, :k], s[:k], v[:, :k]
     else:
-        u, s, v = truncated_svd(a, p.k, svd)
+        u, s, v = truncated_svd(a, p.k, svd, omega, power_iters)
     z = u * s                                         # U_k S_k
     basis = basis_from_factors(f, s, v, z, p)
     basis["i_ref"] = np.asarray(i_ref, dtype=np.float64)

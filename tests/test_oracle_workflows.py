@@ -273,3 +273,55 @@ def test_fit_with_rank_rule_equals_fit_at_that_rank():
     # too, up to k_max
     auto64 = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p.with_(k_max=12))
     assert auto64["basis"]["s"].shape == (12,)
+
+
+# --------------------------------------------------------------------------
+# Randomized range finder (Halko, Martinsson & Tropp 2011)
+# --------------------------------------------------------------------------
+
+def _matrix_with_spectrum(m, n, s, seed):
+    rng = np.random.default_rng(seed)
+    u, _ = np.linalg.qr(rng.standard_normal((m, len(s))))
+    v, _ = np.linalg.qr(rng.standard_normal((n, len(s))))
+    return (u * s) @ v.T, u, v
+
+
+@pytest.mark.parametrize("power_iters", [0, 1, 2])
+def test_randomized_svd_exact_on_low_rank(power_iters):
+    # rank r <= l: the range of A Omega is the range of A, so the factors
+    # are the exact ones
+    s_true = np.array([50.0, 20.0, 7.0, 3.0, 1.0, 0.4])
+    a, u, v = _matrix_with_spectrum(400, 120, s_true, 1)
+    omega = np.random.default_rng(2).standard_normal((120, 10))
+    ur, sr, vr = wf.randomized_svd(a, 6, omega, power_iters)
+    np.testing.assert_allclose(sr, s_true, rtol=1e-12)
+    assert np.linalg.norm(vr @ vr.T - v @ v.T, 2) < 1e-12
+    assert np.linalg.norm(ur @ ur.T - u @ u.T, 2) < 1e-12
+    np.testing.assert_allclose((ur * sr) @ vr.T, a, atol=1e-11)
+
+
+def test_randomized_svd_interlaces_and_improves_with_iterations():
+    # singular values of Q^T A never exceed those of A (Q orthonormal);
+    # with a test matrix spanning the top right singular vectors the result
+    # is exact; subspace iteration brings the estimates towards the truth
+    s_true = 1.0 / np.arange(1, 81) ** 1.5
+    a, u, v = _matrix_with_spectrum(300, 80, s_true, 3)
+    omega = np.random.default_rng(4).standard_normal((80, 15))
+    errs = []
+    for q in (0, 1, 3):
+        _, sr, _ = wf.randomized_svd(a, 10, omega, q)
+        assert np.all(sr <= s_true[:10] * (1 + 1e-12))
+        errs.append(np.max(np.abs(sr - s_true[:10]) / s_true[:10]))
+    assert errs[0] > errs[1] > errs[2]
+    _, sr, vr = wf.randomized_svd(a, 10, v[:, :15] @ np.random.default_rng(5).standard_normal((15, 15)), 0)
+    np.testing.assert_allclose(sr, s_true[:10], rtol=1e-10)
+
+
+def test_fit_with_randomized_svd_equals_exact_on_low_rank_data():
+    cube = synth.lowrank_log_cube(1200, 200, rank=5, noise=0.0)
+    p = wf.Params(k=5, sg_window=61)
+    omega = np.random.default_rng(6).standard_normal((200, 15))
+    exact = wf.fit(cube.i_cars, cube.i_ref, p)
+    rr = wf.fit(cube.i_cars, cube.i_ref, p, svd="randomized", omega=omega, power_iters=1)
+    assert np.array_equal(np.sort(rr["basis"]["q"]), np.sort(exact["basis"]["q"]))
+    assert _rel(rr["im"], exact["im"]) < 1e-10
