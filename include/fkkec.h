@@ -68,6 +68,8 @@ enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
  * sub-sampled rows of Eq. 13-15, only by the FP32 rounding of the log ratio.
  * The eigensolve and the basis-vector KK / PEC / SEC are FP64 always. */
 enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2 };
+/* Route of the truncated SVD (Eq. 6) in fkk_fit. */
+enum { FKK_SVD_GRAM = 0, FKK_SVD_RANDOMIZED = 1 };
 
 /*
  * Method parameters.  Fill with fkk_params_default() and override fields.
@@ -105,6 +107,22 @@ typedef struct {
     int32_t output;        /* FKK_OUT_*                                    */
     const int64_t* q_override; /* host, optional: rows used as U_ss       */
     int32_t n_q_override;  /* length of q_override (0 = use Eq. 13-15)    */
+    /* SVD of Eq. 6 in fkk_fit: FKK_SVD_GRAM (Gram on the matrix cores and
+     * the FP64 eigensolve, exact to rounding) or FKK_SVD_RANDOMIZED (the
+     * randomized range finder the paper names as the alternative for very
+     * large data, Sec. 5: Halko, Martinsson & Tropp 2011, subspace iteration
+     * with rrf_power_iters passes of A^T, A on l = k + rrf_oversample test
+     * vectors (l <= min(N, 128)), then the SVD of Q^T A; approximate in the
+     * tail of the spectrum).  gram_prec does not apply to it: its products
+     * of A are the FP32 projection and FP64-accumulated products of the FP32
+     * log ratio. */
+    int32_t svd_mode;
+    int32_t rrf_oversample;   /* l - k, >= 0                                 */
+    int32_t rrf_power_iters;  /* subspace iterations, >= 0                   */
+    uint64_t rrf_seed;        /* test matrix when rrf_omega is NULL          */
+    const double* rrf_omega;  /* host, optional: N x l test matrix (row-major);
+                                 NULL: standard normal numbers from rrf_seed
+                                 (SplitMix64, Box-Muller)                    */
 } fkk_params;
 
 /* Per-fit diagnostics (all fields written by fkk_fit when non-NULL). */

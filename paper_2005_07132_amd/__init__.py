@@ -25,6 +25,7 @@ PAD_EDGE, PAD_ZERO = 0, 1
 F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+SVD_GRAM, SVD_RANDOMIZED = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
@@ -40,6 +41,8 @@ class Params(ctypes.Structure):
         ("ratio_floor", ctypes.c_double), ("strict", ctypes.c_int32), ("gram_prec", ctypes.c_int32),
         ("recon_prec", ctypes.c_int32), ("output", ctypes.c_int32),
         ("q_override", _c_int64_p), ("n_q_override", ctypes.c_int32),
+        ("svd_mode", ctypes.c_int32), ("rrf_oversample", ctypes.c_int32), ("rrf_power_iters", ctypes.c_int32),
+        ("rrf_seed", ctypes.c_uint64), ("rrf_omega", _c_double_p),
     ]
 
 
@@ -171,6 +174,7 @@ def params(**overrides) -> Params:
     p = Params()
     lib().fkk_params_default(ctypes.byref(p))
     q = overrides.pop("q_override", None)
+    omega = overrides.pop("rrf_omega", None)
     for key, val in overrides.items():
         if not hasattr(p, key):
             raise AttributeError(key)
@@ -180,6 +184,10 @@ def params(**overrides) -> Params:
         p._q_keep = q  # keep the buffer alive with the struct
         p.q_override = q.ctypes.data_as(_c_int64_p)
         p.n_q_override = int(q.size)
+    if omega is not None:
+        omega = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        p._omega_keep = omega
+        p.rrf_omega = omega.ctypes.data_as(_c_double_p)
     return p
 
 

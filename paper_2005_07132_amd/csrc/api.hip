@@ -206,6 +206,14 @@ fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = 
                          p->recon_prec);
     if (p->f_mode == FKK_F_NOISE && !(p->alpha >= 0.0 && p->sigma_g >= 0.0 && (p->alpha > 0.0 || p->sigma_g > 0.0)))
         return ctx->fail(FKK_EINVAL, "f_mode=noise needs alpha >= 0, sigma_g >= 0, not both 0");
+    if (p->svd_mode != FKK_SVD_GRAM && p->svd_mode != FKK_SVD_RANDOMIZED) return ctx->fail(FKK_EINVAL, "bad svd_mode");
+    if (p->svd_mode == FKK_SVD_RANDOMIZED) {
+        if (p->k == 0) return ctx->fail(FKK_EINVAL, "the randomized SVD needs k >= 1");
+        if (p->rrf_oversample < 0 || p->rrf_power_iters < 0 || p->rrf_power_iters > 16)
+            return ctx->fail(FKK_EINVAL, "rrf_oversample >= 0 and 0 <= rrf_power_iters <= 16");
+        if (p->k + p->rrf_oversample > std::min(N, 128))
+            return ctx->fail(FKK_ERANK, "k + rrf_oversample = %d above min(N, 128)", p->k + p->rrf_oversample);
+    }
     return FKK_OK;
 }
 
@@ -357,8 +365,9 @@ int npad_for(int N) { return round_up(N, fkk::dev::kGramTile); }
 
 // Log-ratio pass into ctx->L, Gram G_L = l^T l into ctx->G (device, FP64,
 // N x N), column sums into ctx->colsum and the clamp count into ctx->clamps.
+// with_gram false: the log-ratio pass and column sums only (FP32 l).
 fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
-                       double floor, int prec, bool timed) {
+                       double floor, int prec, bool timed, bool with_gram = true) {
     const int npad = npad_for(N);
     const bool bf16 = (prec == FKK_PREC_BF16);
     const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
@@ -369,9 +378,11 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
     const int64_t nlr = fkk::dev::logratio_blocks(M);
     // FP32 l (M x npad) or the packed BF16 l, which needs at most half of it
     FKK_HIP(ctx, ctx->L.ensure(bf16 ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4 : (size_t)M * npad));
-    FKK_HIP(ctx, ctx->partial.ensure(plan.partial_doubles()));
+    if (with_gram) {
+        FKK_HIP(ctx, ctx->partial.ensure(plan.partial_doubles()));
+        FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
+    }
     FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)nlr * npad));
-    FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
     FKK_HIP(ctx, ctx->colsum.ensure(N + fkk::dev::colsum_scratch_doubles(N)));
     FKK_HIP(ctx, ctx->clamps.ensure(1));
     FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
@@ -389,6 +400,11 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
         FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, ctx->rinv.p, (float)floor, ctx->L.p, npad, npad,
                                                ctx->colsum_part.p, ctx->clamps.p, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
+    if (!with_gram) {
+        FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N,
+                                                    ctx->colsum.p, s));
+        return FKK_OK;
+    }
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
     if (bf16)
         FKK_HIP(ctx, fkk::dev::launch_gram16(lp16, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
@@ -515,6 +531,117 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     return eig_finish(ctx, N, k, nv, beta, nullptr, vals, vecs, &failed);
 }
 
+// Standard normal numbers for the range finder's test matrix: SplitMix64
+// (Steele, Lea & Flood 2014) from `seed`, pairs of uniforms in (0, 1]
+// turned into pairs of normals by the Box-Muller transform.
+void rrf_gaussian(uint64_t seed, size_t n, double* out) {
+    uint64_t x = seed;
+    auto next = [&x]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (size_t i = 0; i < n; i += 2) {
+        const double u1 = ((next() >> 11) + 1) * (1.0 / 9007199254740992.0);
+        const double u2 = ((next() >> 11) + 1) * (1.0 / 9007199254740992.0);
+        const double r = std::sqrt(-2.0 * std::log(u1)), t = 6.283185307179586 * u2;
+        out[i] = r * std::cos(t);
+        if (i + 1 < n) out[i + 1] = r * std::sin(t);
+    }
+}
+
+// Top-k singular triplets of A = l diag(f) by the randomized range finder
+// with subspace iteration (Halko, Martinsson & Tropp 2011, Algorithms 4.4
+// and 5.1) on the FP32 log ratio in ctx->L: Y = A W on the matrix cores
+// (projection kernel), Y^T Y with FP64 products and sums, A^T Y as FP64
+// partials of FP32 matrix-core stages; the n x l and l x l algebra in FP64
+// on the host.  Q = Y R^-1 with R from Cholesky of Y^T Y stays implicit:
+// A^T Q = diag(f) (l^T Y) R^-1.  Outputs s (k) and V (N x k, sign rule).
+fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk_params* p, int k, double* sv,
+                      double* V) {
+    const int l = k + p->rrf_oversample;
+    const int npad = npad_for(N), nb = npad / fkk::dev::kGramTile;
+    constexpr int LY = fkk::dev::kGramTile;  // Y is M x 128 (columns past l zero)
+    hipStream_t s = ctx->stream;
+    std::vector<double> W((size_t)N * l);
+    if (p->rrf_omega)
+        std::memcpy(W.data(), p->rrf_omega, W.size() * sizeof(double));
+    else
+        rrf_gaussian(p->rrf_seed, W.size(), W.data());
+    fkk::dev::GramPlan pc = fkk::dev::gram_plan(M, N, 64, 32), py = pc;
+    pc.tiles = nb;  // (bi, 0): l^T Y
+    py.tiles = 1;   // (0, 0): Y^T Y
+    std::vector<int> pairs(2 * (size_t)(nb + 1), 0);
+    for (int bi = 0; bi < nb; ++bi) pairs[2 * bi] = bi;
+    const int64_t nblk = fkk::dev::proj_blocks(M);
+    (void)nblk;
+    FKK_HIP(ctx, ctx->Z.ensure((size_t)M * LY));
+    FKK_HIP(ctx, ctx->X.ensure((size_t)LY * npad));
+    FKK_HIP(ctx, ctx->partial.ensure(pc.partial_doubles()));
+    FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
+    FKK_HIP(ctx, ctx->G.ensure((size_t)npad * LY + (size_t)LY * LY));
+    FKK_HIP(ctx, ctx->hG.ensure((size_t)npad * LY + (size_t)LY * LY));
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    double* d_c = ctx->G.p;                         // l^T Y: N x 128
+    double* d_gy = ctx->G.p + (size_t)npad * LY;    // Y^T Y: 128 x 128
+    double* h_c = ctx->hG.p;
+    double* h_gy = ctx->hG.p + (size_t)npad * LY;
+    std::vector<float> wt((size_t)LY * npad);
+    std::vector<double> AtQ((size_t)N * l), G((size_t)l * l);
+    const fkk::dev::ArgPart none{nullptr, nullptr, nullptr, nullptr};
+    for (int it = 0; it <= p->rrf_power_iters; ++it) {
+        std::fill(wt.begin(), wt.end(), 0.f);
+        for (int c = 0; c < l; ++c)
+            for (int j = 0; j < N; ++j) wt[(size_t)c * npad + j] = (float)(f[j] * W[(size_t)j * l + c]);
+        FKK_HIP(ctx, hipMemcpyAsync(ctx->X.p, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        FKK_HIP(ctx, fkk::dev::launch_project(ctx->L.p, M, N, npad, ctx->rinv.p, (float)p->ratio_floor, ctx->X.p,
+                                              npad, LY, LY, ctx->Z.p, LY, none, 0, s, true));
+        FKK_HIP(ctx, fkk::dev::launch_gram_pair(ctx->Z.p, LY, ctx->Z.p, LY, M, py, ctx->tiles.p + 2 * nb,
+                                                ctx->partial.p, s, true));
+        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(ctx->partial.p, py, ctx->tiles.p + 2 * nb, LY, LY, d_gy, LY,
+                                                       s));
+        FKK_HIP(ctx, fkk::dev::launch_gram_pair(ctx->L.p, npad, ctx->Z.p, LY, M, pc, ctx->tiles.p, ctx->partial.p, s,
+                                                false));
+        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(ctx->partial.p, pc, ctx->tiles.p, N, LY, d_c, LY, s));
+        FKK_HIP(ctx, hipMemcpyAsync(h_c, d_c, (size_t)N * LY * sizeof(double), hipMemcpyDeviceToHost, s));
+        FKK_HIP(ctx, hipMemcpyAsync(h_gy, d_gy, (size_t)LY * LY * sizeof(double), hipMemcpyDeviceToHost, s));
+        FKK_HIP(ctx, hipStreamSynchronize(s));
+        for (int a = 0; a < l; ++a)
+            for (int b = 0; b < l; ++b) G[(size_t)a * l + b] = h_gy[(size_t)a * LY + b];
+        if (!fkk::cholesky_upper(G.data(), l))
+            return ctx->fail(FKK_EINTERNAL, "range finder: Y^T Y not positive definite (rank of A below %d)", l);
+        for (int j = 0; j < N; ++j)
+            for (int c = 0; c < l; ++c) AtQ[(size_t)j * l + c] = f[j] * h_c[(size_t)j * LY + c];
+        fkk::solve_right_upper(AtQ.data(), N, l, G.data());  // A^T Q = A^T Y R^-1
+        if (it < p->rrf_power_iters) {
+            W = AtQ;
+            if (!fkk::orthonormalize_cols(W.data(), N, l))
+                return ctx->fail(FKK_EINTERNAL, "range finder: A^T Q rank deficient");
+        }
+    }
+    // B = Q^T A = (A^T Q)^T: B B^T = (A^T Q)^T (A^T Q); V = B^T U_B / s
+    fkk::gram_cols(AtQ.data(), N, l, G.data());
+    std::vector<double> lam(k), ub((size_t)l * k);
+    if (fkk::eigh_topk(G.data(), l, k, lam.data(), ub.data(), 1) != 0)
+        return ctx->fail(FKK_EINTERNAL, "range finder: small eigensolve failed");
+    for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    for (int j = 0; j < N; ++j)
+        for (int c = 0; c < k; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < l; ++a) acc += AtQ[(size_t)j * l + a] * ub[(size_t)a * k + c];
+            V[(size_t)j * k + c] = sv[c] > 0.0 ? acc / sv[c] : 0.0;
+        }
+    for (int c = 0; c < k; ++c) {  // largest-magnitude entry positive (first on ties)
+        int imax = 0;
+        for (int j = 1; j < N; ++j)
+            if (std::fabs(V[(size_t)j * k + c]) > std::fabs(V[(size_t)imax * k + c])) imax = j;
+        if (V[(size_t)imax * k + c] < 0.0)
+            for (int j = 0; j < N; ++j) V[(size_t)j * k + c] = -V[(size_t)j * k + c];
+    }
+    return FKK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -560,6 +687,11 @@ void fkk_params_default(fkk_params* p) {
     p->output = FKK_OUT_IM;
     p->q_override = nullptr;
     p->n_q_override = 0;
+    p->svd_mode = FKK_SVD_GRAM;
+    p->rrf_oversample = 10;
+    p->rrf_power_iters = 1;
+    p->rrf_seed = 20200514;
+    p->rrf_omega = nullptr;
 }
 
 fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
@@ -698,9 +830,12 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     std::vector<double> colsum(N);
     int64_t clamps = 0;
     FKK_HIP(ctx, ctx->events());
-    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, p->gram_prec, true)) != FKK_OK) return st;
+    const bool rrf = (p->svd_mode == FKK_SVD_RANDOMIZED);
+    // the range finder works from the FP32 log ratio, whatever gram_prec says
+    const int gprec = rrf ? FKK_PREC_FP32 : p->gram_prec;
+    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, gprec, true, !rrf)) != FKK_OK) return st;
     if ((st = fetch_sums(ctx, N, colsum.data(), &clamps)) != FKK_OK) return st;
-    r.dev_ms_gram = ctx->elapsed(0, 1);
+    r.dev_ms_gram = rrf ? 0.0 : ctx->elapsed(0, 1);
     r.dev_ms_logratio = ctx->elapsed(8, 9);
     r.clamps = clamps;
     r.ms_gram = ms_since(t0);
@@ -715,8 +850,14 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
             f[j] = 2.0 * mean / std::sqrt(p->alpha * mean + p->sigma_g * p->sigma_g);
         }
     std::vector<double> lam(kcap), V((size_t)N * kcap), sv(kcap);
-    if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
-    for (int c = 0; c < kcap; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+    if (rrf) {
+        if ((st = rrf_device(ctx, M, N, f.data(), p, kcap, sv.data(), V.data())) != FKK_OK) return st;
+        for (int c = 0; c < kcap; ++c) lam[c] = sv[c] * sv[c];
+    } else {
+        if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
+        for (int c = 0; c < kcap; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+        r.dev_ms_tridiag = ctx->elapsed(6, 7);
+    }
     int k = kcap;
     if (p->k == 0) {
         // singular values above s_max max(M, N) eps, eps of the FP32 input
@@ -734,7 +875,6 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
         }
     }
     const int kp = kp_for(k);
-    r.dev_ms_tridiag = ctx->elapsed(6, 7);
     r.ms_eig = ms_since(t0);
 
     // 3. projection Z = A V_k and per-column arg-extrema (Eq. 13-15)
@@ -772,7 +912,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
         if (pbf16)  // log ratio recomputed from I
             perr = fkk::dev::launch_project16(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt16, b->npad, kq,
                                               kp, ctx->Z.p, kp, part, k, s);
-        else if (p->gram_prec == FKK_PREC_BF16)  // ctx->L holds the packed BF16 l: start from I
+        else if (gprec == FKK_PREC_BF16)  // ctx->L holds the packed BF16 l: start from I
             perr = fkk::dev::launch_project(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
                                             ctx->Z.p, kp, part, k, s, false);
         else  // the FP32 l of the Gram pass

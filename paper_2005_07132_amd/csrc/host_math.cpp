@@ -875,6 +875,73 @@ int eigh_topk(const double* a_in, int n, int k, double* vals, double* vecs, int 
     return eig_tridiag_topk(d.data(), e.data(), beta.data(), vstore.data(), n, k, vals, vecs);
 }
 
+// ---------------------------------------------------------------------------
+// Small dense kernels of the randomized range finder (n x l, l <= 128).
+// ---------------------------------------------------------------------------
+void gram_cols(const double* X, int n, int l, double* G) {
+    Pool& pool = host_pool();
+    const int nt = pool.size();
+    std::vector<double> part((size_t)nt * l * l, 0.0);
+    pool.run([&](int tid, int nthr) {
+        int r0, r1;
+        split(0, n, tid, nthr, &r0, &r1);
+        double* g = &part[(size_t)tid * l * l];
+        for (int r = r0; r < r1; ++r) {
+            const double* x = X + (size_t)r * l;
+            for (int a = 0; a < l; ++a) {
+                const double xa = x[a];
+                double* ga = g + (size_t)a * l;
+                for (int b = a; b < l; ++b) ga[b] += xa * x[b];
+            }
+        }
+    });
+    std::fill(G, G + (size_t)l * l, 0.0);
+    for (int t = 0; t < nt; ++t)  // fixed order: the same sums every call
+        for (size_t i = 0; i < (size_t)l * l; ++i) G[i] += part[(size_t)t * l * l + i];
+    for (int a = 0; a < l; ++a)
+        for (int b = 0; b < a; ++b) G[(size_t)a * l + b] = G[(size_t)b * l + a];
+}
+
+bool cholesky_upper(double* G, int l) {
+    for (int j = 0; j < l; ++j) {
+        double dj = G[(size_t)j * l + j];
+        for (int c = 0; c < j; ++c) dj -= G[(size_t)c * l + j] * G[(size_t)c * l + j];
+        if (!(dj > 0.0) || !std::isfinite(dj)) return false;
+        const double rjj = std::sqrt(dj);
+        G[(size_t)j * l + j] = rjj;
+        for (int col = j + 1; col < l; ++col) {
+            double v = G[(size_t)j * l + col];
+            for (int c = 0; c < j; ++c) v -= G[(size_t)c * l + j] * G[(size_t)c * l + col];
+            G[(size_t)j * l + col] = v / rjj;
+        }
+        for (int r = j + 1; r < l; ++r) G[(size_t)r * l + j] = 0.0;
+    }
+    return true;
+}
+
+void solve_right_upper(double* X, int n, int l, const double* R) {
+    parallel_rows(n, [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r) {
+            double* x = X + (size_t)r * l;
+            for (int j = 0; j < l; ++j) {  // y R = x, column by column
+                double v = x[j];
+                for (int i = 0; i < j; ++i) v -= x[i] * R[(size_t)i * l + j];
+                x[j] = v / R[(size_t)j * l + j];
+            }
+        }
+    });
+}
+
+bool orthonormalize_cols(double* X, int n, int l) {
+    std::vector<double> G((size_t)l * l);
+    for (int pass = 0; pass < 2; ++pass) {  // Cholesky QR, twice
+        gram_cols(X, n, l, G.data());
+        if (!cholesky_upper(G.data(), l)) return false;
+        solve_right_upper(X, n, l, G.data());
+    }
+    return true;
+}
+
 int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double* vals, double* Y) {
     if (n <= 0 || k <= 0 || k > n) return -1;
     Pool& pool = host_pool();

@@ -57,6 +57,16 @@ int eig_tridiag_topk(const double* d, const double* e, const double* beta, const
 int tridiag_eigvecs(const double* d, const double* e, int n, int k, double* vals, double* Y);
 void tridiag_back_transform(const double* beta, const double* vstore, int n, int k, double* Y, double* vecs);
 
+// Small dense FP64 kernels of the randomized range finder (X: n x l
+// row-major, l small): G = X^T X (both triangles; per-thread partial sums
+// added in thread order); in place upper-triangular R with G = R^T R (false
+// if G is not positive definite); X <- X R^-1; an orthonormal basis of the
+// columns of X in place by Cholesky QR applied twice (false on breakdown).
+void gram_cols(const double* X, int n, int l, double* G);
+bool cholesky_upper(double* G, int l);
+void solve_right_upper(double* X, int n, int l, const double* R);
+bool orthonormalize_cols(double* X, int n, int l);
+
 // Default readings of parameters the paper leaves open.
 int default_fft_len(int n);
 double default_als_lambda(int n);

@@ -42,6 +42,15 @@ hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& p
                        double* partial, hipStream_t s, bool fp64 = false);
 hipError_t launch_gram_reduce(const double* partial, const GramPlan& plan, const int* d_tiles, int N, double* G,
                               hipStream_t s);
+// The same kernels for the product of two tall matrices, L^T R: tile
+// (bi, bj) of d_tiles pairs columns 128 bi.. of L with columns 128 bj.. of R
+// (both padded with readable columns up to the tile edges); plan.tiles is
+// the number of listed tiles.  The rect reduction writes the rows x cols
+// block of out (row 128 bi + r, column 128 bj + c) without symmetrising.
+hipError_t launch_gram_pair(const float* L, int64_t ldl, const float* R, int64_t ldr, int64_t M,
+                            const GramPlan& plan, const int* d_tiles, double* partial, hipStream_t s, bool fp64);
+hipError_t launch_gram_reduce_rect(const double* partial, const GramPlan& plan, const int* d_tiles, int rows,
+                                   int cols, double* out, int64_t ld_out, hipStream_t s);
 size_t colsum_scratch_doubles(int N);
 hipError_t launch_colsum_reduce(const double* part, int64_t nparts, int stride, int N, double* mid, double* out,
                                 hipStream_t s);

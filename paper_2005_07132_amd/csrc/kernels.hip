@@ -122,8 +122,11 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // result rows are interleaved differently, see the store).  Needed
 // where the Gram must resolve eigenvalue gaps below the rounding of the
 // FP32 matrix cores, which do not round each sum correctly.
+// Tile (bi, bj) of the list is the product of columns 128 bi.. of L and
+// columns 128 bj.. of R (R = L for the Gram itself).
 template <bool F64>
-__global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restrict__ L, int64_t ldl, int64_t M,
+__global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restrict__ L, int64_t ldl,
+                                                            const float* __restrict__ R, int64_t ldr, int64_t M,
                                                             int T, int64_t rpc, const int* __restrict__ tiles,
                                                             double* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) float sA[2][GKC][GLD];
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
     const int tile = rr % T;
     const int chunk = (rr / T) * 8 + xcd;
     const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
-    const bool diag = (bi == bj);
+    const bool diag = (bi == bj) && (L == R);
     const int64_t m0 = (int64_t)chunk * rpc;
     const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
 
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
     const int lr = tid >> 5;                  // 0..15
     const int lc = (tid & 31) * 4;
     const float* La = L + bi * GT + lc;
-    const float* Lb = L + bj * GT + lc;
+    const float* Lb = R + bj * GT + lc;
 
     doublex4 acc64[2][4];
 #pragma unroll
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const float* __restr
             const int64_t rc = row < m1 ? row : m1 - 1;
             keep[p] = row < m1 ? 1.f : 0.f;
             xa[p] = *reinterpret_cast<const float4*>(La + rc * ldl);
-            xb[p] = *reinterpret_cast<const float4*>(Lb + rc * ldl);
+            xb[p] = *reinterpret_cast<const float4*>(Lb + rc * ldr);
         }
     };
     auto store = [&](int buf) {
@@ -312,13 +315,43 @@ hipError_t launch_logratio(const float* I, int64_t M, int N, int64_t ld, const f
 
 hipError_t launch_gram(const float* L, int64_t ldl, int64_t M, const GramPlan& plan, const int* d_tiles,
                        double* partial, hipStream_t s, bool fp64) {
+    return launch_gram_pair(L, ldl, L, ldl, M, plan, d_tiles, partial, s, fp64);
+}
+
+hipError_t launch_gram_pair(const float* L, int64_t ldl, const float* R, int64_t ldr, int64_t M,
+                            const GramPlan& plan, const int* d_tiles, double* partial, hipStream_t s, bool fp64) {
+    if (plan.tiles < 1 || plan.chunks < 1 || M < 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(kGramThreads);
     if (fp64)
-        hipLaunchKernelGGL(gram_kernel<true>, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles,
-                           partial);
+        hipLaunchKernelGGL(gram_kernel<true>, grid, block, 0, s, L, ldl, R, ldr, M, plan.tiles, plan.rows_per_chunk,
+                           d_tiles, partial);
     else
-        hipLaunchKernelGGL(gram_kernel<false>, grid, block, 0, s, L, ldl, M, plan.tiles, plan.rows_per_chunk, d_tiles,
-                           partial);
+        hipLaunchKernelGGL(gram_kernel<false>, grid, block, 0, s, L, ldl, R, ldr, M, plan.tiles,
+                           plan.rows_per_chunk, d_tiles, partial);
+    return hipGetLastError();
+}
+
+// Sum of the chunk partials of each listed tile, in chunk order, into the
+// rows x cols block of out (tile (bi, bj) at rows 128 bi.., columns 128 bj..).
+__global__ void gram_reduce_rect_kernel(const double* __restrict__ partial, int T, int C,
+                                        const int* __restrict__ tiles, int rows, int cols, double* __restrict__ out,
+                                        int64_t ld_out) {
+    const int tile = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= GT * GT) return;
+    const int r = tiles[2 * tile] * GT + e / GT, c = tiles[2 * tile + 1] * GT + e % GT;
+    if (r >= rows || c >= cols) return;
+    double acc = 0.0;
+    for (int ch = 0; ch < C; ++ch) acc += partial[((size_t)ch * T + tile) * (size_t)(GT * GT) + e];
+    out[(int64_t)r * ld_out + c] = acc;
+}
+
+hipError_t launch_gram_reduce_rect(const double* partial, const GramPlan& plan, const int* d_tiles, int rows,
+                                   int cols, double* out, int64_t ld_out, hipStream_t s) {
+    if (plan.tiles < 1 || ld_out < cols) return hipErrorInvalidValue;
+    dim3 grid(GT * GT / 256, plan.tiles);
+    hipLaunchKernelGGL(gram_reduce_rect_kernel, grid, dim3(256), 0, s, partial, plan.tiles, plan.chunks, d_tiles,
+                       rows, cols, out, ld_out);
     return hipGetLastError();
 }
 
