@@ -400,6 +400,23 @@ def main():
                           "frac_of_fp64_peak": gram_flop / (stage64["dev_ms_gram"] * 1e-3) / PEAK_FP64_MFMA}}
     log(f"fp64-gram fit: {ms64:.2f} ms/step")
 
+    # the same fit with the randomized range finder in place of Gram + eigensolve;
+    # its output against the FP64-Gram fit's (still in `out`)
+    log("fit with the randomized range finder")
+    prr = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
+                    svd_mode=fk.SVD_RANDOMIZED, rrf_oversample=10, rrf_power_iters=1)
+    out_rr = torch.empty_like(out)
+    msrr, stagerr, brr = fit_steps(ctx, I, cube.i_ref, prr, args.steps, 1, out_rr, torch, "randomized")
+    brr.free()
+    per = ((out_rr - out).abs().amax(dim=1) / out.abs().amax(dim=1).clamp_min(1e-30)).double()
+    randomized = {"fit_ms_per_step": msrr, "fit_spectra_per_s": m / (msrr * 1e-3), "stages_ms": stagerr,
+                  "oversample": 10, "power_iters": 1,
+                  "error_vs_fp64_gram_fit": {"max": float(per.max()), "rms": float(per.pow(2).mean().sqrt()),
+                                             "p99": float(torch.quantile(per[:: max(1, m // 100000)], 0.99))}}
+    del out_rr, per
+    log(f"randomized fit: {msrr:.2f} ms/step, max error vs the FP64-Gram fit "
+        f"{randomized['error_vs_fp64_gram_fit']['max']:.2e}")
+
     # the same fit and transforms with BF16 matrix-core operands
     bf16 = None
     if not args.skip_bf16:
@@ -459,6 +476,7 @@ def main():
         "streaming_reference": stream_ref,
         "transform": transform,
         "fp64_gram": fp64_gram,
+        "randomized_svd": randomized,
         "bf16": bf16,
         "plain": plain,
         "serving": serving,
