@@ -294,6 +294,16 @@ def regress_z(i_new, basis) -> np.ndarray:
     return u_new * basis["s"]
 
 
+def basis_residual(i_new, basis) -> float:
+    """How well a stored basis supports new spectra (the retraining
+    criterion of Sec. 5): with A = l diag(f) of the new spectra,
+    ||A - A V V^T||_F / ||A||_F."""
+    ell, _ = log_ratio(i_new, basis["i_ref"], basis["ratio_floor"])
+    a = np.atleast_2d(ell) * basis["f"]
+    v = basis["v"]
+    return float(np.linalg.norm(a - (a @ v) @ v.T) / np.linalg.norm(a))
+
+
 def transform(i_new, basis) -> dict:
     """Apply a stored basis to new spectra."""
     z = regress_z(i_new, basis)

@@ -325,3 +325,28 @@ def test_fit_with_randomized_svd_equals_exact_on_low_rank_data():
     rr = wf.fit(cube.i_cars, cube.i_ref, p, svd="randomized", omega=omega, power_iters=1)
     assert np.array_equal(np.sort(rr["basis"]["q"]), np.sort(exact["basis"]["q"]))
     assert _rel(rr["im"], exact["im"]) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Basis adequacy (retraining criterion, Sec. 5)
+# --------------------------------------------------------------------------
+
+def test_basis_residual_in_span_orthogonal_and_mixed():
+    rng = np.random.default_rng(9)
+    n, k = 120, 5
+    v, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    f = rng.uniform(0.5, 2.0, n)
+    i_ref = rng.uniform(1.0, 2.0, n)
+    basis = {"v": v, "f": f, "i_ref": i_ref, "ratio_floor": 1e-6}
+
+    def spectra(a):  # intensities whose A = l diag(f) is a
+        return i_ref * np.exp(2.0 * a / f)
+
+    inside = rng.standard_normal((40, k)) @ v.T
+    outside = rng.standard_normal((40, n))
+    outside -= (outside @ v) @ v.T
+    assert wf.basis_residual(spectra(inside), basis) < 1e-12
+    assert abs(wf.basis_residual(spectra(outside), basis) - 1.0) < 1e-12
+    mix = inside + 0.3 * outside
+    expected = np.linalg.norm(0.3 * outside) / np.linalg.norm(mix)
+    assert abs(wf.basis_residual(spectra(mix), basis) - expected) < 1e-12
