@@ -248,6 +248,17 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
                                   const double* h_x, int32_t n_q, const fkk_params* p,
                                   fkk_basis** out_basis);
 
+/* Adequacy of a stored basis for new spectra d_I (M x N, device), the
+ * retraining criterion of Sec. 5 ("retraining when ... the current basis
+ * vectors do not adequately support new data"): with A = l diag(f) (the
+ * basis's I_ref and f), the relative residual of the projection onto the
+ * basis vectors, ||A - A V V^T||_F / ||A||_F in [0, 1], written to
+ * *h_residual (host).  Computed as sqrt(1 - ||A V||^2 / ||A||^2) from FP64
+ * sums of the FP32 projection, so residuals below about 1e-3 are not
+ * resolved.  Synchronises the context's stream. */
+fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M, int64_t ld,
+                              double* h_residual);
+
 /*
  * Projection and sub-sampling (Eq. 13-15): Z = A V_k = l diag(f) V_k for the
  * rows of d_I (M x N, stride ld) into d_z (M x k FP32, stride ld_z >= k), and

@@ -88,8 +88,8 @@ SYMBOLS = [
     "fkk_version", "fkk_status_string", "fkk_params_default", "fkk_ctx_create", "fkk_ctx_destroy",
     "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
     "fkk_gram",
-    "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
-    "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
+    "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
+    "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
     "fkk_basis_get_precision", "fkk_server_create", "fkk_server_add_basis",
     "fkk_server_submit", "fkk_server_wait", "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats",
     "fkk_server_destroy",
@@ -125,6 +125,7 @@ def lib() -> ctypes.CDLL:
     L.fkk_basis_from_factors.argtypes = [vp, i32, i32, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                          _c_double_p, i32, ctypes.POINTER(Params), ctypes.POINTER(vp)]
     L.fkk_project.argtypes = [vp, vp, vp, i64, i64, vp, i64, _c_int64_p, _c_int64_p]
+    L.fkk_basis_residual.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
     L.fkk_reconstruct.argtypes = [vp, vp, vp, i64, i64, vp, i64, i32]
     L.fkk_basis_import.argtypes = [vp, ctypes.POINTER(BasisDesc), ctypes.POINTER(vp)]
     L.fkk_basis_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -145,8 +146,9 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = ctypes.c_int
     for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64", "fkk_gram",
                  "fkk_eigh_topk",
-                 "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_import",
-                 "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision", "fkk_basis_get_precision"):
+                 "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
+                 "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision",
+                 "fkk_basis_get_precision"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -401,6 +403,15 @@ class Context:
         self._ok(st, "project")
         return (z, qmax, qmin) if want_q else z
 
+    def residual(self, basis: Basis, I) -> float:
+        """||A - A V V^T||_F / ||A||_F of the spectra I against the basis."""
+        _check_tensor(I, "I")
+        m, _ = I.shape
+        r = ctypes.c_double()
+        st = lib().fkk_basis_residual(self._h, basis.handle, I.data_ptr(), m, I.stride(0), ctypes.byref(r))
+        self._ok(st, "basis_residual")
+        return r.value
+
     def reconstruct(self, basis: Basis, z, plane: int = OUT_IM, out=None):
         import torch
         _check_tensor(z, "z")
@@ -495,4 +506,4 @@ class Server:
 
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
            "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16",
-           "PREC_FP64"]
+           "PREC_FP64", "SVD_GRAM", "SVD_RANDOMIZED"]

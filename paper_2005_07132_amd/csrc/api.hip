@@ -1067,6 +1067,45 @@ fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64
     return FKK_OK;
 }
 
+fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld,
+                              double* h_residual) {
+    if (!ctx) return FKK_EINVAL;
+    if (!b || !h_residual) return ctx->fail(FKK_EINVAL, "NULL argument");
+    fkk_status st;
+    if ((st = check_matrix(ctx, d_I, M, b->N, ld, "I")) != FKK_OK) return st;
+    if (b->device != ctx->device) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int N = b->N, k = b->k, kp = b->kp;
+    // W = diag(f) V (FP32, kp x npad), without the Eq. 25 shrink
+    std::vector<float> wt((size_t)kp * b->npad, 0.f);
+    for (int c = 0; c < k; ++c)
+        for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(b->f[j] * b->v[(size_t)j * k + c]);
+    const int64_t nres = fkk::dev::residual_blocks(M);
+    FKK_HIP(ctx, ctx->X.ensure(wt.size()));
+    FKK_HIP(ctx, ctx->Z.ensure((size_t)M * kp));
+    FKK_HIP(ctx, ctx->fdev.ensure(N));
+    FKK_HIP(ctx, ctx->colsum_part.ensure(2 * (size_t)nres));
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->X.p, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, b->f.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+    const fkk::dev::ArgPart none{nullptr, nullptr, nullptr, nullptr};
+    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, ctx->X.p, b->npad, kp, k,
+                                          ctx->Z.p, kp, none, 0, s));
+    FKK_HIP(ctx, fkk::dev::launch_residual_sums(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, ctx->fdev.p, ctx->Z.p,
+                                                kp, k, ctx->colsum_part.p, s));
+    std::vector<double> part(2 * (size_t)nres);
+    FKK_HIP(ctx, hipMemcpyAsync(part.data(), ctx->colsum_part.p, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                s));
+    FKK_HIP(ctx, hipStreamSynchronize(s));
+    double sa = 0.0, sz = 0.0;
+    for (int64_t i = 0; i < nres; ++i) {
+        sa += part[2 * i];
+        sz += part[2 * i + 1];
+    }
+    *h_residual = sa > 0.0 ? std::sqrt(std::max(0.0, 1.0 - sz / sa)) : 0.0;
+    return FKK_OK;
+}
+
 fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, int64_t M, int64_t ld_z,
                            float* d_out, int64_t ld_out, int32_t plane) {
     if (!ctx) return FKK_EINVAL;

@@ -68,6 +68,11 @@ inline int64_t proj_blocks(int64_t M) { return (M + kProjRows - 1) / kProjRows; 
 hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                           const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z,
                           ArgPart part, int k_arg, hipStream_t s, bool logged = false);
+// Basis residual sums: part[2 b], part[2 b + 1] = sums of (l f)^2 and of
+// the squared first k columns of Z over block b's residual_blocks rows.
+int64_t residual_blocks(int64_t M);
+hipError_t launch_residual_sums(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                                const double* f, const float* Z, int64_t ld_z, int k, double* part, hipStream_t s);
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
                                 long long* qmin, hipStream_t s);
 

@@ -568,6 +568,61 @@ hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, lo
     return hipGetLastError();
 }
 
+// Sums for the basis residual: per block of 64 spectra, the FP64 sums of
+// (l_j f_j)^2 over the spectra's columns and of z_c^2 over their first k
+// projections (Z = A V from the projection kernel).
+constexpr int kResRows = 64;
+__global__ __launch_bounds__(256) void residual_sums_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                            const float* __restrict__ rinv, float floor,
+                                                            const double* __restrict__ f, const float* __restrict__ Z,
+                                                            int64_t ld_z, int k, double* __restrict__ part) {
+    __shared__ double red[2][4];
+    const int64_t r0 = (int64_t)blockIdx.x * kResRows;
+    const int64_t r1 = r0 + kResRows < M ? r0 + kResRows : M;
+    double sa = 0.0, sz = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const float* row = I + r * ld;
+        for (int j = threadIdx.x; j < N; j += blockDim.x) {
+            bool bad;
+            const double a = (double)log_ratio(row[j], rinv[j], rinv[N + j], floor, bad) * f[j];
+            sa += a * a;
+        }
+        for (int c = threadIdx.x; c < k; c += blockDim.x) {
+            const double z = Z[r * ld_z + c];
+            sz += z * z;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        sa += __shfl_xor(sa, off);
+        sz += __shfl_xor(sz, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = sa;
+        red[1][wave] = sz;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tz = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            ta += red[0][w];
+            tz += red[1][w];
+        }
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tz;
+    }
+}
+
+int64_t residual_blocks(int64_t M) { return (M + kResRows - 1) / kResRows; }
+
+hipError_t launch_residual_sums(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                                const double* f, const float* Z, int64_t ld_z, int k, double* part, hipStream_t s) {
+    if (M < 1) return hipSuccess;
+    hipLaunchKernelGGL(residual_sums_kernel, dim3((unsigned)residual_blocks(M)), dim3(256), 0, s, I, M, N, ld, rinv,
+                       floor, f, Z, ld_z, k, part);
+    return hipGetLastError();
+}
+
 __global__ void gather_rows_kernel(const float* __restrict__ Z, int64_t ld_z, int k, const long long* __restrict__ q,
                                    int n_q, float* __restrict__ X) {
     const int r = blockIdx.x;

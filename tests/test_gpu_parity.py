@@ -363,6 +363,27 @@ def test_fit_randomized_svd_tissue_and_default_test_matrix(ctx):
         f"output vs exact fit max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
 
 
+def test_basis_residual_matches_oracle(ctx):
+    # the retraining criterion on the training data, on new frames from the
+    # same components, and on frames from other components (the basis no
+    # longer supports them); device vs the FP64 oracle on the same basis
+    say("basis residual")
+    cube = tissue(rows=48, cols=48, n=256, key=41)
+    p = oracle_params(cube, k=10)
+    b, _, _ = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p), want_out=False)
+    e = b.export()
+    other = synth.tissue_cube(rows=32, cols=32, n=256, map_key=42, noise_key=42, comp_key=43)
+    same = synth.tissue_cube(rows=32, cols=32, n=256, map_key=44, noise_key=44)
+    res = {}
+    for name, data in (("train", cube), ("same components", same), ("other components", other)):
+        got = ctx.residual(b, dev(data.i_cars))
+        ref = wf.basis_residual(data.i_cars.astype(np.float64), e)
+        res[name] = (got, ref)
+        assert abs(got - ref) <= 1e-4 * ref + 1e-3
+    say("basis residual: " + ", ".join(f"{k} {g:.4f} (oracle {r:.4f})" for k, (g, r) in res.items()))
+    assert res["other components"][1] > 1.25 * res["same components"][1]
+
+
 def test_fit_tissue_with_oracle_subsample(ctx):
     say("fit tissue q_override")
     cube = tissue(rows=64, cols=64, n=256, key=5)
