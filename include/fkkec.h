@@ -115,7 +115,7 @@ typedef struct {
      * vectors (l <= min(N, 128)), then the SVD of Q^T A; approximate in the
      * tail of the spectrum).  gram_prec does not apply to it: its products
      * of A are the FP32 projection and FP64-accumulated products of the FP32
-     * log ratio. */
+     * log ratio.  A of rank below l fails with FKK_ERANK. */
     int32_t svd_mode;
     int32_t rrf_oversample;   /* l - k, >= 0                                 */
     int32_t rrf_power_iters;  /* subspace iterations, >= 0                   */

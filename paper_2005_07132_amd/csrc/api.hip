@@ -574,8 +574,6 @@ fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk
     py.tiles = 1;   // (0, 0): Y^T Y
     std::vector<int> pairs(2 * (size_t)(nb + 1), 0);
     for (int bi = 0; bi < nb; ++bi) pairs[2 * bi] = bi;
-    const int64_t nblk = fkk::dev::proj_blocks(M);
-    (void)nblk;
     FKK_HIP(ctx, ctx->Z.ensure((size_t)M * LY));
     FKK_HIP(ctx, ctx->X.ensure((size_t)LY * npad));
     FKK_HIP(ctx, ctx->partial.ensure(pc.partial_doubles()));
@@ -610,14 +608,14 @@ fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk
         for (int a = 0; a < l; ++a)
             for (int b = 0; b < l; ++b) G[(size_t)a * l + b] = h_gy[(size_t)a * LY + b];
         if (!fkk::cholesky_upper(G.data(), l))
-            return ctx->fail(FKK_EINTERNAL, "range finder: Y^T Y not positive definite (rank of A below %d)", l);
+            return ctx->fail(FKK_ERANK, "range finder: Y^T Y not positive definite (rank of A below l = %d)", l);
         for (int j = 0; j < N; ++j)
             for (int c = 0; c < l; ++c) AtQ[(size_t)j * l + c] = f[j] * h_c[(size_t)j * LY + c];
         fkk::solve_right_upper(AtQ.data(), N, l, G.data());  // A^T Q = A^T Y R^-1
         if (it < p->rrf_power_iters) {
             W = AtQ;
             if (!fkk::orthonormalize_cols(W.data(), N, l))
-                return ctx->fail(FKK_EINTERNAL, "range finder: A^T Q rank deficient");
+                return ctx->fail(FKK_ERANK, "range finder: A^T Q rank deficient (rank of A below l = %d)", l);
         }
     }
     // B = Q^T A = (A^T Q)^T: B B^T = (A^T Q)^T (A^T Q); V = B^T U_B / s
