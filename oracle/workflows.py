@@ -52,6 +52,7 @@ class Params:
     ml_lambda: float = 0.0
     ratio_floor: float = 1.0e-6
     k_max: int = 128        # k = 0: at most this many vectors from the rank rule
+    sec_form: int = 0       # plain workflow: 0 log form (Eq. 19), 1 real-part form (Eq. 4-5)
     q_override: np.ndarray | None = field(default=None, repr=False)
 
     def with_(self, **kw) -> "Params":
@@ -198,8 +199,15 @@ def plain(i_cars, i_ref, p: Params) -> dict:
     phi = _hilbert(ell, p)                     # KK phase, Eq. 2
     phi_err = _detrend(phi, p)                 # PEC: phase error by D
     amp_log = ell + _hilbert(phi_err, p)       # ln|K| + H{phi_err}, Eq. 5
-    amp_log = amp_log - _trend(amp_log, p)     # SEC, log form (Eq. 19)
-    out = retrieve(amp_log, phi - phi_err)
+    if p.sec_form == 1:
+        # SEC as Eq. 4-5: K e^{H{phi_err}} e^{-i phi_err} divided by the
+        # trendline (or mean) of its real part
+        out = retrieve(amp_log, phi - phi_err)
+        scale = _trend(out["re"], p)
+        out = {"im": out["im"] / scale, "re": out["re"] / scale, "abs": out["abs"] / np.abs(scale)}
+    else:
+        amp_log = amp_log - _trend(amp_log, p)     # SEC, log form (Eq. 19)
+        out = retrieve(amp_log, phi - phi_err)
     out.update(phi=phi, phi_err=phi_err, clamps=clamps)
     return out
 

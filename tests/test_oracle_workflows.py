@@ -350,3 +350,29 @@ def test_basis_residual_in_span_orthogonal_and_mixed():
     mix = inside + 0.3 * outside
     expected = np.linalg.norm(0.3 * outside) / np.linalg.norm(mix)
     assert abs(wf.basis_residual(spectra(mix), basis) - expected) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# SEC in the real-part form of Eq. 4-5 (conventional workflow)
+# --------------------------------------------------------------------------
+
+def test_sec_real_part_form_mean_and_scale():
+    cube = _small_cube(key=16)
+    p = wf.Params(sec_mode=op.SEC_MEAN, sec_form=1, als_lambda=1e4)
+    out = wf.plain(cube.i_cars, cube.i_ref, p)
+    # Eq. 4: after correction the mean real part over frequency is 1
+    assert np.abs(out["re"].mean(axis=1) - 1.0).max() < 1e-13
+    # SEC removes the constant amplitude error Xi of the reference (Sec. 2.1)
+    for sec_mode in (op.SEC_MEAN, op.SEC_SAVGOL):
+        q = p.with_(sec_mode=sec_mode, sg_window=51)
+        a = wf.plain(cube.i_cars, cube.i_ref, q)
+        b = wf.plain(cube.i_cars, 3.7 * cube.i_ref, q)
+        assert _rel(b["im"], a["im"]) < 1e-11
+    # the phase (and so Im/Re up to the positive scale) is the log form's
+    lg = wf.plain(cube.i_cars, cube.i_ref, p.with_(sec_form=0))
+    np.testing.assert_allclose(np.arctan2(out["im"], out["re"]), np.arctan2(lg["im"], lg["re"]), atol=1e-12)
+    # NRB-only input: zero Raman
+    w = synth.wavenumbers(200)
+    ref = synth.reference(w)
+    nrb = wf.plain(np.tile(ref, (20, 1)), ref, wf.Params(sec_form=1, als_lambda=1e4))
+    assert np.abs(nrb["im"]).max() < 1e-15 and np.abs(nrb["re"] - 1.0).max() < 1e-14
