@@ -52,6 +52,10 @@ typedef enum {
 enum { FKK_DETREND_ALS = 0, FKK_DETREND_WHITTAKER = 1 };
 /* Trendline operator M of SEC (Eq. 4, Eq. 22). */
 enum { FKK_SEC_SAVGOL = 0, FKK_SEC_MEAN = 1 };
+/* Form of SEC in the conventional method: subtract M{.} of the log
+ * magnitude (Eq. 19, as fSEC does on the basis) or divide K' = K e^{H{phi_err}}
+ * e^{-i phi_err} by M{Re K'} (Eq. 4-5).  fkk_fit takes the log form only. */
+enum { FKK_SEC_FORM_LOG = 0, FKK_SEC_FORM_RE = 1 };
 /* Padding of the discrete Hilbert transform. */
 enum { FKK_PAD_EDGE = 0, FKK_PAD_ZERO = 1 };
 /* Variance scaling f(w) of Eq. 9-10. */
@@ -117,6 +121,7 @@ typedef struct {
      * of A are the FP32 projection and FP64-accumulated products of the FP32
      * log ratio.  A of rank below l fails with FKK_ERANK. */
     int32_t svd_mode;
+    int32_t sec_form;         /* FKK_SEC_FORM_* (fkk_plain / fkk_plain_f64)   */
     int32_t rrf_oversample;   /* l - k, >= 0                                 */
     int32_t rrf_power_iters;  /* subspace iterations, >= 0                   */
     uint64_t rrf_seed;        /* test matrix when rrf_omega is NULL          */

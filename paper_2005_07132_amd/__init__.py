@@ -26,6 +26,7 @@ F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
 SVD_GRAM, SVD_RANDOMIZED = 0, 1
+SEC_FORM_LOG, SEC_FORM_RE = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
@@ -41,7 +42,8 @@ class Params(ctypes.Structure):
         ("ratio_floor", ctypes.c_double), ("strict", ctypes.c_int32), ("gram_prec", ctypes.c_int32),
         ("recon_prec", ctypes.c_int32), ("output", ctypes.c_int32),
         ("q_override", _c_int64_p), ("n_q_override", ctypes.c_int32),
-        ("svd_mode", ctypes.c_int32), ("rrf_oversample", ctypes.c_int32), ("rrf_power_iters", ctypes.c_int32),
+        ("svd_mode", ctypes.c_int32), ("sec_form", ctypes.c_int32), ("rrf_oversample", ctypes.c_int32),
+        ("rrf_power_iters", ctypes.c_int32),
         ("rrf_seed", ctypes.c_uint64), ("rrf_omega", _c_double_p),
     ]
 
@@ -506,4 +508,4 @@ class Server:
 
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
            "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16",
-           "PREC_FP64", "SVD_GRAM", "SVD_RANDOMIZED"]
+           "PREC_FP64", "SVD_GRAM", "SVD_RANDOMIZED", "SEC_FORM_LOG", "SEC_FORM_RE"]

@@ -178,8 +178,11 @@ struct fkk_ctx {
 namespace {
 
 // auto_k: k = 0 (the rank rule of Sec. 4.1) is allowed.
-fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = false) {
+// plain: the conventional method, the only one with the real-part SEC form.
+fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = false, bool plain = false) {
     if (!p) return ctx->fail(FKK_EINVAL, "params is NULL");
+    if (p->sec_form != FKK_SEC_FORM_LOG && !(plain && p->sec_form == FKK_SEC_FORM_RE))
+        return ctx->fail(FKK_EINVAL, "sec_form=%d (the real-part form is for fkk_plain only)", p->sec_form);
     if (!(auto_k && p->k == 0) && (p->k < 1 || p->k > N))
         return ctx->fail(FKK_EINVAL, "k=%d outside 1..N=%d", p->k, N);
     if (p->k > 128) return ctx->fail(FKK_ERANK, "k=%d above the supported 128", p->k);
@@ -685,6 +688,7 @@ void fkk_params_default(fkk_params* p) {
     p->output = FKK_OUT_IM;
     p->q_override = nullptr;
     p->n_q_override = 0;
+    p->sec_form = FKK_SEC_FORM_LOG;
     p->svd_mode = FKK_SVD_GRAM;
     p->rrf_oversample = 10;
     p->rrf_power_iters = 1;
@@ -1198,7 +1202,7 @@ fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
     if (f64 && (reinterpret_cast<uintptr_t>(d_I) & 7) != 0) return ctx->fail(FKK_EINVAL, "I must be 8-byte aligned");
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
-    if ((st = check_params(ctx, p, N)) != FKK_OK) return st;
+    if ((st = check_params(ctx, p, N, false, true)) != FKK_OK) return st;
     if (!d_out || ld_out < N) return ctx->fail(FKK_EINVAL, "bad output");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     fkk::plain::Config cfg;
@@ -1210,6 +1214,7 @@ fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t
     cfg.p = p->als_p;
     cfg.iters = p->als_iters;
     cfg.sec_mode = p->sec_mode;
+    cfg.sec_re = p->sec_form == FKK_SEC_FORM_RE ? 1 : 0;
     cfg.window = p->sg_window ? p->sg_window : fkk::default_sg_window(N);
     cfg.order = p->sg_order;
     cfg.floor = p->ratio_floor;

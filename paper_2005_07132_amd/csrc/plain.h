@@ -21,6 +21,7 @@ struct Config {
     double p = 1e-3;
     int iters = 10;
     int sec_mode = 0;   // 0 Savitzky-Golay, 1 mean
+    int sec_re = 0;     // SEC form: 0 log magnitude minus its trendline (Eq. 19), 1 divide by the trendline of Re (Eq. 4-5)
     int window = 0;
     int order = 2;
     double floor = 1e-6;

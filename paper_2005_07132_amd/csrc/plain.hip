@@ -251,9 +251,9 @@ template <typename TOut>
 __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, int N, int L, int bits, int pad_mode,
                                                        const double2* __restrict__ tw, const double* __restrict__ ell,
                                                        const double* __restrict__ phi,
-                                                       const double* __restrict__ err, int sec_mode, int half,
-                                                       int order, const double* __restrict__ ginv, int plane,
-                                                       TOut* __restrict__ out, int64_t ld_out) {
+                                                       const double* __restrict__ err, int sec_mode, int sec_re,
+                                                       int half, int order, const double* __restrict__ ginv,
+                                                       int plane, TOut* __restrict__ out, int64_t ld_out) {
     extern __shared__ double2 z[];
     __shared__ double part[4][kThreads + 1];
     const int64_t la = 2 * (int64_t)blockIdx.x, lb = la + 1;
@@ -293,9 +293,27 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
     __syncthreads();
     double* pre = reinterpret_cast<double*>(z);  // 4 prefix arrays of N + 1
     for (int s = 0; s < (hb ? 2 : 1); ++s) {
-        const double* y = rho + (size_t)s * N;
+        double* y = rho + (size_t)s * N;
         const int64_t lrow = la + s;
         TOut* orow = out + (m0 + lrow) * ld_out;
+        // the corrected spectrum K' = exp(rho) exp(i (phi - phi_err)); the
+        // real-part form of SEC (Eq. 4-5) divides it by the trendline of
+        // Re K', so the trendline then acts on Re K' instead of rho
+        auto corrected = [&](int i, int cnt_i, double trend) -> TOut {
+            const double ph = phi[lrow * N + i] - err[lrow * N + i];
+            if (sec_re) {
+                const double mag = exp(ell[lrow * N + i] + hv[s][cnt_i]);
+                return (TOut)(plane == 0 ? mag * sin(ph) / trend
+                                         : (plane == 1 ? mag * cos(ph) / trend : mag / fabs(trend)));
+            }
+            const double mag = exp(y[i] - trend);
+            return (TOut)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
+        };
+        if (sec_re) {
+            for (int i = threadIdx.x; i < N; i += blockDim.x)
+                y[i] = exp(y[i]) * cos(phi[lrow * N + i] - err[lrow * N + i]);
+            __syncthreads();
+        }
         if (sec_mode == 1) {
             double acc = 0.0;
             for (int i = threadIdx.x; i < N; i += blockDim.x) acc += y[i];
@@ -308,12 +326,8 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
             }
             __syncthreads();
             const double mean = part[1][0];
-            for (int i = threadIdx.x; i < N; i += blockDim.x) {
-                const double r = y[i] - mean;
-                const double ph = phi[lrow * N + i] - err[lrow * N + i];
-                const double mag = exp(r);
-                orow[i] = (TOut)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
-            }
+            int ci = 0;
+            for (int i = threadIdx.x; i < N; i += blockDim.x, ++ci) orow[i] = corrected(i, ci, mean);
             __syncthreads();
             continue;
         }
@@ -359,7 +373,8 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
         }
         __syncthreads();
         const int m = order + 1;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        int ci = 0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x, ++ci) {
             // window [s0, s0 + 2h] and the point's offset from its centre
             int s0 = i - half;
             if (s0 < 0) s0 = 0;
@@ -389,10 +404,7 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
                 val += tp * g;
                 tp *= t;
             }
-            const double r = y[i] - val;
-            const double ph = phi[lrow * N + i] - err[lrow * N + i];
-            const double mag = exp(r);
-            orow[i] = (TOut)(plane == 0 ? mag * sin(ph) : (plane == 1 ? mag * cos(ph) : mag));
+            orow[i] = corrected(i, ci, val);
         }
         __syncthreads();
     }
@@ -542,11 +554,13 @@ hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, i
         if (out_f64)
             hipLaunchKernelGGL(sec_kernel<double>, dim3(pairs), dim3(kThreads), lds, s, m0, nb, N, L, bits,
                                cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi, ws.err,
-                               cfg.sec_mode, half, cfg.order, d_ginv, cfg.plane, static_cast<double*>(d_out), ld_out);
+                               cfg.sec_mode, cfg.sec_re, half, cfg.order, d_ginv, cfg.plane, static_cast<double*>(d_out),
+                               ld_out);
         else
             hipLaunchKernelGGL(sec_kernel<float>, dim3(pairs), dim3(kThreads), lds, s, m0, nb, N, L, bits,
                                cfg.pad_mode, reinterpret_cast<const double2*>(ws.twiddle), ws.ell, ws.phi, ws.err,
-                               cfg.sec_mode, half, cfg.order, d_ginv, cfg.plane, static_cast<float*>(d_out), ld_out);
+                               cfg.sec_mode, cfg.sec_re, half, cfg.order, d_ginv, cfg.plane, static_cast<float*>(d_out),
+                               ld_out);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

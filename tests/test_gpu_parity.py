@@ -456,6 +456,20 @@ def test_plain_path_whittaker_matches_oracle(ctx, sec):
     assert spectrum_err(out, ref).max() < TOL
 
 
+@pytest.mark.parametrize("sec", [op.SEC_SAVGOL, op.SEC_MEAN])
+@pytest.mark.parametrize("plane,key", [(fk.OUT_IM, "im"), (fk.OUT_RE, "re"), (fk.OUT_ABS, "abs")])
+def test_plain_path_real_part_sec_matches_oracle(ctx, sec, plane, key):
+    # SEC of Eq. 4-5: division by the trendline of the real part
+    say(f"plain real-part sec={sec} plane={key}")
+    cube = tissue(rows=20, cols=33, n=256, key=8)
+    p = wf.Params(k=5, detrend=op.DETREND_WHITTAKER, sec_mode=sec, sec_form=1)
+    out = host(ctx.plain(dev(cube.i_cars), cube.i_ref, lib_params(p, sec_form=fk.SEC_FORM_RE, output=plane)))
+    ref = wf.plain(cube.i_cars.astype(np.float64), cube.i_ref, p)[key]
+    assert spectrum_err(out, ref).max() < TOL
+    with pytest.raises(fk.FkkError):  # the factorized SEC is the log form
+        ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p, sec_form=fk.SEC_FORM_RE))
+
+
 def test_plain_path_als_matches_oracle(ctx):
     say("plain als")
     cube = synth.pixel_cube(side=24, n=512)
