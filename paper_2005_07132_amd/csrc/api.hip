@@ -443,8 +443,10 @@ fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) 
 // come first; the packed reflectors follow asynchronously while the host
 // finds the eigenpairs of T, and are waited for only by the back-
 // transformation.  *failed reports a set flag (outputs then unused).
+// With rel_cut > 0 only the pairs above the cut (relative to the largest
+// singular value) get vectors: *k_used of them, vecs then N x *k_used.
 fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta, const double* flag, double* vals,
-                      double* vecs, bool* failed) {
+                      double* vecs, bool* failed, double rel_cut, int* k_used) {
     hipStream_t s = ctx->stream;
     double* h = ctx->hG.p;  // beta | d | e | vstore | flag
     *failed = false;
@@ -464,14 +466,15 @@ fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta,
         }
     }
     std::vector<double> Y((size_t)(k + 3) / 4 * 4 * N, 0.0);
-    const int rc = fkk::tridiag_eigvecs(h + N, h + 2 * N, N, k, vals, Y.data());
+    const int rc = fkk::tridiag_eigvecs(h + N, h + 2 * N, N, k, vals, Y.data(), rel_cut, k_used);
     FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
     if (rc != 0) return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
-    fkk::tridiag_back_transform(h, h + 3 * N, N, k, Y.data(), vecs);
+    fkk::tridiag_back_transform(h, h + 3 * N, N, *k_used, Y.data(), vecs);
     return FKK_OK;
 }
 
-fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed) {
+fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed,
+                      double rel_cut, int* k_used) {
     const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
     const size_t nx = fkk::dev::tridiag_resident_xch_doubles(N);
     // layout of ctx->tri: p0 | p1 | beta | d | e | vstore | flags (2) | exchange (nx)
@@ -494,7 +497,7 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
                                               ctx->tri_spin_limit, s) == hipSuccess) {
             if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
             bool failed = false;
-            const fkk_status st = eig_finish(ctx, N, k, nv, beta, flags, vals, vecs, &failed);
+            const fkk_status st = eig_finish(ctx, N, k, nv, beta, flags, vals, vecs, &failed, rel_cut, k_used);
             if (st != FKK_OK || !failed) return st;
         } else {
             (void)hipGetLastError();  // launch refused (e.g. the grid cannot be co-resident)
@@ -531,7 +534,7 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
         FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     bool failed = false;
-    return eig_finish(ctx, N, k, nv, beta, nullptr, vals, vecs, &failed);
+    return eig_finish(ctx, N, k, nv, beta, nullptr, vals, vecs, &failed, rel_cut, k_used);
 }
 
 // Standard normal numbers for the range finder's test matrix: SplitMix64
@@ -852,18 +855,27 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
             f[j] = 2.0 * mean / std::sqrt(p->alpha * mean + p->sigma_g * p->sigma_g);
         }
     std::vector<double> lam(kcap), V((size_t)N * kcap), sv(kcap);
+    // the rank rule keeps singular values above s_max max(M, N) eps, eps of
+    // the FP32 input
+    const double rank_rel = p->k == 0 ? (double)std::max<int64_t>(M, N) * (double)FLT_EPSILON : 0.0;
+    int k = kcap;
     if (rrf) {
         if ((st = rrf_device(ctx, M, N, f.data(), p, kcap, sv.data(), V.data())) != FKK_OK) return st;
         for (int c = 0; c < kcap; ++c) lam[c] = sv[c] * sv[c];
     } else {
-        if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true)) != FKK_OK) return st;
-        for (int c = 0; c < kcap; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+        // with the rank rule, the eigenvalues come first and only the kept
+        // pairs get eigenvectors; V is then N x k
+        if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true, rank_rel, &k)) != FKK_OK) return st;
+        for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
+        if (k < kcap) {
+            V.resize((size_t)N * k);
+            lam.resize(k);
+            sv.resize(k);
+        }
         r.dev_ms_tridiag = ctx->elapsed(6, 7);
     }
-    int k = kcap;
-    if (p->k == 0) {
-        // singular values above s_max max(M, N) eps, eps of the FP32 input
-        const double cut = sv[0] * (double)std::max<int64_t>(M, N) * (double)FLT_EPSILON;
+    if (p->k == 0 && rrf) {
+        const double cut = sv[0] * rank_rel;
         int cnt = 0;
         for (int c = 0; c < kcap; ++c) cnt += sv[c] > cut ? 1 : 0;
         k = std::max(cnt, 1);

@@ -942,8 +942,10 @@ bool orthonormalize_cols(double* X, int n, int l) {
     return true;
 }
 
-int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double* vals, double* Y) {
+int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double* vals, double* Y, double rel_cut,
+                    int* k_out) {
     if (n <= 0 || k <= 0 || k > n) return -1;
+    if (k_out) *k_out = k;
     Pool& pool = host_pool();
     std::vector<double> d(d_in, d_in + n), e(std::max(n - 1, 1), 0.0);
     for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
@@ -1002,6 +1004,14 @@ int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double
             for (int l = 0; l < 4 && jb + l < j1; ++l) vals[jb + l] = 0.5 * (a[l] + b[l]);
         }
     });
+
+    if (rel_cut > 0.0) {
+        const double cut = std::sqrt(std::max(vals[0], 0.0)) * rel_cut;
+        int cnt = 0;
+        for (int j = 0; j < k; ++j) cnt += std::sqrt(std::max(vals[j], 0.0)) > cut ? 1 : 0;
+        k = std::max(cnt, 1);
+        if (k_out) *k_out = k;
+    }
 
     // ---- eigenvectors of T by inverse iteration ----
     // Each vector is iterated with its own shift (independently, in

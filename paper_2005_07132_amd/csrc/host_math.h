@@ -53,8 +53,12 @@ int eig_tridiag_topk(const double* d, const double* e, const double* beta, const
 // Its two halves: the top-k eigenpairs of T (values descending, vector j of
 // T at Y + j n), which need only d and e; then x = Q y for each vector, the
 // sign rule, and the transpose into vecs (n x k).  Y has room for k rounded
-// up to a multiple of 4 vectors, the ones past k zero.
-int tridiag_eigvecs(const double* d, const double* e, int n, int k, double* vals, double* Y);
+// up to a multiple of 4 vectors, the ones past k zero.  With rel_cut > 0
+// only the pairs whose sqrt(max(value, 0)) exceeds rel_cut times that of
+// the largest (at least one) get vectors; *k_out (when given) receives
+// their count, and values past it are left as bisected.
+int tridiag_eigvecs(const double* d, const double* e, int n, int k, double* vals, double* Y, double rel_cut = 0.0,
+                    int* k_out = nullptr);
 void tridiag_back_transform(const double* beta, const double* vstore, int n, int k, double* Y, double* vecs);
 
 // Small dense FP64 kernels of the randomized range finder (X: n x l
