@@ -306,6 +306,135 @@ def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n
     return bf16
 
 
+def mean_rss(out, cube, chunk=32768):
+    """<RSS> over pixels of sum_w (K - Im{chi/chi_nr})^2, the null RSS (K = 0)
+    beside it; K is a retrieved Im plane copied back from the device."""
+    k = out.cpu().numpy()
+    m = k.shape[0]
+    rss = null = 0.0
+    for i0 in range(0, m, chunk):
+        rows = np.arange(i0, min(i0 + chunk, m))
+        ideal = cube.ideal_im(rows)
+        rss += float(((k[rows].astype(np.float64) - ideal) ** 2).sum())
+        null += float((ideal ** 2).sum())
+    return rss / m, null / m
+
+
+def paper_sim(args):
+    """Replica of the paper's simulation study (Sec. 4.1): the noiseless
+    three-chemical mixture at 4,551 to 291,264 spectra x 810 points.  For
+    each size, three timed runs each of the fKK-EC fit (rank rule, and k=40
+    inside the paper's 35-50 with the FP32 Gram, the FP64 Gram and the range
+    finder), the conventional per-spectrum method and the
+    stored-basis variant (fit on a training strip, then transform every
+    spectrum), all on this GPU; then <RSS> of each against the known
+    Im{chi/chi_nr}.  Prints one JSON line."""
+    import torch
+    import synth
+    import paper_2005_07132_amd as fk
+
+    dev = torch.device("cuda:0")
+    ctx = fk.Context(0)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = args.sim_runs
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            start.record()
+            r = fn()
+            stop.record()
+            torch.cuda.synchronize()
+            ms.append(start.elapsed_time(stop))
+        return r, {"mean": float(np.mean(ms)), "std": float(np.std(ms)), "runs": ms}
+
+    sizes = []
+    for scale in synth.PAPER_SIM_SCALES:
+        cube = synth.paper_sim_cube(scale)
+        m, n = cube.shape
+        rows, cols = cube.meta["rows"], cube.meta["cols"]
+        log(f"paper simulation x{scale}: {rows} x {cols} = {m} spectra x {n}")
+        I = torch.from_numpy(cube.i_cars).to(dev)
+        entry = {"scale": scale, "rows": rows, "cols": cols, "M": m, "N": n}
+        rss = {}
+        for tag, k, extra in (("fkk_ec_rank_rule", 0, {}), ("fkk_ec_k40", 40, {}),
+                              ("fkk_ec_k40_fp64_gram", 40, {"gram_prec": fk.PREC_FP64}),
+                              ("fkk_ec_k40_randomized", 40, {"svd_mode": fk.SVD_RANDOMIZED})):
+            p = fk.params(k=k, **extra)
+            out = torch.empty_like(I)
+            holder = {}
+
+            def run_fit():
+                if "b" in holder:
+                    holder["b"].free()
+                holder["b"], _, holder["rep"] = ctx.fit(I, cube.i_ref, p, out=out)
+
+            _, t = timed(run_fit)
+            kept = holder["b"].info()[1]
+            holder["b"].free()
+            rep = holder["rep"]
+            entry[tag] = {"k": kept, "ms": t, "stages_ms": {key: rep[key] for key in
+                                                            ("ms_gram", "ms_eig", "ms_project", "ms_basis",
+                                                             "ms_recon", "ms_total", "dev_ms_tridiag")}}
+            rss[tag], null = mean_rss(out, cube)
+            del out
+        p = fk.params(k=40)
+        pout = torch.empty_like(I)
+        _, t = timed(lambda: ctx.plain(I, cube.i_ref, p, out=pout))
+        entry["conventional"] = {"ms": t}
+        rss["conventional"], _ = mean_rss(pout, cube)
+        del pout
+        # stored basis: train on the leftmost sixth of the map, transform all
+        ct = max(1, cols // 6)
+        train = I.view(rows, cols, n)[:, :ct].reshape(-1, n).contiguous()
+        holder = {}
+
+        def run_train():
+            if "b" in holder:
+                holder["b"].free()
+            holder["b"], _, _ = ctx.fit(train, cube.i_ref, p, want_out=False)
+
+        _, t_train = timed(run_train)
+        tout = torch.empty_like(I)
+        _, t_apply = timed(lambda: ctx.transform(holder["b"], I, out=tout))
+        entry["stored_basis"] = {"training_spectra": int(train.shape[0]), "k": holder["b"].info()[1],
+                                 "train_ms": t_train, "transform_ms": t_apply,
+                                 "residual_of_all_spectra": ctx.residual(holder["b"], I)}
+        holder["b"].free()
+        rss["stored_basis"], _ = mean_rss(tout, cube)
+        del tout, train
+        conv = entry["conventional"]["ms"]["mean"]
+        entry["speed_enhancement"] = {
+            "fkk_ec_rank_rule": conv / entry["fkk_ec_rank_rule"]["ms"]["mean"],
+            "fkk_ec_k40": conv / entry["fkk_ec_k40"]["ms"]["mean"],
+            "fkk_ec_k40_fp64_gram": conv / entry["fkk_ec_k40_fp64_gram"]["ms"]["mean"],
+            "fkk_ec_k40_randomized": conv / entry["fkk_ec_k40_randomized"]["ms"]["mean"],
+            "stored_basis_plus_train": conv / (t_train["mean"] + t_apply["mean"]),
+            "stored_basis_minus_train": conv / t_apply["mean"]}
+        entry["us_per_spectrum"] = {"fkk_ec_rank_rule": 1e3 * entry["fkk_ec_rank_rule"]["ms"]["mean"] / m,
+                                    "fkk_ec_k40": 1e3 * entry["fkk_ec_k40"]["ms"]["mean"] / m,
+                                    "conventional": 1e3 * conv / m,
+                                    "stored_basis_minus_train": 1e3 * t_apply["mean"] / m}
+        entry["mean_rss"] = rss
+        entry["null_rss"] = null
+        log(f"  k={entry['fkk_ec_rank_rule']['k']}: fit {entry['fkk_ec_rank_rule']['ms']['mean']:.2f} ms, "
+            f"conventional {conv:.2f} ms, enhancement {entry['speed_enhancement']['fkk_ec_rank_rule']:.1f}; "
+            f"<RSS> fit {rss['fkk_ec_rank_rule']:.4g} conventional {rss['conventional']:.4g} null {null:.4g}")
+        sizes.append(entry)
+        del I
+        torch.cuda.empty_cache()
+    line = {"metric": "paper simulation replica: speed enhancement of fKK-EC over the conventional method, "
+                      "and <RSS> against Im{chi/chi_nr}",
+            "unit": "x", "n_gpus": 1, "runs": reps, "dtype": "fp32", "data": "synthetic",
+            "config": {"workload": "noiseless 3-chemical mixture (22/25/10 Lorentzians in 500-1700 cm^-1, "
+                                   "quadratic chi_nr per chemical, linear chi_ref), 74x246 base map side-scaled "
+                                   "x0.5/1/2/3/4, N=810 over -500..2500 cm^-1"},
+            "sizes": sizes}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,11 +453,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device-to-device copy: the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a --pmc run to bytes")
+    ap.add_argument("--paper-sim", action="store_true",
+                    help="run the replica of the paper's simulation study instead of the headline benchmark")
+    ap.add_argument("--sim-runs", type=int, default=3, help="timed runs per method and size in --paper-sim")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path is data-parallel over spectra and this build runs on a "
               "single MI355X; rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.paper_sim:
+        paper_sim(args)
+        return
 
     import torch
     import synth

@@ -102,7 +102,11 @@ class Cube:
     def ideal_im(self, rows) -> np.ndarray:
         """Known Im{chi / chi_nr} for the given rows (chi_nr = 1)."""
         if self.chi_components is not None:
-            return self.abundance[rows].astype(np.float64) @ self.chi_components.imag
+            a = self.abundance[rows].astype(np.float64)
+            im = a @ self.chi_components.imag
+            if "nrb_components" in self.meta:
+                im /= a @ self.meta["nrb_components"]
+            return im
         return self.meta["ideal_im"][rows]
 
 
@@ -230,3 +234,74 @@ def lowrank_log_cube(m: int, n: int, rank: int, noise: float = 1e-6, key: int = 
     ell = weights @ basis + noise * rng_for(key, ROLE_NOISE).standard_normal((m, n))
     i_cars = (ref * np.exp(2.0 * ell)).astype(dtype)
     return Cube(i_cars=i_cars, i_ref=ref, w=w, meta={"rank": rank})
+
+
+# ---------------------------------------------------------------------------
+# Replica of the paper's simulation workload (Sec. 4.1): a noiseless mixture
+# of three chemicals whose NRBs differ, on a 74 x 246 base map side-scaled by
+# 0.5, 1, 2, 3 or 4.
+# ---------------------------------------------------------------------------
+
+PAPER_SIM_BASE = (74, 246)
+PAPER_SIM_SCALES = (0.5, 1.0, 2.0, 3.0, 4.0)
+PAPER_SIM_PEAKS = (22, 25, 10)
+ROLE_SIM_NRB = 6
+
+
+def paper_sim_shape(scale: float) -> tuple[int, int]:
+    """Map of the base 74 x 246 grid side-scaled by `scale`."""
+    return int(round(PAPER_SIM_BASE[0] * scale)), int(round(PAPER_SIM_BASE[1] * scale))
+
+
+def paper_sim_cube(scale: float = 1.0, n: int = 810, lo: float = -500.0, hi: float = 2500.0,
+                   peak_lo: float = 500.0, peak_hi: float = 1700.0, key: int = 11, blur: float = 8.0,
+                   constant_nrb: bool = False, dtype=np.float32, chunk: int = 16384) -> Cube:
+    """Noiseless three-chemical mixture cube of (74 s) x (246 s) spectra.
+
+    Chemical c has a Raman susceptibility of 22, 25 or 10 complex Lorentzians
+    with centres in [peak_lo, peak_hi] and a real NRB chi_nr,c(w) that is a
+    quadratic in wt = (w - lo) / (hi - lo) with non-negative coefficients.  A
+    pixel's susceptibility is the abundance-weighted sum of the chemicals'
+    chi_R,c + chi_nr,c, so its NRB is the same mixture of the chi_nr,c.  The
+    reference is |chi_ref|^2 of a linear chi_ref, and the stimulation profile
+    is constant (1).  The abundance maps are drawn once on the 74 x 246 base
+    grid and resampled bilinearly, so every scale shows the same image.
+    ideal_im(rows) is the known Im{chi / chi_nr} of those pixels.
+    constant_nrb sets every chi_nr,c and chi_ref to 1 (same peaks and maps).
+    """
+    rows, cols = paper_sim_shape(scale)
+    w = wavenumbers(n, lo, hi)
+    wt = (w - lo) / (hi - lo)
+    rng = rng_for(key, ROLE_COMPONENTS)
+    chi = np.empty((3, n), dtype=np.complex128)
+    for c, n_peaks in enumerate(PAPER_SIM_PEAKS):
+        amp = rng.uniform(0.05, 1.0, n_peaks)
+        width = rng.uniform(5.0, 20.0, n_peaks)
+        centre = rng.uniform(peak_lo, peak_hi, n_peaks)
+        chi[c] = lorentz_chi(w, amp, centre, width)
+    nrng = rng_for(key, ROLE_SIM_NRB)
+    coef = np.column_stack([nrng.uniform(0.25, 1.0, 3), nrng.uniform(0.0, 1.0, (3, 2))])
+    nrb = coef[:, :1] + coef[:, 1:2] * wt + coef[:, 2:3] * wt ** 2
+    ref_coef = np.array([nrng.uniform(0.25, 1.0), nrng.uniform(0.0, 1.0)])
+    i_ref = (ref_coef[0] + ref_coef[1] * wt) ** 2
+    if constant_nrb:
+        nrb = np.ones_like(nrb)
+        i_ref = np.ones_like(i_ref)
+
+    base = abundances(rng_for(key, ROLE_ABUNDANCE), *PAPER_SIM_BASE, 3, blur)
+    base = base.reshape(*PAPER_SIM_BASE, 3)
+    ab = np.stack([scipy.ndimage.zoom(base[..., c], (rows / PAPER_SIM_BASE[0], cols / PAPER_SIM_BASE[1]),
+                                      order=1, mode="nearest", grid_mode=True) for c in range(3)], axis=-1)
+    assert ab.shape[:2] == (rows, cols), ab.shape
+    ab = np.maximum(ab.reshape(rows * cols, 3), 0.0)
+    ab /= ab.sum(axis=1, keepdims=True)
+
+    m = rows * cols
+    out = np.empty((m, n), dtype=dtype)
+    chi_tot = chi + nrb
+    for i0 in range(0, m, chunk):
+        x = ab[i0:i0 + chunk] @ chi_tot
+        out[i0:i0 + chunk] = x.real ** 2 + x.imag ** 2
+    return Cube(i_cars=out, i_ref=i_ref, w=w, chi_components=chi, abundance=ab,
+                meta={"rows": rows, "cols": cols, "scale": scale, "nrb_components": nrb,
+                      "ref_coef": ref_coef, "nrb_coef": coef})
