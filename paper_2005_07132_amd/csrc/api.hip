@@ -114,7 +114,7 @@ struct fkk_ctx {
     std::string err;
     DevBuf<double> partial;
     DevBuf<float> L;
-    DevBuf<double> colsum_part, G, colsum, fdev, tri;
+    DevBuf<double> colsum_part, G, colsum, fdev, tri, eigv;
     DevBuf<unsigned long long> clamps;
     DevBuf<int> tiles;
     DevBuf<float> rinv, Z, X;
@@ -161,7 +161,8 @@ struct fkk_ctx {
         return s;
     }
     size_t bytes() const {
-        return partial.n * 8 + L.n * 4 + fdev.n * 8 + tri.n * 8 + colsum_part.n * 8 + G.n * 8 + colsum.n * 8 +
+        return partial.n * 8 + L.n * 4 + fdev.n * 8 + tri.n * 8 + eigv.n * 8 + colsum_part.n * 8 + G.n * 8 +
+               colsum.n * 8 +
                clamps.n * 8 + tiles.n * 4 +
                rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
                qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
@@ -435,44 +436,67 @@ fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) 
     return FKK_OK;
 }
 
-// Top-k eigenpairs of diag(f) G diag(f) with G = ctx->G: scaling and the
-// Householder reduction on the device, the tridiagonal eigenproblem and the
-// back-transformation on the host.  Overwrites ctx->G.
 // Host end of the eigensolve once the reduction is queued on s: the small
 // arrays (beta | d | e, and the exchange error flag when flag != nullptr)
-// come first; the packed reflectors follow asynchronously while the host
-// finds the eigenpairs of T, and are waited for only by the back-
-// transformation.  *failed reports a set flag (outputs then unused).
-// With rel_cut > 0 only the pairs above the cut (relative to the largest
+// come back to the host, which finds the eigenpairs of T; the vectors go
+// back to the device for x = Q y against the reflectors left there (on the
+// host instead, from a copy of the reflectors, past the kernel's order
+// limit).  *failed reports a set flag (outputs then unused).  With
+// rel_cut > 0 only the pairs above the cut (relative to the largest
 // singular value) get vectors: *k_used of them, vecs then N x *k_used.
 fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta, const double* flag, double* vals,
                       double* vecs, bool* failed, double rel_cut, int* k_used) {
     hipStream_t s = ctx->stream;
-    double* h = ctx->hG.p;  // beta | d | e | vstore | flag
+    const bool dev_bt = N <= fkk::dev::back_transform_max_n();
+    const size_t k4n = (size_t)(k + 3) / 4 * 4 * N;
+    // pinned: beta | d | e | flag | Y (k rounded up to 4 vectors) | x (N k), or the reflectors
+    FKK_HIP(ctx, ctx->hG.ensure(3 * (size_t)N + 1 + k4n + (dev_bt ? (size_t)N * k : nv)));
+    double* h = ctx->hG.p;
+    double* hflag = h + 3 * N;
+    double* hY = hflag + 1;
+    double* hx = hY + k4n;
     *failed = false;
     FKK_HIP(ctx, hipMemcpyAsync(h, beta, 3 * (size_t)N * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (flag) FKK_HIP(ctx, hipMemcpyAsync(h + 3 * N + nv, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (flag) FKK_HIP(ctx, hipMemcpyAsync(hflag, flag, sizeof(double), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipEventRecord(ctx->ev[10], s));
-    FKK_HIP(ctx, hipMemcpyAsync(h + 3 * N, beta + 3 * N, nv * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipEventRecord(ctx->ev[11], s));
+    if (!dev_bt) {
+        FKK_HIP(ctx, hipMemcpyAsync(hx, beta + 3 * N, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+        FKK_HIP(ctx, hipEventRecord(ctx->ev[11], s));
+    }
     FKK_HIP(ctx, hipEventSynchronize(ctx->ev[10]));
     if (flag) {
         int berr = 0;
-        std::memcpy(&berr, h + 3 * N + nv, sizeof berr);
+        std::memcpy(&berr, hflag, sizeof berr);
         if (berr != 0) {
             *failed = true;
-            FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
+            if (!dev_bt) FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
             return FKK_OK;
         }
     }
-    std::vector<double> Y((size_t)(k + 3) / 4 * 4 * N, 0.0);
-    const int rc = fkk::tridiag_eigvecs(h + N, h + 2 * N, N, k, vals, Y.data(), rel_cut, k_used);
-    FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
+    std::fill(hY, hY + k4n, 0.0);
+    const int rc = fkk::tridiag_eigvecs(h + N, h + 2 * N, N, k, vals, hY, rel_cut, k_used);
+    if (!dev_bt) FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
     if (rc != 0) return ctx->fail(FKK_EINTERNAL, "tridiagonal eigensolver failed");
-    fkk::tridiag_back_transform(h, h + 3 * N, N, *k_used, Y.data(), vecs);
+    const int ku = *k_used;
+    if (!dev_bt) {
+        fkk::tridiag_back_transform(h, hx, N, ku, hY, vecs);
+        return FKK_OK;
+    }
+    FKK_HIP(ctx, ctx->eigv.ensure(2 * (size_t)N * ku));
+    double* dY = ctx->eigv.p;
+    double* dx = dY + (size_t)N * ku;
+    FKK_HIP(ctx, hipMemcpyAsync(dY, hY, (size_t)N * ku * sizeof(double), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, fkk::dev::launch_back_transform(beta, beta + 3 * N, N, ku, dY, dx, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hx, dx, (size_t)N * ku * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipEventRecord(ctx->ev[11], s));
+    FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));
+    std::memcpy(vecs, hx, (size_t)N * ku * sizeof(double));
     return FKK_OK;
 }
 
+// Top-k eigenpairs of diag(f) G diag(f) with G = ctx->G: scaling, the
+// Householder reduction and the back-transformation on the device, the
+// tridiagonal eigenproblem on the host.  Overwrites ctx->G.
 fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed,
                       double rel_cut, int* k_used) {
     const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
@@ -480,7 +504,6 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
     // layout of ctx->tri: p0 | p1 | beta | d | e | vstore | flags (2) | exchange (nx)
     FKK_HIP(ctx, ctx->tri.ensure(5 * (size_t)N + nv + 2 + nx));
     FKK_HIP(ctx, ctx->fdev.ensure(N));
-    FKK_HIP(ctx, ctx->hG.ensure(3 * (size_t)N + nv + 1));
     hipStream_t s = ctx->stream;
     double* t = ctx->tri.p;
     double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
@@ -731,6 +754,7 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     ctx->L.release();
     ctx->fdev.release();
     ctx->tri.release();
+    ctx->eigv.release();
     ctx->colsum_part.release();
     ctx->G.release();
     ctx->colsum.release();

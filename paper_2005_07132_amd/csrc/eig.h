@@ -34,6 +34,14 @@ size_t tridiag_resident_xch_doubles(int n);
 hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, int* err, double* vstore,
                                    double* beta, double* d, double* e, int spin_limit, hipStream_t s);
 
+// x = Q y for k eigenvectors y of T (vector j at Y + j n) with the
+// reflectors of either reduction above (beta on the device, n - 2 values;
+// vstore packed), then the sign rule (largest-magnitude entry positive,
+// first on ties) into vecs (n x k row-major).  n <= back_transform_max_n().
+int back_transform_max_n();
+hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,
+                                 double* vecs, hipStream_t s);
+
 // G(r, c) *= f(r) f(c).
 hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s);
 

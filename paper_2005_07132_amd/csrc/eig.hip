@@ -612,5 +612,120 @@ hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vsto
     return hipSuccess;
 }
 
+namespace {
+
+// Back-transformation x = H_0 H_1 ... H_{n-3} y of k eigenvectors of T: one
+// wave per vector, held in registers (lane l owns rows l + 64 t).  The
+// reflectors are applied from the last to the first, each one's entries
+// loaded three steps ahead; a zero reflector (beta = 0) is skipped.  Then the sign rule (largest-magnitude entry positive, the first
+// on ties) and the transposed store into vecs (n x k, row-major).
+template <int T>
+__global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* __restrict__ beta,
+                                                                  const double* __restrict__ vstore, int n, int k,
+                                                                  const double* __restrict__ Y,
+                                                                  double* __restrict__ vecs) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (j >= k) return;  // the whole wave: no block-level synchronisation below
+    double y[T], v[T], vn[T], vn2[T];
+    const double* yj = Y + (size_t)j * n;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int r = lane + 64 * t;
+        y[t] = yj[r < n ? r : n - 1] * (r < n ? 1.0 : 0.0);
+    }
+    // entries of reflector i act on rows i+1 .. n-1; indices are clamped
+    // into that range so every load is inside column i's packed values, and
+    // the rows outside it are masked where the values are used (so nothing
+    // waits for the next reflector's loads before the end of a step)
+    auto load = [&](int i, double* dst) {
+        const double* vs = vstore + voff(i, n) - (i + 1);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int r = lane + 64 * t;
+            dst[t] = vs[r <= i ? i + 1 : (r < n ? r : n - 1)];
+        }
+    };
+    // reflector i's entries are loaded three steps before step i uses them,
+    // into one of three buffers taken in turn; a step reads its buffer (the
+    // masked copy) and refills it with reflector i - 3
+    auto step = [&](int i, double* buf) {
+        const double b = beta[i];
+        double vm[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int r = lane + 64 * t;
+            vm[t] = (r > i && r < n) ? buf[t] : 0.0;
+        }
+        if (i >= 3) load(i - 3, buf);
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; t += 2) {
+            p0 += vm[t] * y[t];
+            if (t + 1 < T) p1 += vm[t + 1] * y[t + 1];
+        }
+        const double sc = wave_sum(p0 + p1) * b;
+        if (b != 0.0) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) y[t] -= sc * vm[t];
+        }
+    };
+    if (n >= 3) load(n - 3, v);
+    if (n >= 4) load(n - 4, vn);
+    if (n >= 5) load(n - 5, vn2);
+    for (int i = n - 3; i >= 0; i -= 3) {
+        step(i, v);
+        if (i >= 1) step(i - 1, vn);
+        if (i >= 2) step(i - 2, vn2);
+    }
+    // sign rule: (|y|, row, y) of the largest magnitude, the lowest row on ties
+    double best = -1.0, bval = 0.0;
+    int brow = n;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int r = lane + 64 * t;
+        if (r < n && fabs(y[t]) > best) {
+            best = fabs(y[t]);
+            bval = y[t];
+            brow = r;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const double ov = __shfl_xor(bval, off);
+        const int orow = __shfl_xor(brow, off);
+        if (ob > best || (ob == best && orow < brow)) {
+            best = ob;
+            bval = ov;
+            brow = orow;
+        }
+    }
+    const double sg = bval < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int r = lane + 64 * t;
+        if (r < n) vecs[(size_t)r * k + j] = sg * y[t];
+    }
+}
+
+}  // namespace
+
+int back_transform_max_n() { return 64 * 32; }
+
+hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,
+                                 double* vecs, hipStream_t s) {
+    if (n < 1 || k < 1 || n > back_transform_max_n()) return hipErrorInvalidValue;
+    const dim3 grid((k + kThreads / 64 - 1) / (kThreads / 64)), block(kThreads);
+    if (n <= 256)
+        hipLaunchKernelGGL(back_transform_kernel<4>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+    else if (n <= 512)
+        hipLaunchKernelGGL(back_transform_kernel<8>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+    else if (n <= 1024)
+        hipLaunchKernelGGL(back_transform_kernel<16>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+    else
+        hipLaunchKernelGGL(back_transform_kernel<32>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+    return hipGetLastError();
+}
+
 }  // namespace dev
 }  // namespace fkk
