@@ -53,6 +53,7 @@ class Params:
     ratio_floor: float = 1.0e-6
     k_max: int = 128        # k = 0: at most this many vectors from the rank rule
     sec_form: int = 0       # plain workflow: 0 log form (Eq. 19), 1 real-part form (Eq. 4-5)
+    q_between: int = 0      # rows per column between the extrema added to q (Sec. 2.3)
     q_override: np.ndarray | None = field(default=None, repr=False)
 
     def with_(self, **kw) -> "Params":
@@ -148,15 +149,27 @@ def rank_cutoff(s: np.ndarray, m: int, n: int, eps: float) -> int:
     return int(np.count_nonzero(s > s.max() * max(m, n) * eps))
 
 
-def subsample_rows(z: np.ndarray) -> np.ndarray:
+def subsample_rows(z: np.ndarray, between: int = 0) -> np.ndarray:
     """q = union over columns of argmax and argmin over rows (Eq. 13-15).
 
     Z = U S with s > 0 has the same per-column arg-extrema as U.  Ties take
     the first row; the union is returned sorted ascending.
+
+    between > 0 adds the optional sub-sample between the extrema (Sec. 2.3,
+    after Eq. 15), read as: for each column, the rows whose values lie
+    nearest to the `between` evenly spaced levels min + (max - min) j /
+    (between + 1), j = 1..between (first row on ties).  Z = U S scales each
+    column by s > 0, which maps these levels and rows onto U's.
     """
     qmax = np.argmax(z, axis=0)
     qmin = np.argmin(z, axis=0)
-    return np.unique(np.concatenate([qmax, qmin]))
+    picked = [qmax, qmin]
+    for c in range(z.shape[1]):
+        lo, hi = z[qmin[c], c], z[qmax[c], c]
+        for j in range(1, between + 1):
+            level = lo + (hi - lo) * (j / (between + 1))
+            picked.append(np.array([np.argmin(np.abs(z[:, c] - level))]))
+    return np.unique(np.concatenate(picked))
 
 
 def ridge_lambda(x: np.ndarray, rel: float) -> float:
@@ -227,7 +240,7 @@ def basis_from_factors(f, s, v, z, p: Params, q=None) -> dict:
     vt_f = v.T / f                                   # V^T / f (k x N)
     h_v = _hilbert(vt_f, p)                          # fKK, Eq. 7 / 11
     if q is None:
-        q = p.q_override if p.q_override is not None else subsample_rows(z)
+        q = p.q_override if p.q_override is not None else subsample_rows(z, p.q_between)
     q = np.asarray(q, dtype=np.int64)
     x = z[q, :]                                      # X = U_ss S (Eq. 16)
     phi_raw = x @ h_v                                # U_ss S H{V^T/f}

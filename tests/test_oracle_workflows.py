@@ -238,6 +238,53 @@ def test_q_is_union_of_column_extrema():
     np.testing.assert_array_equal(wf.subsample_rows(z), [0, 1, 3])
 
 
+def test_q_between_on_monotone_columns_is_evenly_spaced():
+    # a column rising linearly from row 0 to row 60 has the level
+    # min + (max - min) j / (s + 1) at row 60 j / (s + 1) exactly; a falling
+    # column takes the mirrored rows; s = 0 is Eq. 13-15 alone
+    m = 61
+    z = np.column_stack([np.arange(m, dtype=float), 2.5 * (m - 1 - np.arange(m))])
+    np.testing.assert_array_equal(wf.subsample_rows(z, 0), [0, 60])
+    np.testing.assert_array_equal(wf.subsample_rows(z, 3), [0, 15, 30, 45, 60])
+    np.testing.assert_array_equal(wf.subsample_rows(z, 2), [0, 20, 40, 60])
+    # s = 4 puts the levels at 12, 24, 36, 48 of the rising column and at
+    # the same rows of the falling one
+    np.testing.assert_array_equal(wf.subsample_rows(z[:, 1:], 4), [0, 12, 24, 36, 48, 60])
+
+
+def test_q_between_is_the_nearest_row_to_each_level_by_brute_force():
+    # tiny random columns: every level's nearest row (first on ties), found
+    # by checking all rows, is in q, and q holds nothing else
+    rng = np.random.default_rng(9)
+    z = np.round(rng.standard_normal((23, 3)), 1)  # repeated values: ties
+    s = 3
+    expect = set()
+    for c in range(3):
+        col = list(z[:, c])
+        hi, lo = max(col), min(col)
+        expect.add(col.index(hi))
+        expect.add(col.index(lo))
+        for j in range(1, s + 1):
+            level = lo + (hi - lo) * j / (s + 1)
+            dist = [abs(v - level) for v in col]
+            expect.add(dist.index(min(dist)))
+    np.testing.assert_array_equal(wf.subsample_rows(z, s), sorted(expect))
+
+
+def test_q_between_keeps_the_factorisation_identity():
+    # with linear detrending and no ridge, Phi_PEC solves the regression
+    # exactly for any q of full column rank, so the extra rows leave the
+    # output equal to the conventional workflow on the rank-k data
+    cube = _small_cube()
+    p = wf.Params(k=6, q_between=3, **LINEAR)
+    res = wf.fit(cube.i_cars, cube.i_ref, p)
+    b = res["basis"]
+    assert len(b["q"]) > len(wf.subsample_rows(res["z"]))
+    ell_k = res["z"] @ b["v"].T / b["f"]
+    ref = wf.plain(cube.i_ref * np.exp(2.0 * ell_k), cube.i_ref, p)
+    assert _rel(res["im"], ref["im"]) < 1e-11
+
+
 # --------------------------------------------------------------------------
 # Rank rule of Sec. 4.1 (k = 0)
 # --------------------------------------------------------------------------
