@@ -128,6 +128,12 @@ typedef struct {
     const double* rrf_omega;  /* host, optional: N x l test matrix (row-major);
                                  NULL: standard normal numbers from rrf_seed
                                  (SplitMix64, Box-Muller)                    */
+    /* fkk_fit, 0..16: the optional sub-sample between the column extrema
+     * of Sec. 2.3 (after Eq. 15).  For each column c of Z = A V_k and
+     * j = 1..q_between, the row whose Z value lies nearest (FP32, first row on
+     * ties) to min_c + (max_c - min_c) j / (q_between + 1) joins q.
+     * Ignored when q_override is given. */
+    int32_t q_between;
 } fkk_params;
 
 /* Per-fit diagnostics (all fields written by fkk_fit when non-NULL). */

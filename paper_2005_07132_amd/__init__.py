@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("q_override", _c_int64_p), ("n_q_override", ctypes.c_int32),
         ("svd_mode", ctypes.c_int32), ("sec_form", ctypes.c_int32), ("rrf_oversample", ctypes.c_int32),
         ("rrf_power_iters", ctypes.c_int32),
-        ("rrf_seed", ctypes.c_uint64), ("rrf_omega", _c_double_p),
+        ("rrf_seed", ctypes.c_uint64), ("rrf_omega", _c_double_p), ("q_between", ctypes.c_int32),
     ]
 
 

@@ -119,7 +119,8 @@ struct fkk_ctx {
     DevBuf<int> tiles;
     DevBuf<float> rinv, Z, X;
     DevBuf<float> pmaxv, pminv;
-    DevBuf<long long> pmaxi, pmini, qext, qdev;
+    DevBuf<long long> pmaxi, pmini, qext, qdev, bidx, qbet;
+    DevBuf<float> bval;
     PinnedBuf<double> hG;
     PinnedBuf<double> hstage;  // basis uploads
     fkk::plain::Workspace plain_ws;
@@ -165,7 +166,7 @@ struct fkk_ctx {
                colsum.n * 8 +
                clamps.n * 8 + tiles.n * 4 +
                rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
-               qext.n * 8 + qdev.n * 8 + plain_ws.bytes();
+               qext.n * 8 + qdev.n * 8 + bidx.n * 8 + qbet.n * 8 + bval.n * 4 + plain_ws.bytes();
     }
 };
 
@@ -210,6 +211,7 @@ fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = 
                          p->recon_prec);
     if (p->f_mode == FKK_F_NOISE && !(p->alpha >= 0.0 && p->sigma_g >= 0.0 && (p->alpha > 0.0 || p->sigma_g > 0.0)))
         return ctx->fail(FKK_EINVAL, "f_mode=noise needs alpha >= 0, sigma_g >= 0, not both 0");
+    if (p->q_between < 0 || p->q_between > 16) return ctx->fail(FKK_EINVAL, "q_between=%d outside 0..16", p->q_between);
     if (p->svd_mode != FKK_SVD_GRAM && p->svd_mode != FKK_SVD_RANDOMIZED) return ctx->fail(FKK_EINVAL, "bad svd_mode");
     if (p->svd_mode == FKK_SVD_RANDOMIZED) {
         if (p->k == 0) return ctx->fail(FKK_EINVAL, "the randomized SVD needs k >= 1");
@@ -720,6 +722,7 @@ void fkk_params_default(fkk_params* p) {
     p->rrf_power_iters = 1;
     p->rrf_seed = 20200514;
     p->rrf_omega = nullptr;
+    p->q_between = 0;
 }
 
 fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
@@ -769,6 +772,9 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     ctx->pmini.release();
     ctx->qext.release();
     ctx->qdev.release();
+    ctx->bidx.release();
+    ctx->qbet.release();
+    ctx->bval.release();
     ctx->hG.release();
     ctx->hstage.release();
     ctx->plain_ws.release();
@@ -960,9 +966,22 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     if (perr != hipSuccess || hipEventRecord(ctx->ev[3], s) != hipSuccess ||
         fkk::dev::launch_argext_reduce(part, nblk, ka, k, ctx->qext.p, ctx->qext.p + ka, s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));
+    // the optional rows between the extrema (Sec. 2.3), from the stored Z
+    const int nbet = (p->n_q_override > 0) ? 0 : k * p->q_between;
+    if (nbet > 0) {
+        const size_t np = (size_t)fkk::dev::between_blocks(M, kp) * nbet;
+        if (ctx->bval.ensure(np) != hipSuccess || ctx->bidx.ensure(np) != hipSuccess ||
+            ctx->qbet.ensure(nbet) != hipSuccess)
+            return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
+        if (fkk::dev::launch_between(ctx->Z.p, M, kp, kp, k, p->q_between, ctx->qext.p, ctx->qext.p + ka, ctx->bval.p,
+                                     ctx->bidx.p, ctx->qbet.p, s) != hipSuccess)
+            return cleanup(ctx->fail(FKK_EDEVICE, "sub-sample launch failed"));
+    }
     basis_fkk(b, p);  // host FP64 while the projection runs
-    std::vector<long long> qe(2 * (size_t)ka);
+    std::vector<long long> qe(2 * (size_t)ka), qb(nbet);
     if (hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (nbet > 0 && hipMemcpyAsync(qb.data(), ctx->qbet.p, qb.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                                    s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection failed"));
     r.dev_ms_project = ctx->elapsed(2, 3);
@@ -974,6 +993,8 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
             if (qe[c] >= 0) q.push_back(qe[c]);
             if (qe[ka + c] >= 0) q.push_back(qe[ka + c]);
         }
+        for (long long r : qb)
+            if (r >= 0) q.push_back(r);
         std::sort(q.begin(), q.end());
         q.erase(std::unique(q.begin(), q.end()), q.end());
     }

@@ -75,6 +75,15 @@ hipError_t launch_residual_sums(const float* I, int64_t M, int N, int64_t ld, co
                                 const double* f, const float* Z, int64_t ld_z, int k, double* part, hipStream_t s);
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
                                 long long* qmin, hipStream_t s);
+// Sub-sample between the extrema (Sec. 2.3): for each of the k columns of Z
+// (M rows, stride ld_z, kp in {16, 32, 64, 128} columns stored) and each of
+// s levels evenly spaced strictly between Z[qmin[c], c] and Z[qmax[c], c]
+// (device), the row nearest to the level (first on ties) into q[c s + j - 1]
+// (device, -1 when the column has no extrema).  pval / pidx: scratch of
+// between_blocks(M, kp) * k * s entries each.
+int64_t between_blocks(int64_t M, int kp);
+hipError_t launch_between(const float* Z, int64_t M, int64_t ld_z, int kp, int k, int s, const long long* qmax,
+                          const long long* qmin, float* pval, long long* pidx, long long* q, hipStream_t st);
 
 // Reconstruction: out = plane of exp(Z B_re) exp(i Z B_im); BreT / BimT are
 // (rows = wavenumbers) x kp with the vectors in kgroup_pos order.

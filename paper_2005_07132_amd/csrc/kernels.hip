@@ -531,6 +531,96 @@ __global__ void argext_reduce_kernel(ArgPart part, int64_t nblocks, int kp, long
     }
 }
 
+// Optional sub-sample between the column extrema (Sec. 2.3, after Eq. 15).
+// For column c and level j = 1..s the target is min_c + (max_c - min_c) j /
+// (s + 1), from the stored Z at the arg-extrema rows; each block stages
+// kBetweenFloats / kp rows of Z in LDS (rows padded by one float, so a
+// wave reading one column of 64 rows hits 64 banks) and reports, per
+// (column, level) pair, its row nearest to the target (smallest |Z - target|,
+// lowest row on ties).  A column without extrema (qmax or qmin < 0) reports
+// no row.
+constexpr int kBetweenFloats = 8192;
+
+__global__ __launch_bounds__(256) void between_partial_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z,
+                                                              int kp, int k, int s, const long long* __restrict__ qmax,
+                                                              const long long* __restrict__ qmin,
+                                                              float* __restrict__ pval, long long* __restrict__ pidx) {
+    __shared__ float zs[kBetweenFloats + kBetweenFloats / 16];
+    const int rows = kBetweenFloats / kp;  // kp in {16, 32, 64, 128}
+    const int ldl = kp + 1;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    for (int e = threadIdx.x; e < rows * kp; e += blockDim.x) {
+        const int rr = e / kp, c = e - rr * kp;
+        zs[rr * ldl + c] = (r0 + rr < M) ? Z[(r0 + rr) * ld_z + c] : 0.f;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int npairs = k * s;
+    for (int pr = wave; pr < npairs; pr += (int)(blockDim.x >> 6)) {
+        const int c = pr / s, j = pr - c * s + 1;
+        const long long ix = qmax[c], in = qmin[c];
+        float best = INFINITY;
+        long long brow = LLONG_MAX;
+        if (ix >= 0 && in >= 0) {
+            const float hi = Z[ix * ld_z + c], lo = Z[in * ld_z + c];
+            const float level = lo + (hi - lo) * ((float)j / (float)(s + 1));
+            for (int rr = lane; rr < rows; rr += 64) {
+                if (r0 + rr >= M) break;
+                const float d = fabsf(zs[rr * ldl + c] - level);
+                if (d < best) {
+                    best = d;
+                    brow = r0 + rr;
+                }
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float ob = __shfl_xor(best, off);
+            const long long orow = __shfl_xor(brow, off);
+            if (ob < best || (ob == best && orow < brow)) {
+                best = ob;
+                brow = orow;
+            }
+        }
+        if (lane == 0) {
+            pval[(size_t)blockIdx.x * npairs + pr] = best;
+            pidx[(size_t)blockIdx.x * npairs + pr] = brow;
+        }
+    }
+}
+
+// One block per (column, level) pair: the nearest row over the partials of
+// every row block (lowest row on ties), -1 when there is none.
+__global__ void between_reduce_kernel(const float* __restrict__ pval, const long long* __restrict__ pidx,
+                                      int64_t nblocks, int npairs, long long* __restrict__ q) {
+    const int pr = blockIdx.x;
+    float best = INFINITY;
+    long long brow = LLONG_MAX;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        const float v = pval[(size_t)b * npairs + pr];
+        const long long r = pidx[(size_t)b * npairs + pr];
+        if (r != LLONG_MAX && (v < best || (v == best && r < brow))) {
+            best = v;
+            brow = r;
+        }
+    }
+    __shared__ float sv[256];
+    __shared__ long long sr[256];
+    sv[threadIdx.x] = best;
+    sr[threadIdx.x] = brow;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            const int o = threadIdx.x + st;
+            if (sv[o] < sv[threadIdx.x] || (sv[o] == sv[threadIdx.x] && sr[o] < sr[threadIdx.x])) {
+                sv[threadIdx.x] = sv[o];
+                sr[threadIdx.x] = sr[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q[pr] = (sr[0] == LLONG_MAX) ? -1 : sr[0];
+}
+
 template <int KB>
 static hipError_t project_dispatch(int mode, dim3 grid, hipStream_t s, const float* I, int64_t M, int N, int64_t ld,
                                    const float* rinv, float floor, const float* Wt, int ldw, int k_store, float* Z,
@@ -565,6 +655,21 @@ hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const fl
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax, long long* qmin,
                                 hipStream_t s) {
     hipLaunchKernelGGL(argext_reduce_kernel, dim3(k), dim3(256), 0, s, part, nblocks, kp, qmax, qmin);
+    return hipGetLastError();
+}
+
+int64_t between_blocks(int64_t M, int kp) { return (M + kBetweenFloats / kp - 1) / (kBetweenFloats / kp); }
+
+hipError_t launch_between(const float* Z, int64_t M, int64_t ld_z, int kp, int k, int s, const long long* qmax,
+                          const long long* qmin, float* pval, long long* pidx, long long* q, hipStream_t st) {
+    if (M < 1 || k < 1 || s < 1 || (kp != 16 && kp != 32 && kp != 64 && kp != 128) || k > kp || ld_z < kp)
+        return hipErrorInvalidValue;
+    const int64_t nb = between_blocks(M, kp);
+    hipLaunchKernelGGL(between_partial_kernel, dim3((unsigned)nb), dim3(256), 0, st, Z, M, ld_z, kp, k, s, qmax, qmin,
+                       pval, pidx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(between_reduce_kernel, dim3(k * s), dim3(256), 0, st, pval, pidx, nb, k * s, q);
     return hipGetLastError();
 }
 

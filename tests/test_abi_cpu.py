@@ -124,7 +124,7 @@ def test_host_basis_zero_x_gives_no_phase_error():
                                 dict(f_mode=1, alpha=0.0, sigma_g=0.0), dict(gram_prec=3), dict(recon_prec=2), dict(recon_prec=-1),
                                 dict(svd_mode=2), dict(svd_mode=1, rrf_power_iters=-1),
                                 dict(svd_mode=1, rrf_oversample=-1), dict(svd_mode=1, k=120, rrf_oversample=10),
-                                dict(sec_form=1), dict(sec_form=2)])
+                                dict(sec_form=1), dict(sec_form=2), dict(q_between=-1), dict(q_between=17)])
 def test_parameter_validation(kw):
     n = 256
     base = dict(k=4)

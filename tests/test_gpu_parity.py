@@ -265,6 +265,33 @@ def test_fit_lowrank_matches_independent_oracle(ctx, detrend, n):
     assert rep["n_q"] == len(ref["basis"]["q"])
 
 
+@pytest.mark.parametrize("between", [1, 3])
+def test_fit_subsample_between_matches_oracle(ctx, between):
+    # the optional rows between the column extrema (Sec. 2.3): every level
+    # of every column has a row of q within FP32 rounding of the nearest one
+    # (judged on the device's own Z, which selects them), q grows beyond the
+    # extrema, and the fit with those rows matches the oracle's with the same
+    # rows
+    say(f"fit q_between={between}")
+    cube = synth.lowrank_log_cube(4000, 300, rank=6, dtype=np.float32)
+    p = wf.Params(k=6, q_between=between)
+    b, out, rep = ctx.fit(dev(cube.i_cars), cube.i_ref, lib_params(p, q_between=between))
+    q = np.sort(b.export()["q"])
+    z, qmax, qmin = ctx.project(b, dev(cube.i_cars))
+    z = host(z)[:, :6]
+    assert set(qmax) | set(qmin) <= set(q)
+    assert len(q) > len(set(qmax) | set(qmin)) and len(q) <= 6 * (2 + between)
+    for c in range(6):
+        lo, hi = z[qmin[c], c], z[qmax[c], c]
+        for j in range(1, between + 1):
+            level = lo + (hi - lo) * (j / (between + 1))
+            best = np.abs(z[:, c] - level).min()
+            assert np.abs(z[q, c] - level).min() <= best + 1e-6 * (hi - lo), (c, j)
+    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p.with_(q_override=q))
+    assert spectrum_err(host(out), ref["im"]).max() < TOL
+    assert rep["n_q"] == len(q)
+
+
 def test_fit_rank_rule_matches_oracle(ctx):
     # k = 0: the rank rule of Sec. 4.1 with the FP32 epsilon of the input
     # keeps the 6 components of an exact rank-6 log ratio (noise 1e-6 lies
