@@ -23,9 +23,30 @@ static_assert(64 * kPrefetch <= 4 * kThreads, "pivot loads of a prefetching step
 
 __device__ __forceinline__ int64_t voff(int64_t i, int64_t n) { return i * (n - 1) - i * (i - 1) / 2; }
 
+// x from the lane `CTRL` names within the same row of 16 lanes (DPP), both
+// halves of the double moved alike.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Sum over the 64 lanes of a wave (all active), returned in every lane:
+// rotations by 8, 4, 2 and 1 within each row of 16 lanes leave each lane
+// with its row's sum, and the four row sums are read from lanes 0, 16, 32
+// and 48 and added in that fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_move<0x128>(v);  // row_ror:8
+    v += dpp_move<0x124>(v);  // row_ror:4
+    v += dpp_move<0x122>(v);  // row_ror:2
+    v += dpp_move<0x121>(v);  // row_ror:1
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Block-wide sum; every thread gets the result.  red: 4 doubles of LDS.
