@@ -297,6 +297,7 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // The arithmetic of a column is that of tridiag_step.
 // ---------------------------------------------------------------------------
 constexpr int kMaxOwnedRows = 16;
+constexpr int kRowsPerBlock = 2 * (kThreads / 64);  // preferred rows per block
 constexpr int kXchPerThread = 8;  // exchange entries per thread and column: n - 1 <= 8 * kThreads
 constexpr size_t kResidentLdsMax = 160 * 1024 - 512;  // dynamic part; the static part is < 200 bytes
 
@@ -511,7 +512,27 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
             const double vr = va[r - lo], wr = w[r - lo];
             const bool pivot = next && r == lo + 1;  // pivot row of the next column
             double sacc = 0.0;
-            for (int c = lane; c < m; c += 64) {
+            int c = lane;
+            // four columns per lane in flight (m > 192 implies next); sacc
+            // takes the columns in the same order as the loop below
+            for (; c + 192 < m; c += 256) {
+                double u[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cc = c + 64 * q;
+                    u[q] = row[cc] - (vr * w[cc] + wr * va[cc]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int cc = c + 64 * q;
+                    row[cc] = u[q];
+                    if (cc >= 1) {
+                        sacc += u[q] * vb[cc - 1];
+                        if (pivot) xch_put(xout + 2 * (cc - 1), u[q], ntag);
+                    }
+                }
+            }
+            for (; c < m; c += 64) {
                 const double u = row[c] - (vr * w[c] + wr * va[c]);
                 row[c] = u;
                 if (next && c >= 1) {
@@ -561,7 +582,10 @@ int tridiag_resident_grid(int n, int device) {
     int coop = 0, cus = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) return 0;
-    const int G = cus < n ? cus : n;
+    // two rows per wave where the CUs allow: fewer blocks exchange less,
+    // and a wave's second row overlaps the first one's LDS latency
+    const int want = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    const int G = want < cus ? want : cus;
     if ((n + G - 1) / G > kMaxOwnedRows) return 0;
     if (tridiag_resident_lds(n, G) > kResidentLdsMax) return 0;
     return G;
