@@ -1070,18 +1070,35 @@ int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double
         }
     });
     if (failed.load()) return -2;
-    for (int j = 1; j < k; ++j) {
-        double* b = &Y[(size_t)j * n];
-        for (int c = 0; c < j; ++c) {
-            const double* yc = &Y[(size_t)c * n];
-            const double s = dotn(yc, b);
-            for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
+    // Final modified Gram-Schmidt pass, pipelined over the pool: vector j
+    // takes the finished vectors 0..j-1 in order as soon as each one is
+    // final, so every vector sees exactly the operations of the sequential
+    // pass.  A vector that fails marks the pass failed and every waiter
+    // leaves.
+    std::unique_ptr<std::atomic<int>[]> fin(new std::atomic<int>[k]);
+    for (int j = 0; j < k; ++j) fin[j].store(j == 0 ? 1 : 0, std::memory_order_relaxed);
+    pool.run([&](int tid, int nthr) {
+        for (int j = 1 + tid; j < k; j += nthr) {
+            double* b = &Y[(size_t)j * n];
+            for (int c = 0; c < j; ++c) {
+                while (!fin[c].load(std::memory_order_acquire)) {
+                    if (failed.load(std::memory_order_relaxed)) return;
+                    std::this_thread::yield();
+                }
+                const double* yc = &Y[(size_t)c * n];
+                const double s = dotn(yc, b);
+                for (int i = 0; i < n; ++i) b[i] -= s * yc[i];
+            }
+            const double nrm = std::sqrt(dotn(b, b));
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+                failed.store(1);
+                return;
+            }
+            for (int i = 0; i < n; ++i) b[i] /= nrm;
+            fin[j].store(1, std::memory_order_release);
         }
-        const double nrm = std::sqrt(dotn(b, b));
-        if (!(nrm > 0.0) || !std::isfinite(nrm)) return -2;
-        for (int i = 0; i < n; ++i) b[i] /= nrm;
-    }
-    return 0;
+    });
+    return failed.load() ? -2 : 0;
 }
 
 void tridiag_back_transform(const double* beta, const double* vstore, int n, int k, double* Y, double* vecs) {
