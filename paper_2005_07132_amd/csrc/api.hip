@@ -484,11 +484,12 @@ fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta,
         fkk::tridiag_back_transform(h, hx, N, ku, hY, vecs);
         return FKK_OK;
     }
-    FKK_HIP(ctx, ctx->eigv.ensure(2 * (size_t)N * ku));
+    FKK_HIP(ctx, ctx->eigv.ensure(2 * (size_t)N * ku + fkk::dev::back_transform_vpad_doubles(N)));
     double* dY = ctx->eigv.p;
     double* dx = dY + (size_t)N * ku;
+    double* vpad = dx + (size_t)N * ku;
     FKK_HIP(ctx, hipMemcpyAsync(dY, hY, (size_t)N * ku * sizeof(double), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, fkk::dev::launch_back_transform(beta, beta + 3 * N, N, ku, dY, dx, s));
+    FKK_HIP(ctx, fkk::dev::launch_back_transform(beta, beta + 3 * N, N, ku, dY, dx, vpad, s));
     FKK_HIP(ctx, hipMemcpyAsync(hx, dx, (size_t)N * ku * sizeof(double), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipEventRecord(ctx->ev[11], s));
     FKK_HIP(ctx, hipEventSynchronize(ctx->ev[11]));

@@ -38,9 +38,12 @@ hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, i
 // reflectors of either reduction above (beta on the device, n - 2 values;
 // vstore packed), then the sign rule (largest-magnitude entry positive,
 // first on ties) into vecs (n x k row-major).  n <= back_transform_max_n().
+// vpad: back_transform_vpad_doubles(n) doubles of scratch (the reflectors
+// as zero-padded rows).
 int back_transform_max_n();
+size_t back_transform_vpad_doubles(int n);
 hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,
-                                 double* vecs, hipStream_t s);
+                                 double* vecs, double* vpad, hipStream_t s);
 
 // G(r, c) *= f(r) f(c).
 hipError_t launch_scale_sym(double* G, const double* f, int n, hipStream_t s);

@@ -659,16 +659,30 @@ hipError_t launch_tridiag(double* A, int n, double* p0, double* p1, double* vsto
 
 namespace {
 
+// Reflector i (packed, rows i+1 .. n-1) into row i of vpad (npad doubles,
+// zero at rows <= i and >= n), so the back-transformation loads whole rows
+// at one stride without clamping or masking.
+__global__ void expand_reflectors_kernel(const double* __restrict__ vstore, int n, int npad,
+                                         double* __restrict__ vpad) {
+    const int i = blockIdx.x;
+    const double* vs = vstore + voff(i, n) - (i + 1);
+    double* dst = vpad + (size_t)i * npad;
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) dst[r] = (r > i && r < n) ? vs[r] : 0.0;
+}
+
 // Back-transformation x = H_0 H_1 ... H_{n-3} y of k eigenvectors of T: one
 // wave per vector, held in registers (lane l owns rows l + 64 t).  The
-// reflectors are applied from the last to the first, each one's entries
-// loaded three steps ahead; a zero reflector (beta = 0) is skipped.  Then the sign rule (largest-magnitude entry positive, the first
-// on ties) and the transposed store into vecs (n x k, row-major).
+// reflectors are applied from the last to the first from their zero-padded
+// rows (no clamping or masking per step), each one loaded three steps
+// ahead; a zero reflector (beta = 0) is skipped.  Then the sign rule
+// (largest-magnitude entry positive, the first on ties) and the transposed
+// store into vecs (n x k, row-major).
 template <int T>
 __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* __restrict__ beta,
-                                                                  const double* __restrict__ vstore, int n, int k,
+                                                                  const double* __restrict__ vpad, int n, int k,
                                                                   const double* __restrict__ Y,
                                                                   double* __restrict__ vecs) {
+    constexpr int NP = 64 * T;  // padded row length
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (j >= k) return;  // the whole wave: no block-level synchronisation below
@@ -679,30 +693,25 @@ __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* 
         const int r = lane + 64 * t;
         y[t] = yj[r < n ? r : n - 1] * (r < n ? 1.0 : 0.0);
     }
-    // entries of reflector i act on rows i+1 .. n-1; indices are clamped
-    // into that range so every load is inside column i's packed values, and
-    // the rows outside it are masked where the values are used (so nothing
-    // waits for the next reflector's loads before the end of a step)
     auto load = [&](int i, double* dst) {
-        const double* vs = vstore + voff(i, n) - (i + 1);
+        const double* row = vpad + (size_t)i * NP + lane;
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int r = lane + 64 * t;
-            dst[t] = vs[r <= i ? i + 1 : (r < n ? r : n - 1)];
-        }
+        for (int t = 0; t < T; ++t) dst[t] = row[64 * t];
     };
-    // reflector i's entries are loaded three steps before step i uses them,
-    // into one of three buffers taken in turn; a step reads its buffer (the
-    // masked copy) and refills it with reflector i - 3
+    // reflector i's row is loaded three steps before step i uses it, into
+    // one of three buffers taken in turn; a step refills its buffer with
+    // reflector i - 3.  The step count is rounded up to a multiple of three
+    // with steps i < 0 that change nothing, and every step loads (row 0 when
+    // i - 3 < 0), so no branch decides which buffer a load fills: the
+    // buffers keep their registers across iterations and a step waits only
+    // for its own row, not for the loads in flight for the next two.
     auto step = [&](int i, double* buf) {
-        const double b = beta[i];
+        const bool live = i >= 0;
+        const double b = live ? beta[live ? i : 0] : 0.0;
         double vm[T];
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int r = lane + 64 * t;
-            vm[t] = (r > i && r < n) ? buf[t] : 0.0;
-        }
-        if (i >= 3) load(i - 3, buf);
+        for (int t = 0; t < T; ++t) vm[t] = buf[t];
+        load(i >= 3 ? i - 3 : 0, buf);
         double p0 = 0.0, p1 = 0.0;
 #pragma unroll
         for (int t = 0; t < T; t += 2) {
@@ -715,13 +724,15 @@ __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* 
             for (int t = 0; t < T; ++t) y[t] -= sc * vm[t];
         }
     };
-    if (n >= 3) load(n - 3, v);
-    if (n >= 4) load(n - 4, vn);
-    if (n >= 5) load(n - 5, vn2);
-    for (int i = n - 3; i >= 0; i -= 3) {
-        step(i, v);
-        if (i >= 1) step(i - 1, vn);
-        if (i >= 2) step(i - 2, vn2);
+    if (n >= 3) {
+        load(n - 3, v);
+        load(n >= 4 ? n - 4 : 0, vn);
+        load(n >= 5 ? n - 5 : 0, vn2);
+        for (int i = n - 3; i > -3; i -= 3) {
+            step(i, v);
+            step(i - 1, vn);
+            step(i - 2, vn2);
+        }
     }
     // sign rule: (|y|, row, y) of the largest magnitude, the lowest row on ties
     double best = -1.0, bval = 0.0;
@@ -757,18 +768,29 @@ __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* 
 
 int back_transform_max_n() { return 64 * 32; }
 
+size_t back_transform_vpad_doubles(int n) {
+    const int T = n <= 256 ? 4 : n <= 512 ? 8 : n <= 1024 ? 16 : 32;
+    return n >= 3 ? (size_t)(n - 2) * 64 * T : 1;
+}
+
 hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,
-                                 double* vecs, hipStream_t s) {
+                                 double* vecs, double* vpad, hipStream_t s) {
     if (n < 1 || k < 1 || n > back_transform_max_n()) return hipErrorInvalidValue;
+    const int T = n <= 256 ? 4 : n <= 512 ? 8 : n <= 1024 ? 16 : 32;
+    if (n >= 3) {
+        hipLaunchKernelGGL(expand_reflectors_kernel, dim3(n - 2), dim3(kThreads), 0, s, vstore, n, 64 * T, vpad);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid((k + kThreads / 64 - 1) / (kThreads / 64)), block(kThreads);
-    if (n <= 256)
-        hipLaunchKernelGGL(back_transform_kernel<4>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
-    else if (n <= 512)
-        hipLaunchKernelGGL(back_transform_kernel<8>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
-    else if (n <= 1024)
-        hipLaunchKernelGGL(back_transform_kernel<16>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+    if (T == 4)
+        hipLaunchKernelGGL(back_transform_kernel<4>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+    else if (T == 8)
+        hipLaunchKernelGGL(back_transform_kernel<8>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+    else if (T == 16)
+        hipLaunchKernelGGL(back_transform_kernel<16>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
     else
-        hipLaunchKernelGGL(back_transform_kernel<32>, grid, block, 0, s, beta, vstore, n, k, Y, vecs);
+        hipLaunchKernelGGL(back_transform_kernel<32>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
     return hipGetLastError();
 }
 
