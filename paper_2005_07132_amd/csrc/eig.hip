@@ -61,6 +61,19 @@ __device__ double block_sum(double v, double* red) {
     return t;
 }
 
+// Block-wide sum with one barrier: red (4 doubles of LDS) must not be read
+// by any thread between the barrier here and the next use of the same red
+// (callers alternate two buffers, with barriers in between).
+__device__ double block_sum_pp(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
 // Reflector of x (length m, in LDS): v = x - alpha e1, beta = 2 / v.v,
 // alpha = -sign(x0) |x|; zero reflector when x[1:] = 0.
 __device__ void make_reflector(const double* x, int m, double* v, double* beta, double* alpha, double* red) {
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
                                                              double* __restrict__ d, double* __restrict__ e,
                                                              int* err, int spin_limit) {
     extern __shared__ double sm[];
-    __shared__ double red[4];
+    __shared__ double red[8];  // [0..3]: p . v, [4..7]: |x_{1:}|^2 (alternating, see block_sum_pp)
     __shared__ double sp0;
     __shared__ int sbad;
     const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -453,14 +466,17 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
         // words of column i: p at xch + 2n (i & 1), pivot row at xch + 4n + 2n (i & 1)
         const size_t half = (i & 1) ? 2 * (size_t)n : 0;
         if (!xch_fetch(xch + half, xch + 4 * (size_t)n + half, m, tag, spin_limit, err, w, x, va, part)) sbad = 1;
+        // p_0 is copied before the barrier: thread 0 overwrites w[0] with w_0
+        // below while other waves may still be about to read it
         if (tid == 0) sp0 = w[0];  // w[0] is this thread's own entry
-        __syncthreads();
+        // the sum's barrier also publishes sbad, sp0 and the fetched w, x
+        const double ptv = block_sum_pp(part, red);
         if (sbad) {
             if (tid == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
         const double p0 = sp0;
-        const double kk = 0.5 * bcur * block_sum(part, red);
+        const double kk = 0.5 * bcur * ptv;
         const double w0 = p0 - kk * v0;
         const bool next = (i + 3 < n);
         double part2 = 0.0;
@@ -473,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
         }
         double bn = 0.0;
         if (next) {
-            const double sig2 = block_sum(part2, red);  // x, w complete after this
+            const double sig2 = block_sum_pp(part2, red + 4);  // x, w complete after this
             const double x0 = x[1];
             double a;
             if (sig2 == 0.0) {

@@ -791,7 +791,7 @@ __device__ __forceinline__ void recon_chunk(const float4 (&zf)[2][KB], const flo
 }
 
 template <int KB, int QL, bool VEC_OUT>
-__global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void recon_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
                                                     const float* __restrict__ BreT, const float* __restrict__ BimT,
                                                     int N, float* __restrict__ out, int64_t ld_out, int plane) {
     constexpr int KP = KB * 16;

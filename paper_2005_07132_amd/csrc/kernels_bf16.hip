@@ -396,7 +396,7 @@ __device__ __forceinline__ void recon16_loop(const u32x4 (&zb)[2][KB2], const u3
 }
 
 template <int KB2, bool VEC_OUT>
-__global__ __launch_bounds__(256) void recon16_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB2 <= 2 ? 3 : 1))) void recon16_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
                                                       const u32x4* __restrict__ BreT, const u32x4* __restrict__ BimT,
                                                       int N, float* __restrict__ out, int64_t ld_out, int plane) {
     constexpr int BLDU = KB2 * 4 + 1;
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void recon16_kernel(const float* __restrict__ 
 // Z tile goes to LDS as 4-value BF16 stores), then reconstruction.
 // ---------------------------------------------------------------------------
 template <int KB2, bool VEC_IN, bool VEC_OUT>
-__global__ __launch_bounds__(256) void transform16_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void transform16_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                           const float* __restrict__ rinv, float floor,
                                                           const unsigned short* __restrict__ Wt, int ldw,
                                                           const u32x4* __restrict__ BreT,
