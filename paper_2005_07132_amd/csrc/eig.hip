@@ -49,7 +49,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
-// Block-wide sum; every thread gets the result.  red: 4 doubles of LDS.
+// Block-wide sum; every thread gets the result.  red: one double of LDS per wave.
 __device__ double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -61,7 +61,7 @@ __device__ double block_sum(double v, double* red) {
     return t;
 }
 
-// Block-wide sum with one barrier: red (4 doubles of LDS) must not be read
+// Block-wide sum with one barrier: red (one double of LDS per wave) must not be read
 // by any thread between the barrier here and the next use of the same red
 // (callers alternate two buffers, with barriers in between).
 __device__ double block_sum_pp(double v, double* red) {
@@ -310,8 +310,9 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // The arithmetic of a column is that of tridiag_step.
 // ---------------------------------------------------------------------------
 constexpr int kMaxOwnedRows = 16;
-constexpr int kRowsPerBlock = 2 * (kThreads / 64);  // preferred rows per block
-constexpr int kXchPerThread = 8;  // exchange entries per thread and column: n - 1 <= 8 * kThreads
+constexpr int kResThreads = 512;  // threads of a tridiag_resident block (8 waves)
+constexpr int kRowsPerBlock = kResThreads / 64;  // preferred rows per block: one per wave
+constexpr int kXchPerThread = 8;  // exchange entries per thread and column: n - 1 <= 8 * kResThreads
 constexpr size_t kResidentLdsMax = 160 * 1024 - 512;  // dynamic part; the static part is < 200 bytes
 
 typedef unsigned long long u64;
@@ -335,7 +336,7 @@ __device__ __forceinline__ double xch_value(u64 lo, u64 hi) {
 
 // Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
 // (LDS), with part += p . v over this thread's entries; NU = ceil(m /
-// kThreads) entries per thread, so a poll loads only live entries.  Gives
+// kResThreads) entries per thread, so a poll loads only live entries.  Gives
 // up after spin_limit polls (spin_limit 0: at once), or when *err is set.
 template <int NU>
 struct XchPoll {
@@ -343,7 +344,7 @@ struct XchPoll {
     __device__ __forceinline__ void issue(const u64* pw, const u64* xw, int m) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {  // clamped: every load in bounds, none waits for another
-            const int j = min((int)threadIdx.x + kThreads * u, m - 1);
+            const int j = min((int)threadIdx.x + kResThreads * u, m - 1);
             a[u][0] = xch_word(pw + 2 * j);
             a[u][1] = xch_word(pw + 2 * j + 1);
             c[u][0] = xch_word(xw + 2 * j);
@@ -354,7 +355,7 @@ struct XchPoll {
         bool all = true;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            const int j = threadIdx.x + kThreads * u;
+            const int j = threadIdx.x + kResThreads * u;
             if (j < m) all = all && xch_tagged(a[u][0], a[u][1], tag) && xch_tagged(c[u][0], c[u][1], tag);
         }
         return all;
@@ -362,7 +363,7 @@ struct XchPoll {
     __device__ __forceinline__ void use(int m, double* w, double* x, const double* v, double& part) const {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            const int j = threadIdx.x + kThreads * u;
+            const int j = threadIdx.x + kResThreads * u;
             if (j < m) {
                 const double pj = xch_value(a[u][0], a[u][1]);
                 w[j] = pj;
@@ -375,7 +376,7 @@ struct XchPoll {
 
 // Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
 // (LDS), with part += p . v over this thread's entries; NU = ceil(m /
-// kThreads) entries per thread, so a poll loads only live entries.  (Two
+// kResThreads) entries per thread, so a poll loads only live entries.  (Two
 // polls in flight at a time measured slower: the extra traffic to the
 // coherence point costs more than the earlier detection gains.)  Gives up
 // after spin_limit polls (spin_limit 0: at once), or when *err is set.
@@ -398,7 +399,7 @@ __device__ bool xch_fetch_n(const u64* pw, const u64* xw, int m, unsigned tag, i
 
 __device__ bool xch_fetch(const u64* pw, const u64* xw, int m, unsigned tag, int spin_limit, const int* err,
                           double* w, double* x, const double* v, double& part) {
-    switch ((m + kThreads - 1) / kThreads) {  // uniform over the block
+    switch ((m + kResThreads - 1) / kResThreads) {  // uniform over the block
         case 1: return xch_fetch_n<1>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
         case 2: return xch_fetch_n<2>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
         case 3: return xch_fetch_n<3>(pw, xw, m, tag, spin_limit, err, w, x, v, part);
@@ -410,12 +411,12 @@ __device__ bool xch_fetch(const u64* pw, const u64* xw, int m, unsigned tag, int
     }
 }
 
-__global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __restrict__ A, int n, int R, u64* xch,
+__global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __restrict__ A, int n, int R, u64* xch,
                                                              double* __restrict__ vstore, double* __restrict__ beta,
                                                              double* __restrict__ d, double* __restrict__ e,
                                                              int* err, int spin_limit) {
     extern __shared__ double sm[];
-    __shared__ double red[8];  // [0..3]: p . v, [4..7]: |x_{1:}|^2 (alternating, see block_sum_pp)
+    __shared__ double red[16];  // [0..7]: p . v, [8..15]: |x_{1:}|^2 (alternating, see block_sum_pp)
     __shared__ double sp0;
     __shared__ int sbad;
     const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -428,23 +429,23 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
     for (int t = 0; t < R; ++t) {
         const int r = b + t * G;
         if (r >= n) break;
-        for (int c = tid; c < n; c += kThreads) rows[(size_t)t * n + c] = A[(size_t)r * n + c];
+        for (int c = tid; c < n; c += kResThreads) rows[(size_t)t * n + c] = A[(size_t)r * n + c];
     }
     // column 0: reflector of row 0 and p_0 = beta_0 B_0 v_0, from A itself
     const int m0 = n - 1;
-    for (int j = tid; j < m0; j += kThreads) x[j] = A[1 + j];
+    for (int j = tid; j < m0; j += kResThreads) x[j] = A[1 + j];
     __syncthreads();
     double bcur, a0;
     make_reflector(x, m0, va, &bcur, &a0, red);
     if (b == 0) {
-        for (int j = tid; j < m0; j += kThreads) vstore[j] = va[j];
+        for (int j = tid; j < m0; j += kResThreads) vstore[j] = va[j];
         if (tid == 0) {
             beta[0] = bcur;
             d[0] = A[0];
             e[0] = a0;
         }
     }
-    for (int t = wave; t < R; t += kThreads / 64) {
+    for (int t = wave; t < R; t += kResThreads / 64) {
         const int r = b + t * G;
         if (r < 1 || r >= n) continue;
         const double* row = rows + (size_t)t * n + 1;
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
         const double w0 = p0 - kk * v0;
         const bool next = (i + 3 < n);
         double part2 = 0.0;
-        for (int j = tid; j < m; j += kThreads) {
+        for (int j = tid; j < m; j += kResThreads) {
             const double wj = w[j] - kk * va[j];
             const double xj = x[j] - (v0 * wj + w0 * va[j]);
             w[j] = wj;
@@ -489,21 +490,21 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
         }
         double bn = 0.0;
         if (next) {
-            const double sig2 = block_sum_pp(part2, red + 4);  // x, w complete after this
+            const double sig2 = block_sum_pp(part2, red + 8);  // x, w complete after this
             const double x0 = x[1];
             double a;
             if (sig2 == 0.0) {
                 a = x0;
-                for (int j = tid; j < m - 1; j += kThreads) vb[j] = 0.0;
+                for (int j = tid; j < m - 1; j += kResThreads) vb[j] = 0.0;
             } else {
                 const double norm = sqrt(x0 * x0 + sig2);
                 a = (x0 >= 0.0) ? -norm : norm;
                 bn = 2.0 / ((x0 - a) * (x0 - a) + sig2);
-                for (int j = tid; j < m - 1; j += kThreads) vb[j] = (j == 0) ? x0 - a : x[1 + j];
+                for (int j = tid; j < m - 1; j += kResThreads) vb[j] = (j == 0) ? x0 - a : x[1 + j];
             }
             if (b == 0) {
                 double* vso = vstore + voff(lo, n);
-                for (int j = tid; j < m - 1; j += kThreads) vso[j] = vb[j];
+                for (int j = tid; j < m - 1; j += kResThreads) vso[j] = vb[j];
                 if (tid == 0) {
                     beta[lo] = bn;
                     d[lo] = x[0];
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void tridiag_resident(const double* __res
         const unsigned ntag = tag + 1u;
         u64* pout = xch + (half ? 0 : 2 * (size_t)n);
         u64* xout = xch + 4 * (size_t)n + (half ? 0 : 2 * (size_t)n);
-        for (int t = wave; t < R; t += kThreads / 64) {
+        for (int t = wave; t < R; t += kResThreads / 64) {
             const int r = b + t * G;
             if (r <= lo || r >= n) continue;
             double* row = rows + (size_t)t * n + lo;
@@ -594,7 +595,7 @@ size_t tridiag_resident_lds(int n, int G) {
 }
 
 int tridiag_resident_grid(int n, int device) {
-    if (n < 3 || n - 1 > kXchPerThread * kThreads) return 0;
+    if (n < 3 || n - 1 > kXchPerThread * kResThreads) return 0;
     int coop = 0, cus = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) return 0;
@@ -611,7 +612,7 @@ size_t tridiag_resident_xch_doubles(int n) { return 8 * (size_t)n; }
 
 hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, int* err, double* vstore,
                                    double* beta, double* d, double* e, int spin_limit, hipStream_t s) {
-    if (n < 3 || n - 1 > kXchPerThread * kThreads || G < 1 || G > n || spin_limit < 0) return hipErrorInvalidValue;
+    if (n < 3 || n - 1 > kXchPerThread * kResThreads || G < 1 || G > n || spin_limit < 0) return hipErrorInvalidValue;
     const int R = (n + G - 1) / G;
     if (R > kMaxOwnedRows) return hipErrorInvalidValue;
     const size_t lds = tridiag_resident_lds(n, G);
@@ -623,7 +624,7 @@ hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, i
     int nn = n, rr = R;
     void* args[] = {(void*)&A,    (void*)&nn,   (void*)&rr, (void*)&words, (void*)&vstore,
                     (void*)&beta, (void*)&d,    (void*)&e,  (void*)&err,   (void*)&spin_limit};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_resident), dim3(G), dim3(kThreads), args,
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_resident), dim3(G), dim3(kResThreads), args,
                                       (unsigned)lds, s);
 }
 
