@@ -599,10 +599,15 @@ int tridiag_resident_grid(int n, int device) {
     int coop = 0, cus = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) return 0;
-    // two rows per wave where the CUs allow: fewer blocks exchange less,
-    // and a wave's second row overlaps the first one's LDS latency
-    const int want = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    const int G = want < cus ? want : cus;
+    // one row per wave where LDS and the CUs allow: fewer blocks exchange
+    // less; more blocks where a block's rows would not fit its LDS
+    int G = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    const long long rmax = ((long long)(kResidentLdsMax / sizeof(double)) - 4LL * n) / n;
+    if (rmax < 1) return 0;
+    const int g_lds = (int)((n + rmax - 1) / rmax);
+    if (G < g_lds) G = g_lds;
+    if (G > cus) G = cus;
+    if (G > n) G = n;
     if ((n + G - 1) / G > kMaxOwnedRows) return 0;
     if (tridiag_resident_lds(n, G) > kResidentLdsMax) return 0;
     return G;
