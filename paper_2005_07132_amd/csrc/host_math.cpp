@@ -440,8 +440,11 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
     // Weight tables depend only on (n, window, order): build once, reuse.
     struct Tables {
         int n = -1, window = -1, order = -1;
-        std::vector<double> wmid, wedge;
-        std::vector<int> estart, eat;
+        // wmid: interior weights; emat: (order+1) x window operator from a
+        // window's values to the coefficients of its least-squares polynomial
+        // in (position - window centre) / scale; epow: for each edge output
+        // (left 0..half-1, then right n-half..n-1) the powers of its offset
+        std::vector<double> wmid, emat, epow;
     };
     static std::mutex cache_mu;
     static std::shared_ptr<const Tables> cache;
@@ -455,17 +458,43 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
         const double scale = std::max(1, half);
         t.wmid.resize(window);
         sg_weights(0, window, half, order, scale, t.wmid.data());
-        t.wedge.resize((size_t)2 * half * window);
-        t.estart.resize(2 * half);
-        t.eat.resize(2 * half);
+        // edges ("interp"): the polynomial fitted to the first (last) window,
+        // evaluated at the edge positions; its coefficients are computed once
+        // per row and side instead of one window-long sum per edge point
+        const int m = order + 1;
+        std::vector<double> vp((size_t)window * m), gm((size_t)m * m, 0.0);
+        for (int j = 0; j < window; ++j) {
+            const double u = (j - half) / scale;
+            double pw = 1.0;
+            for (int e = 0; e < m; ++e) {
+                vp[(size_t)j * m + e] = pw;
+                pw *= u;
+            }
+        }
+        for (int j = 0; j < window; ++j)
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) gm[r * m + c] += vp[(size_t)j * m + r] * vp[(size_t)j * m + c];
+        t.emat.assign((size_t)m * window, 0.0);
+        for (int k = 0; k < m; ++k) {
+            std::vector<double> g2(gm), bk(m, 0.0);
+            bk[k] = 1.0;
+            small_solve(g2, bk, m);  // row k of (V^T V)^-1 (symmetric)
+            for (int j = 0; j < window; ++j) {
+                double v = 0.0;
+                for (int l = 0; l < m; ++l) v += bk[l] * vp[(size_t)j * m + l];
+                t.emat[(size_t)k * window + j] = v;
+            }
+        }
+        t.epow.resize((size_t)2 * half * m);
         for (int i = 0; i < half; ++i) {
-            sg_weights(0, window, i, order, scale, &t.wedge[(size_t)i * window]);
-            t.estart[i] = 0;
-            t.eat[i] = i;
-            const int at = n - half + i;
-            sg_weights(n - window, window, at, order, scale, &t.wedge[(size_t)(half + i) * window]);
-            t.estart[half + i] = n - window;
-            t.eat[half + i] = at;
+            const double ul = (i - half) / scale, ur = (i + 1) / scale;  // left: position i; right: n - half + i
+            double pl = 1.0, pr = 1.0;
+            for (int e = 0; e < m; ++e) {
+                t.epow[(size_t)i * m + e] = pl;
+                t.epow[(size_t)(half + i) * m + e] = pr;
+                pl *= ul;
+                pr *= ur;
+            }
         }
         t.n = n;
         t.window = window;
@@ -475,10 +504,11 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
         cache = tp;
     }
     const std::vector<double>& wmid = tp->wmid;
-    const std::vector<double>& wedge = tp->wedge;
-    const std::vector<int>& estart = tp->estart;
-    const std::vector<int>& eat = tp->eat;
+    const std::vector<double>& emat = tp->emat;
+    const std::vector<double>& epow = tp->epow;
+    const int m = order + 1;
     parallel_rows(rows, [&](int ra, int rb) {
+        std::vector<double> coef(m);
         for (int r = ra; r < rb; ++r) {
             const double* xr = x + (size_t)r * n;
             double* yr = y + (size_t)r * n;
@@ -515,12 +545,29 @@ void trendline_rows(const double* x, double* y, int rows, int n, int mode, int w
                 for (; j < window; ++j) s0 += wmid[j] * src[j];
                 yr[i] = (s0 + s1) + (s2 + s3);
             }
-            for (int e = 0; e < 2 * half; ++e) {
-                double s = 0.0;
-                const double* wts = &wedge[(size_t)e * window];
-                const double* src = xr + estart[e];
-                for (int j = 0; j < window; ++j) s += wts[j] * src[j];
-                yr[eat[e]] = s;
+            for (int side = 0; side < 2; ++side) {
+                const double* src = xr + (side ? n - window : 0);
+                double* c = coef.data();
+                for (int k = 0; k < m; ++k) {
+                    const double* mk = &emat[(size_t)k * window];
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    int j = 0;
+                    for (; j + 3 < window; j += 4) {
+                        s0 += mk[j] * src[j];
+                        s1 += mk[j + 1] * src[j + 1];
+                        s2 += mk[j + 2] * src[j + 2];
+                        s3 += mk[j + 3] * src[j + 3];
+                    }
+                    for (; j < window; ++j) s0 += mk[j] * src[j];
+                    c[k] = (s0 + s1) + (s2 + s3);
+                }
+                double* dst = yr + (side ? n - half : 0);
+                const double* pw = &epow[(size_t)side * half * m];
+                for (int i = 0; i < half; ++i) {
+                    double v = 0.0;
+                    for (int k = m - 1; k >= 0; --k) v += c[k] * pw[(size_t)i * m + k];
+                    dst[i] = v;
+                }
             }
         }
     });
