@@ -140,6 +140,7 @@ struct FftPlan {
     int n = 0;
     std::vector<int> rev;
     std::vector<cplx> tw;  // exp(-2 pi i j / n), j < n/2
+    std::vector<double> stw;  // per stage (half = 1, 2, 4, ...): the half twiddles it uses, re/im interleaved
     explicit FftPlan(int len) : n(len), rev(len), tw(len / 2) {
         int bits = 0;
         while ((1 << bits) < n) ++bits;
@@ -153,6 +154,12 @@ struct FftPlan {
             const double ang = -2.0 * M_PI * (double)j / (double)n;
             tw[j] = cplx(std::cos(ang), std::sin(ang));
         }
+        stw.resize(2 * (size_t)std::max(n - 1, 1));
+        for (int half = 1; half < n; half *= 2)
+            for (int j = 0; j < half; ++j) {
+                stw[2 * (size_t)(half - 1 + j)] = tw[(size_t)j * (n / (2 * half))].real();
+                stw[2 * (size_t)(half - 1 + j) + 1] = tw[(size_t)j * (n / (2 * half))].imag();
+            }
     }
     void run(cplx* a, bool inverse) const {
         double* z = reinterpret_cast<double*>(a);
@@ -160,10 +167,10 @@ struct FftPlan {
             if (i < rev[i]) std::swap(a[i], a[rev[i]]);
         const double sgn = inverse ? -1.0 : 1.0;
         for (int half = 1; half < n; half *= 2) {
-            const int step = n / (2 * half);
+            const double* w = &stw[2 * (size_t)(half - 1)];
             for (int s = 0; s < n; s += 2 * half) {
                 for (int j = 0; j < half; ++j) {
-                    const double wr = tw[j * step].real(), wi = sgn * tw[j * step].imag();
+                    const double wr = w[2 * j], wi = sgn * w[2 * j + 1];
                     double* x = z + 2 * (s + j);
                     double* y = z + 2 * (s + j + half);
                     const double tr = wr * y[0] - wi * y[1], ti = wr * y[1] + wi * y[0];
@@ -183,11 +190,23 @@ struct FftPlan {
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// Plans depend only on the length: built once per length and shared.
+std::shared_ptr<const FftPlan> fft_plan(int len) {
+    static std::mutex mu;
+    static std::vector<std::shared_ptr<const FftPlan>> plans;
+    std::lock_guard<std::mutex> g(mu);
+    for (const auto& p : plans)
+        if (p->n == len) return p;
+    plans.push_back(std::make_shared<const FftPlan>(len));
+    return plans.back();
+}
+
 }  // namespace
 
 void hilbert_rows(const double* x, double* y, int rows, int n, int len, int pad_mode) {
     if (!is_pow2(len) || len < n) return;
-    const FftPlan plan(len);
+    const std::shared_ptr<const FftPlan> plan_p = fft_plan(len);
+    const FftPlan& plan = *plan_p;
     const int pl = (len - n) / 2;
     // Two real rows per complex transform: H is real and complex-linear, so
     // H{a + i b} = H{a} + i H{b}.
