@@ -307,7 +307,8 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // alternate between columns: a block writes the words of column i+1 only
 // after it has read all words of column i, and every block wrote those
 // only after reading all of column i-1, the previous content of the buffer.
-// The arithmetic of a column is that of tridiag_step.
+// The arithmetic of a column is that of tridiag_step, with the block sums
+// split over 512 threads (one owned row per wave) instead of 256.
 // ---------------------------------------------------------------------------
 constexpr int kMaxOwnedRows = 16;
 constexpr int kResThreads = 512;  // threads of a tridiag_resident block (8 waves)
