@@ -1035,48 +1035,59 @@ int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double
     }
     lo -= 2 * eps * tnorm;
     hi += 2 * eps * tnorm;
-    pool.run([&](int tid, int nthr) {
-        int j0, j1;
-        split(0, k, tid, nthr, &j0, &j1);
-        // four eigenvalues bisected together; a lane stops moving its
-        // interval once converged, exactly as the one-at-a-time loop would
-        for (int jb = j0; jb < j1; jb += 4) {
-            double a[4], b[4], mid[4];
-            bool live[4];
-            int cnt[4];
-            for (int l = 0; l < 4; ++l) {
-                a[l] = lo;
-                b[l] = hi;
-                live[l] = (jb + l < j1);
-            }
-            for (int it = 0; it < 200; ++it) {
-                bool any = false;
+    // eigenvalues jfrom..jto-1 (descending order) by bisection over the pool
+    auto bisect_range = [&](int jfrom, int jto) {
+        pool.run([&](int tid, int nthr) {
+            int j0, j1;
+            split(jfrom, jto, tid, nthr, &j0, &j1);
+            // four eigenvalues bisected together; a lane stops moving its
+            // interval once converged, exactly as the one-at-a-time loop would
+            for (int jb = j0; jb < j1; jb += 4) {
+                double a[4], b[4], mid[4];
+                bool live[4];
+                int cnt[4];
                 for (int l = 0; l < 4; ++l) {
-                    mid[l] = 0.5 * (a[l] + b[l]);
-                    if (live[l] && (b[l] - a[l] <= 2 * eps * std::max(std::fabs(a[l]), std::fabs(b[l])) + pivmin ||
-                                    mid[l] <= a[l] || mid[l] >= b[l]))
-                        live[l] = false;
-                    any = any || live[l];
+                    a[l] = lo;
+                    b[l] = hi;
+                    live[l] = (jb + l < j1);
                 }
-                if (!any) break;
-                sturm_count4(d.data(), e2.data(), n, mid, pivmin, cnt);
-                for (int l = 0; l < 4; ++l) {
-                    if (!live[l]) continue;
-                    const int idx = n - 1 - (jb + l);  // ascending index of the j-th largest
-                    if (cnt[l] > idx) b[l] = mid[l];
-                    else a[l] = mid[l];
+                for (int it = 0; it < 200; ++it) {
+                    bool any = false;
+                    for (int l = 0; l < 4; ++l) {
+                        mid[l] = 0.5 * (a[l] + b[l]);
+                        if (live[l] && (b[l] - a[l] <= 2 * eps * std::max(std::fabs(a[l]), std::fabs(b[l])) + pivmin ||
+                                        mid[l] <= a[l] || mid[l] >= b[l]))
+                            live[l] = false;
+                        any = any || live[l];
+                    }
+                    if (!any) break;
+                    sturm_count4(d.data(), e2.data(), n, mid, pivmin, cnt);
+                    for (int l = 0; l < 4; ++l) {
+                        if (!live[l]) continue;
+                        const int idx = n - 1 - (jb + l);  // ascending index of the j-th largest
+                        if (cnt[l] > idx) b[l] = mid[l];
+                        else a[l] = mid[l];
+                    }
                 }
+                for (int l = 0; l < 4 && jb + l < j1; ++l) vals[jb + l] = 0.5 * (a[l] + b[l]);
             }
-            for (int l = 0; l < 4 && jb + l < j1; ++l) vals[jb + l] = 0.5 * (a[l] + b[l]);
-        }
-    });
+        });
+    };
 
     if (rel_cut > 0.0) {
+        // the largest eigenvalue first; the number above the cut then comes
+        // from one Sturm count at cut^2, and only those are bisected
+        bisect_range(0, 1);
         const double cut = std::sqrt(std::max(vals[0], 0.0)) * rel_cut;
-        int cnt = 0;
-        for (int j = 0; j < k; ++j) cnt += std::sqrt(std::max(vals[j], 0.0)) > cut ? 1 : 0;
-        k = std::max(cnt, 1);
+        const double x2 = cut * cut;
+        const double xs[4] = {x2, x2, x2, x2};
+        int below[4];
+        sturm_count4(d.data(), e2.data(), n, xs, pivmin, below);
+        k = std::min(std::max(n - below[0], 1), k);
         if (k_out) *k_out = k;
+        if (k > 1) bisect_range(1, k);
+    } else {
+        bisect_range(0, k);
     }
 
     // ---- eigenvectors of T by inverse iteration ----
