@@ -138,7 +138,9 @@ def pixel_cube(side: int = 64, n: int = 512, peaks: int = 8, snr: float = 50.0,
 def smooth_field(rng: np.random.Generator, rows: int, cols: int, blur: float) -> np.ndarray:
     """White N(0,1) field blurred by a Gaussian of `blur` px, standardised."""
     z = scipy.ndimage.gaussian_filter(rng.standard_normal((rows, cols)), blur, mode="wrap")
-    return (z - z.mean()) / z.std()
+    sd = z.std()
+    # a one-pixel grid has no spread to standardise: a flat field
+    return (z - z.mean()) / sd if sd > 0.0 else np.zeros_like(z)
 
 
 def abundances(rng: np.random.Generator, rows: int, cols: int, n_comp: int,

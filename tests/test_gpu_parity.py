@@ -216,7 +216,9 @@ def test_transform_with_oracle_basis(ctx, fitted, m):
     say(f"transform m={m}")
     cube, p, res = fitted
     b = ctx.basis_import(res["basis"])
-    new = synth.tissue_cube(rows=1, cols=m, n=cube.shape[1], map_key=100 + m, noise_key=200 + m, blur=2.0)
+    # the first m pixels of a 4 x 256 grid: real spectra also for m = 1
+    new = synth.tissue_cube(rows=4, cols=256, m=m, n=cube.shape[1], map_key=100 + m, noise_key=200 + m, blur=2.0)
+    assert np.all(np.isfinite(new.i_cars)) and new.shape[0] == m
     out = host(ctx.transform(b, dev(new.i_cars)))
     ref = wf.transform(new.i_cars.astype(np.float64), res["basis"])["im"]
     assert spectrum_err(out, ref).max() < TOL

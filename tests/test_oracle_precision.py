@@ -76,3 +76,30 @@ def test_bf16_transform_close_to_fp64_transform():
     low = pr.transform(cube.i_cars, basis)
     err = np.abs(low["im"] - exact["im"]).max(axis=1) / np.abs(exact["im"]).max(axis=1)
     assert 1e-5 < err.max() < 5e-2  # BF16 operands: ~1e-3, not exact
+
+
+def test_contract_rule_exact_on_bf16_operands_and_bounded_otherwise():
+    rng = np.random.default_rng(8)
+    a16 = pr.round_bf16(rng.standard_normal((30, 20)))
+    b16 = pr.round_bf16(rng.standard_normal((20, 10)))
+    np.testing.assert_array_equal(pr.contract(a16, b16), a16 @ b16)  # operands already BF16
+    a = rng.standard_normal((30, 20))
+    b = rng.standard_normal((20, 10))
+    err = np.abs(pr.contract(a, b) - a @ b)
+    assert np.all(err <= (2 * 2.0 ** -8 + 2.0 ** -16) * (np.abs(a) @ np.abs(b)))
+    assert err.max() > 0
+
+
+def test_bf16_transform_is_the_rule_applied_to_each_contraction():
+    cube = synth.tissue_cube(rows=8, cols=8, n=96, map_key=9, noise_key=9, blur=2.0, dtype=np.float64)
+    p = wf.Params(k=6, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    basis = wf.fit(cube.i_cars, cube.i_ref, p)["basis"]
+    ell, _ = wf.log_ratio(cube.i_cars, basis["i_ref"], basis["ratio_floor"])
+    # written out: every operand of the three products rounded, sums exact
+    z = pr.round_bf16(ell) @ pr.round_bf16(pr.projection_weights(basis))
+    z16 = pr.round_bf16(z)
+    want = wf.retrieve(z16 @ pr.round_bf16(basis["b_re"]), z16 @ pr.round_bf16(basis["b_im"]))["im"]
+    np.testing.assert_array_equal(pr.transform(cube.i_cars, basis)["im"], want)
+    # the labelled variant that leaves Z unrounded differs, by about one BF16 rounding of Z
+    other = pr.transform_full_precision_z(cube.i_cars, basis)["im"]
+    assert 0 < np.abs(other - want).max() < 5e-2 * np.abs(want).max()

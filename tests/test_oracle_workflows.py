@@ -423,3 +423,67 @@ def test_sec_real_part_form_mean_and_scale():
     ref = synth.reference(w)
     nrb = wf.plain(np.tile(ref, (20, 1)), ref, wf.Params(sec_form=1, als_lambda=1e4))
     assert np.abs(nrb["im"]).max() < 1e-15 and np.abs(nrb["re"] - 1.0).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Ridge weight of Eq. 17 on hand-worked cases
+# --------------------------------------------------------------------------
+
+def test_ridge_lambda_hand_cases():
+    # X = diag(3, 1): X^T X = diag(9, 1), largest eigenvalue 9 (not the trace
+    # 10, the largest singular value 3 or the smallest eigenvalue 1)
+    x = np.array([[3.0, 0.0], [0.0, 1.0]])
+    assert wf.ridge_lambda(x, 1e-6) == pytest.approx(9e-6, rel=1e-14)
+    # rank one: rows (1, 2) and (2, 4): X^T X = [[5, 10], [10, 20]], eigenvalues 25 and 0
+    x = np.array([[1.0, 2.0], [2.0, 4.0]])
+    assert wf.ridge_lambda(x, 0.5) == pytest.approx(12.5, rel=1e-14)
+    # 3 x 2 with orthogonal columns of norms 2 and sqrt(2): X^T X = diag(4, 2)
+    x = np.array([[2.0, 0.0], [0.0, 1.0], [0.0, -1.0]])
+    assert wf.ridge_lambda(x, 1.0) == pytest.approx(4.0, rel=1e-14)
+    # rel = 0 (the identity tests) and X = 0 give no regularisation
+    assert wf.ridge_lambda(x, 0.0) == 0.0
+    assert wf.ridge_lambda(np.zeros((4, 3)), 1e-6) == 0.0
+
+
+def test_ridge_lambda_is_what_the_fit_uses():
+    cube = _small_cube(m_side=12, n=128, key=21)
+    p = wf.Params(k=5, ridge_rel=1e-3)
+    b = wf.fit(cube.i_cars, cube.i_ref, p)["basis"]
+    x = b["x"]
+    assert b["ridge_lambda"] == pytest.approx(1e-3 * np.linalg.norm(x, 2) ** 2, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Variance scaling f of Eq. 9: its purpose is unit variance of f A over an
+# image of one repeated spectrum under Poisson + Gaussian noise (first-order
+# error propagation through the logarithm)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,sigma_g", [(4e-4, 5e-3), (1e-5, 2e-2), (5e-4, 0.0)])
+def test_scaling_f_gives_unit_variance_on_repeated_spectrum(alpha, sigma_g):
+    n, m = 64, 200_000
+    w = np.linspace(0.0, 1.0, n)
+    i0 = 2.0 + 6.0 * np.exp(-((w - 0.4) / 0.15) ** 2)      # 2 ... 8: I0^2 differs from I0
+    i_ref = 1.5 + w                                          # noiseless reference
+    rng = np.random.default_rng(909)
+    sd = np.sqrt(alpha * i0 + sigma_g ** 2)                  # Poisson (Gaussian limit) + Gaussian
+    assert np.all(sd / i0 < 0.02)                            # inside the first-order regime
+    i_cars = i0 + sd * rng.standard_normal((m, n))
+    p = wf.Params(f_mode=wf.F_NOISE, alpha=alpha, sigma_g=sigma_g)
+    f = wf.scaling_f(i_cars, p)
+    ell, _ = wf.log_ratio(i_cars, i_ref, 1e-6)
+    std = (ell * f).std(axis=0)
+    # sampling error of a standard deviation over 2e5 rows: 0.16 %
+    assert np.all(np.abs(std - 1.0) < 0.01), (std.min(), std.max())
+    # f itself: 2 <I> / sqrt(alpha <I> + sigma_g^2), computed per wavenumber
+    mean = i_cars.mean(axis=0)
+    np.testing.assert_allclose(f, 2.0 * mean / np.sqrt(alpha * mean + sigma_g ** 2), rtol=1e-14)
+
+
+def test_scaling_f_one_mode_and_awgn_form():
+    # f_mode one gives f = 1; with alpha = 0 (AWGN) f = 2 <I> / sigma_g
+    rng = np.random.default_rng(3)
+    i_cars = 1.0 + rng.random((50, 16))
+    np.testing.assert_array_equal(wf.scaling_f(i_cars, wf.Params()), np.ones(16))
+    f = wf.scaling_f(i_cars, wf.Params(f_mode=wf.F_NOISE, alpha=0.0, sigma_g=0.25))
+    np.testing.assert_allclose(f, 8.0 * i_cars.mean(axis=0), rtol=1e-14)
