@@ -10,8 +10,13 @@
  * Memory: pointers named d_* are device pointers on the context's device,
  * h_* are host pointers.  The caller owns every buffer it passes and keeps it
  * alive until the call's work has finished on the context's stream.  The
- * library owns only what it returns (contexts and bases) and its internal
- * workspace, which lives in the context.
+ * library owns only what it returns (contexts, bases, servers).  Device
+ * scratch of fkk_fit, fkk_plain and fkk_transform comes from the caller when
+ * it passes a workspace (d_ws, ws_bytes; fkk_workspace_size gives the size):
+ * such a call allocates no device memory except the basis fkk_fit returns.
+ * With d_ws NULL (ws_bytes 0) the context uses a workspace of its own, grown
+ * on demand and kept until the context is destroyed; the stage calls
+ * (fkk_gram, fkk_project, fkk_basis_residual) always use that one.
  *
  * Errors: every call returns an fkk_status; no exception crosses the ABI.
  * Arguments are checked before any launch.  fkk_ctx_last_error() returns a
@@ -63,9 +68,10 @@ enum { FKK_F_ONE = 0, FKK_F_NOISE = 1 };
 /* Which plane of K_CARS (Eq. 23) the output holds. */
 enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
 /* Precision of the matrix-core contractions.  FP32 and BF16 accumulate in
- * FP32 (the Gram sums its 32- or 64-row stages in FP64); BF16 rounds the
- * operands (log ratio, projection weights, Z and the corrected bases) to
- * BF16, nearest even, as they are staged.  FP64 (Gram only) promotes the
+ * FP32.  The FP32 Gram sums each 32-row stage in FP32 and the stages in FP64;
+ * the BF16 Gram sums a whole row chunk (about M / 64 rows) in FP32 and the
+ * chunks in FP64.  BF16 rounds the operands (log ratio, projection weights, Z
+ * and the corrected bases) to BF16, nearest even, as they are staged.  FP64 (Gram only) promotes the
  * FP32 log ratio to FP64 and accumulates in FP64 on the FP64 matrix cores:
  * the tail of the Gram's spectrum (eigenvalue gaps of ~1e-9 of the largest
  * on tissue cubes) then moves the retained subspace, and with it the
@@ -154,7 +160,13 @@ typedef struct {
     double dev_ms_recon;   /* reconstruction + epilogue kernel             */
     double dev_ms_tridiag; /* Householder tridiagonalisation (device)      */
     double dev_ms_logratio;/* log-ratio pass (device)                      */
+    int32_t tridiag_path;  /* how the tridiagonalisation ran: FKK_TRIDIAG_* */
 } fkk_fit_report;
+
+/* fkk_fit_report.tridiag_path: none (randomized SVD), one cooperative launch
+ * with the rows resident in LDS, or one launch per column (forced, beyond
+ * the resident size, or after a resident wait gave up). */
+enum { FKK_TRIDIAG_NONE = 0, FKK_TRIDIAG_RESIDENT = 1, FKK_TRIDIAG_PER_COLUMN = 2 };
 
 /* Host description of a basis set (Sec. 2.6: f, S, V and the corrected
  * bases).  Arrays are row-major FP64. */
@@ -188,8 +200,22 @@ void fkk_params_default(fkk_params* p);
 fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out);
 void fkk_ctx_destroy(fkk_ctx* ctx);
 const char* fkk_ctx_last_error(const fkk_ctx* ctx);
-/* Bytes of device workspace the context currently holds. */
+/* Bytes of device workspace the context currently holds (its own
+ * workspace; 0 while every call brought one). */
 size_t fkk_ctx_workspace_bytes(const fkk_ctx* ctx);
+
+/* Operations whose device scratch a caller can provide. */
+enum { FKK_OP_FIT = 0, FKK_OP_TRANSFORM = 1, FKK_OP_PLAIN = 2 };
+/*
+ * Bytes of device workspace the operation needs for M spectra of N points
+ * with parameters p (FKK_OP_TRANSFORM: p may be NULL; it needs none, so 0).
+ * FKK_OP_PLAIN covers fkk_plain and fkk_plain_f64; it may also run in less
+ * (its spectra then go through in smaller batches, down to 256 rows).  The
+ * size does not depend on the device; ctx may be NULL.  FKK_EINVAL for a bad
+ * op, size or parameter set.
+ */
+fkk_status fkk_workspace_size(const fkk_ctx* ctx, int32_t op, int64_t M, int32_t N, const fkk_params* p,
+                              size_t* bytes);
 
 /*
  * fKK-EC on a dataset ("training", Fig. 1b; Eq. 6-23).
@@ -199,33 +225,43 @@ size_t fkk_ctx_workspace_bytes(const fkk_ctx* ctx);
  * projection and (if d_out != NULL) the reconstruction of Eq. 23 into d_out
  * (M x N FP32, stride ld_out, plane selected by p->output).  Returns a new
  * basis in *out_basis (may be NULL if the caller does not want it).
- * Synchronous: returns after d_out is written.
+ * d_ws: device workspace of at least fkk_workspace_size(FKK_OP_FIT) bytes,
+ * 256-byte aligned, or NULL (the context's own).  Synchronous: returns after
+ * d_out is written.
  */
 fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
                    const double* h_iref, const fkk_params* p, fkk_basis** out_basis,
-                   float* d_out, int64_t ld_out, fkk_fit_report* rep);
+                   float* d_out, int64_t ld_out, void* d_ws, size_t ws_bytes,
+                   fkk_fit_report* rep);
 
 /*
  * ML:fKK-EC (Fig. 1c; Eq. 24-25 then Eq. 23): applies a stored basis to new
- * spectra.  Z_new = A_new V diag(s^2/(s^2+ml_lambda)), out = plane of
- * exp(Z B_re + i Z B_im).  d_I: M x basis.N FP32 (stride ld); d_out: M x N
- * FP32 (stride ld_out).  Asynchronous on the context's stream; no host
- * synchronisation.  Each output row depends only on its input row.
+ * spectra.  Z_new = A_new V diag(s^2/(s^2+ml_lambda)), out = plane (FKK_OUT_*)
+ * of exp(Z B_re + i Z B_im).  d_I: M x basis.N FP32 (stride ld); d_out: M x N
+ * FP32 (stride ld_out).  The fused kernel keeps Z in LDS and needs no
+ * workspace: pass d_ws NULL, ws_bytes 0 (a workspace given is not used).
+ * Asynchronous on the context's stream; no host synchronisation and no
+ * allocation.  Each output row depends only on its input row.
  */
 fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M,
-                         int64_t ld, float* d_out, int64_t ld_out);
+                         int64_t ld, float* d_out, int64_t ld_out, int32_t plane, void* d_ws,
+                         size_t ws_bytes);
 
 /*
  * Conventional per-spectrum KK -> PEC -> SEC (Eq. 2-5, SEC in the log form
  * of Eq. 19) for every row: the comparator of Fig. 1a without the SVD
- * denoising.  Same data conventions as fkk_fit.  Asynchronous.
+ * denoising.  Same data conventions as fkk_fit; workspace as in fkk_fit
+ * (FKK_OP_PLAIN; a smaller one of at least 256 spectra's share runs the
+ * spectra in smaller batches).  Asynchronous.
  */
 fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,
-                     const double* h_iref, const fkk_params* p, float* d_out, int64_t ld_out);
+                     const double* h_iref, const fkk_params* p, float* d_out, int64_t ld_out,
+                     void* d_ws, size_t ws_bytes);
 /* Same with FP64 intensities in and FP64 K_CARS out (d_I 8-byte aligned);
  * the arithmetic is FP64 in both variants. */
 fkk_status fkk_plain_f64(fkk_ctx* ctx, const double* d_I, int64_t M, int32_t N, int64_t ld,
-                         const double* h_iref, const fkk_params* p, double* d_out, int64_t ld_out);
+                         const double* h_iref, const fkk_params* p, double* d_out, int64_t ld_out,
+                         void* d_ws, size_t ws_bytes);
 
 /* ---- stages of the fit (each step of Fig. 1b on its own) ---------------- */
 
@@ -301,7 +337,9 @@ fkk_status fkk_basis_info(const fkk_basis* b, int32_t* N, int32_t* k, int32_t* n
 fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double* s,
                             double* v, double* b_re, double* b_im, double* phi_pec_t,
                             double* v_sec_t, double* h_v, int64_t* q, double* scalars3);
-void fkk_basis_free(fkk_basis* b);
+/* Frees a basis (NULL: nothing).  FKK_EBUSY, and nothing freed, while a
+ * server holds it (fkk_server_add_basis until fkk_server_destroy). */
+fkk_status fkk_basis_free(fkk_basis* b);
 /* Matrix-core precision (FKK_PREC_*) of the projection and reconstruction
  * that fkk_transform, fkk_project, fkk_reconstruct and the server run with
  * this basis (both copies are kept on the device).  Imported bases start in
@@ -345,7 +383,8 @@ typedef struct {
 fkk_status fkk_server_create(int device, const fkk_server_config* cfg, fkk_server** out);
 /* Makes a basis resident for this server; *basis_id identifies it in
  * fkk_server_submit.  Its tiles run in the basis's precision at the time of
- * this call.  The basis must stay alive until the server is destroyed. */
+ * this call.  The server holds the basis until it is destroyed:
+ * fkk_basis_free fails with FKK_EBUSY meanwhile. */
 fkk_status fkk_server_add_basis(fkk_server* srv, const fkk_basis* basis, int32_t* basis_id);
 /* Queues one tile: h_in (rows x N FP32, stride ld) -> h_out (rows x N FP32,
  * stride ld_out), both host memory (page-locked memory overlaps best) that

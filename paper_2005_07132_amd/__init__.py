@@ -7,8 +7,10 @@ importing works but every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -18,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfkkec.so")
 FKK_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
           -4: "invalid intensities", -5: "basis / data mismatch", -7: "rank not available",
-          -8: "internal numerical failure"}
+          -8: "internal numerical failure", -9: "busy"}
 DETREND_ALS, DETREND_WHITTAKER = 0, 1
 SEC_SAVGOL, SEC_MEAN = 0, 1
 PAD_EDGE, PAD_ZERO = 0, 1
@@ -26,7 +28,9 @@ F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
 SVD_GRAM, SVD_RANDOMIZED = 0, 1
+TRIDIAG_NONE, TRIDIAG_RESIDENT, TRIDIAG_PER_COLUMN = 0, 1, 2
 SEC_FORM_LOG, SEC_FORM_RE = 0, 1
+OP_FIT, OP_TRANSFORM, OP_PLAIN = 0, 1, 2
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
@@ -55,6 +59,7 @@ class FitReport(ctypes.Structure):
         ("ms_basis", ctypes.c_double), ("ms_recon", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("dev_ms_gram", ctypes.c_double), ("dev_ms_project", ctypes.c_double), ("dev_ms_recon", ctypes.c_double),
         ("dev_ms_tridiag", ctypes.c_double), ("dev_ms_logratio", ctypes.c_double),
+        ("tridiag_path", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -88,7 +93,7 @@ _LIB = None
 
 SYMBOLS = [
     "fkk_version", "fkk_status_string", "fkk_params_default", "fkk_ctx_create", "fkk_ctx_destroy",
-    "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
+    "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_workspace_size", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
     "fkk_gram",
     "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
     "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
@@ -117,11 +122,13 @@ def lib() -> ctypes.CDLL:
     L.fkk_ctx_last_error.argtypes = [vp]
     L.fkk_ctx_workspace_bytes.restype = ctypes.c_size_t
     L.fkk_ctx_workspace_bytes.argtypes = [vp]
+    sz = ctypes.c_size_t
+    L.fkk_workspace_size.argtypes = [vp, i32, i64, i32, ctypes.POINTER(Params), ctypes.POINTER(sz)]
     L.fkk_fit.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), ctypes.POINTER(vp), vp, i64,
-                          ctypes.POINTER(FitReport)]
-    L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64]
-    L.fkk_plain.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64]
-    L.fkk_plain_f64.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64]
+                          vp, sz, ctypes.POINTER(FitReport)]
+    L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64, i32, vp, sz]
+    L.fkk_plain.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64, vp, sz]
+    L.fkk_plain_f64.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64, vp, sz]
     L.fkk_gram.argtypes = [vp, vp, i64, i32, i64, _c_double_p, dbl, i32, _c_double_p, _c_double_p, _c_int64_p]
     L.fkk_eigh_topk.argtypes = [_c_double_p, i32, i32, _c_double_p, _c_double_p]
     L.fkk_basis_from_factors.argtypes = [vp, i32, i32, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
@@ -146,7 +153,8 @@ def lib() -> ctypes.CDLL:
     for name in ("fkk_server_create", "fkk_server_add_basis", "fkk_server_submit", "fkk_server_wait",
                  "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("fkk_ctx_create", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64", "fkk_gram",
+    for name in ("fkk_ctx_create", "fkk_workspace_size", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
+                 "fkk_gram", "fkk_basis_free",
                  "fkk_eigh_topk",
                  "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
                  "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision",
@@ -154,6 +162,50 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
+
+
+# Live library objects, closed in dependency order (servers, then
+# contexts, then bases) by an exit handler that runs while the interpreter
+# and the HIP runtime are still whole.  After it, __del__ does nothing.
+_LIVE = {"server": weakref.WeakSet(), "ctx": weakref.WeakSet(), "basis": weakref.WeakSet()}
+_SHUTDOWN = False
+
+
+def close_all():
+    """Closes every live server, context and basis (servers first, since
+    they hold bases).  Registered to run at interpreter exit."""
+    global _SHUTDOWN
+    for kind in ("server", "ctx", "basis"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close() if kind != "basis" else obj.free()
+            except Exception:
+                pass
+    _SHUTDOWN = True
+
+
+atexit.register(close_all)
+
+
+def workspace_size(op: int, m: int, n: int, p: "Params | None" = None) -> int:
+    """Device bytes fkk_fit (OP_FIT), fkk_plain (OP_PLAIN) or fkk_transform
+    (OP_TRANSFORM) needs for m spectra of n points."""
+    b = ctypes.c_size_t()
+    st = lib().fkk_workspace_size(None, int(op), int(m), int(n), ctypes.byref(p) if p is not None else None,
+                                  ctypes.byref(b))
+    if st != FKK_OK:
+        raise FkkError(st, "workspace_size")
+    return int(b.value)
+
+
+def _ws_args(ws):
+    """(pointer, bytes) of a caller workspace tensor, or (None, 0)."""
+    if ws is None:
+        return None, 0
+    import torch
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise TypeError("ws must be a contiguous device tensor")
+    return ws.data_ptr(), ws.numel() * ws.element_size()
 
 
 class FkkError(RuntimeError):
@@ -222,6 +274,8 @@ class Basis:
 
     def __init__(self, handle: int):
         self._h = ctypes.c_void_p(handle)
+        if handle:
+            _LIVE["basis"].add(self)
 
     @property
     def handle(self):
@@ -264,11 +318,16 @@ class Basis:
         return out
 
     def free(self):
+        """Frees the basis; FkkError (busy) while a server holds it."""
         if self._h and self._h.value:
-            lib().fkk_basis_free(self._h)
+            st = lib().fkk_basis_free(self._h)
+            if st != FKK_OK:
+                raise FkkError(st, "basis_free: held by a server")
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
+        if _SHUTDOWN:
+            return
         try:
             self.free()
         except Exception:
@@ -303,6 +362,7 @@ class Context:
         if st != FKK_OK:
             raise FkkError(st, "context creation")
         self._h = h
+        _LIVE["ctx"].add(self)
 
     @property
     def handle(self):
@@ -324,13 +384,16 @@ class Context:
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
+        if _SHUTDOWN:
+            return
         try:
             self.close()
         except Exception:
             pass
 
     # -- whole workflows --------------------------------------------------
-    def fit(self, I, i_ref, p: Params, out=None, want_out: bool = True):
+    def fit(self, I, i_ref, p: Params, out=None, want_out: bool = True, ws=None, want_basis: bool = True):
+        """fKK-EC fit; ws: optional device workspace tensor (workspace_size(OP_FIT))."""
         import torch
         _check_tensor(I, "I")
         m, n = I.shape
@@ -339,28 +402,32 @@ class Context:
             out = torch.empty((m, n), dtype=torch.float32, device=I.device)
         if out is not None:
             _check_tensor(out, "out")
+        wp, wb = _ws_args(ws)
         rep = FitReport()
         b = ctypes.c_void_p()
-        st = lib().fkk_fit(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ctypes.byref(p), ctypes.byref(b),
+        st = lib().fkk_fit(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ctypes.byref(p),
+                           ctypes.byref(b) if want_basis else None,
                            out.data_ptr() if out is not None else None, out.stride(0) if out is not None else n,
-                           ctypes.byref(rep))
+                           wp, wb, ctypes.byref(rep))
         self._ok(st, "fit")
-        return Basis(b.value), out, rep.as_dict()
+        return (Basis(b.value) if want_basis else None), out, rep.as_dict()
 
-    def transform(self, basis: Basis, I, out=None):
+    def transform(self, basis: Basis, I, out=None, plane: int = OUT_IM):
         import torch
         _check_tensor(I, "I")
         m, n = I.shape
         if out is None:
             out = torch.empty((m, n), dtype=torch.float32, device=I.device)
         _check_tensor(out, "out")
-        st = lib().fkk_transform(self._h, basis.handle, I.data_ptr(), m, I.stride(0), out.data_ptr(), out.stride(0))
+        st = lib().fkk_transform(self._h, basis.handle, I.data_ptr(), m, I.stride(0), out.data_ptr(), out.stride(0),
+                                 int(plane), None, 0)
         self._ok(st, "transform")
         return out
 
-    def plain(self, I, i_ref, p: Params, out=None):
+    def plain(self, I, i_ref, p: Params, out=None, ws=None):
         """Conventional per-spectrum KK / PEC / SEC.  float32 tensors use
-        fkk_plain, float64 tensors fkk_plain_f64 (output of the same dtype)."""
+        fkk_plain, float64 tensors fkk_plain_f64 (output of the same dtype);
+        ws: optional device workspace tensor (workspace_size(OP_PLAIN))."""
         import torch
         f64 = I.dtype == torch.float64
         dt = "float64" if f64 else "float32"
@@ -371,8 +438,9 @@ class Context:
             out = torch.empty((m, n), dtype=I.dtype, device=I.device)
         _check_tensor(out, "out", dt)
         fn = lib().fkk_plain_f64 if f64 else lib().fkk_plain
+        wp, wb = _ws_args(ws)
         st = fn(self._h, I.data_ptr(), m, n, I.stride(0), _dptr(i_ref), ctypes.byref(p), out.data_ptr(),
-                out.stride(0))
+                out.stride(0), wp, wb)
         self._ok(st, "plain")
         return out
 
@@ -450,6 +518,9 @@ class Server:
             raise FkkError(st, "server creation")
         self._h = h
         self._bases = []
+        self._n = []
+        self._held = {}  # ticket -> (tile, out): host buffers stay referenced until the tile completes
+        _LIVE["server"].add(self)
 
     def add_basis(self, basis: Basis) -> int:
         bid = ctypes.c_int32()
@@ -457,19 +528,41 @@ class Server:
         if st != FKK_OK:
             raise FkkError(st, "add_basis")
         self._bases.append(basis)  # keep it alive as long as the server
+        self._n.append(basis.info()[0])
         return bid.value
 
+    @staticmethod
+    def _host_view(a, name):
+        """(pointer, rows, cols, row stride in elements) of a host float32
+        2-D buffer with unit column stride."""
+        if hasattr(a, "data_ptr"):
+            if a.is_cuda:
+                raise TypeError(f"{name} must be in host memory")
+            if str(a.dtype) != "torch.float32" or a.dim() != 2 or a.stride(1) != 1:
+                raise TypeError(f"{name} must be a 2-D float32 tensor with unit column stride")
+            return a.data_ptr(), a.shape[0], a.shape[1], a.stride(0)
+        if not isinstance(a, np.ndarray) or a.dtype != np.float32 or a.ndim != 2 or a.strides[1] != 4 \
+                or a.strides[0] % 4:
+            raise TypeError(f"{name} must be a 2-D float32 array with unit column stride")
+        return a.ctypes.data, a.shape[0], a.shape[1], a.strides[0] // 4
+
     def submit(self, basis_id: int, tile, out) -> int:
-        """tile, out: host (preferably pinned) float32 2-D tensors or arrays."""
-        def ptr(a):
-            return a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data
-        def stride(a):
-            return a.stride(0) if hasattr(a, "data_ptr") else a.strides[0] // 4
+        """tile, out: host (preferably pinned) float32 2-D tensors or arrays;
+        out needs at least the tile's rows and both the basis's N columns."""
+        if not 0 <= basis_id < len(self._n):
+            raise FkkError(-1, f"submit: no basis {basis_id}")
+        n = self._n[basis_id]
+        tp, trows, tcols, tld = self._host_view(tile, "tile")
+        op, orows, ocols, old = self._host_view(out, "out")
+        if tcols < n or ocols < n:
+            raise FkkError(-1, f"submit: tile and out need {n} columns (got {tcols}, {ocols})")
+        if orows < trows:
+            raise FkkError(-1, f"submit: out has {orows} rows for a tile of {trows}")
         t = ctypes.c_int64()
-        st = lib().fkk_server_submit(self._h, basis_id, ptr(tile), tile.shape[0], stride(tile), ptr(out),
-                                     stride(out), ctypes.byref(t))
+        st = lib().fkk_server_submit(self._h, basis_id, tp, trows, tld, op, old, ctypes.byref(t))
         if st != FKK_OK:
             raise FkkError(st, "submit")
+        self._held[t.value] = (tile, out)
         return t.value
 
     def wait(self, ticket: int, timeout_ms: float = -1.0):
@@ -477,12 +570,14 @@ class Server:
         st = lib().fkk_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat))
         if st != FKK_OK:
             raise FkkError(st, "wait")
+        self._held.pop(ticket, None)
         return lat.value
 
     def drain(self):
         st = lib().fkk_server_drain(self._h)
         if st != FKK_OK:
             raise FkkError(st, "drain")
+        self._held.clear()
 
     def stats(self) -> dict:
         s = ServerStats()
@@ -498,8 +593,11 @@ class Server:
         if self._h and self._h.value:
             lib().fkk_server_destroy(self._h)
             self._h = ctypes.c_void_p(0)
+            self._held.clear()
 
     def __del__(self):
+        if _SHUTDOWN:
+            return
         try:
             self.close()
         except Exception:
@@ -507,5 +605,6 @@ class Server:
 
 
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
+           "workspace_size", "close_all", "OP_FIT", "OP_TRANSFORM", "OP_PLAIN",
            "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16",
            "PREC_FP64", "SVD_GRAM", "SVD_RANDOMIZED", "SEC_FORM_LOG", "SEC_FORM_RE"]

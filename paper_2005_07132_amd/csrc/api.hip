@@ -106,24 +106,33 @@ int host_threads() {
     return (int)std::min(16u, hw);
 }
 
+// Consecutive 256-byte aligned parts of one device region.  With a null
+// base it only counts bytes: the same code sizes a workspace and lays it out.
+struct Carve {
+    unsigned char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base(static_cast<unsigned char*>(b)) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
 }  // namespace
 
 struct fkk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    DevBuf<double> partial;
-    DevBuf<float> L;
-    DevBuf<double> colsum_part, G, colsum, fdev, tri, eigv;
-    DevBuf<unsigned long long> clamps;
-    DevBuf<int> tiles;
-    DevBuf<float> rinv, Z, X;
-    DevBuf<float> pmaxv, pminv;
-    DevBuf<long long> pmaxi, pmini, qext, qdev, bidx, qbet;
-    DevBuf<float> bval;
+    // The context's own device workspace, used by calls that get none from
+    // the caller (grown on demand, kept until the context is destroyed).
+    DevBuf<unsigned char> ws;
     PinnedBuf<double> hG;
     PinnedBuf<double> hstage;  // basis uploads
-    fkk::plain::Workspace plain_ws;
     hipEvent_t ev[12] = {};  // 0-9 stage timing, 10-11 eigensolve copies
     // The n - 1 launches of the tridiagonalisation, recorded once per order
     // and buffer set on a private stream and replayed on `stream`.
@@ -161,13 +170,7 @@ struct fkk_ctx {
         err = buf;
         return s;
     }
-    size_t bytes() const {
-        return partial.n * 8 + L.n * 4 + fdev.n * 8 + tri.n * 8 + eigv.n * 8 + colsum_part.n * 8 + G.n * 8 +
-               colsum.n * 8 +
-               clamps.n * 8 + tiles.n * 4 +
-               rinv.n * 4 + Z.n * 4 + X.n * 4 + pmaxv.n * 4 + pminv.n * 4 + pmaxi.n * 8 + pmini.n * 8 +
-               qext.n * 8 + qdev.n * 8 + bidx.n * 8 + qbet.n * 8 + bval.n * 4 + plain_ws.bytes();
-    }
+    size_t bytes() const { return ws.n; }
 };
 
 #define FKK_HIP(ctx, call)                                                                          \
@@ -369,11 +372,134 @@ fkk_basis* new_basis(int N, int k, const double* iref, const double* f, const do
 
 int npad_for(int N) { return round_up(N, fkk::dev::kGramTile); }
 
-// Log-ratio pass into ctx->L, Gram G_L = l^T l into ctx->G (device, FP64,
-// N x N), column sums into ctx->colsum and the clamp count into ctx->clamps.
+// ---- device workspace layouts ------------------------------------------------
+
+// Log ratio, Gram and column sums (Eq. 2, 6, 9).  with_gram false: the
+// log-ratio pass and column sums only; rrf: the range finder's products
+// (l^T Y, N x 128, and Y^T Y, 128 x 128) in place of the Gram.
+struct GramWs {
+    float* L = nullptr;                  // M x npad FP32 l, or the packed BF16 l
+    double* partial = nullptr;           // FP64 chunk partials of the tiles
+    double* G = nullptr;                 // N x N FP64 (rrf: npad x 128 + 128 x 128)
+    double* colsum_part = nullptr;       // per-block column sums
+    double* colsum = nullptr;            // N sums + reduction scratch
+    unsigned long long* clamps = nullptr;
+    int* tiles = nullptr;                // tile pairs
+    float* rinv = nullptr;               // 1/I_ref as two floats per wavenumber
+};
+
+void gram_layout(Carve& c, int64_t M, int N, int prec, bool with_gram, bool rrf, GramWs* w) {
+    const int npad = npad_for(N), nb = npad / fkk::dev::kGramTile;
+    const bool bf16 = (prec == FKK_PREC_BF16);
+    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
+    const fkk::dev::GramPlan pr = fkk::dev::gram_plan(M, N, 64, 32);
+    w->L = c.take<float>(bf16 ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4 : (size_t)M * npad);
+    size_t part = 0, g = 0, tiles = 0;
+    if (with_gram) {
+        part = plan.partial_doubles();
+        g = (size_t)N * N;
+        tiles = 2 * (size_t)plan.tiles;
+    } else if (rrf) {
+        part = (size_t)pr.chunks * nb * fkk::dev::kGramTile * fkk::dev::kGramTile;
+        g = (size_t)npad * fkk::dev::kGramTile + (size_t)fkk::dev::kGramTile * fkk::dev::kGramTile;
+        tiles = 2 * (size_t)(nb + 1);
+    }
+    w->partial = c.take<double>(part);
+    w->G = c.take<double>(g);
+    w->colsum_part = c.take<double>((size_t)fkk::dev::logratio_blocks(M) * npad);
+    w->colsum = c.take<double>(N + fkk::dev::colsum_scratch_doubles(N));
+    w->clamps = c.take<unsigned long long>(1);
+    w->tiles = c.take<int>(tiles);
+    w->rinv = c.take<float>(2 * (size_t)N);
+}
+
+// Everything fkk_fit uses on the device, in one region.
+struct FitWs {
+    GramWs g;
+    double* tri = nullptr;    // p0 | p1 | beta | d | e | reflectors | flags (2) | exchange
+    double* fdev = nullptr;   // f (N)
+    double* eigv = nullptr;   // Y, x = Q y and the expanded reflectors
+    float* Z = nullptr;       // M x kp (range finder: M x 128)
+    float* X = nullptr;       // projection weights kp x npad (range finder: 128 x npad)
+    float* pmaxv = nullptr;
+    float* pminv = nullptr;
+    long long* pmaxi = nullptr;
+    long long* pmini = nullptr;
+    long long* qext = nullptr;
+    long long* qdev = nullptr;
+    float* bval = nullptr;
+    long long* bidx = nullptr;
+    long long* qbet = nullptr;
+    float* rows = nullptr;    // the sub-sampled input rows, n_q x N
+};
+
+// Parameters are assumed valid (check_params).  The layout depends only on
+// the sizes and the parameters, never on the device.
+size_t fit_layout(void* base, int64_t M, int N, const fkk_params* p, FitWs* w) {
+    Carve c(base);
+    const bool rrf = (p->svd_mode == FKK_SVD_RANDOMIZED);
+    const int gprec = rrf ? FKK_PREC_FP32 : p->gram_prec;
+    gram_layout(c, M, N, gprec, !rrf, rrf, &w->g);
+    const int npad = npad_for(N);
+    const int kcap = p->k > 0 ? p->k : std::min(N, 128);
+    const int kp = kp_for(kcap), kq = std::max(kp, 32);
+    constexpr int LY = fkk::dev::kGramTile;
+    if (!rrf) {
+        const size_t nv = fkk::dev::tridiag_vstore_doubles(N), nx = fkk::dev::tridiag_resident_xch_doubles(N);
+        w->tri = c.take<double>(5 * (size_t)N + nv + 2 + nx);
+        w->eigv = c.take<double>(N <= fkk::dev::back_transform_max_n()
+                                     ? 2 * (size_t)N * kcap + fkk::dev::back_transform_vpad_doubles(N)
+                                     : 0);
+    }
+    w->fdev = c.take<double>(N);
+    w->Z = c.take<float>((size_t)M * (rrf ? std::max(kp, LY) : kp));
+    w->X = c.take<float>((size_t)(rrf ? std::max(kp, LY) : kp) * npad);
+    const int ka = (p->recon_prec == FKK_PREC_BF16) ? kq : kp;
+    const size_t nblk = (size_t)fkk::dev::proj_blocks(M);
+    w->pmaxv = c.take<float>(nblk * ka);
+    w->pminv = c.take<float>(nblk * ka);
+    w->pmaxi = c.take<long long>(nblk * ka);
+    w->pmini = c.take<long long>(nblk * ka);
+    w->qext = c.take<long long>(2 * (size_t)ka);
+    const bool ovr = p->n_q_override > 0;
+    const size_t nq = ovr ? (size_t)p->n_q_override : (size_t)kcap * (2 + p->q_between);
+    const size_t nbet = ovr ? 0 : (size_t)kcap * p->q_between;
+    const size_t np = nbet ? (size_t)fkk::dev::between_blocks(M, kp) * nbet : 0;
+    w->qdev = c.take<long long>(nq);
+    w->bval = c.take<float>(np);
+    w->bidx = c.take<long long>(np);
+    w->qbet = c.take<long long>(nbet);
+    w->rows = c.take<float>(nq * N);
+    return c.bytes();
+}
+
+size_t plain_layout_bytes(int64_t M, int N, const fkk_params* p) {
+    const int len = p->fft_len ? p->fft_len : fkk::default_fft_len(N);
+    return fkk::plain::layout_bytes(N, len, fkk::plain::full_batch(M));
+}
+
+// The region a call works in: the caller's (d_ws, at least `need` bytes,
+// 256-byte aligned), or the context's own, grown to `need`.
+fkk_status acquire_ws(fkk_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, void** out) {
+    if (d_ws) {
+        if (reinterpret_cast<uintptr_t>(d_ws) & 255)
+            return ctx->fail(FKK_EINVAL, "workspace must be 256-byte aligned");
+        if (ws_bytes < need)
+            return ctx->fail(FKK_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        *out = d_ws;
+        return FKK_OK;
+    }
+    if (ws_bytes != 0) return ctx->fail(FKK_EINVAL, "ws_bytes without a workspace");
+    FKK_HIP(ctx, ctx->ws.ensure(need));
+    *out = ctx->ws.p;
+    return FKK_OK;
+}
+
+// Log-ratio pass into w.L, Gram G_L = l^T l into w.G (device, FP64, N x N),
+// column sums into w.colsum and the clamp count into w.clamps.
 // with_gram false: the log-ratio pass and column sums only (FP32 l).
-fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t ld, const double* h_iref,
-                       double floor, int prec, bool timed, bool with_gram = true) {
+fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t M, int N, int64_t ld,
+                       const double* h_iref, double floor, int prec, bool timed, bool with_gram = true) {
     const int npad = npad_for(N);
     const bool bf16 = (prec == FKK_PREC_BF16);
     const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
@@ -382,54 +508,42 @@ fkk_status gram_device(fkk_ctx* ctx, const float* d_I, int64_t M, int N, int64_t
     std::vector<float> rinv(2 * (size_t)N);
     split_reciprocal(h_iref, N, rinv.data());
     const int64_t nlr = fkk::dev::logratio_blocks(M);
-    // FP32 l (M x npad) or the packed BF16 l, which needs at most half of it
-    FKK_HIP(ctx, ctx->L.ensure(bf16 ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4 : (size_t)M * npad));
-    if (with_gram) {
-        FKK_HIP(ctx, ctx->partial.ensure(plan.partial_doubles()));
-        FKK_HIP(ctx, ctx->G.ensure((size_t)N * N));
-    }
-    FKK_HIP(ctx, ctx->colsum_part.ensure((size_t)nlr * npad));
-    FKK_HIP(ctx, ctx->colsum.ensure(N + fkk::dev::colsum_scratch_doubles(N)));
-    FKK_HIP(ctx, ctx->clamps.ensure(1));
-    FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
-    FKK_HIP(ctx, ctx->rinv.ensure(2 * (size_t)N));
     hipStream_t s = ctx->stream;
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->rinv.p, rinv.data(), rinv.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemsetAsync(ctx->clamps.p, 0, sizeof(unsigned long long), s));
+    if (with_gram)
+        FKK_HIP(ctx, hipMemcpyAsync(w.tiles, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemcpyAsync(w.rinv, rinv.data(), rinv.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemsetAsync(w.clamps, 0, sizeof(unsigned long long), s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
-    uint16_t* lp16 = reinterpret_cast<uint16_t*>(ctx->L.p);
+    uint16_t* lp16 = reinterpret_cast<uint16_t*>(w.L);
     if (bf16)
-        FKK_HIP(ctx, fkk::dev::launch_logratio16(d_I, M, N, ld, ctx->rinv.p, (float)floor, lp16, npad,
-                                                 ctx->colsum_part.p, ctx->clamps.p, s));
+        FKK_HIP(ctx, fkk::dev::launch_logratio16(d_I, M, N, ld, w.rinv, (float)floor, lp16, npad, w.colsum_part,
+                                                 w.clamps, s));
     else
-        FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, ctx->rinv.p, (float)floor, ctx->L.p, npad, npad,
-                                               ctx->colsum_part.p, ctx->clamps.p, s));
+        FKK_HIP(ctx, fkk::dev::launch_logratio(d_I, M, N, ld, w.rinv, (float)floor, w.L, npad, npad, w.colsum_part,
+                                               w.clamps, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
     if (!with_gram) {
-        FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N,
-                                                    ctx->colsum.p, s));
+        FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(w.colsum_part, nlr, npad, N, w.colsum + N, w.colsum, s));
         return FKK_OK;
     }
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
     if (bf16)
-        FKK_HIP(ctx, fkk::dev::launch_gram16(lp16, npad, M, plan, ctx->tiles.p, ctx->partial.p, s));
+        FKK_HIP(ctx, fkk::dev::launch_gram16(lp16, npad, M, plan, w.tiles, w.partial, s));
     else
-        FKK_HIP(ctx, fkk::dev::launch_gram(ctx->L.p, npad, M, plan, ctx->tiles.p, ctx->partial.p, s,
-                                           prec == FKK_PREC_FP64));
+        FKK_HIP(ctx, fkk::dev::launch_gram(w.L, npad, M, plan, w.tiles, w.partial, s, prec == FKK_PREC_FP64));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
-    FKK_HIP(ctx, fkk::dev::launch_gram_reduce(ctx->partial.p, plan, ctx->tiles.p, N, ctx->G.p, s));
-    FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(ctx->colsum_part.p, nlr, npad, N, ctx->colsum.p + N, ctx->colsum.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_gram_reduce(w.partial, plan, w.tiles, N, w.G, s));
+    FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(w.colsum_part, nlr, npad, N, w.colsum + N, w.colsum, s));
     return FKK_OK;
 }
 
 // Column sums and clamp count back to the host (synchronises the stream).
-fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) {
+fkk_status fetch_sums(fkk_ctx* ctx, const GramWs& w, int N, double* h_colsum, int64_t* h_clamps) {
     FKK_HIP(ctx, ctx->hG.ensure((size_t)N + 1));
     hipStream_t s = ctx->stream;
     double* hg = ctx->hG.p;
-    FKK_HIP(ctx, hipMemcpyAsync(hg, ctx->colsum.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipMemcpyAsync(hg + N, ctx->clamps.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg, w.colsum, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg + N, w.clamps, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     std::memcpy(h_colsum, hg, N * sizeof(double));
     unsigned long long c;
@@ -441,13 +555,14 @@ fkk_status fetch_sums(fkk_ctx* ctx, int N, double* h_colsum, int64_t* h_clamps) 
 // Host end of the eigensolve once the reduction is queued on s: the small
 // arrays (beta | d | e, and the exchange error flag when flag != nullptr)
 // come back to the host, which finds the eigenpairs of T; the vectors go
-// back to the device for x = Q y against the reflectors left there (on the
-// host instead, from a copy of the reflectors, past the kernel's order
-// limit).  *failed reports a set flag (outputs then unused).  With
-// rel_cut > 0 only the pairs above the cut (relative to the largest
-// singular value) get vectors: *k_used of them, vecs then N x *k_used.
-fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta, const double* flag, double* vals,
-                      double* vecs, bool* failed, double rel_cut, int* k_used) {
+// back to the device (eigv: 2 N k + expanded reflectors) for x = Q y
+// against the reflectors left there (on the host instead, from a copy of
+// the reflectors, past the kernel's order limit).  *failed reports a set
+// flag (outputs then unused).  With rel_cut > 0 only the pairs above the
+// cut (relative to the largest singular value) get vectors: *k_used of
+// them, vecs then N x *k_used.
+fkk_status eig_finish(fkk_ctx* ctx, double* eigv, int N, int k, size_t nv, const double* beta, const double* flag,
+                      double* vals, double* vecs, bool* failed, double rel_cut, int* k_used) {
     hipStream_t s = ctx->stream;
     const bool dev_bt = N <= fkk::dev::back_transform_max_n();
     const size_t k4n = (size_t)(k + 3) / 4 * 4 * N;
@@ -484,8 +599,7 @@ fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta,
         fkk::tridiag_back_transform(h, hx, N, ku, hY, vecs);
         return FKK_OK;
     }
-    FKK_HIP(ctx, ctx->eigv.ensure(2 * (size_t)N * ku + fkk::dev::back_transform_vpad_doubles(N)));
-    double* dY = ctx->eigv.p;
+    double* dY = eigv;
     double* dx = dY + (size_t)N * ku;
     double* vpad = dx + (size_t)N * ku;
     FKK_HIP(ctx, hipMemcpyAsync(dY, hY, (size_t)N * ku * sizeof(double), hipMemcpyHostToDevice, s));
@@ -497,48 +611,50 @@ fkk_status eig_finish(fkk_ctx* ctx, int N, int k, size_t nv, const double* beta,
     return FKK_OK;
 }
 
-// Top-k eigenpairs of diag(f) G diag(f) with G = ctx->G: scaling, the
+// Top-k eigenpairs of diag(f) G diag(f) with G = w.g.G: scaling, the
 // Householder reduction and the back-transformation on the device, the
-// tridiagonal eigenproblem on the host.  Overwrites ctx->G.
-fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals, double* vecs, bool timed,
-                      double rel_cut, int* k_used) {
+// tridiagonal eigenproblem on the host.  Overwrites G.
+fkk_status eig_device(fkk_ctx* ctx, const FitWs& w, int N, int k, const double* f, double* vals, double* vecs,
+                      bool timed, double rel_cut, int* k_used, int* path) {
     const size_t nv = fkk::dev::tridiag_vstore_doubles(N);
     const size_t nx = fkk::dev::tridiag_resident_xch_doubles(N);
-    // layout of ctx->tri: p0 | p1 | beta | d | e | vstore | flags (2) | exchange (nx)
-    FKK_HIP(ctx, ctx->tri.ensure(5 * (size_t)N + nv + 2 + nx));
-    FKK_HIP(ctx, ctx->fdev.ensure(N));
     hipStream_t s = ctx->stream;
-    double* t = ctx->tri.p;
+    double* G = w.g.G;
+    double* t = w.tri;
     double *p0 = t, *p1 = t + N, *beta = t + 2 * N, *d = t + 3 * N, *e = t + 4 * N, *vs = t + 5 * N;
     double* flags = vs + nv;  // [0]: exchange error (int), [1]: unused
     double* xch = flags + 2;
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, f, N * sizeof(double), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, fkk::dev::launch_scale_sym(ctx->G.p, ctx->fdev.p, N, s));
+    FKK_HIP(ctx, hipMemcpyAsync(w.fdev, f, N * sizeof(double), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, fkk::dev::launch_scale_sym(G, w.fdev, N, s));
     const int rg = ctx->resident_tri ? fkk::dev::tridiag_resident_grid(N, ctx->device) : 0;
     if (rg > 0) {
         // G is read only, so a failed exchange leaves it for the per-column path
         if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
         FKK_HIP(ctx, hipMemsetAsync(flags, 0, (2 + nx) * sizeof(double), s));
-        if (fkk::dev::launch_tridiag_resident(ctx->G.p, N, rg, xch, reinterpret_cast<int*>(flags), vs, beta, d, e,
+        if (fkk::dev::launch_tridiag_resident(G, N, rg, xch, reinterpret_cast<int*>(flags), vs, beta, d, e,
                                               ctx->tri_spin_limit, s) == hipSuccess) {
             if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
             bool failed = false;
-            const fkk_status st = eig_finish(ctx, N, k, nv, beta, flags, vals, vecs, &failed, rel_cut, k_used);
-            if (st != FKK_OK || !failed) return st;
+            const fkk_status st =
+                eig_finish(ctx, w.eigv, N, k, nv, beta, flags, vals, vecs, &failed, rel_cut, k_used);
+            if (st != FKK_OK || !failed) {
+                if (path) *path = FKK_TRIDIAG_RESIDENT;
+                return st;
+            }
         } else {
             (void)hipGetLastError();  // launch refused (e.g. the grid cannot be co-resident)
         }
         ctx->resident_tri = false;
     }
     FKK_HIP(ctx, fkk::dev::tridiag_prepare(N));
-    if (ctx->graphs && !(ctx->tri_exec && ctx->tri_n == N && ctx->tri_key[0] == ctx->G.p && ctx->tri_key[1] == t)) {
+    if (ctx->graphs && !(ctx->tri_exec && ctx->tri_n == N && ctx->tri_key[0] == G && ctx->tri_key[1] == t)) {
         if (ctx->tri_exec) {
             hipGraphExecDestroy(ctx->tri_exec);
             ctx->tri_exec = nullptr;
         }
         if (!ctx->cap_stream) FKK_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         FKK_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, ctx->cap_stream);
+        const hipError_t le = fkk::dev::launch_tridiag(G, N, p0, p1, vs, beta, d, e, ctx->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
         hipError_t ie = hipSuccess;
@@ -550,17 +666,18 @@ fkk_status eig_device(fkk_ctx* ctx, int N, int k, const double* f, double* vals,
                              hipGetErrorString(le != hipSuccess ? le : ce != hipSuccess ? ce : ie));
         }
         ctx->tri_n = N;
-        ctx->tri_key[0] = ctx->G.p;
+        ctx->tri_key[0] = G;
         ctx->tri_key[1] = t;
     }
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     if (ctx->graphs)
         FKK_HIP(ctx, hipGraphLaunch(ctx->tri_exec, s));
     else
-        FKK_HIP(ctx, fkk::dev::launch_tridiag(ctx->G.p, N, p0, p1, vs, beta, d, e, s));
+        FKK_HIP(ctx, fkk::dev::launch_tridiag(G, N, p0, p1, vs, beta, d, e, s));
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     bool failed = false;
-    return eig_finish(ctx, N, k, nv, beta, nullptr, vals, vecs, &failed, rel_cut, k_used);
+    if (path) *path = FKK_TRIDIAG_PER_COLUMN;
+    return eig_finish(ctx, w.eigv, N, k, nv, beta, nullptr, vals, vecs, &failed, rel_cut, k_used);
 }
 
 // Standard normal numbers for the range finder's test matrix: SplitMix64
@@ -585,13 +702,13 @@ void rrf_gaussian(uint64_t seed, size_t n, double* out) {
 
 // Top-k singular triplets of A = l diag(f) by the randomized range finder
 // with subspace iteration (Halko, Martinsson & Tropp 2011, Algorithms 4.4
-// and 5.1) on the FP32 log ratio in ctx->L: Y = A W on the matrix cores
+// and 5.1) on the FP32 log ratio in w.g.L: Y = A W on the matrix cores
 // (projection kernel), Y^T Y with FP64 products and sums, A^T Y as FP64
 // partials of FP32 matrix-core stages; the n x l and l x l algebra in FP64
 // on the host.  Q = Y R^-1 with R from Cholesky of Y^T Y stays implicit:
 // A^T Q = diag(f) (l^T Y) R^-1.  Outputs s (k) and V (N x k, sign rule).
-fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk_params* p, int k, double* sv,
-                      double* V) {
+fkk_status rrf_device(fkk_ctx* ctx, const FitWs& w, int64_t M, int N, const double* f, const fkk_params* p, int k,
+                      double* sv, double* V) {
     const int l = k + p->rrf_oversample;
     const int npad = npad_for(N), nb = npad / fkk::dev::kGramTile;
     constexpr int LY = fkk::dev::kGramTile;  // Y is M x 128 (columns past l zero)
@@ -606,15 +723,10 @@ fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk
     py.tiles = 1;   // (0, 0): Y^T Y
     std::vector<int> pairs(2 * (size_t)(nb + 1), 0);
     for (int bi = 0; bi < nb; ++bi) pairs[2 * bi] = bi;
-    FKK_HIP(ctx, ctx->Z.ensure((size_t)M * LY));
-    FKK_HIP(ctx, ctx->X.ensure((size_t)LY * npad));
-    FKK_HIP(ctx, ctx->partial.ensure(pc.partial_doubles()));
-    FKK_HIP(ctx, ctx->tiles.ensure(pairs.size()));
-    FKK_HIP(ctx, ctx->G.ensure((size_t)npad * LY + (size_t)LY * LY));
     FKK_HIP(ctx, ctx->hG.ensure((size_t)npad * LY + (size_t)LY * LY));
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->tiles.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    double* d_c = ctx->G.p;                         // l^T Y: N x 128
-    double* d_gy = ctx->G.p + (size_t)npad * LY;    // Y^T Y: 128 x 128
+    FKK_HIP(ctx, hipMemcpyAsync(w.g.tiles, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    double* d_c = w.g.G;                         // l^T Y: N x 128
+    double* d_gy = w.g.G + (size_t)npad * LY;    // Y^T Y: 128 x 128
     double* h_c = ctx->hG.p;
     double* h_gy = ctx->hG.p + (size_t)npad * LY;
     std::vector<float> wt((size_t)LY * npad);
@@ -624,16 +736,16 @@ fkk_status rrf_device(fkk_ctx* ctx, int64_t M, int N, const double* f, const fkk
         std::fill(wt.begin(), wt.end(), 0.f);
         for (int c = 0; c < l; ++c)
             for (int j = 0; j < N; ++j) wt[(size_t)c * npad + j] = (float)(f[j] * W[(size_t)j * l + c]);
-        FKK_HIP(ctx, hipMemcpyAsync(ctx->X.p, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
-        FKK_HIP(ctx, fkk::dev::launch_project(ctx->L.p, M, N, npad, ctx->rinv.p, (float)p->ratio_floor, ctx->X.p,
-                                              npad, LY, LY, ctx->Z.p, LY, none, 0, s, true));
-        FKK_HIP(ctx, fkk::dev::launch_gram_pair(ctx->Z.p, LY, ctx->Z.p, LY, M, py, ctx->tiles.p + 2 * nb,
-                                                ctx->partial.p, s, true));
-        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(ctx->partial.p, py, ctx->tiles.p + 2 * nb, LY, LY, d_gy, LY,
+        FKK_HIP(ctx, hipMemcpyAsync(w.X, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        FKK_HIP(ctx, fkk::dev::launch_project(w.g.L, M, N, npad, w.g.rinv, (float)p->ratio_floor, w.X,
+                                              npad, LY, LY, w.Z, LY, none, 0, s, true));
+        FKK_HIP(ctx, fkk::dev::launch_gram_pair(w.Z, LY, w.Z, LY, M, py, w.g.tiles + 2 * nb,
+                                                w.g.partial, s, true));
+        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(w.g.partial, py, w.g.tiles + 2 * nb, LY, LY, d_gy, LY,
                                                        s));
-        FKK_HIP(ctx, fkk::dev::launch_gram_pair(ctx->L.p, npad, ctx->Z.p, LY, M, pc, ctx->tiles.p, ctx->partial.p, s,
+        FKK_HIP(ctx, fkk::dev::launch_gram_pair(w.g.L, npad, w.Z, LY, M, pc, w.g.tiles, w.g.partial, s,
                                                 false));
-        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(ctx->partial.p, pc, ctx->tiles.p, N, LY, d_c, LY, s));
+        FKK_HIP(ctx, fkk::dev::launch_gram_reduce_rect(w.g.partial, pc, w.g.tiles, N, LY, d_c, LY, s));
         FKK_HIP(ctx, hipMemcpyAsync(h_c, d_c, (size_t)N * LY * sizeof(double), hipMemcpyDeviceToHost, s));
         FKK_HIP(ctx, hipMemcpyAsync(h_gy, d_gy, (size_t)LY * LY * sizeof(double), hipMemcpyDeviceToHost, s));
         FKK_HIP(ctx, hipStreamSynchronize(s));
@@ -754,31 +866,9 @@ void fkk_ctx_destroy(fkk_ctx* ctx) {
     hipStreamSynchronize(ctx->stream);
     if (ctx->tri_exec) hipGraphExecDestroy(ctx->tri_exec);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-    ctx->partial.release();
-    ctx->L.release();
-    ctx->fdev.release();
-    ctx->tri.release();
-    ctx->eigv.release();
-    ctx->colsum_part.release();
-    ctx->G.release();
-    ctx->colsum.release();
-    ctx->clamps.release();
-    ctx->tiles.release();
-    ctx->rinv.release();
-    ctx->Z.release();
-    ctx->X.release();
-    ctx->pmaxv.release();
-    ctx->pminv.release();
-    ctx->pmaxi.release();
-    ctx->pmini.release();
-    ctx->qext.release();
-    ctx->qdev.release();
-    ctx->bidx.release();
-    ctx->qbet.release();
-    ctx->bval.release();
+    ctx->ws.release();
     ctx->hG.release();
     ctx->hstage.release();
-    ctx->plain_ws.release();
     for (auto& e : ctx->ev)
         if (e) hipEventDestroy(e);
     delete ctx;
@@ -797,12 +887,19 @@ fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_
     if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
     if (!valid_gram_prec(prec)) return ctx->fail(FKK_EINVAL, "bad precision %d", prec);
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, ratio_floor, prec, false)) != FKK_OK) return st;
-    if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, ctx->G.p, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,
+    GramWs w;
+    Carve sizing(nullptr);
+    gram_layout(sizing, M, N, prec, true, false, &w);
+    void* base = nullptr;
+    if ((st = acquire_ws(ctx, nullptr, 0, sizing.bytes(), &base)) != FKK_OK) return st;
+    Carve c(base);
+    gram_layout(c, M, N, prec, true, false, &w);
+    if ((st = gram_device(ctx, w, d_I, M, N, ld, h_iref, ratio_floor, prec, false)) != FKK_OK) return st;
+    if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, w.G, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,
                                             ctx->stream));
     std::vector<double> cs(N);
     int64_t cl = 0;
-    if ((st = fetch_sums(ctx, N, cs.data(), &cl)) != FKK_OK) return st;
+    if ((st = fetch_sums(ctx, w, N, cs.data(), &cl)) != FKK_OK) return st;
     if (h_colsum) std::memcpy(h_colsum, cs.data(), N * sizeof(double));
     if (h_clamps) *h_clamps = cl;
     return FKK_OK;
@@ -839,7 +936,8 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
 }
 
 fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                   const fkk_params* p, fkk_basis** out_basis, float* d_out, int64_t ld_out, fkk_fit_report* rep) {
+                   const fkk_params* p, fkk_basis** out_basis, float* d_out, int64_t ld_out, void* d_ws,
+                   size_t ws_bytes, fkk_fit_report* rep) {
     if (!ctx) return FKK_EINVAL;
     const auto t_all = std::chrono::steady_clock::now();
     fkk_status st;
@@ -860,6 +958,10 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     // those above the cut-off (Sec. 4.1)
     const int kcap = p->k > 0 ? p->k : std::min(N, 128);
     fkk_fit_report r{};
+    FitWs w;
+    void* base = nullptr;
+    if ((st = acquire_ws(ctx, d_ws, ws_bytes, fit_layout(nullptr, M, N, p, &w), &base)) != FKK_OK) return st;
+    fit_layout(base, M, N, p, &w);
 
     // 1. log ratio, Gram and column sums on the device (Eq. 2, 6, 9)
     auto t0 = std::chrono::steady_clock::now();
@@ -869,8 +971,8 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     const bool rrf = (p->svd_mode == FKK_SVD_RANDOMIZED);
     // the range finder works from the FP32 log ratio, whatever gram_prec says
     const int gprec = rrf ? FKK_PREC_FP32 : p->gram_prec;
-    if ((st = gram_device(ctx, d_I, M, N, ld, h_iref, p->ratio_floor, gprec, true, !rrf)) != FKK_OK) return st;
-    if ((st = fetch_sums(ctx, N, colsum.data(), &clamps)) != FKK_OK) return st;
+    if ((st = gram_device(ctx, w.g, d_I, M, N, ld, h_iref, p->ratio_floor, gprec, true, !rrf)) != FKK_OK) return st;
+    if ((st = fetch_sums(ctx, w.g, N, colsum.data(), &clamps)) != FKK_OK) return st;
     r.dev_ms_gram = rrf ? 0.0 : ctx->elapsed(0, 1);
     r.dev_ms_logratio = ctx->elapsed(8, 9);
     r.clamps = clamps;
@@ -891,12 +993,14 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     const double rank_rel = p->k == 0 ? (double)std::max<int64_t>(M, N) * (double)FLT_EPSILON : 0.0;
     int k = kcap;
     if (rrf) {
-        if ((st = rrf_device(ctx, M, N, f.data(), p, kcap, sv.data(), V.data())) != FKK_OK) return st;
+        if ((st = rrf_device(ctx, w, M, N, f.data(), p, kcap, sv.data(), V.data())) != FKK_OK) return st;
         for (int c = 0; c < kcap; ++c) lam[c] = sv[c] * sv[c];
     } else {
         // with the rank rule, the eigenvalues come first and only the kept
         // pairs get eigenvectors; V is then N x k
-        if ((st = eig_device(ctx, N, kcap, f.data(), lam.data(), V.data(), true, rank_rel, &k)) != FKK_OK) return st;
+        if ((st = eig_device(ctx, w, N, kcap, f.data(), lam.data(), V.data(), true, rank_rel, &k, &r.tridiag_path)) !=
+            FKK_OK)
+            return st;
         for (int c = 0; c < k; ++c) sv[c] = std::sqrt(std::max(lam[c], 0.0));
         if (k < kcap) {
             V.resize((size_t)N * k);
@@ -939,49 +1043,40 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     }
     auto cleanup = [&](fkk_status e) { delete b; return e; };
     const int64_t nblk = fkk::dev::proj_blocks(M);
-    // ctx->X holds the weights: kp x npad FP32, or kq x npad BF16 (kq <= 2 kp)
-    if (ctx->Z.ensure((size_t)M * kp) != hipSuccess || ctx->X.ensure((size_t)kp * b->npad) != hipSuccess ||
-        ctx->pmaxv.ensure((size_t)nblk * ka) != hipSuccess || ctx->pminv.ensure((size_t)nblk * ka) != hipSuccess ||
-        ctx->pmaxi.ensure((size_t)nblk * ka) != hipSuccess || ctx->pmini.ensure((size_t)nblk * ka) != hipSuccess ||
-        ctx->qext.ensure(2 * (size_t)ka) != hipSuccess)
-        return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
-    float* d_wt = ctx->X.p;  // the fit's projection weights (no ML shrink)
-    uint16_t* d_wt16 = reinterpret_cast<uint16_t*>(ctx->X.p);
+    // w.X holds the weights: kp x npad FP32, or kq x npad BF16 (kq <= 2 kp)
+    float* d_wt = w.X;  // the fit's projection weights (no ML shrink)
+    uint16_t* d_wt16 = reinterpret_cast<uint16_t*>(w.X);
     const hipError_t wcopy =
         pbf16 ? hipMemcpyAsync(d_wt16, wt16.data(), wt16.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s)
               : hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s);
     if (wcopy != hipSuccess) return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
-    fkk::dev::ArgPart part{ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
+    fkk::dev::ArgPart part{w.pmaxv, w.pminv, w.pmaxi, w.pmini};
     hipError_t perr = hipEventRecord(ctx->ev[2], s);
     if (perr == hipSuccess) {
         if (pbf16)  // log ratio recomputed from I
-            perr = fkk::dev::launch_project16(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt16, b->npad, kq,
-                                              kp, ctx->Z.p, kp, part, k, s);
-        else if (gprec == FKK_PREC_BF16)  // ctx->L holds the packed BF16 l: start from I
-            perr = fkk::dev::launch_project(d_I, M, N, ld, ctx->rinv.p, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
-                                            ctx->Z.p, kp, part, k, s, false);
+            perr = fkk::dev::launch_project16(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt16, b->npad, kq,
+                                              kp, w.Z, kp, part, k, s);
+        else if (gprec == FKK_PREC_BF16)  // w.g.L holds the packed BF16 l: start from I
+            perr = fkk::dev::launch_project(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
+                                            w.Z, kp, part, k, s, false);
         else  // the FP32 l of the Gram pass
-            perr = fkk::dev::launch_project(ctx->L.p, M, N, npad_for(N), ctx->rinv.p, (float)p->ratio_floor, d_wt,
-                                            b->npad, kp, kp, ctx->Z.p, kp, part, k, s, true);
+            perr = fkk::dev::launch_project(w.g.L, M, N, npad_for(N), w.g.rinv, (float)p->ratio_floor, d_wt,
+                                            b->npad, kp, kp, w.Z, kp, part, k, s, true);
     }
     if (perr != hipSuccess || hipEventRecord(ctx->ev[3], s) != hipSuccess ||
-        fkk::dev::launch_argext_reduce(part, nblk, ka, k, ctx->qext.p, ctx->qext.p + ka, s) != hipSuccess)
+        fkk::dev::launch_argext_reduce(part, nblk, ka, k, w.qext, w.qext + ka, s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection launch failed"));
     // the optional rows between the extrema (Sec. 2.3), from the stored Z
     const int nbet = (p->n_q_override > 0) ? 0 : k * p->q_between;
     if (nbet > 0) {
-        const size_t np = (size_t)fkk::dev::between_blocks(M, kp) * nbet;
-        if (ctx->bval.ensure(np) != hipSuccess || ctx->bidx.ensure(np) != hipSuccess ||
-            ctx->qbet.ensure(nbet) != hipSuccess)
-            return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
-        if (fkk::dev::launch_between(ctx->Z.p, M, kp, kp, k, p->q_between, ctx->qext.p, ctx->qext.p + ka, ctx->bval.p,
-                                     ctx->bidx.p, ctx->qbet.p, s) != hipSuccess)
+        if (fkk::dev::launch_between(w.Z, M, kp, kp, k, p->q_between, w.qext, w.qext + ka, w.bval, w.bidx, w.qbet,
+                                     s) != hipSuccess)
             return cleanup(ctx->fail(FKK_EDEVICE, "sub-sample launch failed"));
     }
     basis_fkk(b, p);  // host FP64 while the projection runs
     std::vector<long long> qe(2 * (size_t)ka), qb(nbet);
-    if (hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        (nbet > 0 && hipMemcpyAsync(qb.data(), ctx->qbet.p, qb.size() * sizeof(long long), hipMemcpyDeviceToHost,
+    if (hipMemcpyAsync(qe.data(), w.qext, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (nbet > 0 && hipMemcpyAsync(qb.data(), w.qbet, qb.size() * sizeof(long long), hipMemcpyDeviceToHost,
                                     s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "projection failed"));
@@ -1004,20 +1099,12 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     // device Z only selects q.  fPEC's ridge solve amplifies errors of X
     // along its weak directions, so X is not taken from the FP32 projection.
     std::vector<float> rows((size_t)n_q * N);
-    if (ctx->qdev.ensure(std::max(n_q, 1)) != hipSuccess)
-        return cleanup(ctx->fail(FKK_ENOMEM, "workspace allocation failed"));
-    DevBuf<float> rtmp;
-    float* d_rows = ctx->pmaxv.p;  // reused when large enough
-    if ((size_t)n_q * N > ctx->pmaxv.n) {
-        if (rtmp.ensure((size_t)n_q * N) != hipSuccess) return cleanup(ctx->fail(FKK_ENOMEM, "allocation failed"));
-        d_rows = rtmp.p;
-    }
-    if (hipMemcpyAsync(ctx->qdev.p, q.data(), n_q * sizeof(long long), hipMemcpyHostToDevice, s) != hipSuccess ||
-        fkk::dev::launch_gather_rows(d_I, ld, N, ctx->qdev.p, n_q, d_rows, s) != hipSuccess ||
-        hipMemcpyAsync(rows.data(), d_rows, rows.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    // (n_q is at most the layout's 2 k + k q_between, or n_q_override)
+    if (hipMemcpyAsync(w.qdev, q.data(), n_q * sizeof(long long), hipMemcpyHostToDevice, s) != hipSuccess ||
+        fkk::dev::launch_gather_rows(d_I, ld, N, w.qdev, n_q, w.rows, s) != hipSuccess ||
+        hipMemcpyAsync(rows.data(), w.rows, rows.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(ctx->fail(FKK_EDEVICE, "gather of sub-sampled rows failed"));
-    rtmp.release();
     r.ms_project = ms_since(t0);
 
     // 4. fKK, fPEC, fSEC on the basis vectors (host FP64)
@@ -1050,9 +1137,9 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     t0 = std::chrono::steady_clock::now();
     if (d_out) {
         if (hipEventRecord(ctx->ev[4], s) != hipSuccess ||
-            (pbf16 ? fkk::dev::launch_reconstruct16(ctx->Z.p, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
+            (pbf16 ? fkk::dev::launch_reconstruct16(w.Z, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
                                                     p->output, s)
-                   : fkk::dev::launch_reconstruct(ctx->Z.p, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
+                   : fkk::dev::launch_reconstruct(w.Z, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
                                                   p->output, s)) != hipSuccess ||
             hipEventRecord(ctx->ev[5], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return cleanup(ctx->fail(FKK_EDEVICE, "reconstruction failed"));
@@ -1067,21 +1154,24 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
 }
 
 fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld, float* d_out,
-                         int64_t ld_out) {
+                         int64_t ld_out, int32_t plane, void* d_ws, size_t ws_bytes) {
     if (!ctx) return FKK_EINVAL;
     if (!b) return ctx->fail(FKK_EINVAL, "basis is NULL");
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, b->N, ld, "I")) != FKK_OK) return st;
     if (!d_out || ld_out < b->N) return ctx->fail(FKK_EINVAL, "bad output");
+    if (plane < FKK_OUT_IM || plane > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad output plane %d", plane);
+    if (!d_ws && ws_bytes != 0) return ctx->fail(FKK_EINVAL, "ws_bytes without a workspace");
+    (void)ws_bytes;  // the fused kernel keeps its Z tile in LDS: no workspace
     if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     if (b->prec == FKK_PREC_BF16)
         FKK_HIP(ctx, fkk::dev::launch_transform16(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt16,
-                                                  b->npad, b->kq, b->d_bre16, b->d_bim16, d_out, ld_out, FKK_OUT_IM,
+                                                  b->npad, b->kq, b->d_bre16, b->d_bim16, d_out, ld_out, plane,
                                                   ctx->stream));
     else
         FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
-                                                b->kp, b->k, b->d_bre_t, b->d_bim_t, d_out, ld_out, FKK_OUT_IM,
+                                                b->kp, b->k, b->d_bre_t, b->d_bim_t, d_out, ld_out, plane,
                                                 ctx->stream));
     return FKK_OK;
 }
@@ -1100,14 +1190,21 @@ fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64
     const bool bf16 = (b->prec == FKK_PREC_BF16);
     const int ka = bf16 ? b->kq : b->kp;
     fkk::dev::ArgPart part{nullptr, nullptr, nullptr, nullptr};
+    long long* qext = nullptr;
     const bool want = h_qmax || h_qmin;
     if (want) {
-        FKK_HIP(ctx, ctx->pmaxv.ensure((size_t)nblk * ka));
-        FKK_HIP(ctx, ctx->pminv.ensure((size_t)nblk * ka));
-        FKK_HIP(ctx, ctx->pmaxi.ensure((size_t)nblk * ka));
-        FKK_HIP(ctx, ctx->pmini.ensure((size_t)nblk * ka));
-        FKK_HIP(ctx, ctx->qext.ensure(2 * (size_t)ka));
-        part = {ctx->pmaxv.p, ctx->pminv.p, ctx->pmaxi.p, ctx->pmini.p};
+        auto layout = [&](void* base) {
+            Carve c(base);
+            part.maxv = c.take<float>((size_t)nblk * ka);
+            part.minv = c.take<float>((size_t)nblk * ka);
+            part.maxi = c.take<long long>((size_t)nblk * ka);
+            part.mini = c.take<long long>((size_t)nblk * ka);
+            qext = c.take<long long>(2 * (size_t)ka);
+            return c.bytes();
+        };
+        void* base = nullptr;
+        if ((st = acquire_ws(ctx, nullptr, 0, layout(nullptr), &base)) != FKK_OK) return st;
+        layout(base);
     }
     if (bf16)
         FKK_HIP(ctx, fkk::dev::launch_project16(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt16, b->npad,
@@ -1116,9 +1213,9 @@ fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64
         FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
                                               b->kp, b->k, d_z, ld_z, part, b->k, s));
     if (!want) return FKK_OK;
-    FKK_HIP(ctx, fkk::dev::launch_argext_reduce(part, nblk, ka, b->k, ctx->qext.p, ctx->qext.p + ka, s));
+    FKK_HIP(ctx, fkk::dev::launch_argext_reduce(part, nblk, ka, b->k, qext, qext + ka, s));
     std::vector<long long> qe(2 * (size_t)ka);
-    FKK_HIP(ctx, hipMemcpyAsync(qe.data(), ctx->qext.p, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(qe.data(), qext, qe.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     for (int c = 0; c < b->k; ++c) {
         if (h_qmax) h_qmax[c] = qe[c];
@@ -1142,20 +1239,28 @@ fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* b, const float* d_I
     for (int c = 0; c < k; ++c)
         for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(b->f[j] * b->v[(size_t)j * k + c]);
     const int64_t nres = fkk::dev::residual_blocks(M);
-    FKK_HIP(ctx, ctx->X.ensure(wt.size()));
-    FKK_HIP(ctx, ctx->Z.ensure((size_t)M * kp));
-    FKK_HIP(ctx, ctx->fdev.ensure(N));
-    FKK_HIP(ctx, ctx->colsum_part.ensure(2 * (size_t)nres));
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->X.p, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemcpyAsync(ctx->fdev.p, b->f.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+    float *X = nullptr, *Z = nullptr;
+    double *fdev = nullptr, *psum = nullptr;
+    auto layout = [&](void* base) {
+        Carve c(base);
+        X = c.take<float>(wt.size());
+        Z = c.take<float>((size_t)M * kp);
+        fdev = c.take<double>(N);
+        psum = c.take<double>(2 * (size_t)nres);
+        return c.bytes();
+    };
+    void* base = nullptr;
+    if ((st = acquire_ws(ctx, nullptr, 0, layout(nullptr), &base)) != FKK_OK) return st;
+    layout(base);
+    FKK_HIP(ctx, hipMemcpyAsync(X, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    FKK_HIP(ctx, hipMemcpyAsync(fdev, b->f.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
     const fkk::dev::ArgPart none{nullptr, nullptr, nullptr, nullptr};
-    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, ctx->X.p, b->npad, kp, k,
-                                          ctx->Z.p, kp, none, 0, s));
-    FKK_HIP(ctx, fkk::dev::launch_residual_sums(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, ctx->fdev.p, ctx->Z.p,
-                                                kp, k, ctx->colsum_part.p, s));
+    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, X, b->npad, kp, k, Z, kp,
+                                          none, 0, s));
+    FKK_HIP(ctx, fkk::dev::launch_residual_sums(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, fdev, Z, kp, k, psum,
+                                                s));
     std::vector<double> part(2 * (size_t)nres);
-    FKK_HIP(ctx, hipMemcpyAsync(part.data(), ctx->colsum_part.p, part.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                s));
+    FKK_HIP(ctx, hipMemcpyAsync(part.data(), psum, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     double sa = 0.0, sz = 0.0;
     for (int64_t i = 0; i < nres; ++i) {
@@ -1249,12 +1354,17 @@ fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double
     return FKK_OK;
 }
 
-void fkk_basis_free(fkk_basis* b) { delete b; }
+fkk_status fkk_basis_free(fkk_basis* b) {
+    if (!b) return FKK_OK;
+    if (b->holders.load() > 0) return FKK_EBUSY;  // a server still transforms with it
+    delete b;
+    return FKK_OK;
+}
 
 namespace {
 
 fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                     const fkk_params* p, void* d_out, int64_t ld_out) {
+                     const fkk_params* p, void* d_out, int64_t ld_out, void* d_ws, size_t ws_bytes) {
     if (!ctx) return FKK_EINVAL;
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
@@ -1277,9 +1387,24 @@ fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t
     cfg.order = p->sg_order;
     cfg.floor = p->ratio_floor;
     cfg.plane = p->output;
+    // a caller's workspace may be smaller than the full batch: the spectra
+    // then run in smaller batches (at least 256 rows)
+    int64_t batch = fkk::plain::full_batch(M);
+    void* base = nullptr;
+    if (d_ws) {
+        if (reinterpret_cast<uintptr_t>(d_ws) & 255) return ctx->fail(FKK_EINVAL, "workspace must be 256-byte aligned");
+        batch = fkk::plain::batch_for_bytes(N, cfg.len, M, ws_bytes);
+        if (batch < 1)
+            return ctx->fail(FKK_EINVAL, "workspace of %zu bytes below the %zu a batch of 256 spectra needs", ws_bytes,
+                             fkk::plain::layout_bytes(N, cfg.len, 256));
+        base = d_ws;
+    } else if ((st = acquire_ws(ctx, nullptr, ws_bytes, fkk::plain::layout_bytes(N, cfg.len, batch), &base)) !=
+               FKK_OK) {
+        return st;
+    }
+    const fkk::plain::Layout lay = fkk::plain::carve(base, N, cfg.len, batch);
     std::string why;
-    const hipError_t e =
-        fkk::plain::run(ctx->plain_ws, cfg, d_I, f64, M, ld, h_iref, d_out, f64, ld_out, ctx->stream, &why);
+    const hipError_t e = fkk::plain::run(lay, cfg, d_I, f64, M, ld, h_iref, d_out, f64, ld_out, ctx->stream, &why);
     if (e != hipSuccess)
         return ctx->fail(FKK_EDEVICE, "plain path: %s (%s)", hipGetErrorString(e), why.c_str());
     return FKK_OK;
@@ -1288,13 +1413,38 @@ fkk_status plain_any(fkk_ctx* ctx, const void* d_I, bool f64, int64_t M, int32_t
 }  // namespace
 
 fkk_status fkk_plain(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                     const fkk_params* p, float* d_out, int64_t ld_out) {
-    return plain_any(ctx, d_I, false, M, N, ld, h_iref, p, d_out, ld_out);
+                     const fkk_params* p, float* d_out, int64_t ld_out, void* d_ws, size_t ws_bytes) {
+    return plain_any(ctx, d_I, false, M, N, ld, h_iref, p, d_out, ld_out, d_ws, ws_bytes);
 }
 
 fkk_status fkk_plain_f64(fkk_ctx* ctx, const double* d_I, int64_t M, int32_t N, int64_t ld, const double* h_iref,
-                         const fkk_params* p, double* d_out, int64_t ld_out) {
-    return plain_any(ctx, d_I, true, M, N, ld, h_iref, p, d_out, ld_out);
+                         const fkk_params* p, double* d_out, int64_t ld_out, void* d_ws, size_t ws_bytes) {
+    return plain_any(ctx, d_I, true, M, N, ld, h_iref, p, d_out, ld_out, d_ws, ws_bytes);
+}
+
+fkk_status fkk_workspace_size(const fkk_ctx* ctx, int32_t op, int64_t M, int32_t N, const fkk_params* p,
+                              size_t* bytes) {
+    (void)ctx;
+    if (!bytes) return FKK_EINVAL;
+    *bytes = 0;
+    if (M < 1 || N < 4) return FKK_EINVAL;
+    fkk_ctx sink;  // check_params reports through a context
+    switch (op) {
+        case FKK_OP_FIT: {
+            if (!p || check_params(&sink, p, N, true) != FKK_OK) return FKK_EINVAL;
+            FitWs w;
+            *bytes = fit_layout(nullptr, M, N, p, &w);
+            return FKK_OK;
+        }
+        case FKK_OP_PLAIN:
+            if (!p || check_params(&sink, p, N, false, true) != FKK_OK) return FKK_EINVAL;
+            *bytes = plain_layout_bytes(M, N, p);
+            return FKK_OK;
+        case FKK_OP_TRANSFORM:
+            return FKK_OK;  // the fused kernel needs no workspace
+        default:
+            return FKK_EINVAL;
+    }
 }
 
 }  // extern "C"

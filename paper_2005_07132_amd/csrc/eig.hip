@@ -305,8 +305,12 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // it belongs to; a reader polls its words until all of them carry the
 // expected number, so no separate grid barrier is needed.  Two buffers
 // alternate between columns: a block writes the words of column i+1 only
-// after it has read all words of column i, and every block wrote those
-// only after reading all of column i-1, the previous content of the buffer.
+// after it has read all words of column i, and every block still reading
+// column i-1 (the previous content of that buffer) writes at least one word
+// of column i after it has read column i-1: a block leaves the column loop
+// as soon as it owns no row below the pivot, so every block in the loop
+// owns such a row and writes its p entry.  The block owning row n-1, which
+// stays in the loop to the end, writes d, e, beta and the reflectors.
 // The arithmetic of a column is that of tridiag_step, with the block sums
 // split over 512 threads (one owned row per wave) instead of 256.
 // ---------------------------------------------------------------------------
@@ -421,6 +425,8 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
     __shared__ double sp0;
     __shared__ int sbad;
     const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int writer = (n - 1) % G;                       // owns row n-1: in the loop to the end
+    const int last_row = b + ((n - 1 - b) / G) * G;       // largest row this block owns
     double* rows = sm;                   // local row t = matrix row b + t G, all n columns
     double* va = sm + (size_t)R * n;     // v_i
     double* vb = va + n;                 // v_{i+1}
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
     __syncthreads();
     double bcur, a0;
     make_reflector(x, m0, va, &bcur, &a0, red);
-    if (b == 0) {
+    if (b == writer) {
         for (int j = tid; j < m0; j += kResThreads) vstore[j] = va[j];
         if (tid == 0) {
             beta[0] = bcur;
@@ -461,6 +467,9 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
 
     for (int i = 0; i + 2 < n; ++i) {
         const int lo = i + 1, m = n - lo;
+        // no row below the pivot left: nothing to update or send from here
+        // on (uniform over the block; the writer block never leaves early)
+        if (last_row <= lo) return;
         const unsigned tag = (unsigned)i + 1u;  // words of column i
         const double v0 = va[0];
         double part = 0.0;
@@ -503,7 +512,7 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
                 bn = 2.0 / ((x0 - a) * (x0 - a) + sig2);
                 for (int j = tid; j < m - 1; j += kResThreads) vb[j] = (j == 0) ? x0 - a : x[1 + j];
             }
-            if (b == 0) {
+            if (b == writer) {
                 double* vso = vstore + voff(lo, n);
                 for (int j = tid; j < m - 1; j += kResThreads) vso[j] = vb[j];
                 if (tid == 0) {
@@ -514,7 +523,7 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
             }
         } else {
             __syncthreads();
-            if (b == 0 && tid == 0) {
+            if (b == writer && tid == 0) {
                 d[lo] = x[0];
                 e[lo] = x[1];
             }

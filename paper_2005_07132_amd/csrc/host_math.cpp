@@ -41,8 +41,11 @@ class Pool {
         for (auto& t : th_) t.join();
     }
     int size() const { return n_; }
-    // run fn(tid, nthreads) on every thread, return when all are done
+    // run fn(tid, nthreads) on every thread, return when all are done.
+    // Callers on different host threads (one context each) take turns: the
+    // job slot, the generation and the completion count are the pool's own.
     void run(const std::function<void(int, int)>& fn) {
+        std::lock_guard<std::mutex> turn(run_mu_);
         job_ = &fn;
         done_.store(0);
         {
@@ -79,6 +82,7 @@ class Pool {
     std::atomic<int> done_{0};
     const std::function<void(int, int)>* job_ = nullptr;
     std::mutex mu_;
+    std::mutex run_mu_;  // one job at a time
     std::condition_variable cv_;
     bool stop_ = false;
 };
@@ -89,12 +93,15 @@ void split(int lo, int hi, int tid, int nt, int* a, int* b) {
     *b = lo + (int)((int64_t)len * (tid + 1) / nt);
 }
 
+// Created on first use and never destroyed: its workers sleep in the pool
+// until the process ends, so no static destructor joins threads while the
+// process (and the runtimes loaded into it) is being torn down.
 Pool& host_pool() {
-    static Pool pool([] {
+    static Pool* pool = new Pool([] {
         unsigned hw = std::thread::hardware_concurrency();
         return (int)std::min(16u, hw == 0 ? 1u : hw);
     }());
-    return pool;
+    return *pool;
 }
 
 }  // namespace

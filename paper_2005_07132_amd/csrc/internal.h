@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <vector>
 
@@ -18,6 +19,7 @@ struct fkk_basis {
     std::vector<double> i_ref, f, s, v, b_re, b_im, phi_pec_t, v_sec_t, h_v;
     std::vector<int64_t> q;
     double ml_lambda = 0.0, ratio_floor = 1e-6, ridge_lambda = 0.0;
+    mutable std::atomic<int> holders{0}; // servers holding the basis (fkk_basis_free: FKK_EBUSY)
     void* d_arena = nullptr;     // one allocation holding the arrays below
     float* d_rinv = nullptr;     // 2N: 1/I_ref as hi, lo floats
     float* d_wt = nullptr;       // kp x npad: f(j) V(j,c) shrink(c)

@@ -16,21 +16,37 @@
 namespace fkk {
 namespace plain {
 
-size_t Workspace::bytes() const { return cap_row * 8 * 7 + (size_t)tw_len * 8 + sg_doubles * 8; }
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
 
-void Workspace::release() {
-    for (double** p : {&ell, &phi, &err, &scratch, &sg})
-        if (*p) {
-            hipFree(*p);
-            *p = nullptr;
-        }
-    for (auto& t : tw_tables) hipFree(t.second);
-    tw_tables.clear();
-    twiddle = nullptr;
-    batch = 0;
-    cap_row = 0;
-    n = len = tw_len = 0;
-    sg_doubles = 0;
+int64_t full_batch(int64_t M) { return std::min<int64_t>(((M + 255) / 256) * 256, 131072); }
+
+size_t layout_bytes(int N, int len, int64_t batch) {
+    const size_t row = al256((size_t)batch * N * sizeof(double));
+    return 3 * row + al256(4 * (size_t)batch * N * sizeof(double)) + al256((size_t)len * sizeof(double)) +
+           al256(((size_t)N + 16) * sizeof(double));
+}
+
+int64_t batch_for_bytes(int N, int len, int64_t M, size_t bytes) {
+    int64_t b = full_batch(M);
+    while (b >= 256 && layout_bytes(N, len, b) > bytes) b -= 256;
+    return b >= 256 ? b : 0;
+}
+
+Layout carve(void* base, int N, int len, int64_t batch) {
+    Layout w;
+    char* p = static_cast<char*>(base);
+    const size_t row = al256((size_t)batch * N * sizeof(double));
+    w.ell = reinterpret_cast<double*>(p);
+    w.phi = reinterpret_cast<double*>(p + row);
+    w.err = reinterpret_cast<double*>(p + 2 * row);
+    w.scratch = reinterpret_cast<double*>(p + 3 * row);
+    const size_t o_tw = 3 * row + al256(4 * (size_t)batch * N * sizeof(double));
+    w.twiddle = reinterpret_cast<double*>(p + o_tw);
+    w.sg = reinterpret_cast<double*>(p + o_tw + al256((size_t)len * sizeof(double)));
+    w.batch = batch;
+    return w;
 }
 
 namespace {
@@ -412,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void sec_kernel(int64_t m0, int64_t nb, i
 
 }  // namespace
 
-hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, int64_t M, int64_t ld,
+hipError_t run(const Layout& ws, const Config& cfg, const void* d_I, bool in_f64, int64_t M, int64_t ld,
                const double* h_iref, void* d_out, bool out_f64, int64_t ld_out, hipStream_t s, std::string* why) {
     const int N = cfg.N, L = cfg.len;
     int bits = 0;
@@ -433,45 +449,22 @@ hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, i
         if (why) *why = "N above 4096";
         return hipErrorInvalidValue;
     }
-    const int64_t batch = std::min<int64_t>(((M + kThreads - 1) / kThreads) * kThreads, 131072);
+    const int64_t batch = ws.batch;
+    if (batch < 1 || !ws.ell) {
+        if (why) *why = "no workspace";
+        return hipErrorInvalidValue;
+    }
     hipError_t e;
-    // arrays are sized batch x N doubles; grow only, so alternating spectral
-    // lengths and tile sizes reuse the same buffers
-    const size_t need = (size_t)batch * N;
-    if (ws.cap_row < need) {
-        for (double** p : {&ws.ell, &ws.phi, &ws.err, &ws.scratch})
-            if (*p) {
-                hipFree(*p);
-                *p = nullptr;
-            }
-        ws.cap_row = 0;
-        const size_t row = need * sizeof(double);
-        if ((e = hipMalloc(&ws.ell, row)) != hipSuccess) return e;
-        if ((e = hipMalloc(&ws.phi, row)) != hipSuccess) return e;
-        if ((e = hipMalloc(&ws.err, row)) != hipSuccess) return e;
-        if ((e = hipMalloc(&ws.scratch, 4 * row)) != hipSuccess) return e;
-        ws.cap_row = need;
+    // twiddle table of the length (copied with the call: the workspace is
+    // the caller's and holds nothing between calls)
+    std::vector<double> tw(L);
+    for (int j = 0; j < L / 2; ++j) {
+        const double a = -2.0 * M_PI * (double)j / (double)L;
+        tw[2 * j] = std::cos(a);
+        tw[2 * j + 1] = std::sin(a);
     }
-    ws.batch = batch;
-    ws.n = N;
-    ws.twiddle = nullptr;
-    for (auto& t : ws.tw_tables)
-        if (t.first == L) ws.twiddle = t.second;
-    if (!ws.twiddle) {
-        std::vector<double> tw(L);
-        for (int j = 0; j < L / 2; ++j) {
-            const double a = -2.0 * M_PI * (double)j / (double)L;
-            tw[2 * j] = std::cos(a);
-            tw[2 * j + 1] = std::sin(a);
-        }
-        double* dtw = nullptr;
-        if ((e = hipMalloc(&dtw, L * sizeof(double))) != hipSuccess) return e;
-        if ((e = hipMemcpy(dtw, tw.data(), L * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return e;
-        ws.tw_tables.emplace_back(L, dtw);
-        ws.twiddle = dtw;
-        ws.tw_len += L;
-    }
-    ws.len = L;
+    if ((e = hipMemcpyAsync(ws.twiddle, tw.data(), L * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
     // (V^T V)^-1 of the scaled Vandermonde of the window and I_ref
     const int half = cfg.window / 2, m = cfg.order + 1;
     std::vector<double> host((size_t)N + 16, 0.0);
@@ -505,13 +498,6 @@ hipError_t run(Workspace& ws, const Config& cfg, const void* d_I, bool in_f64, i
             }
         }
         for (int q = 0; q < m * m; ++q) host[N + q] = inv[q];
-    }
-    if (ws.sg_doubles < host.size()) {
-        if (ws.sg) hipFree(ws.sg);
-        ws.sg = nullptr;
-        ws.sg_doubles = 0;
-        if ((e = hipMalloc(&ws.sg, host.size() * sizeof(double))) != hipSuccess) return e;
-        ws.sg_doubles = host.size();
     }
     if ((e = hipMemcpyAsync(ws.sg, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
         return e;

@@ -288,6 +288,7 @@ fkk_status fkk_server_add_basis(fkk_server* srv, const fkk_basis* basis, int32_t
     std::lock_guard<std::mutex> g(srv->mu);
     srv->bases.push_back(basis);
     srv->base_prec.push_back(basis->prec);
+    basis->holders.fetch_add(1);  // released by fkk_server_destroy
     *basis_id = (int32_t)srv->bases.size() - 1;
     return FKK_OK;
 }
@@ -401,6 +402,7 @@ void fkk_server_destroy(fkk_server* srv) {
     if (srv->s_in) hipStreamDestroy(srv->s_in);
     if (srv->s_comp) hipStreamDestroy(srv->s_comp);
     if (srv->s_out) hipStreamDestroy(srv->s_out);
+    for (const fkk_basis* b : srv->bases) b->holders.fetch_sub(1);
     delete srv;
 }
 

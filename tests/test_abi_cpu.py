@@ -148,3 +148,62 @@ def test_basis_precision_accessors():
     with pytest.raises(fk.FkkError):
         b.precision = 2
     assert b.precision == fk.PREC_BF16
+
+
+def test_host_stages_from_two_threads_at_once():
+    # separate contexts on separate host threads share the library's host
+    # thread pool: concurrent host stages must give the results of the same
+    # calls made one after the other
+    import threading
+    cube, p, b = _oracle_basis(op.DETREND_ALS, op.SEC_SAVGOL, n=256, k=8)
+    cp = fk.params(k=p.k, f_mode=1, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    rng = np.random.default_rng(12)
+    a = rng.standard_normal((700, 600))
+    g = a.T @ a
+    ref_basis = fk.basis_from_factors(None, cube.i_ref, b["f"], b["s"], b["v"], b["x"], cp).export()
+    ref_vals, ref_vecs = fk.eigh_topk(g, 30)
+    errors = []
+
+    def basis_worker():
+        try:
+            for _ in range(12):
+                e = fk.basis_from_factors(None, cube.i_ref, b["f"], b["s"], b["v"], b["x"], cp).export()
+                for key in ("h_v", "phi_pec_t", "b_re", "b_im"):
+                    np.testing.assert_array_equal(e[key], ref_basis[key])
+        except Exception as exc:  # pragma: no cover - reported below
+            errors.append(exc)
+
+    def eig_worker():
+        try:
+            for _ in range(12):
+                vals, vecs = fk.eigh_topk(g, 30)
+                np.testing.assert_array_equal(vals, ref_vals)
+                np.testing.assert_array_equal(vecs, ref_vecs)
+        except Exception as exc:  # pragma: no cover - reported below
+            errors.append(exc)
+
+    threads = [threading.Thread(target=basis_worker), threading.Thread(target=eig_worker),
+               threading.Thread(target=basis_worker)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+
+
+def test_workspace_sizes():
+    p = fk.params(k=50)
+    fit_small = fk.workspace_size(fk.OP_FIT, 4096, 512, p)
+    fit_large = fk.workspace_size(fk.OP_FIT, 703026, 1000, p)
+    # the log ratio alone is M x npad floats; the whole fit stays well under twice that plus the Gram partials
+    assert 703026 * 1024 * 4 < fit_large < 2 * 703026 * 1024 * 4 + (1 << 30)
+    assert fit_small < fit_large
+    assert fk.workspace_size(fk.OP_FIT, 4096, 512, fk.params(k=0)) >= fit_small  # rank rule sizes for 128 vectors
+    assert fk.workspace_size(fk.OP_TRANSFORM, 703026, 1000) == 0
+    plain = fk.workspace_size(fk.OP_PLAIN, 703026, 1000, p)
+    assert plain >= 131072 * 1000 * 8 * 7  # batches of 131,072 spectra, seven FP64 rows each
+    assert fk.workspace_size(fk.OP_PLAIN, 300, 1000, p) < plain
+    for bad in (lambda: fk.workspace_size(7, 10, 100, p), lambda: fk.workspace_size(fk.OP_FIT, 0, 100, p),
+                lambda: fk.workspace_size(fk.OP_FIT, 10, 100, fk.params(k=500))):
+        with pytest.raises(fk.FkkError):
+            bad()

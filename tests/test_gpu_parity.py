@@ -686,10 +686,12 @@ def test_resident_tridiag_matches_per_column_launches(n, k):
         p = fk.params(k=k, sg_window=3)
     percol = context_with(FKK_NO_RESIDENT_TRIDIAG=1)
     res = fk.Context(0)
-    b0, out0, _ = percol.fit(t, ref_i, p)
+    b0, out0, rep0 = percol.fit(t, ref_i, p)
+    assert rep0["tridiag_path"] == fk.TRIDIAG_PER_COLUMN
     e0, o0 = b0.export(), host(out0).astype(np.float64)
     for _ in range(2):
-        b1, out1, _ = res.fit(t, ref_i, p)
+        b1, out1, rep1 = res.fit(t, ref_i, p)
+        assert rep1["tridiag_path"] == fk.TRIDIAG_RESIDENT  # no wait gave up
         e1 = b1.export()
         assert np.abs(e1["s"] - e0["s"]).max() <= 1e-12 * e0["s"].max()
         assert np.abs(e1["v"] - e0["v"]).max() < 1e-9
@@ -711,7 +713,8 @@ def test_resident_tridiag_wait_timeout_falls_back():
     quick = context_with(FKK_TRIDIAG_SPIN_LIMIT=0)
     b0, out0, _ = percol.fit(t, cube.i_ref, p)
     for _ in range(2):
-        b1, out1, _ = quick.fit(t, cube.i_ref, p)
+        b1, out1, rep1 = quick.fit(t, cube.i_ref, p)
+        assert rep1["tridiag_path"] == fk.TRIDIAG_PER_COLUMN
         np.testing.assert_array_equal(host(out1), host(out0))
         np.testing.assert_array_equal(b1.export()["v"], b0.export()["v"])
     percol.close()
