@@ -238,14 +238,22 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
  * ML:fKK-EC (Fig. 1c; Eq. 24-25 then Eq. 23): applies a stored basis to new
  * spectra.  Z_new = A_new V diag(s^2/(s^2+ml_lambda)), out = plane (FKK_OUT_*)
  * of exp(Z B_re + i Z B_im).  d_I: M x basis.N FP32 (stride ld); d_out: M x N
- * FP32 (stride ld_out).  The fused kernel keeps Z in LDS and needs no
- * workspace: pass d_ws NULL, ws_bytes 0 (a workspace given is not used).
- * Asynchronous on the context's stream; no host synchronisation and no
- * allocation.  Each output row depends only on its input row.
+ * FP32 (stride ld_out).
+ * d_norms (device, optional, 8-byte aligned): M x 2 FP32, written by the same
+ * kernel from the same loads: with A = l diag(f) (the basis's f),
+ * d_norms[2m] = ||A_m||^2 and d_norms[2m+1] = ||A_m V||^2 (sums of FP32
+ * products; in the BF16 mode from the BF16 projection), so that
+ * 1 - sum d_norms[2m+1] / sum d_norms[2m] over any set of rows is the squared
+ * relative residual of fkk_basis_residual (the retraining criterion of
+ * Sec. 5).  NULL: not computed.
+ * The fused kernel keeps Z in LDS and needs no workspace: pass d_ws NULL,
+ * ws_bytes 0 (a workspace given is not used).  Asynchronous on the context's
+ * stream; no host synchronisation and no allocation.  Each output row depends
+ * only on its input row.
  */
 fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M,
-                         int64_t ld, float* d_out, int64_t ld_out, int32_t plane, void* d_ws,
-                         size_t ws_bytes);
+                         int64_t ld, float* d_out, int64_t ld_out, int32_t plane, float* d_norms,
+                         void* d_ws, size_t ws_bytes);
 
 /*
  * Conventional per-spectrum KK -> PEC -> SEC (Eq. 2-5, SEC in the log form
@@ -300,9 +308,11 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
  * vectors do not adequately support new data"): with A = l diag(f) (the
  * basis's I_ref and f), the relative residual of the projection onto the
  * basis vectors, ||A - A V V^T||_F / ||A||_F in [0, 1], written to
- * *h_residual (host).  Computed as sqrt(1 - ||A V||^2 / ||A||^2) from FP64
- * sums of the FP32 projection, so residuals below about 1e-3 are not
- * resolved.  Synchronises the context's stream. */
+ * *h_residual (host).  Computed as sqrt(1 - ||A V||^2 / ||A||^2) from the
+ * per-spectrum sums of the FP32 projection (FP32), summed in FP64 per block
+ * of 128 spectra and over the blocks in a fixed order, so residuals below
+ * about 1e-3 are not resolved.  Works in the context's workspace (16 bytes
+ * per 128 spectra).  Synchronises the context's stream. */
 fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M, int64_t ld,
                               double* h_residual);
 
@@ -365,8 +375,14 @@ typedef struct fkk_server fkk_server;
 
 typedef struct {
     int64_t hbm_budget_bytes;  /* device bytes for in-flight tiles (in + out) */
-    int32_t max_inflight;      /* tiles in flight at once                     */
+    int32_t max_inflight;      /* tiles in flight at once, 1..4096            */
     int64_t max_batch_rows;    /* spectra per launch                          */
+    /* Basis adequacy (Sec. 5: retrain when the basis does not support the
+     * new data): every tile's relative residual against its basis (as
+     * fkk_basis_residual, from the transform's own per-spectrum sums) is
+     * returned by fkk_server_wait; a tile whose residual exceeds this
+     * threshold is counted as flagged (0: no flagging). */
+    double residual_threshold;
 } fkk_server_config;
 
 typedef struct {
@@ -376,6 +392,9 @@ typedef struct {
     double p50_ms, p99_ms, max_ms, mean_ms;  /* submit -> result in host memory */
     double busy_s;             /* wall time from first submit to last completion */
     double mean_batch_tiles;   /* tiles per launch                            */
+    int64_t flagged;           /* completed tiles above residual_threshold:
+                                  the basis should be refitted (Sec. 5)       */
+    double max_residual;       /* largest tile residual seen                  */
 } fkk_server_stats;
 
 /* Creates a server on `device` (own streams, own workspace of
@@ -394,8 +413,10 @@ fkk_status fkk_server_submit(fkk_server* srv, int32_t basis_id, const float* h_i
                              float* h_out, int64_t ld_out, int64_t* ticket);
 /* Waits until the tile has completed (timeout_ms < 0: no limit).  Returns
  * FKK_OK when done, FKK_EBUSY on timeout.  *latency_ms (nullable) receives
- * submit-to-completion time. */
-fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, double* latency_ms);
+ * submit-to-completion time, *residual (nullable) the tile's relative
+ * residual against its basis (see residual_threshold). */
+fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, double* latency_ms,
+                           double* residual);
 /* Blocks until every submitted tile has completed. */
 fkk_status fkk_server_drain(fkk_server* srv);
 fkk_status fkk_server_stats_get(fkk_server* srv, fkk_server_stats* st);

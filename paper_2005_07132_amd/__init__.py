@@ -76,14 +76,15 @@ class BasisDesc(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("max_batch_rows", ctypes.c_int64)]
+                ("max_batch_rows", ctypes.c_int64), ("residual_threshold", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("spectra", ctypes.c_int64), ("launches", ctypes.c_int64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
-                ("busy_s", ctypes.c_double), ("mean_batch_tiles", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("mean_batch_tiles", ctypes.c_double), ("flagged", ctypes.c_int64),
+                ("max_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -126,7 +127,7 @@ def lib() -> ctypes.CDLL:
     L.fkk_workspace_size.argtypes = [vp, i32, i64, i32, ctypes.POINTER(Params), ctypes.POINTER(sz)]
     L.fkk_fit.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), ctypes.POINTER(vp), vp, i64,
                           vp, sz, ctypes.POINTER(FitReport)]
-    L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64, i32, vp, sz]
+    L.fkk_transform.argtypes = [vp, vp, vp, i64, i64, vp, i64, i32, vp, vp, sz]
     L.fkk_plain.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64, vp, sz]
     L.fkk_plain_f64.argtypes = [vp, vp, i64, i32, i64, _c_double_p, ctypes.POINTER(Params), vp, i64, vp, sz]
     L.fkk_gram.argtypes = [vp, vp, i64, i32, i64, _c_double_p, dbl, i32, _c_double_p, _c_double_p, _c_int64_p]
@@ -145,7 +146,7 @@ def lib() -> ctypes.CDLL:
     L.fkk_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     L.fkk_server_add_basis.argtypes = [vp, vp, ctypes.POINTER(i32)]
     L.fkk_server_submit.argtypes = [vp, i32, vp, i64, i64, vp, i64, ctypes.POINTER(i64)]
-    L.fkk_server_wait.argtypes = [vp, i64, dbl, ctypes.POINTER(dbl)]
+    L.fkk_server_wait.argtypes = [vp, i64, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.fkk_server_drain.argtypes = [vp]
     L.fkk_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.fkk_server_reset_stats.argtypes = [vp]
@@ -412,15 +413,21 @@ class Context:
         self._ok(st, "fit")
         return (Basis(b.value) if want_basis else None), out, rep.as_dict()
 
-    def transform(self, basis: Basis, I, out=None, plane: int = OUT_IM):
+    def transform(self, basis: Basis, I, out=None, plane: int = OUT_IM, norms=None):
+        """Stored-basis transform; norms (optional, M x 2 float32 device
+        tensor) receives each spectrum's ||A||^2 and ||A V||^2."""
         import torch
         _check_tensor(I, "I")
         m, n = I.shape
         if out is None:
             out = torch.empty((m, n), dtype=torch.float32, device=I.device)
         _check_tensor(out, "out")
+        if norms is not None:
+            _check_tensor(norms, "norms")
+            if tuple(norms.shape) != (m, 2) or not norms.is_contiguous():
+                raise ValueError("norms must be a contiguous M x 2 tensor")
         st = lib().fkk_transform(self._h, basis.handle, I.data_ptr(), m, I.stride(0), out.data_ptr(), out.stride(0),
-                                 int(plane), None, 0)
+                                 int(plane), norms.data_ptr() if norms is not None else None, None, 0)
         self._ok(st, "transform")
         return out
 
@@ -510,8 +517,8 @@ class Server:
     """Continuous-batching server of stored-basis transforms (host tiles)."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 64,
-                 max_batch_rows: int = 1 << 20):
-        cfg = ServerConfig(hbm_budget_bytes, max_inflight, max_batch_rows)
+                 max_batch_rows: int = 1 << 20, residual_threshold: float = 0.0):
+        cfg = ServerConfig(hbm_budget_bytes, max_inflight, max_batch_rows, residual_threshold)
         h = ctypes.c_void_p()
         st = lib().fkk_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
         if st != FKK_OK:
@@ -565,13 +572,15 @@ class Server:
         self._held[t.value] = (tile, out)
         return t.value
 
-    def wait(self, ticket: int, timeout_ms: float = -1.0):
-        lat = ctypes.c_double()
-        st = lib().fkk_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat))
+    def wait(self, ticket: int, timeout_ms: float = -1.0, with_residual: bool = False):
+        """Latency (ms) of a completed tile, and with with_residual its
+        relative residual against its basis."""
+        lat, res = ctypes.c_double(), ctypes.c_double()
+        st = lib().fkk_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat), ctypes.byref(res))
         if st != FKK_OK:
             raise FkkError(st, "wait")
         self._held.pop(ticket, None)
-        return lat.value
+        return (lat.value, res.value) if with_residual else lat.value
 
     def drain(self):
         st = lib().fkk_server_drain(self._h)

@@ -257,7 +257,9 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     const size_t o_wt16 = o_bim + al((size_t)np * kp * 4);
     const size_t o_bre16 = o_wt16 + al((size_t)kq * np * 2);
     const size_t o_bim16 = o_bre16 + al((size_t)np * kq * 2);
-    const size_t total = o_bim16 + al((size_t)np * kq * 2);
+    const size_t o_f = o_bim16 + al((size_t)np * kq * 2);
+    const size_t o_g = o_f + al((size_t)np * 4);
+    const size_t total = o_g + al(128 * 4);
     FKK_HIP(ctx, ctx->hstage.ensure((total + 7) / 8));  // doubles
     unsigned char* h = reinterpret_cast<unsigned char*>(ctx->hstage.p);
     std::memset(h, 0, total);
@@ -269,12 +271,16 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     uint16_t* bre16 = reinterpret_cast<uint16_t*>(h + o_bre16);
     uint16_t* bim16 = reinterpret_cast<uint16_t*>(h + o_bim16);
     split_reciprocal(b->i_ref.data(), N, rinv);
+    float* fd = reinterpret_cast<float*>(h + o_f);
+    float* gd = reinterpret_cast<float*>(h + o_g);
+    for (int j = 0; j < N; ++j) fd[j] = (float)b->f[j];
     double smax = 0.0;
     for (int c = 0; c < k; ++c) smax = std::max(smax, b->s[c]);
     for (int c = 0; c < k; ++c) {
         double shrink;
         if (shrink_lambda > 0.0) shrink = b->s[c] * b->s[c] / (b->s[c] * b->s[c] + shrink_lambda);
         else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
+        gd[c] = shrink > 0.0 ? (float)(1.0 / shrink) : 0.f;
         for (int j = 0; j < N; ++j) {
             const float w = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
             wt[(size_t)c * np + j] = w;
@@ -301,6 +307,8 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     b->d_wt16 = reinterpret_cast<uint16_t*>(d + o_wt16);
     b->d_bre16 = reinterpret_cast<uint16_t*>(d + o_bre16);
     b->d_bim16 = reinterpret_cast<uint16_t*>(d + o_bim16);
+    b->d_f = reinterpret_cast<float*>(d + o_f);
+    b->d_g = reinterpret_cast<float*>(d + o_g);
     b->device = ctx->device;
     return FKK_OK;
 }
@@ -1154,7 +1162,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
 }
 
 fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld, float* d_out,
-                         int64_t ld_out, int32_t plane, void* d_ws, size_t ws_bytes) {
+                         int64_t ld_out, int32_t plane, float* d_norms, void* d_ws, size_t ws_bytes) {
     if (!ctx) return FKK_EINVAL;
     if (!b) return ctx->fail(FKK_EINVAL, "basis is NULL");
     fkk_status st;
@@ -1164,15 +1172,19 @@ fkk_status fkk_transform(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int
     if (!d_ws && ws_bytes != 0) return ctx->fail(FKK_EINVAL, "ws_bytes without a workspace");
     (void)ws_bytes;  // the fused kernel keeps its Z tile in LDS: no workspace
     if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
+    if (d_norms && (reinterpret_cast<uintptr_t>(d_norms) & 7) != 0)
+        return ctx->fail(FKK_EINVAL, "norms must be 8-byte aligned");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
+    fkk::dev::ResidualArgs res;
+    if (d_norms) res = {b->d_f, b->d_g, d_norms};
     if (b->prec == FKK_PREC_BF16)
         FKK_HIP(ctx, fkk::dev::launch_transform16(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt16,
                                                   b->npad, b->kq, b->d_bre16, b->d_bim16, d_out, ld_out, plane,
-                                                  ctx->stream));
+                                                  ctx->stream, res));
     else
         FKK_HIP(ctx, fkk::dev::launch_transform(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad,
                                                 b->kp, b->k, b->d_bre_t, b->d_bim_t, d_out, ld_out, plane,
-                                                ctx->stream));
+                                                ctx->stream, res));
     return FKK_OK;
 }
 
@@ -1224,51 +1236,48 @@ fkk_status fkk_project(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64
     return FKK_OK;
 }
 
-fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld,
-                              double* h_residual) {
-    if (!ctx) return FKK_EINVAL;
+namespace {
+
+// Residual of Sec. 5 from the two FP64 sums.
+double residual_from_sums(double sa, double sz) { return sa > 0.0 ? std::sqrt(std::max(0.0, 1.0 - sz / sa)) : 0.0; }
+
+fkk_status check_residual_args(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld,
+                               const double* h_residual) {
     if (!b || !h_residual) return ctx->fail(FKK_EINVAL, "NULL argument");
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, b->N, ld, "I")) != FKK_OK) return st;
-    if (b->device != ctx->device) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
-    FKK_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
-    const int N = b->N, k = b->k, kp = b->kp;
-    // W = diag(f) V (FP32, kp x npad), without the Eq. 25 shrink
-    std::vector<float> wt((size_t)kp * b->npad, 0.f);
-    for (int c = 0; c < k; ++c)
-        for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(b->f[j] * b->v[(size_t)j * k + c]);
-    const int64_t nres = fkk::dev::residual_blocks(M);
-    float *X = nullptr, *Z = nullptr;
-    double *fdev = nullptr, *psum = nullptr;
-    auto layout = [&](void* base) {
-        Carve c(base);
-        X = c.take<float>(wt.size());
-        Z = c.take<float>((size_t)M * kp);
-        fdev = c.take<double>(N);
-        psum = c.take<double>(2 * (size_t)nres);
-        return c.bytes();
-    };
-    void* base = nullptr;
-    if ((st = acquire_ws(ctx, nullptr, 0, layout(nullptr), &base)) != FKK_OK) return st;
-    layout(base);
-    FKK_HIP(ctx, hipMemcpyAsync(X, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemcpyAsync(fdev, b->f.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
-    const fkk::dev::ArgPart none{nullptr, nullptr, nullptr, nullptr};
-    FKK_HIP(ctx, fkk::dev::launch_project(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, X, b->npad, kp, k, Z, kp,
-                                          none, 0, s));
-    FKK_HIP(ctx, fkk::dev::launch_residual_sums(d_I, M, N, ld, b->d_rinv, (float)b->ratio_floor, fdev, Z, kp, k, psum,
-                                                s));
-    std::vector<double> part(2 * (size_t)nres);
-    FKK_HIP(ctx, hipMemcpyAsync(part.data(), psum, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipStreamSynchronize(s));
-    double sa = 0.0, sz = 0.0;
-    for (int64_t i = 0; i < nres; ++i) {
-        sa += part[2 * i];
-        sz += part[2 * i + 1];
-    }
-    *h_residual = sa > 0.0 ? std::sqrt(std::max(0.0, 1.0 - sz / sa)) : 0.0;
+    if (b->device != ctx->device || !b->d_wt) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     return FKK_OK;
+}
+
+// Partials per block of spectra into part, their total into part + 2 nblk,
+// the total to the host.  The kernels are those of every residual call.
+fkk_status residual_device(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld, double* part,
+                           double* h_residual) {
+    const int64_t nblk = fkk::dev::proj_blocks(M);
+    hipStream_t s = ctx->stream;
+    FKK_HIP(ctx, fkk::dev::launch_residual_partials(d_I, M, b->N, ld, b->d_rinv, (float)b->ratio_floor, b->d_wt,
+                                                    b->npad, b->kp, b->d_f, b->d_g, part, s));
+    FKK_HIP(ctx, fkk::dev::launch_residual_total(part, nblk, part + 2 * nblk, s));
+    double h[2] = {0.0, 0.0};
+    FKK_HIP(ctx, hipMemcpyAsync(h, part + 2 * nblk, sizeof h, hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipStreamSynchronize(s));
+    *h_residual = residual_from_sums(h[0], h[1]);
+    return FKK_OK;
+}
+
+}  // namespace
+
+fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld,
+                              double* h_residual) {
+    if (!ctx) return FKK_EINVAL;
+    fkk_status st;
+    if ((st = check_residual_args(ctx, b, d_I, M, ld, h_residual)) != FKK_OK) return st;
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    void* base = nullptr;
+    const size_t need = (2 * (size_t)fkk::dev::proj_blocks(M) + 2) * sizeof(double);
+    if ((st = acquire_ws(ctx, nullptr, 0, need, &base)) != FKK_OK) return st;
+    return residual_device(ctx, b, d_I, M, ld, static_cast<double*>(base), h_residual);
 }
 
 fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, int64_t M, int64_t ld_z,

@@ -152,6 +152,59 @@ __device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_ou
 }
 
 
+// ---- per-spectrum sums for the basis residual (retraining criterion, Sec. 5)
+// With A = l diag(f), a spectrum's relative residual against the basis is
+// ||A_m - A_m V V^T||^2 / ||A_m||^2 = 1 - ||A_m V||^2 / ||A_m||^2; the kernels
+// below write the two sums of each row m as norms[2m] and norms[2m + 1].
+
+// Sum over the 16 lanes that differ in their four low bits.
+__device__ __forceinline__ float sum16(float v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    return v;
+}
+
+// ||A_m||^2 from the staging loop's partial sums: thread t of the block
+// staged rows (t >> 4) + 16 p (p < 8), four columns at a time.
+__device__ __forceinline__ void store_anorms(const float (&asq)[8], float* __restrict__ norms, int64_t r0,
+                                             int64_t M) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const float v = sum16(asq[p]);
+        const int64_t row = r0 + (tid >> 4) + 16 * p;
+        if ((tid & 15) == 0 && row < M) norms[2 * row] = v;
+    }
+}
+
+// ||A_m V||^2 from a projection tile held as in project_finish (acc[rb][cb][v]
+// = Z[r0 + 32 w + 16 rb + 4 (l/16) + v][16 cb + l%16]), with Z = A W and
+// g[c] = 1 / shrink_c (0 for a dropped vector), so Z_c g_c = (A V)_c.
+template <int KB>
+__device__ __forceinline__ void store_znorms(const floatx4 (&acc)[2][KB], const float* __restrict__ g,
+                                             float* __restrict__ norms, int64_t r0, int64_t M) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float gl[KB];
+#pragma unroll
+    for (int cb = 0; cb < KB; ++cb) gl[cb] = g[16 * cb + (lane & 15)];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float sq = 0.f;
+#pragma unroll
+            for (int cb = 0; cb < KB; ++cb) {
+                const float z = acc[rb][cb][v] * gl[cb];
+                sq = fmaf(z, z, sq);
+            }
+            sq = sum16(sq);
+            const int64_t row = r0 + wave * 32 + rb * 16 + 4 * (lane >> 4) + v;
+            if ((lane & 15) == 0 && row < M) norms[2 * row + 1] = sq;
+        }
+}
+
 __device__ __forceinline__ void better_max(float& v, int& i, float ov, int oi) {
     if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
 }

@@ -28,6 +28,8 @@ struct fkk_basis {
     uint16_t* d_wt16 = nullptr;  // kq x npad, BF16 of d_wt
     uint16_t* d_bre16 = nullptr; // npad x kq, BF16, natural order
     uint16_t* d_bim16 = nullptr; // npad x kq
+    float* d_f = nullptr;        // npad: f of the training data (residual sums)
+    float* d_g = nullptr;        // 128: 1 / shrink of each vector, zero past k
     ~fkk_basis() {
         if (d_arena) hipFree(d_arena);
     }

@@ -68,11 +68,27 @@ inline int64_t proj_blocks(int64_t M) { return (M + kProjRows - 1) / kProjRows; 
 hipError_t launch_project(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                           const float* Wt, int ldw, int kp, int k_store, float* Z, int64_t ld_z,
                           ArgPart part, int k_arg, hipStream_t s, bool logged = false);
-// Basis residual sums: part[2 b], part[2 b + 1] = sums of (l f)^2 and of
-// the squared first k columns of Z over block b's residual_blocks rows.
-int64_t residual_blocks(int64_t M);
-hipError_t launch_residual_sums(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                                const double* f, const float* Z, int64_t ld_z, int k, double* part, hipStream_t s);
+// Basis residual (retraining criterion, Sec. 5).  With A = l diag(f), the
+// sums ||A_m||^2 and ||A_m V||^2 of each spectrum (the projection on Wt with
+// g[c] = 1 / shrink_c, kp entries, zero past k, so that Z_c g_c = (A V)_c).
+// f: N floats.  launch_residual_partials: their FP64 sums per block of
+// kProjRows spectra into part[2 b], part[2 b + 1] (proj_blocks(M) pairs);
+// launch_residual_total: the sum of nparts pairs in a fixed order into
+// out[0..1]; launch_segment_sums: the FP64 sums over the rows offs[s] ..
+// offs[s+1]-1 of a per-spectrum norms array (2 floats per row) into
+// out[2 s..2 s+1].
+hipError_t launch_residual_partials(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                                    const float* Wt, int ldw, int kp, const float* f, const float* g, double* part,
+                                    hipStream_t s);
+hipError_t launch_residual_total(const double* part, int64_t nparts, double* out, hipStream_t s);
+hipError_t launch_segment_sums(const float* norms, const long long* offs, int nseg, double* out, hipStream_t s);
+// Optional per-spectrum residual sums of the fused transforms: norms[2 m],
+// norms[2 m + 1] = ||A_m||^2, ||A_m V||^2 (FP32) when norms != nullptr.
+struct ResidualArgs {
+    const float* f = nullptr;  // N
+    const float* g = nullptr;  // 128, 1 / shrink, zero past k
+    float* norms = nullptr;    // M x 2
+};
 hipError_t launch_argext_reduce(ArgPart part, int64_t nblocks, int kp, int k, long long* qmax,
                                 long long* qmin, hipStream_t s);
 // Sub-sample between the extrema (Sec. 2.3): for each of the k columns of Z
@@ -97,7 +113,8 @@ hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, co
 inline int kgroup_pos(int c) { return (c & ~15) + 4 * (c & 3) + ((c & 15) >> 2); }
 hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                             const float* Wt, int ldw, int kp, int k, const float* BreT, const float* BimT,
-                            float* out, int64_t ld_out, int plane, hipStream_t s);
+                            float* out, int64_t ld_out, int plane, hipStream_t s,
+                            const ResidualArgs& res = ResidualArgs{});
 
 // ---- BF16 operands, FP32 accumulation -------------------------------------
 // BF16 arrays are passed as uint16_t (bit patterns).  kq = padded k of the
@@ -123,7 +140,8 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
                                 hipStream_t s);
 hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                               const uint16_t* Wt, int ldw, int kq, const uint16_t* BreT, const uint16_t* BimT,
-                              float* out, int64_t ld_out, int plane, hipStream_t s);
+                              float* out, int64_t ld_out, int plane, hipStream_t s,
+                              const ResidualArgs& res = ResidualArgs{});
 
 // Gather rows q of a row-major FP32 matrix Z (k columns, row stride ld_z)
 // into X (n_q x k).

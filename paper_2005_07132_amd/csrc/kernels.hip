@@ -381,19 +381,22 @@ constexpr int PNC = 64;        // wavenumbers per LDS stage
 constexpr int PLD = PNC + 4;
 
 // Stage one 128 x 64 tile of l = 1/2 ln(I r) into LDS (zeros outside).
-template <bool VEC>
+// NORMS: also adds (l f)^2 of the staged values to asq[p] (row lrow + 16 p).
+template <bool VEC, bool NORMS = false>
 __device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __restrict__ I, int64_t r0,
                                                int64_t M, int N, int64_t ld, int j0,
-                                               const float* __restrict__ rinv, float floor) {
+                                               const float* __restrict__ rinv, float floor,
+                                               const float* __restrict__ f = nullptr, float* asq = nullptr) {
     const int tid = threadIdx.x;
     const int lrow = tid >> 4;
     const int lcol = (tid & 15) * 4;
     const int col = j0 + lcol;
-    float r[4], rl[4];
+    float r[4], rl[4], fq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         r[q] = (col + q < N) ? rinv[col + q] : 0.f;
         rl[q] = (col + q < N) ? rinv[N + col + q] : 0.f;
+        if (NORMS) fq[q] = (col + q < N) ? f[col + q] : 0.f;
     }
     float4 x[8];
 #pragma unroll
@@ -409,6 +412,10 @@ __device__ __forceinline__ void stage_logratio(float (*sL)[PLD], const float* __
         for (int q = 0; q < 4; ++q) {
             bool bad;
             l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], rl[q], floor, bad) : 0.f;
+            if (NORMS) {
+                const float a = l[q] * fq[q];
+                asq[p] = fmaf(a, a, asq[p]);
+            }
         }
         *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
     }
@@ -673,58 +680,143 @@ hipError_t launch_between(const float* Z, int64_t M, int64_t ld_z, int kp, int k
     return hipGetLastError();
 }
 
-// Sums for the basis residual: per block of 64 spectra, the FP64 sums of
-// (l_j f_j)^2 over the spectra's columns and of z_c^2 over their first k
-// projections (Z = A V from the projection kernel).
-constexpr int kResRows = 64;
-__global__ __launch_bounds__(256) void residual_sums_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
-                                                            const float* __restrict__ rinv, float floor,
-                                                            const double* __restrict__ f, const float* __restrict__ Z,
-                                                            int64_t ld_z, int k, double* __restrict__ part) {
-    __shared__ double red[2][4];
-    const int64_t r0 = (int64_t)blockIdx.x * kResRows;
-    const int64_t r1 = r0 + kResRows < M ? r0 + kResRows : M;
-    double sa = 0.0, sz = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-        const float* row = I + r * ld;
-        for (int j = threadIdx.x; j < N; j += blockDim.x) {
-            bool bad;
-            const double a = (double)log_ratio(row[j], rinv[j], rinv[N + j], floor, bad) * f[j];
-            sa += a * a;
-        }
-        for (int c = threadIdx.x; c < k; c += blockDim.x) {
-            const double z = Z[r * ld_z + c];
-            sz += z * z;
-        }
+// Basis residual (retraining criterion, Sec. 5) without an output: the
+// projection of a 128-spectrum block onto the basis, the two sums of every
+// spectrum (store_anorms / store_znorms, FP32), and their FP64 sums over the
+// block in a fixed order into part[2 b], part[2 b + 1].
+template <int KB, bool VEC>
+__global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                       const float* __restrict__ rinv, float floor,
+                                                       const float* __restrict__ Wt, int ldw,
+                                                       const float* __restrict__ f, const float* __restrict__ g,
+                                                       double* __restrict__ part) {
+    constexpr int KP = KB * 16;
+    __shared__ __attribute__((aligned(16))) float sL[PR][PLD];
+    __shared__ __attribute__((aligned(16))) float sW[KP][PLD];
+    __shared__ float sN[2 * PR];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * PR;
+    const int64_t rows = M - r0 < PR ? M - r0 : PR;
+    floatx4 acc[2][KB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float asq[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < N; j0 += PNC) {
+        stage_logratio<VEC, true>(sL, I, r0, M, N, ld, j0, rinv, floor, f, asq);
+        stage_weights<KB>(sW, Wt, ldw, j0);
+        __syncthreads();
+        project_stage<KB>(acc, sL, sW, wave, lane);
+        __syncthreads();
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        sa += __shfl_xor(sa, off);
-        sz += __shfl_xor(sz, off);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wave] = sa;
-        red[1][wave] = sz;
-    }
+    sN[tid] = 0.f;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0.0, tz = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-            ta += red[0][w];
-            tz += red[1][w];
+    store_anorms(asq, sN, 0, rows);  // rows of this block, in LDS
+    store_znorms<KB>(acc, g, sN, 0, rows);
+    __syncthreads();
+    if (wave == 0) {
+        double a = (double)sN[2 * lane] + (double)sN[2 * (lane + 64)];
+        double z = (double)sN[2 * lane + 1] + (double)sN[2 * (lane + 64) + 1];
+        for (int off = 32; off >= 1; off >>= 1) {
+            a += __shfl_xor(a, off);
+            z += __shfl_xor(z, off);
         }
-        part[2 * blockIdx.x] = ta;
-        part[2 * blockIdx.x + 1] = tz;
+        if (lane == 0) {
+            part[2 * blockIdx.x] = a;
+            part[2 * blockIdx.x + 1] = z;
+        }
     }
 }
 
-int64_t residual_blocks(int64_t M) { return (M + kResRows - 1) / kResRows; }
+// Sum of nparts (a, z) pairs in a fixed order: out[0], out[1].
+__global__ __launch_bounds__(256) void residual_total_kernel(const double* __restrict__ part, int64_t nparts,
+                                                             double* __restrict__ out) {
+    __shared__ double red[2][4];
+    double a = 0.0, z = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += 256) {
+        a += part[2 * i];
+        z += part[2 * i + 1];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off);
+        z += __shfl_xor(z, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        out[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
 
-hipError_t launch_residual_sums(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
-                                const double* f, const float* Z, int64_t ld_z, int k, double* part, hipStream_t s) {
+// Per segment s (rows offs[s] .. offs[s+1]-1 of a norms array), the FP64
+// sums of both norms: out[2 s], out[2 s + 1].  One block per segment.
+__global__ __launch_bounds__(256) void segment_sums_kernel(const float* __restrict__ norms,
+                                                           const long long* __restrict__ offs,
+                                                           double* __restrict__ out) {
+    __shared__ double red[2][4];
+    const long long b = offs[blockIdx.x], e = offs[blockIdx.x + 1];
+    double a = 0.0, z = 0.0;
+    for (long long r = b + threadIdx.x; r < e; r += 256) {
+        a += norms[2 * r];
+        z += norms[2 * r + 1];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off);
+        z += __shfl_xor(z, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        out[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+hipError_t launch_residual_partials(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
+                                    const float* Wt, int ldw, int kp, const float* f, const float* g, double* part,
+                                    hipStream_t s) {
     if (M < 1) return hipSuccess;
-    hipLaunchKernelGGL(residual_sums_kernel, dim3((unsigned)residual_blocks(M)), dim3(256), 0, s, I, M, N, ld, rinv,
-                       floor, f, Z, ld_z, k, part);
+    if (!f || !g || !part) return hipErrorInvalidValue;
+    const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    dim3 grid((unsigned)proj_blocks(M));
+#define FKK_RS(KB)                                                                                                  \
+    do {                                                                                                            \
+        if (vec)                                                                                                    \
+            hipLaunchKernelGGL((residual_kernel<KB, true>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt,   \
+                               ldw, f, g, part);                                                                    \
+        else                                                                                                        \
+            hipLaunchKernelGGL((residual_kernel<KB, false>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt,  \
+                               ldw, f, g, part);                                                                    \
+    } while (0)
+    switch (kp) {
+        case 16: FKK_RS(1); break;
+        case 32: FKK_RS(2); break;
+        case 64: FKK_RS(4); break;
+        case 128: FKK_RS(8); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FKK_RS
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_total(const double* part, int64_t nparts, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(residual_total_kernel, dim3(1), dim3(256), 0, s, part, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sums(const float* norms, const long long* offs, int nseg, double* out, hipStream_t s) {
+    if (nseg < 1) return hipSuccess;
+    hipLaunchKernelGGL(segment_sums_kernel, dim3((unsigned)nseg), dim3(256), 0, s, norms, offs, out);
     return hipGetLastError();
 }
 
@@ -891,13 +983,17 @@ hipError_t launch_reconstruct(const float* Z, int64_t M, int64_t ld_z, int k, co
 // (Z tile kept in LDS) and reconstructs them; I is read once, out written
 // once.
 // ===========================================================================
-template <int KB, int QL, bool VEC_IN, bool VEC_OUT>
+// NORMS: also the residual sums of every spectrum (store_anorms /
+// store_znorms) into norms, from the same loads and the same projection.
+template <int KB, int QL, bool VEC_IN, bool VEC_OUT, bool NORMS>
 __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                         const float* __restrict__ rinv, float floor,
                                                         const float* __restrict__ Wt, int ldw,
                                                         const float* __restrict__ BreT,
                                                         const float* __restrict__ BimT, int k,
-                                                        float* __restrict__ out, int64_t ld_out, int plane) {
+                                                        float* __restrict__ out, int64_t ld_out, int plane,
+                                                        const float* __restrict__ f, const float* __restrict__ g,
+                                                        float* __restrict__ norms) {
     constexpr int KP = KB * 16;
     constexpr int BLD = KP + 4;
     constexpr int P1 = PR * PLD + KP * PLD;             // projection phase
@@ -918,12 +1014,17 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < KB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float asq[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int j0 = 0; j0 < N; j0 += PNC) {
-        stage_logratio<VEC_IN>(sL, I, r0, M, N, ld, j0, rinv, floor);
+        stage_logratio<VEC_IN, NORMS>(sL, I, r0, M, N, ld, j0, rinv, floor, f, asq);
         stage_weights<KB>(sW, Wt, ldw, j0);
         __syncthreads();
         project_stage<KB>(acc, sL, sW, wave, lane);
         __syncthreads();
+    }
+    if (NORMS) {
+        store_anorms(asq, norms, r0, M);
+        store_znorms<KB>(acc, g, norms, r0, M);
     }
     // Z tile to LDS: sZ[row][c]
 #pragma unroll
@@ -987,15 +1088,15 @@ __global__ __launch_bounds__(256) void transform_kernel(const float* __restrict_
     }
 }
 
-template <int KB>
+template <int KB, bool NORMS>
 static hipError_t transform_dispatch(bool vin, bool vout, dim3 grid, hipStream_t s, const float* I, int64_t M, int N,
                                      int64_t ld, const float* rinv, float floor, const float* Wt, int ldw,
                                      const float* BreT, const float* BimT, int k, float* out, int64_t ld_out,
-                                     int plane) {
+                                     int plane, const float* f, const float* g, float* norms) {
     const int ql = ((k - 1 - 16 * (KB - 1)) >> 2) + 1;  // as in recon_dispatch
 #define FKK_TR(Q, a, b)                                                                                              \
-    hipLaunchKernelGGL((transform_kernel<KB, Q, a, b>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, ldw,   \
-                       BreT, BimT, k, out, ld_out, plane)
+    hipLaunchKernelGGL((transform_kernel<KB, Q, a, b, NORMS>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, Wt, \
+                       ldw, BreT, BimT, k, out, ld_out, plane, f, g, norms)
     if (vin && vout) {
         if (ql == 1) FKK_TR(1, true, true);
         else if (ql == 2) FKK_TR(2, true, true);
@@ -1008,19 +1109,36 @@ static hipError_t transform_dispatch(bool vin, bool vout, dim3 grid, hipStream_t
     return hipGetLastError();
 }
 
+template <int KB>
+static hipError_t transform_dispatch_n(bool vin, bool vout, dim3 grid, hipStream_t s, const float* I, int64_t M,
+                                       int N, int64_t ld, const float* rinv, float floor, const float* Wt, int ldw,
+                                       const float* BreT, const float* BimT, int k, float* out, int64_t ld_out,
+                                       int plane, const float* f, const float* g, float* norms) {
+    if (norms)
+        return transform_dispatch<KB, true>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k,
+                                            out, ld_out, plane, f, g, norms);
+    return transform_dispatch<KB, false>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out,
+                                         ld_out, plane, f, g, norms);
+}
+
 hipError_t launch_transform(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                             const float* Wt, int ldw, int kp, int k, const float* BreT, const float* BimT, float* out,
-                            int64_t ld_out, int plane, hipStream_t s) {
+                            int64_t ld_out, int plane, hipStream_t s, const ResidualArgs& res) {
     const bool vin = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
     const bool vout = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
+    if (res.norms && (!res.f || !res.g)) return hipErrorInvalidValue;
     dim3 grid((unsigned)proj_blocks(M));
+#define FKK_TD(KB)                                                                                                 \
+    return transform_dispatch_n<KB>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out,    \
+                                    ld_out, plane, res.f, res.g, res.norms)
     switch (kp) {
-        case 16: return transform_dispatch<1>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
-        case 32: return transform_dispatch<2>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
-        case 64: return transform_dispatch<4>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
-        case 128: return transform_dispatch<8>(vin, vout, grid, s, I, M, N, ld, rinv, floor, Wt, ldw, BreT, BimT, k, out, ld_out, plane);
+        case 16: FKK_TD(1);
+        case 32: FKK_TD(2);
+        case 64: FKK_TD(4);
+        case 128: FKK_TD(8);
         default: return hipErrorInvalidValue;
     }
+#undef FKK_TD
 }
 
 }  // namespace dev

@@ -204,19 +204,23 @@ __global__ __launch_bounds__(256) void gram16_kernel(const u32x4* __restrict__ L
 // ---------------------------------------------------------------------------
 
 // One 128 x 64 tile of l = 1/2 ln(I r) into LDS as BF16 (zeros outside).
-template <bool VEC>
+// NORMS: also adds (l f)^2 of the FP32 log ratio (before the BF16 rounding)
+// to asq[p] (row lrow + 16 p).
+template <bool VEC, bool NORMS = false>
 __device__ __forceinline__ void stage_logratio16(unsigned short (*sL)[SLD], const float* __restrict__ I, int64_t r0,
                                                  int64_t M, int N, int64_t ld, int j0,
-                                                 const float* __restrict__ rinv, float floor) {
+                                                 const float* __restrict__ rinv, float floor,
+                                                 const float* __restrict__ f = nullptr, float* asq = nullptr) {
     const int tid = threadIdx.x;
     const int lrow = tid >> 4;
     const int lcol = (tid & 15) * 4;
     const int col = j0 + lcol;
-    float r[4], rl[4];
+    float r[4], rl[4], fq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         r[q] = (col + q < N) ? rinv[col + q] : 0.f;
         rl[q] = (col + q < N) ? rinv[N + col + q] : 0.f;
+        if (NORMS) fq[q] = (col + q < N) ? f[col + q] : 0.f;
     }
     float4 x[8];
 #pragma unroll
@@ -232,6 +236,10 @@ __device__ __forceinline__ void stage_logratio16(unsigned short (*sL)[SLD], cons
         for (int q = 0; q < 4; ++q) {
             bool bad;
             l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], rl[q], floor, bad) : 0.f;
+            if (NORMS) {
+                const float a = l[q] * fq[q];
+                asq[p] = fmaf(a, a, asq[p]);
+            }
         }
         *reinterpret_cast<uint2*>(&sL[lrow + 16 * p][lcol]) = make_uint2(pack2(l[0], l[1]), pack2(l[2], l[3]));
     }
@@ -427,13 +435,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB2 <= 2 ? 
 // Fused stored-basis transform in BF16: projection (transposed, so that the
 // Z tile goes to LDS as 4-value BF16 stores), then reconstruction.
 // ---------------------------------------------------------------------------
-template <int KB2, bool VEC_IN, bool VEC_OUT>
+// ||A_m V||^2 from the transposed projection tile (accT[cb][rb][v] = Z of
+// spectrum 32 w + 16 rb + l%16, column 16 cb + 4 (l/16) + v), with g as in
+// store_znorms.  Lanes of one spectrum differ in bits 4 and 5.
+template <int NCB>
+__device__ __forceinline__ void store_znorms_t(const floatx4 (&accT)[NCB][2], const float* __restrict__ g,
+                                               float* __restrict__ norms, int64_t r0, int64_t M) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float sq[2] = {0.f, 0.f};
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const float4 gv = *reinterpret_cast<const float4*>(g + 16 * cb + 4 * (lane >> 4));
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float z = accT[cb][rb][v] * f4get(gv, v);
+                sq[rb] = fmaf(z, z, sq[rb]);
+            }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        float t = sq[rb];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        const int64_t row = r0 + wave * 32 + 16 * rb + (lane & 15);
+        if ((lane >> 4) == 0 && row < M) norms[2 * row + 1] = t;
+    }
+}
+
+template <int KB2, bool VEC_IN, bool VEC_OUT, bool NORMS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void transform16_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                           const float* __restrict__ rinv, float floor,
                                                           const unsigned short* __restrict__ Wt, int ldw,
                                                           const u32x4* __restrict__ BreT,
                                                           const u32x4* __restrict__ BimT, float* __restrict__ out,
-                                                          int64_t ld_out, int plane) {
+                                                          int64_t ld_out, int plane, const float* __restrict__ f,
+                                                          const float* __restrict__ g, float* __restrict__ norms) {
     constexpr int KQ = KB2 * 32, NCB = KB2 * 2;
     constexpr int BLDU = KB2 * 4 + 1;
     constexpr int P1 = (PR * SLD + KQ * SLD) * 2;      // projection phase (bytes)
@@ -454,12 +492,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void t
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) accT[cb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float asq[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int j0 = 0; j0 < N; j0 += PNC) {
-        stage_logratio16<VEC_IN>(sL, I, r0, M, N, ld, j0, rinv, floor);
+        stage_logratio16<VEC_IN, NORMS>(sL, I, r0, M, N, ld, j0, rinv, floor, f, asq);
         stage_weights16<KQ>(sW, Wt, ldw, j0);
         __syncthreads();
         project16_stage_t<NCB>(accT, sL, sW, wave, lane);
         __syncthreads();
+    }
+    if (NORMS) {
+        store_anorms(asq, norms, r0, M);
+        store_znorms_t<NCB>(accT, g, norms, r0, M);
     }
     // Z tile (BF16) to LDS: spectrum row, units of 8 columns.
     unsigned short* sZh = reinterpret_cast<unsigned short*>(sZ);
@@ -570,23 +613,27 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
 
 hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                               const uint16_t* Wt, int ldw, int kq, const uint16_t* BreT, const uint16_t* BimT,
-                              float* out, int64_t ld_out, int plane, hipStream_t s) {
+                              float* out, int64_t ld_out, int plane, hipStream_t s, const ResidualArgs& res) {
     if (ldw % 8 != 0) return hipErrorInvalidValue;
+    if (res.norms && (!res.f || !res.g)) return hipErrorInvalidValue;
     const bool vin = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
     const bool vout = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
     dim3 grid((unsigned)proj_blocks(M));
     const unsigned short* w = reinterpret_cast<const unsigned short*>(Wt);
     const u32x4* bre = reinterpret_cast<const u32x4*>(BreT);
     const u32x4* bim = reinterpret_cast<const u32x4*>(BimT);
-#define FKK_TR16(KB2, A, B)                                                                                        \
-    hipLaunchKernelGGL((transform16_kernel<KB2, A, B>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, w, ldw,  \
-                       bre, bim, out, ld_out, plane)
+#define FKK_TR16(KB2, A, B, NR)                                                                                    \
+    hipLaunchKernelGGL((transform16_kernel<KB2, A, B, NR>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, w,   \
+                       ldw, bre, bim, out, ld_out, plane, res.f, res.g, res.norms)
 #define FKK_TR16_K(KB2)                                                        \
     do {                                                                       \
-        if (vin && vout) FKK_TR16(KB2, true, true);                            \
-        else if (vin) FKK_TR16(KB2, true, false);                              \
-        else if (vout) FKK_TR16(KB2, false, true);                             \
-        else FKK_TR16(KB2, false, false);                                      \
+        if (res.norms) {                                                       \
+            if (vin && vout) FKK_TR16(KB2, true, true, true);                  \
+            else FKK_TR16(KB2, false, false, true);                            \
+        } else if (vin && vout) FKK_TR16(KB2, true, true, false);              \
+        else if (vin) FKK_TR16(KB2, true, false, false);                       \
+        else if (vout) FKK_TR16(KB2, false, true, false);                      \
+        else FKK_TR16(KB2, false, false, false);                               \
     } while (0)
     switch (kq) {
         case 32: FKK_TR16_K(1); break;

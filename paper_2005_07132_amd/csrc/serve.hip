@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -81,6 +82,7 @@ class Arena {
 
 struct Request {
     int64_t ticket = 0;
+    double residual = 0.0;  // of the tile against its basis (Sec. 5), set when it completes
     int basis = 0;
     const float* in = nullptr;
     int64_t rows = 0, ld = 0;
@@ -93,10 +95,18 @@ struct Request {
 struct Batch {
     std::vector<Request> reqs;
     size_t off = 0, bytes = 0;
+    int slot = -1;  // pinned host slot: tile offsets out, residual sums back
     hipEvent_t copied = nullptr, computed = nullptr, done = nullptr;
 };
 
-size_t tile_bytes(int64_t rows, int n) { return 2 * (size_t)rows * n * sizeof(float) + 512; }
+// Device bytes of a tile: input and output (rows x n each), the two residual
+// sums of every spectrum, and room for alignment and the batch's per-tile
+// offsets and sums.
+size_t tile_bytes(int64_t rows, int n) { return (2 * (size_t)rows * n + 2 * (size_t)rows) * sizeof(float) + 512; }
+
+struct Finished {
+    double latency_ms = 0.0, residual = 0.0;
+};
 
 }  // namespace
 
@@ -114,9 +124,16 @@ struct fkk_server {
     std::deque<Request> queue;
     std::vector<Batch> inflight;
     int inflight_tiles = 0;
-    std::unordered_map<int64_t, double> finished;  // ticket -> latency (ms)
+    std::unordered_map<int64_t, Finished> finished;  // ticket -> latency (ms), residual
     std::vector<double> latencies;
     int64_t next_ticket = 1, submitted = 0, completed = 0, rejected = 0, spectra = 0, launches = 0, batch_tiles = 0;
+    int64_t flagged = 0;
+    double max_residual = 0.0;
+    // pinned host slots, one per batch in flight: max_inflight + 1 tile
+    // offsets (int64), then 2 max_inflight residual sums (FP64)
+    unsigned char* side = nullptr;
+    size_t slot_bytes = 0;
+    std::vector<int> free_slots;
     Clock::time_point first_submit, last_done;
     bool any_submit = false, stop = false;
     hipError_t error = hipSuccess;
@@ -138,12 +155,23 @@ bool fkk_server::issue(std::vector<Request>& reqs) {
         bytes += r.bytes;
     }
     Batch bt;
-    if (!arena.alloc(bytes, &bt.off)) return false;  // reqs untouched: caller requeues
+    if (free_slots.empty() || !arena.alloc(bytes, &bt.off)) return false;  // reqs untouched: caller requeues
+    bt.slot = free_slots.back();
+    free_slots.pop_back();
     bt.reqs = std::move(reqs);
     bt.bytes = bytes;
-    // device layout: inputs of all tiles (rows x n, contiguous), then outputs
+    const int nt = (int)bt.reqs.size();
+    // device layout: inputs of all tiles (rows x n, contiguous), outputs, the
+    // residual sums of every spectrum (rows x 2), then (256-byte aligned)
+    // the tile offsets and the per-tile sums
     float* din = reinterpret_cast<float*>(arena_base + bt.off);
     float* dout = din + (size_t)rows * n;
+    float* dnorm = dout + (size_t)rows * n;
+    const size_t o_offs = ((size_t)(reinterpret_cast<char*>(dnorm + 2 * rows) - arena_base) + 255) & ~size_t(255);
+    long long* doffs = reinterpret_cast<long long*>(arena_base + o_offs);
+    double* dsums = reinterpret_cast<double*>(doffs + nt + 1);
+    long long* hoffs = reinterpret_cast<long long*>(side + (size_t)bt.slot * slot_bytes);
+    double* hsums = reinterpret_cast<double*>(hoffs + cfg.max_inflight + 1);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
@@ -152,19 +180,26 @@ bool fkk_server::issue(std::vector<Request>& reqs) {
     chk(hipEventCreateWithFlags(&bt.computed, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&bt.done, hipEventDisableTiming));
     int64_t r0 = 0;
-    for (auto& r : bt.reqs) {
+    for (int t = 0; t < nt; ++t) {
+        const Request& r = bt.reqs[t];
+        hoffs[t] = r0;
         chk(hipMemcpy2DAsync(din + (size_t)r0 * n, n * sizeof(float), r.in, r.ld * sizeof(float), n * sizeof(float),
                              r.rows, hipMemcpyHostToDevice, s_in));
         r0 += r.rows;
     }
+    hoffs[nt] = r0;
+    chk(hipMemcpyAsync(doffs, hoffs, (nt + 1) * sizeof(long long), hipMemcpyHostToDevice, s_in));
     chk(hipEventRecord(bt.copied, s_in));
     chk(hipStreamWaitEvent(s_comp, bt.copied, 0));
+    // the transform also writes each spectrum's residual sums (Sec. 5)
+    const fkk::dev::ResidualArgs res{b->d_f, b->d_g, dnorm};
     if (prec == FKK_PREC_BF16)
         chk(fkk::dev::launch_transform16(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt16, b->npad, b->kq,
-                                         b->d_bre16, b->d_bim16, dout, n, FKK_OUT_IM, s_comp));
+                                         b->d_bre16, b->d_bim16, dout, n, FKK_OUT_IM, s_comp, res));
     else
         chk(fkk::dev::launch_transform(din, rows, n, n, b->d_rinv, (float)b->ratio_floor, b->d_wt, b->npad, b->kp,
-                                       b->k, b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp));
+                                       b->k, b->d_bre_t, b->d_bim_t, dout, n, FKK_OUT_IM, s_comp, res));
+    chk(fkk::dev::launch_segment_sums(dnorm, doffs, nt, dsums, s_comp));
     chk(hipEventRecord(bt.computed, s_comp));
     chk(hipStreamWaitEvent(s_out, bt.computed, 0));
     r0 = 0;
@@ -173,6 +208,7 @@ bool fkk_server::issue(std::vector<Request>& reqs) {
                              n * sizeof(float), r.rows, hipMemcpyDeviceToHost, s_out));
         r0 += r.rows;
     }
+    chk(hipMemcpyAsync(hsums, dsums, 2 * (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, s_out));
     chk(hipEventRecord(bt.done, s_out));
     if (e != hipSuccess) error = e;
     ++launches;
@@ -196,13 +232,21 @@ void fkk_server::run() {
             if (q != hipSuccess) error = q;
             const auto now = Clock::now();
             Batch& bt = inflight[i];
-            for (auto& r : bt.reqs) {
+            const double* hsums = reinterpret_cast<const double*>(side + (size_t)bt.slot * slot_bytes +
+                                                                  (cfg.max_inflight + 1) * sizeof(long long));
+            for (size_t t = 0; t < bt.reqs.size(); ++t) {
+                const Request& r = bt.reqs[t];
                 const double lat = ms_between(r.t_submit, now);
+                const double sa = hsums[2 * t], sz = hsums[2 * t + 1];
+                const double res = sa > 0.0 ? std::sqrt(std::max(0.0, 1.0 - sz / sa)) : 0.0;
                 latencies.push_back(lat);
-                finished[r.ticket] = lat;
+                finished[r.ticket] = Finished{lat, res};
+                if (cfg.residual_threshold > 0.0 && res > cfg.residual_threshold) ++flagged;
+                max_residual = std::max(max_residual, res);
                 spectra += r.rows;
                 ++completed;
             }
+            free_slots.push_back(bt.slot);
             last_done = now;
             inflight_tiles -= (int)bt.reqs.size();
             arena.release(bt.off, bt.bytes);
@@ -257,7 +301,8 @@ void fkk_server::run() {
 extern "C" {
 
 fkk_status fkk_server_create(int device, const fkk_server_config* cfg, fkk_server** out) {
-    if (!cfg || !out || cfg->hbm_budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_batch_rows < 1)
+    if (!cfg || !out || cfg->hbm_budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 4096 ||
+        cfg->max_batch_rows < 1 || !(cfg->residual_threshold >= 0.0))
         return FKK_EINVAL;
     *out = nullptr;
     int count = 0;
@@ -277,6 +322,14 @@ fkk_status fkk_server_create(int device, const fkk_server_config* cfg, fkk_serve
         return FKK_ENOMEM;
     }
     s->arena.init((size_t)cfg->hbm_budget_bytes);
+    s->slot_bytes = (((size_t)cfg->max_inflight + 1) * sizeof(long long) + 2 * (size_t)cfg->max_inflight *
+                     sizeof(double) + 255) & ~size_t(255);
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->side), s->slot_bytes * cfg->max_inflight, hipHostMallocDefault) !=
+        hipSuccess) {
+        fkk_server_destroy(s);
+        return FKK_ENOMEM;
+    }
+    for (int i = cfg->max_inflight - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return FKK_OK;
@@ -326,7 +379,8 @@ fkk_status fkk_server_submit(fkk_server* srv, int32_t basis_id, const float* h_i
     return FKK_OK;
 }
 
-fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, double* latency_ms) {
+fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, double* latency_ms,
+                           double* residual) {
     if (!srv) return FKK_EINVAL;
     std::unique_lock<std::mutex> lk(srv->mu);
     auto ready = [&] { return srv->finished.count(ticket) > 0 || srv->error != hipSuccess; };
@@ -334,7 +388,9 @@ fkk_status fkk_server_wait(fkk_server* srv, int64_t ticket, double timeout_ms, d
     else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready))
         return FKK_EBUSY;
     if (srv->error != hipSuccess) return FKK_EDEVICE;
-    if (latency_ms) *latency_ms = srv->finished[ticket];
+    const Finished fin = srv->finished[ticket];
+    if (latency_ms) *latency_ms = fin.latency_ms;
+    if (residual) *residual = fin.residual;
     srv->finished.erase(ticket);
     return FKK_OK;
 }
@@ -358,6 +414,8 @@ fkk_status fkk_server_stats_get(fkk_server* srv, fkk_server_stats* st) {
     st->spectra = srv->spectra;
     st->launches = srv->launches;
     st->mean_batch_tiles = srv->launches ? (double)srv->batch_tiles / srv->launches : 0.0;
+    st->flagged = srv->flagged;
+    st->max_residual = srv->max_residual;
     if (!srv->latencies.empty()) {
         std::vector<double> l = srv->latencies;
         std::sort(l.begin(), l.end());
@@ -382,6 +440,8 @@ fkk_status fkk_server_reset_stats(fkk_server* srv) {
     srv->latencies.clear();
     srv->finished.clear();
     srv->submitted = srv->completed = srv->rejected = srv->spectra = srv->launches = srv->batch_tiles = 0;
+    srv->flagged = 0;
+    srv->max_residual = 0.0;
     srv->any_submit = false;
     return FKK_OK;
 }
@@ -399,6 +459,7 @@ void fkk_server_destroy(fkk_server* srv) {
     if (srv->s_comp) hipStreamSynchronize(srv->s_comp);
     if (srv->s_out) hipStreamSynchronize(srv->s_out);
     if (srv->arena_base) hipFree(srv->arena_base);
+    if (srv->side) hipHostFree(srv->side);
     if (srv->s_in) hipStreamDestroy(srv->s_in);
     if (srv->s_comp) hipStreamDestroy(srv->s_comp);
     if (srv->s_out) hipStreamDestroy(srv->s_out);
