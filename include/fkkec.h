@@ -316,6 +316,22 @@ fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const doub
 fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M, int64_t ld,
                               double* h_residual);
 
+/* fkk_basis_residual for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, with the per-block
+ * partial sums in a fixed device array of the library
+ * (FKK_NOALLOC_MAX_BLOCKS pairs of doubles, about 1 MiB, on every device the
+ * library runs on, held until the process ends), so the call allocates
+ * nothing.  M up to FKK_NOALLOC_MAX_SPECTRA (FKK_EINVAL beyond, before any
+ * launch).  All calls on one device share that array and it keeps the last
+ * call's contents: calls that overlap on one device (from several contexts
+ * or threads) race, and the caller must serialise them.  Synchronises the
+ * context's stream. */
+#define FKK_NOALLOC_MAX_BLOCKS 65536
+#define FKK_NOALLOC_MAX_SPECTRA (128LL * FKK_NOALLOC_MAX_BLOCKS)
+fkk_status fkk_basis_residual_noalloc(fkk_ctx* ctx, const fkk_basis* basis, const float* d_I, int64_t M,
+                                      int64_t ld, double* h_residual);
+
 /*
  * Projection and sub-sampling (Eq. 13-15): Z = A V_k = l diag(f) V_k for the
  * rows of d_I (M x N, stride ld) into d_z (M x k FP32, stride ld_z >= k), and

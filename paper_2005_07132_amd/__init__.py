@@ -97,6 +97,7 @@ SYMBOLS = [
     "fkk_ctx_last_error", "fkk_ctx_workspace_bytes", "fkk_workspace_size", "fkk_fit", "fkk_transform", "fkk_plain", "fkk_plain_f64",
     "fkk_gram",
     "fkk_eigh_topk", "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
+    "fkk_basis_residual_noalloc",
     "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_free", "fkk_basis_set_precision",
     "fkk_basis_get_precision", "fkk_server_create", "fkk_server_add_basis",
     "fkk_server_submit", "fkk_server_wait", "fkk_server_drain", "fkk_server_stats_get", "fkk_server_reset_stats",
@@ -136,6 +137,7 @@ def lib() -> ctypes.CDLL:
                                          _c_double_p, i32, ctypes.POINTER(Params), ctypes.POINTER(vp)]
     L.fkk_project.argtypes = [vp, vp, vp, i64, i64, vp, i64, _c_int64_p, _c_int64_p]
     L.fkk_basis_residual.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
+    L.fkk_basis_residual_noalloc.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
     L.fkk_reconstruct.argtypes = [vp, vp, vp, i64, i64, vp, i64, i32]
     L.fkk_basis_import.argtypes = [vp, ctypes.POINTER(BasisDesc), ctypes.POINTER(vp)]
     L.fkk_basis_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -158,6 +160,7 @@ def lib() -> ctypes.CDLL:
                  "fkk_gram", "fkk_basis_free",
                  "fkk_eigh_topk",
                  "fkk_basis_from_factors", "fkk_project", "fkk_reconstruct", "fkk_basis_residual",
+                 "fkk_basis_residual_noalloc",
                  "fkk_basis_import", "fkk_basis_info", "fkk_basis_export", "fkk_basis_set_precision",
                  "fkk_basis_get_precision"):
         getattr(L, name).restype = ctypes.c_int
@@ -487,6 +490,15 @@ class Context:
         r = ctypes.c_double()
         st = lib().fkk_basis_residual(self._h, basis.handle, I.data_ptr(), m, I.stride(0), ctypes.byref(r))
         self._ok(st, "basis_residual")
+        return r.value
+
+    def residual_noalloc(self, basis: Basis, I) -> float:
+        """residual() with the library's fixed scratch array: no allocation."""
+        _check_tensor(I, "I")
+        m, _ = I.shape
+        r = ctypes.c_double()
+        st = lib().fkk_basis_residual_noalloc(self._h, basis.handle, I.data_ptr(), m, I.stride(0), ctypes.byref(r))
+        self._ok(st, "basis_residual_noalloc")
         return r.value
 
     def reconstruct(self, basis: Basis, z, plane: int = OUT_IM, out=None):

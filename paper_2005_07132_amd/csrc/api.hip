@@ -13,6 +13,7 @@
 #include <cfloat>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -124,6 +125,36 @@ struct Carve {
 
 }  // namespace
 
+// Fixed device array of fkk_basis_residual_noalloc: the per-block partial
+// sums (two doubles per block of 128 spectra) and their total.  Every device
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses this name as an address: the address on each device comes from
+// hipGetSymbolAddress (scratch_address).
+constexpr size_t kScratchDoubles = 2 * (size_t)FKK_NOALLOC_MAX_BLOCKS + 2;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Address of `scratch` on `device` (current), looked up once per device.
+hipError_t scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = p;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+
+}  // namespace
+
 struct fkk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -146,6 +177,7 @@ struct fkk_ctx {
     hipGraphExec_t tri_exec = nullptr;
     int tri_n = 0;
     const double* tri_key[2] = {nullptr, nullptr};
+    void* scratch = nullptr;  // this device's copy of the library's fixed array
 
     hipError_t events() {
         for (auto& e : ev)
@@ -853,9 +885,12 @@ fkk_status fkk_ctx_create(int device, void* hip_stream, fkk_ctx** out) {
     if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return FKK_EDEVICE;
     if (device < 0 || device >= count) return FKK_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return FKK_EDEVICE;
+    void* scr = nullptr;
+    if (scratch_address(device, &scr) != hipSuccess) return FKK_EDEVICE;
     fkk_ctx* c = new fkk_ctx;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->scratch = scr;
     const char* ng = std::getenv("FKK_NO_GRAPHS");
     c->graphs = !(ng && ng[0] == '1');
     const char* nr = std::getenv("FKK_NO_RESIDENT_TRIDIAG");
@@ -921,8 +956,8 @@ fkk_status fkk_eigh_topk(const double* h_a, int32_t N, int32_t k, double* h_eval
 fkk_status fkk_basis_from_factors(fkk_ctx* ctx, int32_t N, int32_t k, const double* h_iref, const double* h_f,
                                   const double* h_s, const double* h_v, const double* h_x, int32_t n_q,
                                   const fkk_params* p, fkk_basis** out_basis) {
-    fkk_ctx scratch;  // error sink when ctx is NULL (host-only basis)
-    fkk_ctx* c = ctx ? ctx : &scratch;
+    fkk_ctx sink;  // error sink when ctx is NULL (host-only basis)
+    fkk_ctx* c = ctx ? ctx : &sink;
     if (!out_basis || !h_iref || !h_f || !h_s || !h_v || !h_x || n_q < 1 || N < 4)
         return c->fail(FKK_EINVAL, "NULL argument or bad size");
     *out_basis = nullptr;
@@ -1278,6 +1313,20 @@ fkk_status fkk_basis_residual(fkk_ctx* ctx, const fkk_basis* b, const float* d_I
     const size_t need = (2 * (size_t)fkk::dev::proj_blocks(M) + 2) * sizeof(double);
     if ((st = acquire_ws(ctx, nullptr, 0, need, &base)) != FKK_OK) return st;
     return residual_device(ctx, b, d_I, M, ld, static_cast<double*>(base), h_residual);
+}
+
+fkk_status fkk_basis_residual_noalloc(fkk_ctx* ctx, const fkk_basis* b, const float* d_I, int64_t M, int64_t ld,
+                                      double* h_residual) {
+    if (!ctx) return FKK_EINVAL;
+    fkk_status st;
+    if ((st = check_residual_args(ctx, b, d_I, M, ld, h_residual)) != FKK_OK) return st;
+    if (M > FKK_NOALLOC_MAX_SPECTRA)
+        return ctx->fail(FKK_EINVAL, "M=%lld above the %lld spectra of the fixed scratch array", (long long)M,
+                         (long long)FKK_NOALLOC_MAX_SPECTRA);
+    if (!ctx->scratch) return ctx->fail(FKK_EDEVICE, "no scratch address for device %d", ctx->device);
+    FKK_HIP(ctx, hipSetDevice(ctx->device));
+    // the kernels write every partial and the total: nothing to clear
+    return residual_device(ctx, b, d_I, M, ld, static_cast<double*>(ctx->scratch), h_residual);
 }
 
 fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, int64_t M, int64_t ld_z,
