@@ -76,8 +76,17 @@ enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
  * the tail of the Gram's spectrum (eigenvalue gaps of ~1e-9 of the largest
  * on tissue cubes) then moves the retained subspace, and with it the
  * sub-sampled rows of Eq. 13-15, only by the FP32 rounding of the log ratio.
+ * SPLIT (Gram only) reaches FP64 accuracy on the int8 matrix cores: the log
+ * ratio is computed in FP64, scaled per column by a power of two and cut
+ * into four int8 slices (an error-free splitting, Ozaki et al. 2012, of 27
+ * bits below the column's largest |l|), the slice products of levels up to
+ * 2^-21 are summed exactly in int32 and recombined exactly in FP64 per row
+ * chunk, and the chunks summed in FP64: the Gram then differs from the
+ * exact Gram of the FP64 log ratio by at most about 2^-27 of the columns'
+ * largest entries per product, below the FP32 rounding of the log ratio
+ * that the FP64 mode keeps.
  * The eigensolve and the basis-vector KK / PEC / SEC are FP64 always. */
-enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2 };
+enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2, FKK_PREC_SPLIT = 3 };
 /* Route of the truncated SVD (Eq. 6) in fkk_fit. */
 enum { FKK_SVD_GRAM = 0, FKK_SVD_RANDOMIZED = 1 };
 
@@ -109,7 +118,8 @@ typedef struct {
     double ml_lambda;      /* Eq. 25 ridge weight of the stored basis      */
     double ratio_floor;    /* ratios I/I_ref not above it are clamped      */
     int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
-    int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6), FP64 allowed */
+    int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6), FP64 and SPLIT
+                              allowed                                      */
     int32_t recon_prec;    /* FKK_PREC_FP32 / _BF16 of the projection
                               (Eq. 13) and the reconstruction (Eq. 23);
                               stored in the basis and used by its later

@@ -26,7 +26,7 @@ SEC_SAVGOL, SEC_MEAN = 0, 1
 PAD_EDGE, PAD_ZERO = 0, 1
 F_ONE, F_NOISE = 0, 1
 OUT_IM, OUT_RE, OUT_ABS = 0, 1, 2
-PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP64, PREC_SPLIT = 0, 1, 2, 3
 SVD_GRAM, SVD_RANDOMIZED = 0, 1
 TRIDIAG_NONE, TRIDIAG_RESIDENT, TRIDIAG_PER_COLUMN = 0, 1, 2
 SEC_FORM_LOG, SEC_FORM_RE = 0, 1
@@ -628,4 +628,4 @@ class Server:
 __all__ = ["Server", "Context", "Basis", "Params", "params", "eigh_topk", "basis_from_factors", "lib", "FkkError",
            "workspace_size", "close_all", "OP_FIT", "OP_TRANSFORM", "OP_PLAIN",
            "SYMBOLS", "LIB_PATH", "PREC_FP32", "PREC_BF16",
-           "PREC_FP64", "SVD_GRAM", "SVD_RANDOMIZED", "SEC_FORM_LOG", "SEC_FORM_RE"]
+           "PREC_FP64", "PREC_SPLIT", "SVD_GRAM", "SVD_RANDOMIZED", "SEC_FORM_LOG", "SEC_FORM_RE"]

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfkkec.so")
 ARCH = os.environ.get("FKK_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["api.hip", "kernels.hip", "kernels_bf16.hip", "plain.hip", "eig.hip", "serve.hip"]
+HIP_SOURCES = ["api.hip", "kernels.hip", "kernels_bf16.hip", "kernels_i8.hip", "plain.hip", "eig.hip", "serve.hip"]
 HOST_SOURCES = ["host_math.cpp"]
 
 # Packed FP32 instructions stay off: the compiler must not form them.

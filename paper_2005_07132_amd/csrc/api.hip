@@ -84,7 +84,7 @@ void split_reciprocal(const double* iref, int N, float* out) {
 }
 
 bool valid_prec(int p) { return p == FKK_PREC_FP32 || p == FKK_PREC_BF16; }
-bool valid_gram_prec(int p) { return valid_prec(p) || p == FKK_PREC_FP64; }
+bool valid_gram_prec(int p) { return valid_prec(p) || p == FKK_PREC_FP64 || p == FKK_PREC_SPLIT; }
 
 // Nearest-even BF16 bit pattern of a finite float.
 uint16_t to_bf16(float x) {
@@ -426,14 +426,21 @@ struct GramWs {
     unsigned long long* clamps = nullptr;
     int* tiles = nullptr;                // tile pairs
     float* rinv = nullptr;               // 1/I_ref as two floats per wavenumber
+    // FKK_PREC_SPLIT only (L then holds the int8 slices)
+    float* colmax = nullptr;             // per-block max |l|
+    int* colexp = nullptr;               // column exponents (npad)
+    double* rinv64 = nullptr;            // 1/I_ref (N)
 };
 
 void gram_layout(Carve& c, int64_t M, int N, int prec, bool with_gram, bool rrf, GramWs* w) {
     const int npad = npad_for(N), nb = npad / fkk::dev::kGramTile;
-    const bool bf16 = (prec == FKK_PREC_BF16);
-    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
+    const bool bf16 = (prec == FKK_PREC_BF16), split = (prec == FKK_PREC_SPLIT);
+    const fkk::dev::GramPlan plan =
+        split ? fkk::dev::split_gram_plan(M, N) : fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
     const fkk::dev::GramPlan pr = fkk::dev::gram_plan(M, N, 64, 32);
-    w->L = c.take<float>(bf16 ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4 : (size_t)M * npad);
+    w->L = c.take<float>(bf16    ? (fkk::dev::logratio16_bytes(M, npad) + 3) / 4
+                         : split ? fkk::dev::split_bytes(M, npad) / 4
+                                 : (size_t)M * npad);
     size_t part = 0, g = 0, tiles = 0;
     if (with_gram) {
         part = plan.partial_doubles();
@@ -451,6 +458,11 @@ void gram_layout(Carve& c, int64_t M, int N, int prec, bool with_gram, bool rrf,
     w->clamps = c.take<unsigned long long>(1);
     w->tiles = c.take<int>(tiles);
     w->rinv = c.take<float>(2 * (size_t)N);
+    if (split) {
+        w->colmax = c.take<float>(fkk::dev::stats_colmax_floats(M, npad));
+        w->colexp = c.take<int>(npad);
+        w->rinv64 = c.take<double>(N);
+    }
 }
 
 // Everything fkk_fit uses on the device, in one region.
@@ -541,8 +553,9 @@ fkk_status acquire_ws(fkk_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, vo
 fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t M, int N, int64_t ld,
                        const double* h_iref, double floor, int prec, bool timed, bool with_gram = true) {
     const int npad = npad_for(N);
-    const bool bf16 = (prec == FKK_PREC_BF16);
-    const fkk::dev::GramPlan plan = fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
+    const bool bf16 = (prec == FKK_PREC_BF16), split = (prec == FKK_PREC_SPLIT) && with_gram;
+    const fkk::dev::GramPlan plan =
+        split ? fkk::dev::split_gram_plan(M, N) : fkk::dev::gram_plan(M, N, 64, bf16 ? 64 : 32);
     std::vector<int> pairs(2 * plan.tiles);
     fkk::dev::gram_tile_list(plan.nb, pairs.data());
     std::vector<float> rinv(2 * (size_t)N);
@@ -553,6 +566,25 @@ fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t 
         FKK_HIP(ctx, hipMemcpyAsync(w.tiles, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemcpyAsync(w.rinv, rinv.data(), rinv.size() * sizeof(float), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemsetAsync(w.clamps, 0, sizeof(unsigned long long), s));
+    if (split) {
+        // column statistics, exponents and the int8 slices of the FP64 log
+        // ratio; then the Gram on the int8 matrix cores
+        std::vector<double> r64(N);
+        for (int j = 0; j < N; ++j) r64[j] = 1.0 / h_iref[j];
+        FKK_HIP(ctx, hipMemcpyAsync(w.rinv64, r64.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+        const int64_t nst = fkk::dev::stats_blocks(M);
+        if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
+        FKK_HIP(ctx, fkk::dev::launch_split_stats(d_I, M, N, ld, w.rinv, (float)floor, npad, w.colsum_part, w.colmax,
+                                                  w.clamps, w.colexp, s));
+        FKK_HIP(ctx, fkk::dev::launch_split_slices(d_I, M, N, ld, w.rinv64, floor, w.colexp, npad, w.L, s));
+        if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
+        if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+        FKK_HIP(ctx, fkk::dev::launch_gram_split(w.L, npad, M, plan, w.tiles, w.colexp, w.partial, s));
+        if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+        FKK_HIP(ctx, fkk::dev::launch_gram_reduce(w.partial, plan, w.tiles, N, w.G, s));
+        FKK_HIP(ctx, fkk::dev::launch_colsum_reduce(w.colsum_part, nst, npad, N, w.colsum + N, w.colsum, s));
+        return FKK_OK;
+    }
     if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
     uint16_t* lp16 = reinterpret_cast<uint16_t*>(w.L);
     if (bf16)
@@ -1099,7 +1131,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
         if (pbf16)  // log ratio recomputed from I
             perr = fkk::dev::launch_project16(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt16, b->npad, kq,
                                               kp, w.Z, kp, part, k, s);
-        else if (gprec == FKK_PREC_BF16)  // w.g.L holds the packed BF16 l: start from I
+        else if (gprec == FKK_PREC_BF16 || gprec == FKK_PREC_SPLIT)  // w.g.L holds no FP32 l: start from I
             perr = fkk::dev::launch_project(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
                                             w.Z, kp, part, k, s, false);
         else  // the FP32 l of the Gram pass

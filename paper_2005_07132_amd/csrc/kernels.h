@@ -143,6 +143,26 @@ hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, cons
                               float* out, int64_t ld_out, int plane, hipStream_t s,
                               const ResidualArgs& res = ResidualArgs{});
 
+// ---- Gram to FP64 accuracy on the int8 matrix cores (error-free splitting)
+// stats: FP64 column sums of I (stats_blocks(M) x npad partials, reduced by
+// launch_colsum_reduce), the clamp count, per-block max |l| (colmax_part,
+// stats_colmax_floats(M, npad) floats) and the column exponents colexp (npad ints).
+int64_t stats_blocks(int64_t M);
+size_t stats_colmax_floats(int64_t M, int npad);  // colmax_part: partials and group maxima
+hipError_t launch_split_stats(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
+                              double* colsum_part, float* colmax_part, unsigned long long* clamps, int* colexp,
+                              hipStream_t s);
+// slices of the FP64 log ratio (rinv64: 1/I_ref, N doubles) into S,
+// split_bytes(M, npad) bytes (rows padded to a multiple of 64 with zeros).
+size_t split_bytes(int64_t M, int npad);
+hipError_t launch_split_slices(const float* I, int64_t M, int N, int64_t ld, const double* rinv64, double floor,
+                               const int* colexp, int npad, void* S, hipStream_t s);
+// chunk partials of the Gram from the slices (plan from split_gram_plan),
+// reduced by launch_gram_reduce.
+GramPlan split_gram_plan(int64_t M, int N);
+hipError_t launch_gram_split(const void* S, int npad, int64_t M, const GramPlan& plan, const int* d_tiles,
+                             const int* colexp, double* partial, hipStream_t s);
+
 // Gather rows q of a row-major FP32 matrix Z (k columns, row stride ld_z)
 // into X (n_q x k).
 hipError_t launch_gather_rows(const float* Z, int64_t ld_z, int k, const long long* q, int n_q, float* X,

@@ -1,0 +1,417 @@
+// Gram of the log ratio (Eq. 6) to FP64 accuracy on the int8 matrix cores:
+// error-free splitting of the operands (Ozaki, Ogita, Oishi & Rump 2012;
+// for integer matrix units, Ootomo, Ozaki & Yokota 2024).
+//
+//   stats:  column sums of I (FP64), clamp count and max |l| per column
+//           (FP32 log ratio), one pass over I.
+//   exps:   e_j with max_j |l_j| < 2^e_j (with a margin for the FP64 l).
+//   slices: l = 1/2 ln(I / I_ref) in FP64 (log_cells), x = l 2^-e_j in
+//           (-1, 1), X = rint(x 2^27) cut into balanced base-128 digits:
+//               x = 2^-6 (a1 + 2^-7 a2 + 2^-14 a3 + 2^-21 a4) + d,
+//           a2..a4 in [-64, 63], |a1| <= 64, |d| <= 2^-28.
+//   gram:   for each 128 x 128 tile (two blocks of 128 x 64) and row chunk,
+//           the int8 products S_i^T S_j summed exactly in int32, grouped by
+//           level t = i + j, t = 2..6 (13 products), and
+//           G_chunk = 2^(e_a + e_b - 12) sum_t 2^(-7 (t - 2)) C_t, exact in
+//           FP64 (54 significant bits at most, see the flush), into the
+//           chunk partials that the FP32 path reduces.  Level 6 holds the
+//           (3, 3) product, which is never negative on the diagonal: dropping
+//           it would bias G_aa by ~2^-40 E[a3^2] per row.  The dropped levels
+//           7 and 8 are products of different digits (zero mean) and (4, 4)
+//           (~2^-54 per row).
+//
+// Slices are stored row-group major, slice-major within a row group:
+// S[g][s][j] is a 16-byte unit holding rows 16 g .. 16 g + 15 of column j,
+// slice s.  v_mfma_i32_16x16x64_i8: lane l holds A[l%16][16 (l/16) + q]
+// and B[16 (l/16) + q][l%16] (q = byte 0..15) and receives
+// D[4 (l/16) + v][l%16] in element v (measured with a one-wave probe).
+#include "kernels.h"
+#include "device_common.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+namespace fkk {
+namespace dev {
+
+namespace {
+
+typedef int8_t i8x16 __attribute__((ext_vector_type(16)));
+typedef int int32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int ST_ROWS = 256;  // rows per stats block
+constexpr int GT = kGramTile;
+constexpr int I8_THREADS = 512;  // 8 waves: 4 (a) x 2 (b), 32 x 32 of the half tile each
+constexpr int HB = GT / 2;       // b columns of a block (half a tile)
+constexpr int KROWS = 64;        // rows per K step (4 row groups)
+
+// ---------------------------------------------------------------------------
+// stats: column sums of I, clamp count, per-block max |l| (FP32 log ratio)
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(256) void stats_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                    const float* __restrict__ rinv, float floor, int npad,
+                                                    double* __restrict__ colsum_part, float* __restrict__ colmax_part,
+                                                    unsigned long long* __restrict__ clamps) {
+    const int64_t r0 = (int64_t)blockIdx.x * ST_ROWS;
+    const int64_t r1 = (r0 + ST_ROWS < M) ? r0 + ST_ROWS : M;
+    unsigned int cnt = 0;
+    for (int g0 = 0; g0 < npad; g0 += 1024) {
+        const int c = g0 + 4 * (int)threadIdx.x;
+        if (c >= npad) continue;
+        float r[4], rl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            r[q] = (c + q < N) ? rinv[c + q] : 0.f;
+            rl[q] = (c + q < N) ? rinv[N + c + q] : 0.f;
+        }
+        double cs[4] = {0.0, 0.0, 0.0, 0.0};
+        float mx[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int64_t row0 = r0; row0 < r1; row0 += 4) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = (row0 + u < r1) ? load4_guarded(I + (row0 + u) * ld, c, N, VEC) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (row0 + u >= r1) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (c + q >= N) continue;
+                    bool bad;
+                    const float xv = f4get(x[u], q);
+                    const float l = log_ratio(xv, r[q], rl[q], floor, bad);
+                    cnt += bad ? 1u : 0u;
+                    cs[q] += (double)xv;
+                    mx[q] = fmaxf(mx[q], fabsf(l));
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            colsum_part[(size_t)blockIdx.x * npad + c + q] = cs[q];
+            colmax_part[(size_t)blockIdx.x * npad + c + q] = mx[q];
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(clamps, (unsigned long long)cnt);
+}
+
+// Column maxima over the per-block partials in two steps: colmax_group_kernel
+// takes the max over part groups (grid.y of them) for 64 columns per block,
+// colexp_kernel the max over the groups and the exponent e_j with
+// |l_j| < 2^e_j over all rows, from the FP32 maximum with room for the FP64
+// log ratio (within 2^-21 relative + 2^-24 absolute of the FP32 one).
+constexpr int kMaxGroups = 32;
+__global__ __launch_bounds__(256) void colmax_group_kernel(const float* __restrict__ colmax_part, int64_t nparts,
+                                                           int npad, float* __restrict__ gmax) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), sub = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)gridDim.y * 4;
+    float m = 0.f;
+    if (c < npad)
+        for (int64_t b = (int64_t)blockIdx.y * 4 + sub; b < nparts; b += stride)
+            m = fmaxf(m, colmax_part[(size_t)b * npad + c]);
+    red[sub][threadIdx.x & 63] = m;
+    __syncthreads();
+    if (sub == 0 && c < npad) {
+        m = fmaxf(fmaxf(red[0][threadIdx.x], red[1][threadIdx.x]), fmaxf(red[2][threadIdx.x], red[3][threadIdx.x]));
+        gmax[(size_t)blockIdx.y * npad + c] = m;
+    }
+}
+
+__global__ void colexp_kernel(const float* __restrict__ gmax, int groups, int npad, int N, int* __restrict__ colexp) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= npad) return;
+    float m = 0.f;
+    if (j < N)
+        for (int g = 0; g < groups; ++g) m = fmaxf(m, gmax[(size_t)g * npad + j]);
+    const double bound = (double)m * (1.0 + 0x1p-16) + 0x1p-20;
+    int e;
+    frexp(bound, &e);  // bound = f 2^e, 1/2 <= f < 1, so bound < 2^e
+    colexp[j] = e;
+}
+
+// ---------------------------------------------------------------------------
+// slices: one thread per (row group, column)
+// ---------------------------------------------------------------------------
+// ln q in FP64 for q > 0 (finite): q = mant 2^k, mant in [1/2, 1); mant =
+// c (1 + u) with c the centre of mant's 1/64-wide cell (tab: 1/c, ln c), so
+// |u| <= 1/64 and ln(1 + u) = u - u^2/2 + ... + u^7/7 leaves below 2^-45.
+__device__ __forceinline__ double log_cells(double q, const double* tab) {
+    int k;
+    const double mant = frexp(q, &k);
+    const int i = (int)((mant - 0.5) * 64.0);  // 0..31
+    const double u = fma(mant, tab[2 * i], -1.0);
+    double p = fma(u, 1.0 / 7.0, -1.0 / 6.0);
+    p = fma(u, p, 0.2);
+    p = fma(u, p, -0.25);
+    p = fma(u, p, 1.0 / 3.0);
+    p = fma(u, p, -0.5);
+    p = fma(u, p, 1.0);
+    return fma((double)k, 0.69314718055994530942, fma(u, p, tab[2 * i + 1]));
+}
+
+__global__ __launch_bounds__(256) void slice_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                    const double* __restrict__ rinv64, double floor,
+                                                    const int* __restrict__ colexp, int npad,
+                                                    u32x4v* __restrict__ S) {
+    __shared__ double tab[64];
+    if (threadIdx.x < 32) {
+        const double c = 0.5 + (threadIdx.x + 0.5) / 64.0;
+        tab[2 * threadIdx.x] = 1.0 / c;
+        tab[2 * threadIdx.x + 1] = log(c);
+    }
+    __syncthreads();
+    const int64_t g = blockIdx.x;
+    const int j = blockIdx.y * 256 + threadIdx.x;
+    if (j >= npad) return;
+    unsigned int w[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[s][u] = 0u;
+    if (j < N) {
+        const double r = rinv64[j];
+        // X = rint(x 2^27) with x = l 2^-e and l = ln(q) / 2: |X| < 2^27
+        const double scale = ldexp(0.5, 27 - colexp[j]);
+        float xs[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t m = 16 * g + q;
+            xs[q] = (m < M) ? I[m * ld + j] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t m = 16 * g + q;
+            int X = 0;
+            if (m < M) {
+                double ratio = (double)xs[q] * r;
+                if (!(ratio > floor) || !(ratio < INFINITY)) ratio = floor;
+                X = (int)rint(log_cells(ratio, tab) * scale);
+            }
+            // balanced base-128 digits: X = a1 2^21 + a2 2^14 + a3 2^7 + a4,
+            // a2..a4 in [-64, 63], |a1| <= 64
+            const int a4 = ((X + 64) & 127) - 64;
+            X = (X - a4) >> 7;
+            const int a3 = ((X + 64) & 127) - 64;
+            X = (X - a3) >> 7;
+            const int a2 = ((X + 64) & 127) - 64;
+            const int a1 = (X - a2) >> 7;
+            const int sh = 8 * (q & 3), u = q >> 2;
+            w[0][u] |= ((unsigned)a1 & 0xffu) << sh;
+            w[1][u] |= ((unsigned)a2 & 0xffu) << sh;
+            w[2][u] |= ((unsigned)a3 & 0xffu) << sh;
+            w[3][u] |= ((unsigned)a4 & 0xffu) << sh;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) S[(g * 4 + s) * npad + j] = u32x4v{w[s][0], w[s][1], w[s][2], w[s][3]};
+}
+
+// ---------------------------------------------------------------------------
+// gram: 128 x 128 tiles, 64-row K steps staged in LDS as sX[slice][row
+// group][column] (16-byte units), double-buffered
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32x4 mfma_i8(const u32x4v& a, const u32x4v& b, int32x4 c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i8x16, a), __builtin_bit_cast(i8x16, b), c, 0,
+                                                 0, 0);
+}
+
+__global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __restrict__ S, int npad, int64_t M,
+                                                             int T, int64_t rpc, const int* __restrict__ tiles,
+                                                             const int* __restrict__ colexp,
+                                                             double* __restrict__ partial) {
+    // [buffer][slice 4][row group 4][column]: a strip (128 columns), b strip (64)
+    __shared__ u32x4v sa[2][4 * 4 * GT];
+    __shared__ u32x4v sb[2][4 * 4 * HB];
+
+    // blockIdx -> (chunk, tile, half): consecutive blocks go to different
+    // XCDs, so the 8 XCDs each take every 8th chunk and run all tiles of it
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int rr = b >> 3;
+    const int th = rr % (2 * T);
+    const int tile = th >> 1, half = th & 1;
+    const int chunk = (rr / (2 * T)) * 8 + xcd;
+    const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
+    const int cb0 = bj * GT + half * HB;  // first b column of the block
+    const int64_t m0 = (int64_t)chunk * rpc;
+    const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
+    const int64_t nst = (m1 > m0) ? (m1 - m0 + KROWS - 1) / KROWS : 0;  // zero rows past M in the slices
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;  // a columns 32 wr.., b columns 32 wc.. of the block
+
+    // staging: a strip units u = tid + 512 p (p < 4): row group u / 512,
+    // slice (u / 128) % 4, column u % 128; b strip units u = tid + 512 p
+    // (p < 2): row group u / 256, slice (u / 64) % 4, column u % 64
+    u32x4v xa[4], xb[2];
+    auto load = [&](int64_t step) {
+        const int64_t g0 = (m0 + step * KROWS) / 16;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int u = tid + I8_THREADS * p;
+            const int rg = u >> 9, s = (u >> 7) & 3, col = u & 127;
+            xa[p] = S[((size_t)(g0 + rg) * 4 + s) * npad + bi * GT + col];
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int u = tid + I8_THREADS * p;
+            const int rg = u >> 8, s = (u >> 6) & 3, col = u & 63;
+            xb[p] = S[((size_t)(g0 + rg) * 4 + s) * npad + cb0 + col];
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int u = tid + I8_THREADS * p;
+            const int rg = u >> 9, s = (u >> 7) & 3, col = u & 127;
+            sa[buf][(s * 4 + rg) * GT + col] = xa[p];
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int u = tid + I8_THREADS * p;
+            const int rg = u >> 8, s = (u >> 6) & 3, col = u & 63;
+            sb[buf][(s * 4 + rg) * HB + col] = xb[p];
+        }
+    };
+
+    // acc[level t - 2][ti][tj]: (16 x 16) blocks
+    int32x4 acc[5][2][2];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[t][i][j] = int32x4{0, 0, 0, 0};
+
+    if (nst > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const int buf = (int)(st & 1);
+        if (st + 1 < nst) load(st + 1);
+        const u32x4v* A = sa[buf];
+        const u32x4v* B = sb[buf];
+        u32x4v bv[4][2];  // [slice][tj]
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[s][j] = B[(s * 4 + (lane >> 4)) * HB + wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            u32x4v av[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s] = A[(s * 4 + (lane >> 4)) * GT + wr * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // level t = s_a + s_b (slices counted from 1), t <= 6
+                acc[0][i][j] = mfma_i8(av[0], bv[0][j], acc[0][i][j]);
+                acc[1][i][j] = mfma_i8(av[0], bv[1][j], acc[1][i][j]);
+                acc[1][i][j] = mfma_i8(av[1], bv[0][j], acc[1][i][j]);
+                acc[2][i][j] = mfma_i8(av[0], bv[2][j], acc[2][i][j]);
+                acc[2][i][j] = mfma_i8(av[1], bv[1][j], acc[2][i][j]);
+                acc[2][i][j] = mfma_i8(av[2], bv[0][j], acc[2][i][j]);
+                acc[3][i][j] = mfma_i8(av[0], bv[3][j], acc[3][i][j]);
+                acc[3][i][j] = mfma_i8(av[1], bv[2][j], acc[3][i][j]);
+                acc[3][i][j] = mfma_i8(av[2], bv[1][j], acc[3][i][j]);
+                acc[3][i][j] = mfma_i8(av[3], bv[0][j], acc[3][i][j]);
+                acc[4][i][j] = mfma_i8(av[1], bv[3][j], acc[4][i][j]);
+                acc[4][i][j] = mfma_i8(av[2], bv[2][j], acc[4][i][j]);
+                acc[4][i][j] = mfma_i8(av[3], bv[1][j], acc[4][i][j]);
+            }
+        }
+        if (st + 1 < nst) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Flush: |C_t| <= (t - 1) 2^12 rpc <= 2^30, so sum_t 2^(-7 (t-2)) C_t
+    // spans bits 2^30 .. 2^-28: the two halves below are exact in FP64 and
+    // their sum rounds once.
+    double* P = partial + ((size_t)chunk * T + tile) * (size_t)(GT * GT);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+                const int c = half * HB + wc * 32 + j * 16 + (lane & 15);
+                const double hi = (double)acc[0][i][j][v] + 0x1p-7 * (double)acc[1][i][j][v];
+                const double lo = 0x1p-14 * (double)acc[2][i][j][v] + 0x1p-21 * (double)acc[3][i][j][v] +
+                                  0x1p-28 * (double)acc[4][i][j][v];
+                P[r * GT + c] = ldexp(hi + lo, colexp[bi * GT + r] + colexp[bj * GT + c] - 12);
+            }
+}
+
+}  // namespace
+
+int64_t stats_blocks(int64_t M) { return (M + ST_ROWS - 1) / ST_ROWS; }
+
+size_t stats_colmax_floats(int64_t M, int npad) { return (size_t)(stats_blocks(M) + kMaxGroups) * npad; }
+
+size_t split_bytes(int64_t M, int npad) { return (size_t)((M + KROWS - 1) / KROWS) * KROWS * (size_t)npad * 4; }
+
+GramPlan split_gram_plan(int64_t M, int N) {
+    // int32 levels stay exact while a chunk has at most 2^31 / (4 * 64 * 64)
+    // = 131,072 rows: chunks of at most 65,536
+    GramPlan p = gram_plan(M, N, 64, KROWS);
+    if (p.rows_per_chunk > 65536) p = gram_plan(M, N, (int)((M + 65535) / 65536), KROWS);
+    return p;
+}
+
+hipError_t launch_split_stats(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
+                              double* colsum_part, float* colmax_part, unsigned long long* clamps, int* colexp,
+                              hipStream_t s) {
+    if (npad % 4 != 0 || npad < N) return hipErrorInvalidValue;
+    const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    const int64_t nb = stats_blocks(M);
+    if (vec)
+        hipLaunchKernelGGL(stats_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor, npad,
+                           colsum_part, colmax_part, clamps);
+    else
+        hipLaunchKernelGGL(stats_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor, npad,
+                           colsum_part, colmax_part, clamps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // group maxima overwrite the first rows of the partials after reading
+    // them all: they go to the rows past the last partial instead
+    float* gmax = colmax_part + (size_t)nb * npad;
+    const int groups = (int)std::min<int64_t>(kMaxGroups, (nb + 3) / 4);
+    hipLaunchKernelGGL(colmax_group_kernel, dim3((unsigned)((npad + 63) / 64), (unsigned)groups), dim3(256), 0, s,
+                       colmax_part, nb, npad, gmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, gmax, groups, npad, N,
+                       colexp);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_slices(const float* I, int64_t M, int N, int64_t ld, const double* rinv64, double floor,
+                               const int* colexp, int npad, void* S, hipStream_t s) {
+    if (npad % 256 != 0 && npad % 128 != 0) return hipErrorInvalidValue;
+    const int64_t groups = (M + KROWS - 1) / KROWS * (KROWS / 16);
+    dim3 grid((unsigned)groups, (unsigned)((npad + 255) / 256));
+    hipLaunchKernelGGL(slice_kernel, grid, dim3(256), 0, s, I, M, N, ld, rinv64, floor, colexp, npad,
+                       static_cast<u32x4v*>(S));
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_split(const void* S, int npad, int64_t M, const GramPlan& plan, const int* d_tiles,
+                             const int* colexp, double* partial, hipStream_t s) {
+    if (plan.tiles < 1 || plan.chunks < 1 || M < 1 || plan.rows_per_chunk % KROWS != 0 ||
+        plan.rows_per_chunk > 65536 || plan.nb * GT > npad)
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)(2 * plan.tiles * plan.chunks)), block(I8_THREADS);
+    hipLaunchKernelGGL(gram_i8_kernel, grid, block, 0, s, static_cast<const u32x4v*>(S), npad, M, plan.tiles,
+                       plan.rows_per_chunk, d_tiles, colexp, partial);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace fkk

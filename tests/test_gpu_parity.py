@@ -93,6 +93,69 @@ def test_gram_matches_oracle(ctx, m, n, ld_pad):
     assert clamps == bad == 0
 
 
+def _split_exponents(ell):
+    """e_j with max |l_j| < 2^e_j (the library's rule, with its margin)."""
+    mx = np.abs(ell).max(axis=0) * (1 + 2.0 ** -16) + 2.0 ** -20
+    return np.frexp(mx)[1].astype(np.float64)
+
+
+@pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3), (130000, 64, 0)])
+def test_gram_split_matches_oracle(ctx, m, n, ld_pad):
+    # int8 splitting of the FP64 log ratio: against the exact Gram of the FP64
+    # log ratio of the same FP32 input, element-wise within the splitting's
+    # bound, and closer to it than the FP64 matrix cores on the FP32 log ratio
+    say(f"gram split m={m} n={n} ld_pad={ld_pad}")
+    cube = synth.tissue_cube(rows=max(1, m // 1000), cols=1000, m=m, n=n, blur=1.0) if m > 50000 else \
+        synth.tissue_cube(rows=1, cols=m, n=n, blur=1.0)
+    data = cube.i_cars
+    if ld_pad:
+        full = np.zeros((m, n + ld_pad), dtype=np.float32)
+        full[:, :n] = data
+        t = dev(full)[:, :n]
+    else:
+        t = dev(data)
+    g, cs, clamps = ctx.gram(t, cube.i_ref, prec=fk.PREC_SPLIT)
+    g64, _, _ = ctx.gram(t, cube.i_ref, prec=fk.PREC_FP64)
+    ell, bad = wf.log_ratio(data.astype(np.float64), cube.i_ref, 1e-6)
+    ref = ell.T @ ell
+    err = np.abs(g - ref)
+    say(f"gram split rel err {err.max() / np.abs(ref).max():.2e}, fp64 mode {np.abs(g64 - ref).max() / np.abs(ref).max():.2e}")
+    # truncation of each entry (2^-28 of 2^e), the digit products dropped
+    # past level 6 (at most 2^-34 of 2^(e_a + e_b) per row), FP64 sums
+    e = 2.0 ** _split_exponents(ell)
+    a1 = np.abs(ell).sum(axis=0)
+    bound = 2.0 ** -28 * (np.outer(e, a1) + np.outer(a1, e)) + m * 2.0 ** -33 * np.outer(e, e) + \
+        1e-13 * (np.abs(ell).T @ np.abs(ell))
+    assert np.all(err <= bound)
+    assert err.max() < np.abs(g64 - ref).max()
+    np.testing.assert_array_equal(g, g.T)
+    np.testing.assert_allclose(cs, data.astype(np.float64).sum(axis=0), rtol=1e-12)
+    assert clamps == bad == 0
+
+
+def test_gram_split_many_chunks_and_clamps(ctx):
+    # 4.4 million rows: chunks of 65,536 rows (the int32 limit of the digit
+    # sums) in more than 64 chunks; one clamped ratio in column 3
+    say("gram split 4.4M rows")
+    m, n = 4_400_000, 8
+    rng = np.random.default_rng(77)
+    i_ref = 1.0 + rng.random(n)
+    data = (i_ref * np.exp(0.4 * rng.standard_normal((m, n)))).astype(np.float32)
+    data[123_457, 3] = -1.0
+    g, cs, clamps = ctx.gram(dev(data), i_ref, prec=fk.PREC_SPLIT)
+    ell, bad = wf.log_ratio(data.astype(np.float64), i_ref, 1e-6)
+    ref = ell.T @ ell
+    assert clamps == bad == 1
+    err = np.abs(g - ref)
+    say(f"gram split 4.4M rows rel err {err.max() / np.abs(ref).max():.2e}")
+    e = 2.0 ** _split_exponents(ell)
+    a1 = np.abs(ell).sum(axis=0)
+    bound = 2.0 ** -28 * (np.outer(e, a1) + np.outer(a1, e)) + m * 2.0 ** -33 * np.outer(e, e) + \
+        1e-13 * (np.abs(ell).T @ np.abs(ell))
+    assert np.all(err <= bound)
+    np.testing.assert_allclose(cs, data.astype(np.float64).sum(axis=0), rtol=1e-12)
+
+
 @pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3)])
 def test_gram_fp64_matches_oracle(ctx, m, n, ld_pad):
     # FP64 matrix cores: the only difference left is the FP32 log ratio
@@ -792,19 +855,22 @@ def tissue703_oracle():
 
 
 @pytest.mark.slow
-def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle):
+@pytest.mark.parametrize("gram_prec", [fk.PREC_FP64, fk.PREC_SPLIT])
+def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle, gram_prec):
     # the 703,026 x 1,000 cube, k = 50: every output spectrum against the
-    # FP64 oracle's own fit of the same FP32 input
-    say("paper-scale fit, FP64 Gram, vs oracle")
+    # FP64 oracle's own fit of the same FP32 input, with the Gram on the FP64
+    # matrix cores and with the int8 splitting
+    say(f"paper-scale fit, gram_prec={gram_prec}, vs oracle")
     cube, p, ref_basis, ref_im = tissue703_oracle
     t = dev(cube.i_cars)
-    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=fk.PREC_FP64))
+    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=gram_prec))
     got = out.cpu().numpy()
     e = b.export()
     np.testing.assert_array_equal(np.sort(e["q"]), np.sort(ref_basis["q"]))
     err = np.concatenate([spectrum_err(got[i:i + 65536].astype(np.float64), ref_im[i:i + 65536])
                           for i in range(0, cube.shape[0], 65536)])
-    say(f"paper-scale fp64-gram fit: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    say(f"paper-scale fit gram_prec={gram_prec}: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}, "
+        f"gram {rep['dev_ms_gram']:.2f} ms, log-ratio passes {rep['dev_ms_logratio']:.2f} ms, total {rep['ms_total']:.1f} ms")
     assert err.max() < TOL
     del t, out
     torch.cuda.empty_cache()
@@ -821,7 +887,7 @@ def test_stored_basis_stream_frames_vs_oracle(ctx, tissue703_oracle):
     t = dev(cube.i_cars)
     frames = [synth.frame(i) for i in range(2)]
     oracle_own = [wf.transform(fr.i_cars.astype(np.float64), ref_basis)["im"] for fr in frames]
-    for gram_prec in (fk.PREC_FP32, fk.PREC_FP64):
+    for gram_prec in (fk.PREC_FP32, fk.PREC_FP64, fk.PREC_SPLIT):
         b, _, _ = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=gram_prec), want_out=False)
         e = b.export()
         for fr, own_ref in zip(frames, oracle_own):
@@ -831,7 +897,7 @@ def test_stored_basis_stream_frames_vs_oracle(ctx, tissue703_oracle):
             say(f"stream gram_prec={gram_prec}: vs device basis {err_dev.max():.2e}, "
                 f"vs oracle basis max {err_own.max():.2e} rms {np.sqrt(np.mean(err_own ** 2)):.2e}")
             assert err_dev.max() < TOL
-            if gram_prec == fk.PREC_FP64:
+            if gram_prec != fk.PREC_FP32:
                 assert err_own.max() < TOL
             else:
                 assert err_own.max() < 1e-2
