@@ -9,7 +9,7 @@
 //           (-1, 1), X = rint(x 2^27) cut into balanced base-128 digits:
 //               x = 2^-6 (a1 + 2^-7 a2 + 2^-14 a3 + 2^-21 a4) + d,
 //           a2..a4 in [-64, 63], |a1| <= 64, |d| <= 2^-28.
-//   gram:   for each 128 x 128 tile (two blocks of 128 x 64) and row chunk,
+//   gram:   for each 128 x 128 tile and row chunk,
 //           the int8 products S_i^T S_j summed exactly in int32, grouped by
 //           level t = i + j, t = 2..6 (13 products), and
 //           G_chunk = 2^(e_a + e_b - 12) sum_t 2^(-7 (t - 2)) C_t, exact in
@@ -22,9 +22,10 @@
 //
 // Slices are stored row-group major, slice-major within a row group:
 // S[g][s][j] is a 16-byte unit holding rows 16 g .. 16 g + 15 of column j,
-// slice s.  v_mfma_i32_16x16x64_i8: lane l holds A[l%16][16 (l/16) + q]
-// and B[16 (l/16) + q][l%16] (q = byte 0..15) and receives
-// D[4 (l/16) + v][l%16] in element v (measured with a one-wave probe).
+// slice s.  v_mfma_i32_32x32x32_i8: lane l holds A[l%32][16 (l/32) + q]
+// and B[16 (l/32) + q][l%32] (q = byte 0..15) and receives
+// D[8 (v/4) + 4 (l/32) + v%4][l%32] in element v (measured with a one-wave
+// probe), so a lane's operand is one 16-byte unit of one row group.
 #include "kernels.h"
 #include "device_common.h"
 
@@ -38,13 +39,12 @@ namespace dev {
 namespace {
 
 typedef int8_t i8x16 __attribute__((ext_vector_type(16)));
-typedef int int32x4 __attribute__((ext_vector_type(4)));
+typedef int int32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
 constexpr int ST_ROWS = 256;  // rows per stats block
 constexpr int GT = kGramTile;
-constexpr int I8_THREADS = 512;  // 8 waves: 4 (a) x 2 (b), 32 x 32 of the half tile each
-constexpr int HB = GT / 2;       // b columns of a block (half a tile)
+constexpr int I8_THREADS = 512;  // 8 waves: 2 (a) x 4 (b), 64 x 32 of the tile each
 constexpr int KROWS = 64;        // rows per K step (4 row groups)
 
 // ---------------------------------------------------------------------------
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) void slice_kernel(const float* __restrict__ I,
 // gram: 128 x 128 tiles, 64-row K steps staged in LDS as sX[slice][row
 // group][column] (16-byte units), double-buffered
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int32x4 mfma_i8(const u32x4v& a, const u32x4v& b, int32x4 c) {
-    return __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i8x16, a), __builtin_bit_cast(i8x16, b), c, 0,
+__device__ __forceinline__ int32x16 mfma_i8(const u32x4v& a, const u32x4v& b, int32x16 c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i8x16, a), __builtin_bit_cast(i8x16, b), c, 0,
                                                  0, 0);
 }
 
@@ -224,129 +224,121 @@ __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __res
                                                              int T, int64_t rpc, const int* __restrict__ tiles,
                                                              const int* __restrict__ colexp,
                                                              double* __restrict__ partial) {
-    // [buffer][slice 4][row group 4][column]: a strip (128 columns), b strip (64)
-    __shared__ u32x4v sa[2][4 * 4 * GT];
-    __shared__ u32x4v sb[2][4 * 4 * HB];
+    // [buffer][operand][slice 4][row group 4][column 128] (16-byte units)
+    __shared__ u32x4v sm[2][2][4 * 4 * GT];
 
-    // blockIdx -> (chunk, tile, half): consecutive blocks go to different
-    // XCDs, so the 8 XCDs each take every 8th chunk and run all tiles of it
+    // blockIdx -> (chunk, tile): consecutive blocks go to different XCDs, so
+    // the 8 XCDs each take every 8th chunk and run all tiles of it
     const int b = blockIdx.x;
     const int xcd = b & 7;
     const int rr = b >> 3;
-    const int th = rr % (2 * T);
-    const int tile = th >> 1, half = th & 1;
-    const int chunk = (rr / (2 * T)) * 8 + xcd;
+    const int tile = rr % T;
+    const int chunk = (rr / T) * 8 + xcd;
     const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
-    const int cb0 = bj * GT + half * HB;  // first b column of the block
+    const bool diag = (bi == bj);
     const int64_t m0 = (int64_t)chunk * rpc;
     const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
     const int64_t nst = (m1 > m0) ? (m1 - m0 + KROWS - 1) / KROWS : 0;  // zero rows past M in the slices
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;  // a columns 32 wr.., b columns 32 wc.. of the block
+    const int wr = wave >> 2, wc = wave & 3;  // a columns 64 wr.., b columns 32 wc..
+    // a wave of a diagonal tile below the diagonal computes nothing needed
+    const bool idle = diag && (64 * wr >= 32 * wc + 32);
 
-    // staging: a strip units u = tid + 512 p (p < 4): row group u / 512,
-    // slice (u / 128) % 4, column u % 128; b strip units u = tid + 512 p
-    // (p < 2): row group u / 256, slice (u / 64) % 4, column u % 64
-    u32x4v xa[4], xb[2];
-    auto load = [&](int64_t step) {
+    // Strips go from HBM to LDS by direct loads (global_load_lds, 16 bytes
+    // per lane, lane i to the instruction's LDS base + 16 i): instruction p
+    // (< 4) of wave w moves units u = 64 (4 w + p) + lane of a strip, i.e.
+    // row group u / 512, slice (u / 128) % 4, columns (u % 128) .. + 63,
+    // contiguous in both layouts.
+    auto fetch = [&](int64_t step, int blk, int buf, int op) {
         const int64_t g0 = (m0 + step * KROWS) / 16;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const int u = tid + I8_THREADS * p;
-            const int rg = u >> 9, s = (u >> 7) & 3, col = u & 127;
-            xa[p] = S[((size_t)(g0 + rg) * 4 + s) * npad + bi * GT + col];
-        }
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int u = tid + I8_THREADS * p;
-            const int rg = u >> 8, s = (u >> 6) & 3, col = u & 63;
-            xb[p] = S[((size_t)(g0 + rg) * 4 + s) * npad + cb0 + col];
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int u = tid + I8_THREADS * p;
-            const int rg = u >> 9, s = (u >> 7) & 3, col = u & 127;
-            sa[buf][(s * 4 + rg) * GT + col] = xa[p];
-        }
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int u = tid + I8_THREADS * p;
-            const int rg = u >> 8, s = (u >> 6) & 3, col = u & 63;
-            sb[buf][(s * 4 + rg) * HB + col] = xb[p];
+            const int u0 = 64 * (4 * wave + p);
+            const int rg = u0 >> 9, s = (u0 >> 7) & 3, col0 = u0 & 127;
+            const u32x4v* src = S + ((size_t)(g0 + rg) * 4 + s) * npad + blk * GT + col0 + lane;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                             (__attribute__((address_space(3))) void*)(
+                                                 &sm[buf][op][(s * 4 + rg) * GT + col0]),
+                                             16, 0, 0);
         }
     };
 
-    // acc[level t - 2][ti][tj]: (16 x 16) blocks
-    int32x4 acc[5][2][2];
+    // acc[level t - 2][ti]: (32 x 32) blocks at a columns 64 wr + 32 ti
+    int32x16 acc[5][2];
 #pragma unroll
     for (int t = 0; t < 5; ++t)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[t][i][j] = int32x4{0, 0, 0, 0};
+            for (int v = 0; v < 16; ++v) acc[t][i][v] = 0;
 
     if (nst > 0) {
-        load(0);
-        store(0);
+        fetch(0, bi, 0, 0);
+        if (!diag) fetch(0, bj, 0, 1);
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the direct loads have landed in LDS
     __syncthreads();
     for (int64_t st = 0; st < nst; ++st) {
         const int buf = (int)(st & 1);
-        if (st + 1 < nst) load(st + 1);
-        const u32x4v* A = sa[buf];
-        const u32x4v* B = sb[buf];
-        u32x4v bv[4][2];  // [slice][tj]
+        const u32x4v* A = sm[buf][0];
+        const u32x4v* B = diag ? sm[buf][0] : sm[buf][1];
+        // the next step's strips go to the other buffer, which every wave
+        // finished reading before the last barrier
+        if (st + 1 < nst) {
+            fetch(st + 1, bi, buf ^ 1, 0);
+            if (!diag) fetch(st + 1, bj, buf ^ 1, 1);
+        }
+        if (!idle) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int kh = 0; kh < 2; ++kh) {
+            const int rg = 2 * kh + (lane >> 5);
+            u32x4v bv[4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[s][j] = B[(s * 4 + (lane >> 4)) * HB + wc * 32 + j * 16 + (lane & 15)];
+            for (int s = 0; s < 4; ++s) bv[s] = B[(s * 4 + rg) * GT + wc * 32 + (lane & 31)];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            u32x4v av[4];
+            for (int i = 0; i < 2; ++i) {
+                u32x4v av[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) av[s] = A[(s * 4 + (lane >> 4)) * GT + wr * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
+                for (int s = 0; s < 4; ++s) av[s] = A[(s * 4 + rg) * GT + wr * 64 + i * 32 + (lane & 31)];
                 // level t = s_a + s_b (slices counted from 1), t <= 6
-                acc[0][i][j] = mfma_i8(av[0], bv[0][j], acc[0][i][j]);
-                acc[1][i][j] = mfma_i8(av[0], bv[1][j], acc[1][i][j]);
-                acc[1][i][j] = mfma_i8(av[1], bv[0][j], acc[1][i][j]);
-                acc[2][i][j] = mfma_i8(av[0], bv[2][j], acc[2][i][j]);
-                acc[2][i][j] = mfma_i8(av[1], bv[1][j], acc[2][i][j]);
-                acc[2][i][j] = mfma_i8(av[2], bv[0][j], acc[2][i][j]);
-                acc[3][i][j] = mfma_i8(av[0], bv[3][j], acc[3][i][j]);
-                acc[3][i][j] = mfma_i8(av[1], bv[2][j], acc[3][i][j]);
-                acc[3][i][j] = mfma_i8(av[2], bv[1][j], acc[3][i][j]);
-                acc[3][i][j] = mfma_i8(av[3], bv[0][j], acc[3][i][j]);
-                acc[4][i][j] = mfma_i8(av[1], bv[3][j], acc[4][i][j]);
-                acc[4][i][j] = mfma_i8(av[2], bv[2][j], acc[4][i][j]);
-                acc[4][i][j] = mfma_i8(av[3], bv[1][j], acc[4][i][j]);
+                acc[0][i] = mfma_i8(av[0], bv[0], acc[0][i]);
+                acc[1][i] = mfma_i8(av[0], bv[1], acc[1][i]);
+                acc[1][i] = mfma_i8(av[1], bv[0], acc[1][i]);
+                acc[2][i] = mfma_i8(av[0], bv[2], acc[2][i]);
+                acc[2][i] = mfma_i8(av[1], bv[1], acc[2][i]);
+                acc[2][i] = mfma_i8(av[2], bv[0], acc[2][i]);
+                acc[3][i] = mfma_i8(av[0], bv[3], acc[3][i]);
+                acc[3][i] = mfma_i8(av[1], bv[2], acc[3][i]);
+                acc[3][i] = mfma_i8(av[2], bv[1], acc[3][i]);
+                acc[3][i] = mfma_i8(av[3], bv[0], acc[3][i]);
+                acc[4][i] = mfma_i8(av[1], bv[3], acc[4][i]);
+                acc[4][i] = mfma_i8(av[2], bv[2], acc[4][i]);
+                acc[4][i] = mfma_i8(av[3], bv[1], acc[4][i]);
             }
         }
-        if (st + 1 < nst) store(buf ^ 1);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
+    if (idle) return;
 
     // Flush: |C_t| <= (t - 1) 2^12 rpc <= 2^30, so sum_t 2^(-7 (t-2)) C_t
     // spans bits 2^30 .. 2^-28: the two halves below are exact in FP64 and
     // their sum rounds once.
     double* P = partial + ((size_t)chunk * T + tile) * (size_t)(GT * GT);
+    const int c = wc * 32 + (lane & 31);
+    const int ec = colexp[bj * GT + c] - 12;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
-                const int c = half * HB + wc * 32 + j * 16 + (lane & 15);
-                const double hi = (double)acc[0][i][j][v] + 0x1p-7 * (double)acc[1][i][j][v];
-                const double lo = 0x1p-14 * (double)acc[2][i][j][v] + 0x1p-21 * (double)acc[3][i][j][v] +
-                                  0x1p-28 * (double)acc[4][i][j][v];
-                P[r * GT + c] = ldexp(hi + lo, colexp[bi * GT + r] + colexp[bj * GT + c] - 12);
-            }
+        for (int v = 0; v < 16; ++v) {
+            const int r = wr * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const double hi = (double)acc[0][i][v] + 0x1p-7 * (double)acc[1][i][v];
+            const double lo = 0x1p-14 * (double)acc[2][i][v] + 0x1p-21 * (double)acc[3][i][v] +
+                              0x1p-28 * (double)acc[4][i][v];
+            P[r * GT + c] = ldexp(hi + lo, colexp[bi * GT + r] + ec);
+        }
 }
 
 }  // namespace
@@ -407,7 +399,7 @@ hipError_t launch_gram_split(const void* S, int npad, int64_t M, const GramPlan&
     if (plan.tiles < 1 || plan.chunks < 1 || M < 1 || plan.rows_per_chunk % KROWS != 0 ||
         plan.rows_per_chunk > 65536 || plan.nb * GT > npad)
         return hipErrorInvalidValue;
-    dim3 grid((unsigned)(2 * plan.tiles * plan.chunks)), block(I8_THREADS);
+    dim3 grid((unsigned)(plan.tiles * plan.chunks)), block(I8_THREADS);
     hipLaunchKernelGGL(gram_i8_kernel, grid, block, 0, s, static_cast<const u32x4v*>(S), npad, M, plan.tiles,
                        plan.rows_per_chunk, d_tiles, colexp, partial);
     return hipGetLastError();
