@@ -3,10 +3,13 @@
 A step is one full fKK-EC fit of the 703,026 x 1,000 FP32 tissue-like cube
 (log ratio + Gram, FP64 eigensolve, projection + sub-sampling, FP64
 basis-vector KK/PEC/SEC, reconstruction + exp/sin epilogue), inputs resident
-in HBM.  Prints one JSON line; beside the headline it reports the
-stored-basis transform and the conventional per-spectrum method on the same
-GPU, the dominant kernel against its roofline, and the oracle timed on the
-host's cores.
+in HBM.  The headline fit computes the Gram to FP64 accuracy on the int8
+matrix cores (error-free splitting); the FP32- and FP64-matrix-core Grams,
+the randomized range finder and BF16 run as legs.  Every fit's output is
+compared with the FP64 oracle's fit of the same cube.  Prints one JSON line;
+beside the headline it reports the stored-basis transform and the
+conventional per-spectrum method on the same GPU, the dominant kernel
+against its roofline, and the oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -25,24 +28,43 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix peak, flop/s
 PEAK_BF16_MFMA = 2.5e15     # MI355X dense BF16 matrix peak, flop/s
 PEAK_FP64_MFMA = 78.6e12    # MI355X dense FP64 matrix peak, flop/s
+PEAK_INT8_MFMA = 5.0e15     # MI355X dense int8 matrix peak, op/s
+SPLIT_PRODUCTS = 13         # digit products of the split Gram (levels 2..6 of four digits)
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 
 
-def profiled_traffic(key):
-    """HBM bytes per launch of a Gram kernel from the committed counter
-    summary, or None once the profiled kernel source has changed."""
-    path = os.path.join(ROOT, "profiles", "gram_kernel_tissue703k_traffic.txt")
+# Counter summaries in profiles/ and the source region each one measured:
+# a summary is used only while that region of the source is unchanged.
+TRAFFIC_FILES = {
+    "gram_kernel": ("gram_kernel_tissue703k_traffic.txt", "kernels.hip",
+                    "constexpr int GT = kGramTile;", "__global__ void gram_reduce_kernel("),
+    "gram_i8_kernel": ("gram_i8_kernel_tissue703k_traffic.txt", "kernels_i8.hip",
+                       "__device__ __forceinline__ int32x16 mfma_i8(", "}  // namespace\n\nint64_t stats_blocks"),
+}
+
+
+def profiled_traffic(kernel, key):
+    """HBM bytes per launch of a kernel from its committed counter summary,
+    or None once the profiled kernel source has changed."""
+    fname, src_name, a, b = TRAFFIC_FILES[kernel]
     try:
-        text = open(path).read()
-        src = open(os.path.join(ROOT, "paper_2005_07132_amd", "csrc", "kernels.hip")).read()
+        text = open(os.path.join(ROOT, "profiles", fname)).read()
+        src = open(os.path.join(ROOT, "paper_2005_07132_amd", "csrc", src_name)).read()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines()
                 if line.startswith(("traffic_bytes_", "source_sha256")))
-    region = src[src.index("constexpr int GT = kGramTile;"):src.index("__global__ void gram_reduce_kernel(")]
+    region = src[src.index(a):src.index(b)]
     if hashlib.sha256(region.encode()).hexdigest() != vals.get("source_sha256", "").strip():
         return None
-    return int(vals[key])
+    return int(vals[key]) if key in vals else None
+
+
+def source_hash(kernel):
+    """sha256 of the source region a counter summary of `kernel` covers."""
+    fname, src_name, a, b = TRAFFIC_FILES[kernel]
+    src = open(os.path.join(ROOT, "paper_2005_07132_amd", "csrc", src_name)).read()
+    return hashlib.sha256(src[src.index(a):src.index(b)].encode()).hexdigest()
 
 
 def stream_bandwidth(torch, dev, out):
@@ -71,14 +93,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_info():
+    """The host's CPU model, logical CPUs and the BLAS threads the oracle uses."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:  # pragma: no cover
+        blas = os.cpu_count() or 1
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "blas_threads": int(blas)}
+
+
 def cpu_baseline(cube, k, seconds_target=20.0):
     """Oracle fKK-EC fit (NumPy FP64, gesdd) on a bounded leading sample."""
     from oracle import workflows as wf
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+    info = cpu_info()
     p = wf.Params(k=k, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
     m = 4096
     while True:
@@ -89,8 +125,57 @@ def cpu_baseline(cube, k, seconds_target=20.0):
         if dt * 2 > seconds_target or m * 2 > 131072:
             break
         m *= 2
-    return {"value": m / dt, "unit": "spectra/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {m} spectra of the cube, full fKK-EC fit (gesdd SVD, k={k}), {dt:.1f} s"}
+    return {"value": m / dt, "unit": "spectra/s", "cores": info["blas_threads"], "kind": "oracle",
+            "sample": f"first {m} spectra of the cube, full fKK-EC fit (gesdd SVD, k={k}), {dt:.1f} s", **info}
+
+
+def cpu_oracle_legs(cube, basis, frame, k):
+    """The oracle's other timings: the conventional workflow on a
+    10,000-spectrum slice scaled to the whole cube (as the paper timed its
+    conventional method), and the stored-basis transform of one
+    256 x 256 x 1,000 frame."""
+    from oracle import workflows as wf
+    p = wf.Params(k=k, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    m = cube.shape[0]
+    ns = min(10000, m)
+    sl = cube.i_cars[:ns].astype(np.float64)
+    t0 = time.perf_counter()
+    wf.plain(sl, cube.i_ref, p)
+    t_plain = time.perf_counter() - t0
+    x = frame.astype(np.float64)
+    t0 = time.perf_counter()
+    wf.transform(x, basis)
+    t_tr = time.perf_counter() - t0
+    return {"conventional": {"slice_spectra": ns, "s": t_plain, "spectra_per_s": ns / t_plain,
+                             "scaled_to_cube_s": t_plain * m / ns},
+            "stored_basis_transform": {"frame_spectra": int(x.shape[0]), "s_per_frame": t_tr,
+                                       "spectra_per_s": x.shape[0] / t_tr}}
+
+
+def oracle_fit(cube, k):
+    """The FP64 oracle's fKK-EC fit of the whole cube (Gram + eigh route;
+    the same subspace as gesdd to 1e-10 on these cubes), Im K_CARS."""
+    from oracle import workflows as wf
+    p = wf.Params(k=k, f_mode=wf.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
+    t0 = time.perf_counter()
+    res = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p, svd="gram")
+    return res["im"], res["basis"], time.perf_counter() - t0
+
+
+def parity(out_host, ref_im, chunk=65536):
+    """Per-spectrum error max |y - y*| / max |y*| of an output (host FP32)
+    against the oracle's FP64 output: max, RMS, median, 99th percentile and
+    the fraction within 1e-5."""
+    m = ref_im.shape[0]
+    errs = []
+    for i0 in range(0, m, chunk):
+        y = out_host[i0:i0 + chunk].astype(np.float64)
+        r = ref_im[i0:i0 + chunk]
+        errs.append(np.abs(y - r).max(axis=1) / np.maximum(np.abs(r).max(axis=1), 1e-30))
+    e = np.concatenate(errs)
+    return {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e * e))), "median": float(np.median(e)),
+            "p99": float(np.percentile(e, 99)), "frac_within_1e-5": float(np.mean(e <= 1e-5)),
+            "vs": "FP64 oracle fit of the same cube"}
 
 
 def serving_bench(ctx, fk, torch, synth, basis1000, seconds=4.0, max_tiles=400):
@@ -282,30 +367,6 @@ def host_streamed(fk, torch, basis, host_frames):
             "note": "pinned host frames -> device -> host, copies included (PCIe)"}
 
 
-def bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n, npad, kq, gram_flop,
-             recon_stats):
-    """The fit and the transforms with BF16 matrix-core operands."""
-    log("BF16 fit and transforms")
-    p16 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
-                    gram_prec=fk.PREC_BF16, recon_prec=fk.PREC_BF16)
-    ms16, stage16, b16 = fit_steps(ctx, I, cube.i_ref, p16, args.steps, 1, out, torch, "bf16")
-    gram16_ms = stage16["dev_ms_gram"]
-    bf16 = {"fit_ms_per_step": ms16, "fit_spectra_per_s": m / (ms16 * 1e-3), "stages_ms": stage16,
-            "gram": {"ms": gram16_ms, "TFLOP/s": gram_flop / (gram16_ms * 1e-3) / 1e12,
-                     "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA,
-                     "bytes_read": 2.0 * m * npad,
-                     "GB/s_algorithmic": 2.0 * m * npad / (gram16_ms * 1e-3) / 1e9},
-            "logratio_pass": {"ms": stage16["dev_ms_logratio"],
-                              "GB/s": (4.0 * m * n + 2.0 * m * npad) / (stage16["dev_ms_logratio"] * 1e-3) / 1e9},
-            "reconstruction": recon_stats(stage16["dev_ms_recon"], kq, 2),
-            "transform": time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)}
-    b16.precision = fk.PREC_BF16
-    bf16["transform"]["host_streamed"] = host_streamed(fk, torch, b16, host_frames)
-    log(f"bf16 fit: {ms16:.2f} ms/step; transform {bf16['transform']['spectra_per_s_full_cube']:.3e}/s")
-    b16.free()
-    return bf16
-
-
 def mean_rss(out, cube, chunk=32768):
     """<RSS> over pixels of sum_w (K - Im{chi/chi_nr})^2, the null RSS (K = 0)
     beside it; K is a retrieved Im plane copied back from the device."""
@@ -450,6 +511,7 @@ def main():
     ap.add_argument("--serving-tiles", type=int, default=400,
                     help="most tiles per serving level (1000 for the full serving workload)")
     ap.add_argument("--skip-bf16", action="store_true")
+    ap.add_argument("--skip-parity", action="store_true", help="skip the FP64 oracle fit the outputs are compared with")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device-to-device copy: the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a --pmc run to bytes")
@@ -478,27 +540,35 @@ def main():
     I = torch.from_numpy(cube.i_cars).to(dev)
     out = torch.empty_like(I)
     ctx = fk.Context(0)
-    p = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
-
-    ms_step, stage, b = fit_steps(ctx, I, cube.i_ref, p, args.steps, args.warmup, out, torch, "fp32")
-    value = m / (ms_step * 1e-3)
-    log(f"fit: {ms_step:.2f} ms/step, {value:.3e} spectra/s")
-    gram_ms = stage["dev_ms_gram"]
-    gram_flop = float(m) * n * (n + 1)  # symmetric Gram: N(N+1)/2 entries x 2M flop
-    roofline = {"bound": "mfma", "kernel": "gram_kernel (FP32 MFMA Gram of the log ratio)",
-                "achieved": gram_flop / (gram_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                "unit": "TFLOP/s", "frac": gram_flop / (gram_ms * 1e-3) / PEAK_FP32_MFMA,
-                "traffic": profiled_traffic("traffic_bytes_gram_kernel_fp32"),
-                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
-                                "profiles/gram_kernel_tissue703k_traffic.txt)",
-                "algorithmic_bytes_per_launch": 4.0 * m * ((n + 127) // 128 * 128) + 8.0 * 64 * 128 * 128 *
-                ((n + 127) // 128) * ((n + 127) // 128 + 1) / 2,
-                "flop_per_launch": gram_flop, "ms_per_launch": gram_ms}
+    base = dict(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g)
     npad = (n + 127) // 128 * 128
-    logratio = {"ms": stage["dev_ms_logratio"],
-                "GB/s": (4.0 * m * n + 4.0 * m * npad) / (stage["dev_ms_logratio"] * 1e-3) / 1e9}
     kp = 16 if args.k <= 16 else 32 if args.k <= 32 else 64 if args.k <= 64 else 128
     kq = max(kp, 32)
+    gram_flop = float(m) * n * (n + 1)  # symmetric Gram: N(N+1)/2 entries x 2M flop
+
+    # headline: the fit with the Gram on the int8 matrix cores (FP64-accurate)
+    p = fk.params(**base, gram_prec=fk.PREC_SPLIT)
+    ms_step, stage, b = fit_steps(ctx, I, cube.i_ref, p, args.steps, args.warmup, out, torch, "split")
+    value = m / (ms_step * 1e-3)
+    log(f"fit: {ms_step:.2f} ms/step, {value:.3e} spectra/s")
+    head_out = out.cpu().numpy()
+    gram_ms = stage["dev_ms_gram"]
+    i8_ops = SPLIT_PRODUCTS * float(m) * n * (n + 1)  # 13 digit products over the symmetric Gram
+    roofline = {"bound": "mfma", "kernel": "gram_i8_kernel (int8 matrix-core Gram of the split log ratio)",
+                "achieved": i8_ops / (gram_ms * 1e-3) / 1e12, "peak": PEAK_INT8_MFMA / 1e12, "unit": "TOP/s",
+                "frac": i8_ops / (gram_ms * 1e-3) / PEAK_INT8_MFMA,
+                "traffic": profiled_traffic("gram_i8_kernel", "traffic_bytes_gram_i8_kernel"),
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                "profiles/gram_i8_kernel_tissue703k_traffic.txt)",
+                "algorithmic_bytes_per_launch": 4.0 * ((m + 63) // 64 * 64) * npad +
+                8.0 * 64 * 128 * 128 * ((n + 127) // 128) * ((n + 127) // 128 + 1) / 2,
+                "ops_per_launch": i8_ops, "ms_per_launch": gram_ms,
+                "fp64_equivalent": {"flop_per_launch": gram_flop,
+                                    "TFLOP/s": gram_flop / (gram_ms * 1e-3) / 1e12,
+                                    "frac_of_fp64_mfma_peak": gram_flop / (gram_ms * 1e-3) / PEAK_FP64_MFMA}}
+    split_passes = {"ms": stage["dev_ms_logratio"],
+                    "GB/s": (2 * 4.0 * m * n + 4.0 * m * npad) / (stage["dev_ms_logratio"] * 1e-3) / 1e9,
+                    "note": "column statistics pass (reads I) + slicing pass (reads I, writes the four int8 slices)"}
 
     def recon_stats(ms, kcols, bytes_per_basis_elem):
         nbytes = 4.0 * m * n + 4.0 * m * kp + 2.0 * n * kcols * bytes_per_basis_elem
@@ -509,8 +579,25 @@ def main():
     recon = recon_stats(stage["dev_ms_recon"], kp, 4)
     recon["frac_of_fp32_mfma_peak"] = recon["TFLOP/s"] * 1e12 / PEAK_FP32_MFMA
     stream_ref = stream_bandwidth(torch, dev, out)
-    for r in (recon, logratio):
-        r["frac_of_measured_copy"] = r["GB/s"] / stream_ref["copy_GB/s"]
+    recon["frac_of_measured_copy"] = recon["GB/s"] / stream_ref["copy_GB/s"]
+
+    # the FP64 oracle's fit of the same cube: every fit below is compared with it
+    ref_im = ref_basis = None
+    oracle_s = None
+    if not args.skip_parity:
+        log("FP64 oracle fit of the whole cube (host)")
+        ref_im, ref_basis, oracle_s = oracle_fit(cube, args.k)
+        log(f"oracle fit in {oracle_s:.1f} s")
+
+    def check(host_out, tag):
+        if ref_im is None:
+            return None
+        r = parity(host_out, ref_im)
+        log(f"{tag}: max error {r['max']:.2e}, RMS {r['rms']:.2e} against the oracle")
+        return r
+
+    head_parity = check(head_out, "split fit")
+    del head_out
 
     # stored-basis stream: args.frames new 256 x 256 x 1000 frames (same
     # components, new abundance maps and noise), each transformed once
@@ -524,47 +611,83 @@ def main():
     fout = torch.empty_like(frames[0])
     transform = time_transform(ctx, b, frames, fout, I, out, args.frames, torch)
     transform["host_streamed"] = host_streamed(fk, torch, b, host_frames)
+    frame_ref = None
+    if ref_basis is not None:
+        from oracle import workflows as wf
+        frame_ref = wf.transform(host_frames[0].numpy().astype(np.float64), ref_basis)["im"]
+        ctx.transform(b, frames[0], out=fout)
+        transform["frame_error_vs_oracle"] = parity(fout.cpu().numpy(), frame_ref)
+        transform["frame_error_vs_oracle"]["vs"] = "oracle's own basis (FP64 fit) applied to frame 0"
 
-    # the same fit with the FP64 Gram (products and sums in FP64)
+    def leg(tag, steps, **kw):
+        pl = fk.params(**base, **kw)
+        ms, st, bl = fit_steps(ctx, I, cube.i_ref, pl, steps, 1, out, torch, tag)
+        r = {"fit_ms_per_step": ms, "fit_spectra_per_s": m / (ms * 1e-3), "stages_ms": st,
+             "parity": check(out.cpu().numpy(), tag)}
+        log(f"{tag} fit: {ms:.2f} ms/step")
+        return r, bl
+
+    log("fit with the FP32 Gram")
+    fp32_gram, bl = leg("fp32-gram", args.steps, gram_prec=fk.PREC_FP32)
+    bl.free()
+    fp32_gram["gram"] = {"kernel": "gram_kernel<false>", "ms": fp32_gram["stages_ms"]["dev_ms_gram"],
+                         "TFLOP/s": gram_flop / (fp32_gram["stages_ms"]["dev_ms_gram"] * 1e-3) / 1e12,
+                         "frac_of_fp32_mfma_peak": gram_flop / (fp32_gram["stages_ms"]["dev_ms_gram"] * 1e-3) /
+                         PEAK_FP32_MFMA,
+                         "traffic": profiled_traffic("gram_kernel", "traffic_bytes_gram_kernel_fp32")}
     log("fit with the FP64 Gram")
-    p64 = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g, gram_prec=fk.PREC_FP64)
-    ms64, stage64, b64 = fit_steps(ctx, I, cube.i_ref, p64, args.steps, 1, out, torch, "fp64-gram")
-    b64.free()
-    fp64_gram = {"fit_ms_per_step": ms64, "fit_spectra_per_s": m / (ms64 * 1e-3), "stages_ms": stage64,
-                 "gram": {"ms": stage64["dev_ms_gram"], "TFLOP/s": gram_flop / (stage64["dev_ms_gram"] * 1e-3) / 1e12,
-                          "frac_of_fp64_peak": gram_flop / (stage64["dev_ms_gram"] * 1e-3) / PEAK_FP64_MFMA}}
-    log(f"fp64-gram fit: {ms64:.2f} ms/step")
-
-    # the same fit with the randomized range finder in place of Gram + eigensolve;
-    # its output against the FP64-Gram fit's (still in `out`)
+    fp64_gram, bl = leg("fp64-gram", args.steps, gram_prec=fk.PREC_FP64)
+    bl.free()
+    fp64_gram["gram"] = {"ms": fp64_gram["stages_ms"]["dev_ms_gram"],
+                         "TFLOP/s": gram_flop / (fp64_gram["stages_ms"]["dev_ms_gram"] * 1e-3) / 1e12,
+                         "frac_of_fp64_peak": gram_flop / (fp64_gram["stages_ms"]["dev_ms_gram"] * 1e-3) /
+                         PEAK_FP64_MFMA}
     log("fit with the randomized range finder")
-    prr = fk.params(k=args.k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
-                    svd_mode=fk.SVD_RANDOMIZED, rrf_oversample=10, rrf_power_iters=1)
-    out_rr = torch.empty_like(out)
-    msrr, stagerr, brr = fit_steps(ctx, I, cube.i_ref, prr, args.steps, 1, out_rr, torch, "randomized")
+    randomized, brr = leg("randomized", args.steps, svd_mode=fk.SVD_RANDOMIZED, rrf_oversample=20,
+                          rrf_power_iters=3)
+    randomized.update({"oversample": 20, "power_iters": 3})
+    if ref_basis is not None:
+        v = brr.export()["v"]
+        vr = ref_basis["v"]
+        s_ref = np.asarray(ref_basis["s"])
+        # largest principal angle between the two k-dimensional subspaces
+        sv = np.linalg.svd(vr.T @ v, compute_uv=False)
+        randomized["subspace_sin_angle_vs_oracle"] = float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
+        randomized["s_k_relative_error"] = float(abs(brr.export()["s"][-1] - s_ref[-1]) / s_ref[-1])
     brr.free()
-    per = ((out_rr - out).abs().amax(dim=1) / out.abs().amax(dim=1).clamp_min(1e-30)).double()
-    randomized = {"fit_ms_per_step": msrr, "fit_spectra_per_s": m / (msrr * 1e-3), "stages_ms": stagerr,
-                  "oversample": 10, "power_iters": 1,
-                  "error_vs_fp64_gram_fit": {"max": float(per.max()), "rms": float(per.pow(2).mean().sqrt()),
-                                             "p99": float(torch.quantile(per[:: max(1, m // 100000)], 0.99))}}
-    del out_rr, per
-    log(f"randomized fit: {msrr:.2f} ms/step, max error vs the FP64-Gram fit "
-        f"{randomized['error_vs_fp64_gram_fit']['max']:.2e}")
 
-    # the same fit and transforms with BF16 matrix-core operands
     bf16 = None
     if not args.skip_bf16:
-        bf16 = bf16_leg(ctx, fk, torch, I, cube, out, frames, fout, host_frames, args, m, n, npad, kq, gram_flop,
-                        recon_stats)
-    del frames, fout, host_frames
-    copy_gbps = stream_ref["copy_GB/s"]
-    transform["frac_of_measured_copy_full_cube"] = transform["HBM_GB/s_full_cube"] / copy_gbps
-    if bf16 is not None:
-        bf16["reconstruction"]["frac_of_measured_copy"] = bf16["reconstruction"]["GB/s"] / copy_gbps
-        bf16["transform"]["frac_of_measured_copy_full_cube"] = bf16["transform"]["HBM_GB/s_full_cube"] / copy_gbps
+        log("BF16 fit and transforms")
+        bf16, b16 = leg("bf16", args.steps, gram_prec=fk.PREC_BF16, recon_prec=fk.PREC_BF16)
+        gram16_ms = bf16["stages_ms"]["dev_ms_gram"]
+        bf16["gram"] = {"ms": gram16_ms, "TFLOP/s": gram_flop / (gram16_ms * 1e-3) / 1e12,
+                        "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA}
+        bf16["reconstruction"] = recon_stats(bf16["stages_ms"]["dev_ms_recon"], kq, 2)
+        bf16["reconstruction"]["frac_of_measured_copy"] = bf16["reconstruction"]["GB/s"] / stream_ref["copy_GB/s"]
+        b16.free()
+        # the split (FP64-accurate) basis with BF16 projection and reconstruction operands
+        split16, b16 = leg("split-gram + bf16 reconstruction", args.steps, gram_prec=fk.PREC_SPLIT,
+                           recon_prec=fk.PREC_BF16)
+        split16["reconstruction"] = recon_stats(split16["stages_ms"]["dev_ms_recon"], kq, 2)
+        split16["reconstruction"]["frac_of_measured_copy"] = (split16["reconstruction"]["GB/s"] /
+                                                             stream_ref["copy_GB/s"])
+        split16["transform"] = time_transform(ctx, b16, frames, fout, I, out, args.frames, torch)
+        split16["transform"]["frac_of_measured_copy_full_cube"] = (split16["transform"]["HBM_GB/s_full_cube"] /
+                                                                  stream_ref["copy_GB/s"])
+        b16.precision = fk.PREC_BF16
+        split16["transform"]["host_streamed"] = host_streamed(fk, torch, b16, host_frames)
+        if frame_ref is not None:
+            # the transform the server runs in the serving workload (BF16 basis)
+            ctx.transform(b16, frames[0], out=fout)
+            split16["transform"]["frame_error_vs_oracle"] = parity(fout.cpu().numpy(), frame_ref)
+            split16["transform"]["frame_error_vs_oracle"]["vs"] = ("oracle's own basis (FP64 fit) applied to "
+                                                                   "frame 0")
+        bf16["split_gram_bf16_reconstruction"] = split16
+        b16.free()
+    del frames, fout
+    transform["frac_of_measured_copy_full_cube"] = transform["HBM_GB/s_full_cube"] / stream_ref["copy_GB/s"]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
 
     plain = None
     if not args.skip_plain:
@@ -579,7 +702,15 @@ def main():
         stop.record()
         torch.cuda.synchronize()
         pl_ms = start.elapsed_time(stop)
-        plain = {"spectra": mp, "ms": pl_ms, "spectra_per_s": mp / (pl_ms * 1e-3)}
+        # HBM bytes per spectrum of this design: KK pass reads I (4N) and
+        # writes l and the phase (16N); each of the 10 ALS solves streams
+        # its LDL^T state and iterate (72N); SEC reads l, the phase and the
+        # phase error (24N) and writes the output (4N); ALS writes its result (8N)
+        per = (20 + 10 * 72 + 8 + 28) * n
+        plain = {"spectra": mp, "ms": pl_ms, "spectra_per_s": mp / (pl_ms * 1e-3),
+                 "bytes_per_spectrum": per, "GB/s": per * mp / (pl_ms * 1e-3) / 1e9,
+                 "HBM_frac": per * mp / (pl_ms * 1e-3) / PEAK_HBM,
+                 "note": "HBM-bound: the ALS state of 256 spectra per block does not fit in LDS"}
         del pout
 
     serving = None
@@ -592,24 +723,33 @@ def main():
         log("oracle on the host")
         cpu = cpu_baseline(cube, args.k)
         log(f"oracle: {cpu['value']:.1f} spectra/s on {cpu['cores']} threads")
+        if ref_basis is not None:
+            cpu["other_legs"] = cpu_oracle_legs(cube, ref_basis, host_frames[0].numpy(), args.k)
+        if oracle_s is not None:
+            cpu["full_cube_fit"] = {"s": oracle_s, "spectra_per_s": m / oracle_s,
+                                    "note": "FP64 Gram + eigh route on all 703,026 spectra (the parity reference)"}
+    del host_frames
 
     line = {
         "metric": "fKK-EC spectra/s at 703k x 1000 (full fit: Gram, eigensolve, KK/PEC/SEC on k vectors, "
                   "reconstruction)",
         "value": value, "unit": "spectra/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32", "data": "synthetic",
+        "dtype": "int8+fp32", "data": "synthetic",
         "config": {"workload": "tissue-like CARS cube 703,026 spectra x 1,000 points, 5 Lorentzian components, "
-                               "Poisson+Gaussian noise SNR 20-100; fKK-EC fit k=50 (FP32 MFMA Gram and "
-                               "reconstruction, FP64 eigensolve and basis KK/PEC/SEC)",
-                   "M": m, "N": n, "k": args.k},
+                               "Poisson+Gaussian noise SNR 20-100; fKK-EC fit k=50 (Gram to FP64 accuracy by "
+                               "int8 error-free splitting on the matrix cores; FP32 MFMA projection and "
+                               "reconstruction; FP64 eigensolve and basis KK/PEC/SEC)",
+                   "M": m, "N": n, "k": args.k, "gram": "int8 error-free splitting (13 digit products)"},
+        "parity": head_parity,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": stage,
+        "split_passes": split_passes,
         "reconstruction": recon,
-        "logratio_pass": logratio,
         "streaming_reference": stream_ref,
         "transform": transform,
+        "fp32_gram": fp32_gram,
         "fp64_gram": fp64_gram,
         "randomized_svd": randomized,
         "bf16": bf16,
@@ -628,7 +768,6 @@ def main():
         c.copy_(a)
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
-
 
 if __name__ == "__main__":
     main()

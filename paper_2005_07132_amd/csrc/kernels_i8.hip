@@ -220,12 +220,31 @@ __device__ __forceinline__ int32x16 mfma_i8(const u32x4v& a, const u32x4v& b, in
                                                  0, 0);
 }
 
+// s_waitcnt immediate (gfx9 encoding) that waits until at most n vector
+// memory operations of the wave are outstanding, ignoring the other counters.
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
+// Workgroup barrier without a memory fence: __syncthreads() also waits for
+// every outstanding vector memory operation, which would drain the direct
+// loads in flight for later half steps.  Ordering is explicit instead: the
+// loads a half step reads are waited for (wait_vm) before the barrier, its
+// LDS reads are consumed by the matrix cores before the barrier, and the
+// clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
+
+constexpr int HROWS = 32;  // rows per half step (2 row groups)
+constexpr int RING = 4;    // half steps held in LDS
+
 __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __restrict__ S, int npad, int64_t M,
                                                              int T, int64_t rpc, const int* __restrict__ tiles,
                                                              const int* __restrict__ colexp,
                                                              double* __restrict__ partial) {
-    // [buffer][operand][slice 4][row group 4][column 128] (16-byte units)
-    __shared__ u32x4v sm[2][2][4 * 4 * GT];
+    // ring of half steps: [slot][operand][slice 4][row group 2][column 128]
+    // (16-byte units, 32 KB per slot)
+    __shared__ u32x4v sm[RING][2][4 * 2 * GT];
 
     // blockIdx -> (chunk, tile): consecutive blocks go to different XCDs, so
     // the 8 XCDs each take every 8th chunk and run all tiles of it
@@ -238,7 +257,8 @@ __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __res
     const bool diag = (bi == bj);
     const int64_t m0 = (int64_t)chunk * rpc;
     const int64_t m1 = (m0 + rpc < M) ? m0 + rpc : M;
-    const int64_t nst = (m1 > m0) ? (m1 - m0 + KROWS - 1) / KROWS : 0;  // zero rows past M in the slices
+    // half steps (zero rows past M in the slices, which cover whole 64-row steps)
+    const int64_t nh = (m1 > m0) ? 2 * ((m1 - m0 + KROWS - 1) / KROWS) : 0;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 2, wc = wave & 3;  // a columns 64 wr.., b columns 32 wc..
@@ -247,21 +267,26 @@ __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __res
 
     // Strips go from HBM to LDS by direct loads (global_load_lds, 16 bytes
     // per lane, lane i to the instruction's LDS base + 16 i): instruction p
-    // (< 4) of wave w moves units u = 64 (4 w + p) + lane of a strip, i.e.
-    // row group u / 512, slice (u / 128) % 4, columns (u % 128) .. + 63,
-    // contiguous in both layouts.
-    auto fetch = [&](int64_t step, int blk, int buf, int op) {
-        const int64_t g0 = (m0 + step * KROWS) / 16;
+    // (< 2) of wave w moves units u = 64 (2 w + p) + lane of a half-step
+    // strip, i.e. row group u / 512, slice (u / 128) % 4, columns
+    // (u % 128) .. + 63, contiguous in both layouts.
+    auto fetch = [&](int64_t h, int blk, int op) {
+        const int64_t g0 = (m0 + h * HROWS) / 16;
+        const int slot = (int)(h & (RING - 1));
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int u0 = 64 * (4 * wave + p);
+        for (int p = 0; p < 2; ++p) {
+            const int u0 = 64 * (2 * wave + p);
             const int rg = u0 >> 9, s = (u0 >> 7) & 3, col0 = u0 & 127;
             const u32x4v* src = S + ((size_t)(g0 + rg) * 4 + s) * npad + blk * GT + col0 + lane;
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
                                              (__attribute__((address_space(3))) void*)(
-                                                 &sm[buf][op][(s * 4 + rg) * GT + col0]),
+                                                 &sm[slot][op][(s * 2 + rg) * GT + col0]),
                                              16, 0, 0);
         }
+    };
+    auto fetch_step = [&](int64_t h) {
+        fetch(h, bi, 0);
+        if (!diag) fetch(h, bj, 1);
     };
 
     // acc[level t - 2][ti]: (32 x 32) blocks at a columns 64 wr + 32 ti
@@ -273,53 +298,60 @@ __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __res
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[t][i][v] = 0;
 
-    if (nst > 0) {
-        fetch(0, bi, 0, 0);
-        if (!diag) fetch(0, bj, 0, 1);
+    for (int64_t h = 0; h < 3 && h < nh; ++h) fetch_step(h);
+    if (diag) {  // two loads per half step
+        if (nh > 2) wait_vm<4>(); else if (nh > 1) wait_vm<2>(); else wait_vm<0>();
+    } else {
+        if (nh > 2) wait_vm<8>(); else if (nh > 1) wait_vm<4>(); else wait_vm<0>();
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the direct loads have landed in LDS
-    __syncthreads();
-    for (int64_t st = 0; st < nst; ++st) {
-        const int buf = (int)(st & 1);
-        const u32x4v* A = sm[buf][0];
-        const u32x4v* B = diag ? sm[buf][0] : sm[buf][1];
-        // the next step's strips go to the other buffer, which every wave
+    barrier_only();
+    for (int64_t h = 0; h < nh; ++h) {
+        const int slot = (int)(h & (RING - 1));
+        const u32x4v* A = sm[slot][0];
+        const u32x4v* B = diag ? sm[slot][0] : sm[slot][1];
+        // half step h + 3 goes to the slot of h - 1, which every wave
         // finished reading before the last barrier
-        if (st + 1 < nst) {
-            fetch(st + 1, bi, buf ^ 1, 0);
-            if (!diag) fetch(st + 1, bj, buf ^ 1, 1);
-        }
+        if (h + 3 < nh) fetch_step(h + 3);
         if (!idle) {
+            const int rg = lane >> 5;
+            u32x4v bv[4], av[2][4];
 #pragma unroll
-        for (int kh = 0; kh < 2; ++kh) {
-            const int rg = 2 * kh + (lane >> 5);
-            u32x4v bv[4];
+            for (int s = 0; s < 4; ++s) bv[s] = B[(s * 2 + rg) * GT + wc * 32 + (lane & 31)];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) bv[s] = B[(s * 4 + rg) * GT + wc * 32 + (lane & 31)];
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                u32x4v av[4];
+                for (int s = 0; s < 4; ++s) av[i][s] = A[(s * 2 + rg) * GT + wr * 64 + i * 32 + (lane & 31)];
+            // level t = s_a + s_b (slices counted from 1), t <= 6: the r-th
+            // product of every level of both blocks in turn, so that the
+            // products added to one accumulator issue 6 to 10 apart; the
+            // scheduling barriers keep the operand reads ahead of the
+            // products and the rounds in this order
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) av[s] = A[(s * 4 + rg) * GT + wr * 64 + i * 32 + (lane & 31)];
-                // level t = s_a + s_b (slices counted from 1), t <= 6
-                acc[0][i] = mfma_i8(av[0], bv[0], acc[0][i]);
-                acc[1][i] = mfma_i8(av[0], bv[1], acc[1][i]);
-                acc[1][i] = mfma_i8(av[1], bv[0], acc[1][i]);
-                acc[2][i] = mfma_i8(av[0], bv[2], acc[2][i]);
-                acc[2][i] = mfma_i8(av[1], bv[1], acc[2][i]);
-                acc[2][i] = mfma_i8(av[2], bv[0], acc[2][i]);
-                acc[3][i] = mfma_i8(av[0], bv[3], acc[3][i]);
-                acc[3][i] = mfma_i8(av[1], bv[2], acc[3][i]);
-                acc[3][i] = mfma_i8(av[2], bv[1], acc[3][i]);
-                acc[3][i] = mfma_i8(av[3], bv[0], acc[3][i]);
-                acc[4][i] = mfma_i8(av[1], bv[3], acc[4][i]);
-                acc[4][i] = mfma_i8(av[2], bv[2], acc[4][i]);
-                acc[4][i] = mfma_i8(av[3], bv[1], acc[4][i]);
+            for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) {
+                        // with slices counted from 0, level t + 2 pairs
+                        // (a, t - a): a = 0..t for t <= 3, a = 1..3 for t = 4
+                        const int nprod = (t <= 3) ? t + 1 : 3;
+                        if (r < nprod) {
+                            const int sa = (t <= 3) ? r : r + 1;
+                            acc[t][i] = mfma_i8(av[i][sa], bv[t - sa], acc[t][i]);
+                        }
+                    }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+        // half step h + 1 must have landed: the loads issued after it (of
+        // h + 2 and h + 3, where they exist) may still be in flight
+        if (diag) {
+            if (h + 3 < nh) wait_vm<4>(); else if (h + 2 < nh) wait_vm<2>(); else wait_vm<0>();
+        } else {
+            if (h + 3 < nh) wait_vm<8>(); else if (h + 2 < nh) wait_vm<4>(); else wait_vm<0>();
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        barrier_only();
     }
     if (idle) return;
 
