@@ -845,15 +845,6 @@ def test_paper_scale_fit_sampled(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.fixture(scope="module")
-def tissue703_oracle():
-    """The 703,026 x 1,000 cube and the FP64 oracle's fit of it (k = 50)."""
-    cube = synth.tissue_703k()
-    p = oracle_params(cube, k=50)
-    ref = wf.fit(cube.i_cars.astype(np.float64), cube.i_ref, p, svd="gram")
-    return cube, p, ref["basis"], ref["im"]
-
-
 @pytest.mark.slow
 @pytest.mark.parametrize("gram_prec", [fk.PREC_FP64, fk.PREC_SPLIT])
 def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle, gram_prec):
@@ -861,7 +852,8 @@ def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle, gram_pr
     # FP64 oracle's own fit of the same FP32 input, with the Gram on the FP64
     # matrix cores and with the int8 splitting
     say(f"paper-scale fit, gram_prec={gram_prec}, vs oracle")
-    cube, p, ref_basis, ref_im = tissue703_oracle
+    o = tissue703_oracle
+    cube, p, ref_basis, ref_im = o.cube, o.p, o.basis, o.im
     t = dev(cube.i_cars)
     b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=gram_prec))
     got = out.cpu().numpy()
@@ -883,7 +875,7 @@ def test_stored_basis_stream_frames_vs_oracle(ctx, tissue703_oracle):
     # Eq. 23 of the exported device basis (1e-5); with the FP64 Gram it also
     # matches the oracle's own basis (1e-5); with the FP32 Gram that distance
     # is reported
-    cube, p, ref_basis, _ = tissue703_oracle
+    cube, p, ref_basis = tissue703_oracle.cube, tissue703_oracle.p, tissue703_oracle.basis
     t = dev(cube.i_cars)
     frames = [synth.frame(i) for i in range(2)]
     oracle_own = [wf.transform(fr.i_cars.astype(np.float64), ref_basis)["im"] for fr in frames]
