@@ -580,6 +580,7 @@ def main():
     recon["frac_of_fp32_mfma_peak"] = recon["TFLOP/s"] * 1e12 / PEAK_FP32_MFMA
     stream_ref = stream_bandwidth(torch, dev, out)
     recon["frac_of_measured_copy"] = recon["GB/s"] / stream_ref["copy_GB/s"]
+    recon["frac_of_measured_fill"] = recon["GB/s"] / stream_ref["fill_GB/s"]
 
     # the FP64 oracle's fit of the same cube: every fit below is compared with it
     ref_im = ref_basis = None
@@ -665,6 +666,7 @@ def main():
                         "frac_of_bf16_peak": gram_flop / (gram16_ms * 1e-3) / PEAK_BF16_MFMA}
         bf16["reconstruction"] = recon_stats(bf16["stages_ms"]["dev_ms_recon"], kq, 2)
         bf16["reconstruction"]["frac_of_measured_copy"] = bf16["reconstruction"]["GB/s"] / stream_ref["copy_GB/s"]
+        bf16["reconstruction"]["frac_of_measured_fill"] = bf16["reconstruction"]["GB/s"] / stream_ref["fill_GB/s"]
         b16.free()
         # the split (FP64-accurate) basis with BF16 projection and reconstruction operands
         split16, b16 = leg("split-gram + bf16 reconstruction", args.steps, gram_prec=fk.PREC_SPLIT,

@@ -94,18 +94,19 @@ __device__ __forceinline__ float epilogue_hw(float re, float im) {
     return mag * (PLANE == 0 ? __builtin_amdgcn_sinf(t) : __builtin_amdgcn_cosf(t));
 }
 
-// Epilogue of a 128-spectrum reconstruction tile: lane l of wave w holds,
-// in acc[ib][jb][v], wavenumber j0 + 16 ib + 4 (l/16) + v of spectrum
-// r0 + 32 w + 16 jb + l%16.  All 32 values of a lane are evaluated in one
-// straight-line block before any store; only the stores are guarded, and
-// a tile that lies inside the matrix takes an unguarded path.
-template <int PLANE, bool VEC_OUT, bool HW_SIN>
+// Epilogue of a 128-spectrum reconstruction tile over 16 NIB wavenumbers:
+// lane l of wave w holds, in acc[ib][jb][v], wavenumber j0 + 16 ib +
+// 4 (l/16) + v of spectrum r0 + 32 w + 16 jb + l%16.  All values of a lane
+// are evaluated in one straight-line block before any store; only the
+// stores are guarded, and a tile that lies inside the matrix takes an
+// unguarded path.
+template <int PLANE, bool VEC_OUT, bool HW_SIN, int NIB>
 __device__ __forceinline__ void store_plane(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
-                                            int wave, int lane, int j0, const floatx4 (&are)[4][2],
-                                            const floatx4 (&aim)[4][2]) {
-    float o[4][2][4];
+                                            int wave, int lane, int j0, const floatx4 (&are)[NIB][2],
+                                            const floatx4 (&aim)[NIB][2]) {
+    float o[NIB][2][4];
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
+    for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
@@ -114,9 +115,9 @@ __device__ __forceinline__ void store_plane(float* __restrict__ out, int64_t ld_
                                       : epilogue<PLANE>(are[ib][jb][v], aim[ib][jb][v]);
     const int64_t row0 = r0 + wave * 32 + (lane & 15);
     const int col0 = j0 + 4 * (lane >> 4);
-    if (VEC_OUT && j0 + 64 <= N && r0 + 128 <= M) {  // uniform: whole tile inside
+    if (VEC_OUT && j0 + 16 * NIB <= N && r0 + 128 <= M) {  // uniform: whole tile inside
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib)
+        for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb)
                 *reinterpret_cast<float4*>(out + (row0 + jb * 16) * ld_out + col0 + ib * 16) =
@@ -124,7 +125,7 @@ __device__ __forceinline__ void store_plane(float* __restrict__ out, int64_t ld_
         return;
     }
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
+    for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb) {
             const int64_t row = row0 + jb * 16;
@@ -142,13 +143,13 @@ __device__ __forceinline__ void store_plane(float* __restrict__ out, int64_t ld_
 }
 
 // The plane is chosen once per tile, outside the per-value code.
-template <bool VEC_OUT, bool HW_SIN = false>
+template <bool VEC_OUT, bool HW_SIN = false, int NIB = 4>
 __device__ __forceinline__ void store_out(float* __restrict__ out, int64_t ld_out, int64_t M, int N, int64_t r0,
-                                          int wave, int lane, int j0, const floatx4 (&are)[4][2],
-                                          const floatx4 (&aim)[4][2], int plane) {
-    if (plane == 0) store_plane<0, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
-    else if (plane == 1) store_plane<1, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
-    else store_plane<2, VEC_OUT, HW_SIN>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
+                                          int wave, int lane, int j0, const floatx4 (&are)[NIB][2],
+                                          const floatx4 (&aim)[NIB][2], int plane) {
+    if (plane == 0) store_plane<0, VEC_OUT, HW_SIN, NIB>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
+    else if (plane == 1) store_plane<1, VEC_OUT, HW_SIN, NIB>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
+    else store_plane<2, VEC_OUT, HW_SIN, NIB>(out, ld_out, M, N, r0, wave, lane, j0, are, aim);
 }
 
 

@@ -329,12 +329,13 @@ __global__ __launch_bounds__(256) void project16_kernel(const float* __restrict_
 // in registers).  B^T is (rows = wavenumbers) x KQ BF16, 16-byte units
 // staged with one unit of padding per row.
 // ---------------------------------------------------------------------------
-template <int KB2>
+template <int KB2, int NIB = 4>
 __device__ __forceinline__ void recon16_chunk(const u32x4 (&zb)[2][KB2], const u32x4* sRe, const u32x4* sIm,
-                                              int lane, floatx4 (&are)[4][2], floatx4 (&aim)[4][2]) {
+                                              int lane, floatx4 (&are)[NIB][2], floatx4 (&aim)[NIB][2],
+                                              int ib0 = 0) {
     constexpr int BLDU = KB2 * 4 + 1;
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
+    for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb) {
             are[ib][jb] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -343,8 +344,8 @@ __device__ __forceinline__ void recon16_chunk(const u32x4 (&zb)[2][KB2], const u
 #pragma unroll
     for (int kg = 0; kg < KB2; ++kg)
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            const int off = (ib * 16 + (lane & 15)) * BLDU + kg * 4 + (lane >> 4);
+        for (int ib = 0; ib < NIB; ++ib) {
+            const int off = ((ib0 + ib) * 16 + (lane & 15)) * BLDU + kg * 4 + (lane >> 4);
             const u32x4 bre = sRe[off];
             const u32x4 bim = sIm[off];
 #pragma unroll
@@ -403,32 +404,131 @@ __device__ __forceinline__ void recon16_loop(const u32x4 (&zb)[2][KB2], const u3
     }
 }
 
-template <int KB2, bool VEC_OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB2 <= 2 ? 3 : 1))) void recon16_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z, int k,
-                                                      const u32x4* __restrict__ BreT, const u32x4* __restrict__ BimT,
-                                                      int N, float* __restrict__ out, int64_t ld_out, int plane) {
-    constexpr int BLDU = KB2 * 4 + 1;
-    __shared__ u32x4 sRe[RCN * BLDU];
-    __shared__ u32x4 sIm[RCN * BLDU];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * PR;
-    u32x4 zb[2][KB2];
+// ---------------------------------------------------------------------------
+// Reconstruction with the basis resident in LDS.  A block of 8 waves holds a
+// slice of CW wavenumbers of B_re^T and B_im^T (zero rows past N) for the
+// whole launch and walks TPB consecutive tiles of 256 spectra, 32 per wave.
+// The main loop has no barrier and no basis load: its only vector loads are
+// the next tile's Z, issued before the current tile's stores, so the wait
+// for them (one counter covers loads and stores) reaches only stores of two
+// tiles back.
+// ---------------------------------------------------------------------------
+constexpr int RS_THREADS = 512;
+constexpr int RS_ROWS = 256;                 // spectra per tile
+constexpr int RS_LDS_UNITS = 144 * 1024 / 16;  // LDS for the two basis slices
+
+// Largest slice width (multiple of RCN) whose two planes fit the LDS budget.
+constexpr int rs_cw_max(int kb2) { return (RS_LDS_UNITS / (2 * (kb2 * 4 + 1))) / RCN * RCN; }
+
+// Raw FP32 Z of one wave's 32 spectra: zr[jb][kg][q] = Z[row][kg 32 + 8 (l/16) + q],
+// row = r0 + 16 jb + l%16 (zero past M or k; loads from clamped addresses;
+// VEC: rows 16-byte aligned, eight-value groups inside k read as two float4).
+template <int KB2, bool VEC>
+__device__ __forceinline__ void rs_load_z(float (&zr)[2][KB2][8], const float* __restrict__ Z, int64_t ld_z,
+                                          int64_t M, int k, int64_t r0, int lane) {
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
+    for (int jb = 0; jb < 2; ++jb) {
+        const int64_t row = r0 + jb * 16 + (lane & 15);
+        const float* zrow = Z + (row < M ? row : M - 1) * ld_z;
+        const float live = row < M ? 1.f : 0.f;
 #pragma unroll
         for (int kg = 0; kg < KB2; ++kg) {
-            const int64_t row = r0 + wave * 32 + jb * 16 + (lane & 15);
             const int c = kg * 32 + 8 * (lane >> 4);
-            // unconditional loads from clamped (in-bounds) addresses, masked
-            // by a multiply: guarded loads each wait for the previous one
-            const float* zr = Z + (row < M ? row : M - 1) * ld_z;
-            float v[8];
+            if (VEC && c + 8 <= k) {
+                const float4 a = *reinterpret_cast<const float4*>(zrow + c);
+                const float4 b = *reinterpret_cast<const float4*>(zrow + c + 4);
+                zr[jb][kg][0] = a.x * live; zr[jb][kg][1] = a.y * live;
+                zr[jb][kg][2] = a.z * live; zr[jb][kg][3] = a.w * live;
+                zr[jb][kg][4] = b.x * live; zr[jb][kg][5] = b.y * live;
+                zr[jb][kg][6] = b.z * live; zr[jb][kg][7] = b.w * live;
+            } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                v[q] = zr[c + q < k ? c + q : k - 1] * ((row < M && c + q < k) ? 1.f : 0.f);
-            zb[jb][kg] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+                for (int q = 0; q < 8; ++q)
+                    zr[jb][kg][q] = zrow[c + q < k ? c + q : k - 1] * ((c + q < k) ? live : 0.f);
+            }
         }
-    recon16_loop<KB2, VEC_OUT>(zb, BreT, BimT, sRe, sIm, N, out, ld_out, M, r0, plane);
+    }
+}
+
+template <int KB2, bool VEC_OUT, bool VEC_Z>
+__global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z,
+                                                              int k, const u32x4* __restrict__ BreT,
+                                                              const u32x4* __restrict__ BimT, int N, int npad, int cw,
+                                                              int nslice, int tpb, float* __restrict__ out,
+                                                              int64_t ld_out, int plane) {
+    constexpr int UPR = KB2 * 4;   // 16-byte units per basis row
+    constexpr int BLDU = UPR + 1;  // padded LDS row
+    __shared__ u32x4 sB[RS_LDS_UNITS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // blockIdx -> (slice, tile group): the nslice blocks of one tile group are
+    // 8 apart, so they run on the same XCD and share its L2 for Z
+    const int b = blockIdx.x;
+    const int xcd = b & 7, rr = b >> 3;
+    const int slice = rr % nslice;
+    const int64_t group = (int64_t)(rr / nslice) * 8 + xcd;
+    const int64_t ntiles = (M + RS_ROWS - 1) / RS_ROWS;
+    const int64_t t0 = group * tpb;
+    if (t0 >= ntiles) return;
+    const int64_t t1 = (t0 + tpb < ntiles) ? t0 + tpb : ntiles;
+    const int c0 = slice * cw;
+    const int c1 = (c0 + cw < N) ? c0 + cw : N;
+
+    // basis slice to LDS: rows c0 .. c0 + cw - 1 (zero past npad)
+    u32x4* sRe = sB;
+    u32x4* sIm = sB + cw * BLDU;
+    // (eight units per plane in flight per thread before the LDS writes)
+    for (int base = 0; base < cw * UPR; base += 8 * RS_THREADS) {
+        u32x4 vre[8], vim[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int idx = base + p * RS_THREADS + tid;
+            const int j = c0 + idx / UPR;
+            const bool live = idx < cw * UPR && j < npad;
+            const size_t src = live ? (size_t)j * UPR + idx % UPR : 0;
+            vre[p] = BreT[src];
+            vim[p] = BimT[src];
+            if (!live) vre[p] = vim[p] = u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int idx = base + p * RS_THREADS + tid;
+            if (idx < cw * UPR) {
+                sRe[(idx / UPR) * BLDU + idx % UPR] = vre[p];
+                sIm[(idx / UPR) * BLDU + idx % UPR] = vim[p];
+            }
+        }
+    }
+    __syncthreads();
+
+    // rows of this wave within a tile: half h = wave / 4 of the 256, and
+    // 32 (wave % 4) .. + 31 within the half (the layout store_out takes)
+    // (the next tile's Z is loaded ahead where registers allow: KB2 <= 2)
+    constexpr bool PF = KB2 <= 2;
+    const int h = wave >> 2, wq = wave & 3;
+    float zr[2][KB2][8];
+    if (PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, t0 * RS_ROWS + 128 * h + 32 * wq, lane);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t r0 = t * RS_ROWS + 128 * h;
+        if (!PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + 32 * wq, lane);
+        u32x4 zb[2][KB2];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int kg = 0; kg < KB2; ++kg)
+                zb[jb][kg] = u32x4{pack2(zr[jb][kg][0], zr[jb][kg][1]), pack2(zr[jb][kg][2], zr[jb][kg][3]),
+                                   pack2(zr[jb][kg][4], zr[jb][kg][5]), pack2(zr[jb][kg][6], zr[jb][kg][7])};
+        if (PF && t + 1 < t1) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + RS_ROWS + 32 * wq, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        // each 64-wavenumber chunk in two halves, so that the stores of the
+        // first half go out while the second half is multiplied
+        for (int j0 = c0; j0 < c1; j0 += RCN)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                floatx4 are[2][2], aim[2][2];
+                recon16_chunk<KB2, 2>(zb, sRe + (j0 - c0) * BLDU, sIm + (j0 - c0) * BLDU, lane, are, aim, 2 * hh);
+                store_out<VEC_OUT, true, 2>(out, ld_out, M, N, r0, wq, lane, j0 + 32 * hh, are, aim, plane);
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -588,25 +688,42 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
                                 hipStream_t s) {
     if (M <= 0) return hipSuccess;
     if (k < 1 || k > ld_z) return hipErrorInvalidValue;
+    if (kq != 32 && kq != 64 && kq != 128) return hipErrorInvalidValue;
+    const int kb2 = kq / 32;
+    const int npad = (N + kGramTile - 1) / kGramTile * kGramTile;
     const bool vec = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
-    dim3 grid((unsigned)((M + PR - 1) / PR));
+    const bool vz = ((reinterpret_cast<uintptr_t>(Z) & 15) == 0) && (ld_z % 4 == 0);
     const u32x4* bre = reinterpret_cast<const u32x4*>(BreT);
     const u32x4* bim = reinterpret_cast<const u32x4*>(BimT);
-#define FKK_RC16(KB2)                                                                                             \
-    do {                                                                                                          \
-        if (vec)                                                                                                  \
-            hipLaunchKernelGGL((recon16_kernel<KB2, true>), grid, dim3(256), 0, s, Z, M, ld_z, k, bre, bim, N, out, \
-                               ld_out, plane);                                                                    \
-        else                                                                                                      \
-            hipLaunchKernelGGL((recon16_kernel<KB2, false>), grid, dim3(256), 0, s, Z, M, ld_z, k, bre, bim, N,     \
-                               out, ld_out, plane);                                                               \
+    // wavenumber slices of equal width (multiple of RCN) that fit LDS
+    const int cwm = rs_cw_max(kb2);
+    const int nslice = (N + cwm - 1) / cwm;
+    const int cw = ((N + nslice - 1) / nslice + RCN - 1) / RCN * RCN;
+    // tiles per block: about 2048 blocks over the whole launch
+    const int64_t ntiles = (M + RS_ROWS - 1) / RS_ROWS;
+    int64_t tpb = (ntiles * nslice + 2047) / 2048;
+    if (tpb < 1) tpb = 1;
+    const int64_t groups = (ntiles + tpb - 1) / tpb;
+    // block b -> group 8 (b / 8 / nslice) + b % 8: groups padded to a multiple of 8
+    const int64_t nblocks = (groups + 7) / 8 * 8 * nslice;
+    if (nblocks > INT_MAX) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblocks), block(RS_THREADS);
+#define FKK_RC16(KB2, VO, VZ)                                                                                      \
+    hipLaunchKernelGGL((recon16s_kernel<KB2, VO, VZ>), grid, block, 0, s, Z, M, ld_z, k, bre, bim, N, npad, cw,       \
+                       nslice, (int)tpb, out, ld_out, plane)
+#define FKK_RC16_K(KB2)                                             \
+    do {                                                            \
+        if (vec && vz) FKK_RC16(KB2, true, true);                   \
+        else if (vec) FKK_RC16(KB2, true, false);                   \
+        else if (vz) FKK_RC16(KB2, false, true);                    \
+        else FKK_RC16(KB2, false, false);                           \
     } while (0)
-    switch (kq) {
-        case 32: FKK_RC16(1); break;
-        case 64: FKK_RC16(2); break;
-        case 128: FKK_RC16(4); break;
-        default: return hipErrorInvalidValue;
+    switch (kb2) {
+        case 1: FKK_RC16_K(1); break;
+        case 2: FKK_RC16_K(2); break;
+        default: FKK_RC16_K(4); break;
     }
+#undef FKK_RC16_K
 #undef FKK_RC16
     return hipGetLastError();
 }
