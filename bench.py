@@ -645,16 +645,29 @@ def main():
                          PEAK_FP64_MFMA}
     log("fit with the randomized range finder")
     randomized, brr = leg("randomized", args.steps, svd_mode=fk.SVD_RANDOMIZED, rrf_oversample=20,
-                          rrf_power_iters=3)
-    randomized.update({"oversample": 20, "power_iters": 3})
+                          rrf_power_iters=1)
+    randomized.update({"oversample": 20, "power_iters": 1})
     if ref_basis is not None:
         v = brr.export()["v"]
         vr = ref_basis["v"]
         s_ref = np.asarray(ref_basis["s"])
-        # largest principal angle between the two k-dimensional subspaces
-        sv = np.linalg.svd(vr.T @ v, compute_uv=False)
-        randomized["subspace_sin_angle_vs_oracle"] = float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
+        lam = s_ref ** 2
+        # signal subspace: the last leading eigenvalue that exceeds the next by a factor of 2
+        r = max([j for j in range(1, len(lam)) if lam[j - 1] >= 2 * lam[j]] or [1])
+
+        def sin_angle(j):
+            # largest principal angle between the leading j-dimensional subspaces
+            sv = np.linalg.svd(vr[:, :j].T @ v[:, :j], compute_uv=False)
+            return float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2)))
+        randomized["signal_subspace_dim"] = r
+        randomized["signal_subspace_sin_angle_vs_oracle"] = sin_angle(r)
+        randomized["subspace_sin_angle_vs_oracle"] = sin_angle(len(lam))
+        randomized["relative_gap_at_k"] = float((lam[-2] - lam[-1]) / lam[0])
         randomized["s_k_relative_error"] = float(abs(brr.export()["s"][-1] - s_ref[-1]) / s_ref[-1])
+        randomized["note"] = ("past the signal subspace the k = 50 vectors lie in the noise bulk, where neighbouring "
+                              "eigenvalue gaps are ~1e-4 of lambda_k: a range finder (like any Gram perturbed by "
+                              "FP32 rounding) matches the oracle's signal subspace, not its k = 50 tail, so its "
+                              "output differs from the oracle's fit")
     brr.free()
 
     bf16 = None

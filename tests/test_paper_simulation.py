@@ -58,3 +58,25 @@ def test_fkk_ec_matches_conventional_rss(sim64):
     rss_conv = ((conv["im"] - ideal) ** 2).sum(axis=1).mean()
     assert rss_fit < 0.3 * null and rss_conv < 0.3 * null
     assert abs(rss_fit - rss_conv) < 0.05 * rss_conv, (rss_fit, rss_conv)
+
+
+def test_rank_rule_at_fp64_epsilon_needs_the_svd_of_a_itself(sim64):
+    # The FP64 cut-off (s_max max(M, N) eps_64, about 1e-12 s_max here) lies
+    # far below what any route through the Gram A^T A resolves: its
+    # eigenvalues carry an absolute error of order eps_64 lam_max, so the
+    # singular values from it bottom out near sqrt(eps_64) s_max ~ 1e-8 s_max.
+    # LAPACK's SVD of A keeps tens of vectors; the oracle's own FP64 Gram route
+    # keeps hundreds (its floor is above the cut); at the FP32 cut-off both
+    # routes agree.
+    i64 = np.asarray(sim64.i_cars, dtype=np.float64)
+    ell, _ = wf.log_ratio(i64, sim64.i_ref, 1e-6)
+    a = ell * wf.scaling_f(i64, wf.Params(k=0))
+    m, n = a.shape
+    s_svd = np.linalg.svd(a, compute_uv=False)
+    s_gram = np.sqrt(np.maximum(np.linalg.eigvalsh(a.T @ a)[::-1], 0.0))
+    eps64, eps32 = float(np.finfo(np.float64).eps), float(np.finfo(np.float32).eps)
+    k_svd, k_gram = wf.rank_cutoff(s_svd, m, n, eps64), wf.rank_cutoff(s_gram, m, n, eps64)
+    assert 25 <= k_svd <= 50 and k_gram > 4 * k_svd, (k_svd, k_gram)
+    # at the last vector the SVD keeps, the Gram route's value is rounding noise
+    assert s_gram[k_svd - 1] > 1e-9 * s_gram[0] > 1e2 * s_svd[k_svd - 1]
+    assert wf.rank_cutoff(s_svd, m, n, eps32) == wf.rank_cutoff(s_gram, m, n, eps32)
