@@ -566,9 +566,12 @@ def main():
                 "fp64_equivalent": {"flop_per_launch": gram_flop,
                                     "TFLOP/s": gram_flop / (gram_ms * 1e-3) / 1e12,
                                     "frac_of_fp64_mfma_peak": gram_flop / (gram_ms * 1e-3) / PEAK_FP64_MFMA}}
+    split_bytes = (1.0 + 1.0 / 16) * 4.0 * m * n + 4.0 * m * npad
     split_passes = {"ms": stage["dev_ms_logratio"],
-                    "GB/s": (2 * 4.0 * m * n + 4.0 * m * npad) / (stage["dev_ms_logratio"] * 1e-3) / 1e9,
-                    "note": "column statistics pass (reads I) + slicing pass (reads I, writes the four int8 slices)"}
+                    "GB/s": split_bytes / (stage["dev_ms_logratio"] * 1e-3) / 1e9,
+                    "HBM_frac": split_bytes / (stage["dev_ms_logratio"] * 1e-3) / PEAK_HBM,
+                    "note": "column maxima of every 16th row (exponents) + slicing pass (reads I; writes the four "
+                            "int8 slices, the FP64 column-sum partials and the clamp count)"}
 
     def recon_stats(ms, kcols, bytes_per_basis_elem):
         nbytes = 4.0 * m * n + 4.0 * m * kp + 2.0 * n * kcols * bytes_per_basis_elem

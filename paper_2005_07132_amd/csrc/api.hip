@@ -412,6 +412,9 @@ fkk_basis* new_basis(int N, int k, const double* iref, const double* f, const do
 
 int npad_for(int N) { return round_up(N, fkk::dev::kGramTile); }
 
+// Rows between the sampled rows of the split Gram's column exponents.
+constexpr int kSplitSampleStride = 16;
+
 // ---- device workspace layouts ------------------------------------------------
 
 // Log ratio, Gram and column sums (Eq. 2, 6, 9).  with_gram false: the
@@ -423,7 +426,7 @@ struct GramWs {
     double* G = nullptr;                 // N x N FP64 (rrf: npad x 128 + 128 x 128)
     double* colsum_part = nullptr;       // per-block column sums
     double* colsum = nullptr;            // N sums + reduction scratch
-    unsigned long long* clamps = nullptr;
+    unsigned long long* clamps = nullptr;  // [0] clamp count, [1] split-slice overflow flag
     int* tiles = nullptr;                // tile pairs
     float* rinv = nullptr;               // 1/I_ref as two floats per wavenumber
     // FKK_PREC_SPLIT only (L then holds the int8 slices)
@@ -455,7 +458,7 @@ void gram_layout(Carve& c, int64_t M, int N, int prec, bool with_gram, bool rrf,
     w->G = c.take<double>(g);
     w->colsum_part = c.take<double>((size_t)fkk::dev::logratio_blocks(M) * npad);
     w->colsum = c.take<double>(N + fkk::dev::colsum_scratch_doubles(N));
-    w->clamps = c.take<unsigned long long>(1);
+    w->clamps = c.take<unsigned long long>(2);
     w->tiles = c.take<int>(tiles);
     w->rinv = c.take<float>(2 * (size_t)N);
     if (split) {
@@ -550,8 +553,12 @@ fkk_status acquire_ws(fkk_ctx* ctx, void* d_ws, size_t ws_bytes, size_t need, vo
 // Log-ratio pass into w.L, Gram G_L = l^T l into w.G (device, FP64, N x N),
 // column sums into w.colsum and the clamp count into w.clamps.
 // with_gram false: the log-ratio pass and column sums only (FP32 l).
+// Split Gram: exact_exp false takes the column exponents from a sample of
+// the rows (one bit of headroom); gram_with_sums redoes the pass with exact
+// ones when a row did not fit.
 fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t M, int N, int64_t ld,
-                       const double* h_iref, double floor, int prec, bool timed, bool with_gram = true) {
+                       const double* h_iref, double floor, int prec, bool timed, bool with_gram = true,
+                       bool exact_exp = false) {
     const int npad = npad_for(N);
     const bool bf16 = (prec == FKK_PREC_BF16), split = (prec == FKK_PREC_SPLIT) && with_gram;
     const fkk::dev::GramPlan plan =
@@ -565,7 +572,7 @@ fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t 
     if (with_gram)
         FKK_HIP(ctx, hipMemcpyAsync(w.tiles, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
     FKK_HIP(ctx, hipMemcpyAsync(w.rinv, rinv.data(), rinv.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    FKK_HIP(ctx, hipMemsetAsync(w.clamps, 0, sizeof(unsigned long long), s));
+    FKK_HIP(ctx, hipMemsetAsync(w.clamps, 0, 2 * sizeof(unsigned long long), s));
     if (split) {
         // column statistics, exponents and the int8 slices of the FP64 log
         // ratio; then the Gram on the int8 matrix cores
@@ -574,9 +581,18 @@ fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t 
         FKK_HIP(ctx, hipMemcpyAsync(w.rinv64, r64.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
         const int64_t nst = fkk::dev::stats_blocks(M);
         if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[8], s));
-        FKK_HIP(ctx, fkk::dev::launch_split_stats(d_I, M, N, ld, w.rinv, (float)floor, npad, w.colsum_part, w.colmax,
-                                                  w.clamps, w.colexp, s));
-        FKK_HIP(ctx, fkk::dev::launch_split_slices(d_I, M, N, ld, w.rinv64, floor, w.colexp, npad, w.L, s));
+        if (exact_exp) {
+            // the statistics pass's sums and clamp count are recomputed by
+            // the slicing pass
+            FKK_HIP(ctx, fkk::dev::launch_split_stats(d_I, M, N, ld, w.rinv, (float)floor, npad, w.colsum_part,
+                                                      w.colmax, w.clamps, w.colexp, s));
+            FKK_HIP(ctx, hipMemsetAsync(w.clamps, 0, 2 * sizeof(unsigned long long), s));
+        } else {
+            FKK_HIP(ctx, fkk::dev::launch_split_sample(d_I, M, N, ld, w.rinv, (float)floor, npad, kSplitSampleStride,
+                                                       w.colmax, w.colexp, s));
+        }
+        FKK_HIP(ctx, fkk::dev::launch_split_slices(d_I, M, N, ld, w.rinv64, floor, w.colexp, npad, w.L,
+                                                   w.colsum_part, w.clamps, s));
         if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[9], s));
         if (timed) FKK_HIP(ctx, hipEventRecord(ctx->ev[0], s));
         FKK_HIP(ctx, fkk::dev::launch_gram_split(w.L, npad, M, plan, w.tiles, w.colexp, w.partial, s));
@@ -609,19 +625,39 @@ fkk_status gram_device(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t 
     return FKK_OK;
 }
 
-// Column sums and clamp count back to the host (synchronises the stream).
-fkk_status fetch_sums(fkk_ctx* ctx, const GramWs& w, int N, double* h_colsum, int64_t* h_clamps) {
-    FKK_HIP(ctx, ctx->hG.ensure((size_t)N + 1));
+// Column sums and clamp count back to the host (synchronises the stream);
+// *overflow: the split slicing pass found a row past its column exponent.
+fkk_status fetch_sums(fkk_ctx* ctx, const GramWs& w, int N, double* h_colsum, int64_t* h_clamps,
+                      bool* overflow = nullptr) {
+    FKK_HIP(ctx, ctx->hG.ensure((size_t)N + 2));
     hipStream_t s = ctx->stream;
     double* hg = ctx->hG.p;
     FKK_HIP(ctx, hipMemcpyAsync(hg, w.colsum, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FKK_HIP(ctx, hipMemcpyAsync(hg + N, w.clamps, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    FKK_HIP(ctx, hipMemcpyAsync(hg + N, w.clamps, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     FKK_HIP(ctx, hipStreamSynchronize(s));
     std::memcpy(h_colsum, hg, N * sizeof(double));
-    unsigned long long c;
-    std::memcpy(&c, hg + N, sizeof c);
-    *h_clamps = (int64_t)c;
+    unsigned long long c[2];
+    std::memcpy(c, hg + N, sizeof c);
+    *h_clamps = (int64_t)c[0];
+    if (overflow) *overflow = c[1] != 0;
     return FKK_OK;
+}
+
+// gram_device and fetch_sums; for the split Gram, once more with exact column
+// exponents when the sampled ones were too small for some row.
+fkk_status gram_with_sums(fkk_ctx* ctx, const GramWs& w, const float* d_I, int64_t M, int N, int64_t ld,
+                          const double* h_iref, double floor, int prec, bool timed, bool with_gram, double* h_colsum,
+                          int64_t* h_clamps, bool* redone = nullptr) {
+    fkk_status st = gram_device(ctx, w, d_I, M, N, ld, h_iref, floor, prec, timed, with_gram, false);
+    bool ovf = false;
+    if (st == FKK_OK) st = fetch_sums(ctx, w, N, h_colsum, h_clamps, &ovf);
+    if (redone) *redone = false;
+    if (st != FKK_OK || !ovf || prec != FKK_PREC_SPLIT || !with_gram) return st;
+    if (redone) *redone = true;
+    st = gram_device(ctx, w, d_I, M, N, ld, h_iref, floor, prec, timed, with_gram, true);
+    if (st == FKK_OK) st = fetch_sums(ctx, w, N, h_colsum, h_clamps, &ovf);
+    if (st == FKK_OK && ovf) return ctx->fail(FKK_EINTERNAL, "split Gram: a row exceeds its exact column exponent");
+    return st;
 }
 
 // Host end of the eigensolve once the reduction is queued on s: the small
@@ -969,12 +1005,15 @@ fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_
     if ((st = acquire_ws(ctx, nullptr, 0, sizing.bytes(), &base)) != FKK_OK) return st;
     Carve c(base);
     gram_layout(c, M, N, prec, true, false, &w);
-    if ((st = gram_device(ctx, w, d_I, M, N, ld, h_iref, ratio_floor, prec, false)) != FKK_OK) return st;
-    if (h_gram) FKK_HIP(ctx, hipMemcpyAsync(h_gram, w.G, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost,
-                                            ctx->stream));
     std::vector<double> cs(N);
     int64_t cl = 0;
-    if ((st = fetch_sums(ctx, w, N, cs.data(), &cl)) != FKK_OK) return st;
+    if ((st = gram_with_sums(ctx, w, d_I, M, N, ld, h_iref, ratio_floor, prec, false, true, cs.data(), &cl)) !=
+        FKK_OK)
+        return st;
+    if (h_gram) {
+        FKK_HIP(ctx, hipMemcpyAsync(h_gram, w.G, (size_t)N * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        FKK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
     if (h_colsum) std::memcpy(h_colsum, cs.data(), N * sizeof(double));
     if (h_clamps) *h_clamps = cl;
     return FKK_OK;
@@ -1046,8 +1085,9 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     const bool rrf = (p->svd_mode == FKK_SVD_RANDOMIZED);
     // the range finder works from the FP32 log ratio, whatever gram_prec says
     const int gprec = rrf ? FKK_PREC_FP32 : p->gram_prec;
-    if ((st = gram_device(ctx, w.g, d_I, M, N, ld, h_iref, p->ratio_floor, gprec, true, !rrf)) != FKK_OK) return st;
-    if ((st = fetch_sums(ctx, w.g, N, colsum.data(), &clamps)) != FKK_OK) return st;
+    if ((st = gram_with_sums(ctx, w.g, d_I, M, N, ld, h_iref, p->ratio_floor, gprec, true, !rrf, colsum.data(),
+                             &clamps)) != FKK_OK)
+        return st;
     r.dev_ms_gram = rrf ? 0.0 : ctx->elapsed(0, 1);
     r.dev_ms_logratio = ctx->elapsed(8, 9);
     r.clamps = clamps;

@@ -152,11 +152,18 @@ size_t stats_colmax_floats(int64_t M, int npad);  // colmax_part: partials and g
 hipError_t launch_split_stats(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
                               double* colsum_part, float* colmax_part, unsigned long long* clamps, int* colexp,
                               hipStream_t s);
+// exponents from the maxima of every stride-th row with one bit of headroom
+// (colmax_part as for the stats, at least stats_colmax_floats(M, npad)).
+hipError_t launch_split_sample(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
+                               int stride, float* colmax_part, int* colexp, hipStream_t s);
 // slices of the FP64 log ratio (rinv64: 1/I_ref, N doubles) into S,
-// split_bytes(M, npad) bytes (rows padded to a multiple of 64 with zeros).
+// split_bytes(M, npad) bytes (rows padded to a multiple of 64 with zeros),
+// with the FP64 column-sum partials (stats layout) and flags[0] += clamped
+// ratios, flags[1] set when a row does not fit its column's exponent.
 size_t split_bytes(int64_t M, int npad);
 hipError_t launch_split_slices(const float* I, int64_t M, int N, int64_t ld, const double* rinv64, double floor,
-                               const int* colexp, int npad, void* S, hipStream_t s);
+                               const int* colexp, int npad, void* S, double* colsum_part,
+                               unsigned long long* flags, hipStream_t s);
 // chunk partials of the Gram from the slices (plan from split_gram_plan),
 // reduced by launch_gram_reduce.
 GramPlan split_gram_plan(int64_t M, int N);

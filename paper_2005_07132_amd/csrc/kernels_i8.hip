@@ -122,7 +122,8 @@ __global__ __launch_bounds__(256) void colmax_group_kernel(const float* __restri
     }
 }
 
-__global__ void colexp_kernel(const float* __restrict__ gmax, int groups, int npad, int N, int* __restrict__ colexp) {
+__global__ void colexp_kernel(const float* __restrict__ gmax, int groups, int npad, int N, int margin,
+                              int* __restrict__ colexp) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= npad) return;
     float m = 0.f;
@@ -131,84 +132,162 @@ __global__ void colexp_kernel(const float* __restrict__ gmax, int groups, int np
     const double bound = (double)m * (1.0 + 0x1p-16) + 0x1p-20;
     int e;
     frexp(bound, &e);  // bound = f 2^e, 1/2 <= f < 1, so bound < 2^e
-    colexp[j] = e;
+    colexp[j] = e + margin;
+}
+
+// Column maxima of |l| over every stride-th row only (FP32 log ratio as in
+// stats_kernel): SAMPLE_ROWS sampled rows per block.  The exponents taken
+// from them get one bit of headroom; a row outside it is caught by the
+// slicing pass's overflow flag.
+constexpr int SAMPLE_ROWS = 64;
+__global__ __launch_bounds__(256) void sample_max_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                         const float* __restrict__ rinv, float floor, int npad,
+                                                         int stride, float* __restrict__ colmax_part) {
+    const int64_t nsamp = (M + stride - 1) / stride;
+    const int64_t t0 = (int64_t)blockIdx.x * SAMPLE_ROWS;
+    const int64_t t1 = (t0 + SAMPLE_ROWS < nsamp) ? t0 + SAMPLE_ROWS : nsamp;
+    for (int g0 = 0; g0 < npad; g0 += 1024) {
+        const int c = g0 + 4 * (int)threadIdx.x;
+        if (c >= npad) continue;
+        float r[4], rl[4], mx[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            r[q] = (c + q < N) ? rinv[c + q] : 0.f;
+            rl[q] = (c + q < N) ? rinv[N + c + q] : 0.f;
+        }
+        for (int64_t t = t0; t < t1; ++t) {
+            const float* row = I + t * stride * ld;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (c + q >= N) continue;
+                bool bad;
+                const float l = log_ratio(row[c + q], r[q], rl[q], floor, bad);
+                mx[q] = fmaxf(mx[q], fabsf(l));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) colmax_part[(size_t)blockIdx.x * npad + c + q] = mx[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // slices: one thread per (row group, column)
 // ---------------------------------------------------------------------------
 // ln q in FP64 for q > 0 (finite): q = mant 2^k, mant in [1/2, 1); mant =
-// c (1 + u) with c the centre of mant's 1/64-wide cell (tab: 1/c, ln c), so
-// |u| <= 1/64 and ln(1 + u) = u - u^2/2 + ... + u^7/7 leaves below 2^-45.
+// c (1 + u) with c the centre of mant's 1/128-wide cell (tab: 1/c, ln c), so
+// |u| <= 1/128 and ln(1 + u) = u - u^2/2 + ... + u^5/5 leaves below 4e-14.
 __device__ __forceinline__ double log_cells(double q, const double* tab) {
     int k;
     const double mant = frexp(q, &k);
-    const int i = (int)((mant - 0.5) * 64.0);  // 0..31
+    const int i = (int)fma(mant, 128.0, -64.0);  // 0..63
     const double u = fma(mant, tab[2 * i], -1.0);
-    double p = fma(u, 1.0 / 7.0, -1.0 / 6.0);
-    p = fma(u, p, 0.2);
-    p = fma(u, p, -0.25);
+    double p = fma(u, 0.2, -0.25);
     p = fma(u, p, 1.0 / 3.0);
     p = fma(u, p, -0.5);
     p = fma(u, p, 1.0);
     return fma((double)k, 0.69314718055994530942, fma(u, p, tab[2 * i + 1]));
 }
 
-__global__ __launch_bounds__(256) void slice_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
-                                                    const double* __restrict__ rinv64, double floor,
-                                                    const int* __restrict__ colexp, int npad,
-                                                    u32x4v* __restrict__ S) {
-    __shared__ double tab[64];
-    if (threadIdx.x < 32) {
-        const double c = 0.5 + (threadIdx.x + 0.5) / 64.0;
+// Slices, FP64 column sums and the clamp count in one pass over I.  A block
+// takes ST_ROWS rows (16 row groups) of 256 columns, one column per thread,
+// rows in order, so the column-sum partials have stats_kernel's layout and
+// summation order; the next row group's loads are in flight while one is
+// computed.  Digits: with Y = X + 64 (1 + 2^7 + 2^14 + 2^21) > 0, the
+// balanced digits are a_s = y_s - 64 for the base-128 digits y_s of Y (a1
+// from y1 = Y >> 21 <= 128), so each is one bit-field extract; four rows'
+// bytes are packed per dword and moved to two's complement together:
+// (y + 64) ^ 0x80 for y1, ((y | 0x80) - 0x40) ^ 0x80 for y < 128 (no carry or
+// borrow between bytes in either).  flags[0] counts clamped ratios;
+// flags[1] is set when some |X| would reach 2^27 (exponent too small).
+__global__ __launch_bounds__(256) void slice_kernel(const float* __restrict__ I, int64_t M, int64_t Mpad, int N,
+                                                    int64_t ld, const double* __restrict__ rinv64, double floor,
+                                                    const int* __restrict__ colexp, int npad, u32x4v* __restrict__ S,
+                                                    double* __restrict__ colsum_part,
+                                                    unsigned long long* __restrict__ flags) {
+    __shared__ double tab[128];
+    if (threadIdx.x < 64) {
+        const double c = 0.5 + (threadIdx.x + 0.5) / 128.0;
         tab[2 * threadIdx.x] = 1.0 / c;
         tab[2 * threadIdx.x + 1] = log(c);
     }
     __syncthreads();
-    const int64_t g = blockIdx.x;
     const int j = blockIdx.y * 256 + threadIdx.x;
     if (j >= npad) return;
-    unsigned int w[4][4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w[s][u] = 0u;
-    if (j < N) {
-        const double r = rinv64[j];
-        // X = rint(x 2^27) with x = l 2^-e and l = ln(q) / 2: |X| < 2^27
-        const double scale = ldexp(0.5, 27 - colexp[j]);
-        float xs[16];
+    const bool live = j < N;
+    const double r = live ? rinv64[j] : 0.0;
+    // X = rint(x 2^27) with x = l 2^-e and l = ln(q) / 2
+    const double scale = live ? ldexp(0.5, 27 - colexp[j]) : 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * ST_ROWS;
+    const int64_t g0 = r0 / 16;
+    const int64_t g1 = ((r0 + ST_ROWS < Mpad) ? r0 + ST_ROWS : Mpad) / 16;
+    constexpr int B = 64 * (1 + (1 << 7) + (1 << 14) + (1 << 21));
+    double cs = 0.0;
+    unsigned int bad = 0;
+    bool ovf = false;
+    // loads from an in-range column (columns past N are computed and dropped)
+    const float* colp = I + (live ? j : N - 1);
+    // 16 rows of the column from row mb; rows past M read row M - 1 (and are
+    // masked below).  The pointer steps one row at a time in registers of
+    // its own (the empty asm keeps the compiler from holding 16 row offsets
+    // in scalar registers).
+    auto load = [&](int64_t mb, float (&x)[16]) {
+        const float* p = colp + (mb < M ? mb : M - 1) * ld;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int64_t m = 16 * g + q;
-            xs[q] = (m < M) ? I[m * ld + j] : 0.f;
+            x[q] = *p;
+            if (mb + q + 1 < M) p += ld;
+            asm volatile("" : "+v"(p));
         }
+    };
+    auto slice_group = [&](int64_t g, const float (&xs)[16]) {
+        unsigned int w1[4] = {0u, 0u, 0u, 0u}, w2[4] = {0u, 0u, 0u, 0u};
+        unsigned int w3[4] = {0u, 0u, 0u, 0u}, w4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int64_t m = 16 * g + q;
-            int X = 0;
-            if (m < M) {
-                double ratio = (double)xs[q] * r;
-                if (!(ratio > floor) || !(ratio < INFINITY)) ratio = floor;
-                X = (int)rint(log_cells(ratio, tab) * scale);
-            }
-            // balanced base-128 digits: X = a1 2^21 + a2 2^14 + a3 2^7 + a4,
-            // a2..a4 in [-64, 63], |a1| <= 64
-            const int a4 = ((X + 64) & 127) - 64;
-            X = (X - a4) >> 7;
-            const int a3 = ((X + 64) & 127) - 64;
-            X = (X - a3) >> 7;
-            const int a2 = ((X + 64) & 127) - 64;
-            const int a1 = (X - a2) >> 7;
+            // every element is computed; rows past M and columns past N count
+            // for nothing and slice to zero
+            const bool valid = live && (16 * g + q < M);
+            const double x = valid ? (double)xs[q] : 0.0;
+            cs += x;
+            double ratio = x * r;
+            const bool b = !(ratio > floor) || !(ratio < INFINITY);
+            bad += (b && valid) ? 1u : 0u;
+            ratio = b ? floor : ratio;
+            const double v = log_cells(ratio, tab) * scale;
+            ovf = ovf || (valid && !(fabs(v) < 0x1p27 - 0.5));
+            const int X = valid ? (int)rint(v) : 0;
+            const unsigned int Y = (unsigned int)(X + B);
             const int sh = 8 * (q & 3), u = q >> 2;
-            w[0][u] |= ((unsigned)a1 & 0xffu) << sh;
-            w[1][u] |= ((unsigned)a2 & 0xffu) << sh;
-            w[2][u] |= ((unsigned)a3 & 0xffu) << sh;
-            w[3][u] |= ((unsigned)a4 & 0xffu) << sh;
+            w1[u] |= (Y >> 21) << sh;
+            w2[u] |= __builtin_amdgcn_ubfe(Y, 14, 7) << sh;
+            w3[u] |= __builtin_amdgcn_ubfe(Y, 7, 7) << sh;
+            w4[u] |= (Y & 127u) << sh;
         }
-    }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) S[(g * 4 + s) * npad + j] = u32x4v{w[s][0], w[s][1], w[s][2], w[s][3]};
+        for (int u = 0; u < 4; ++u) {
+            w1[u] = (w1[u] + 0x40404040u) ^ 0x80808080u;
+            w2[u] = ((w2[u] | 0x80808080u) - 0x40404040u) ^ 0x80808080u;
+            w3[u] = ((w3[u] | 0x80808080u) - 0x40404040u) ^ 0x80808080u;
+            w4[u] = ((w4[u] | 0x80808080u) - 0x40404040u) ^ 0x80808080u;
+        }
+        u32x4v* out = S + g * 4 * (int64_t)npad + j;
+        out[0] = u32x4v{w1[0], w1[1], w1[2], w1[3]};
+        out[npad] = u32x4v{w2[0], w2[1], w2[2], w2[3]};
+        out[2 * npad] = u32x4v{w3[0], w3[1], w3[2], w3[3]};
+        out[3 * npad] = u32x4v{w4[0], w4[1], w4[2], w4[3]};
+    };
+    float xs[16], xn[16];
+    if (g0 < g1) load(16 * g0, xs);
+    for (int64_t g = g0; g < g1; ++g) {
+        if (g + 1 < g1) load(16 * (g + 1), xn);
+        slice_group(g, xs);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xs[q] = xn[q];
+    }
+    colsum_part[(size_t)blockIdx.x * npad + j] = live ? cs : 0.0;
+    for (int off = 32; off >= 1; off >>= 1) bad += __shfl_xor(bad, off);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(&flags[0], (unsigned long long)bad);
+    if (ovf) atomicOr(reinterpret_cast<unsigned int*>(&flags[1]), 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +468,25 @@ GramPlan split_gram_plan(int64_t M, int N) {
     return p;
 }
 
+namespace {
+
+// Column maxima partials (nb rows of npad) -> group maxima -> exponents.
+hipError_t colexp_from_parts(float* colmax_part, int64_t nb, int npad, int N, int margin, int* colexp, hipStream_t s) {
+    // group maxima go to the rows past the last partial, so no block
+    // overwrites partials that another block still reads
+    float* gmax = colmax_part + (size_t)nb * npad;
+    const int groups = (int)std::min<int64_t>(kMaxGroups, (nb + 3) / 4);
+    hipLaunchKernelGGL(colmax_group_kernel, dim3((unsigned)((npad + 63) / 64), (unsigned)groups), dim3(256), 0, s,
+                       colmax_part, nb, npad, gmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, gmax, groups, npad, N,
+                       margin, colexp);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_split_stats(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
                               double* colsum_part, float* colmax_part, unsigned long long* clamps, int* colexp,
                               hipStream_t s) {
@@ -403,26 +501,30 @@ hipError_t launch_split_stats(const float* I, int64_t M, int N, int64_t ld, cons
                            colsum_part, colmax_part, clamps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // group maxima overwrite the first rows of the partials after reading
-    // them all: they go to the rows past the last partial instead
-    float* gmax = colmax_part + (size_t)nb * npad;
-    const int groups = (int)std::min<int64_t>(kMaxGroups, (nb + 3) / 4);
-    hipLaunchKernelGGL(colmax_group_kernel, dim3((unsigned)((npad + 63) / 64), (unsigned)groups), dim3(256), 0, s,
-                       colmax_part, nb, npad, gmax);
-    e = hipGetLastError();
+    return colexp_from_parts(colmax_part, nb, npad, N, 0, colexp, s);
+}
+
+int64_t sample_blocks(int64_t M, int stride) { return ((M + stride - 1) / stride + SAMPLE_ROWS - 1) / SAMPLE_ROWS; }
+
+hipError_t launch_split_sample(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor, int npad,
+                               int stride, float* colmax_part, int* colexp, hipStream_t s) {
+    if (npad % 4 != 0 || npad < N || stride < 1 || M < 1) return hipErrorInvalidValue;
+    const int64_t nb = sample_blocks(M, stride);
+    hipLaunchKernelGGL(sample_max_kernel, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor, npad, stride,
+                       colmax_part);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, gmax, groups, npad, N,
-                       colexp);
-    return hipGetLastError();
+    return colexp_from_parts(colmax_part, nb, npad, N, 1, colexp, s);
 }
 
 hipError_t launch_split_slices(const float* I, int64_t M, int N, int64_t ld, const double* rinv64, double floor,
-                               const int* colexp, int npad, void* S, hipStream_t s) {
-    if (npad % 256 != 0 && npad % 128 != 0) return hipErrorInvalidValue;
-    const int64_t groups = (M + KROWS - 1) / KROWS * (KROWS / 16);
-    dim3 grid((unsigned)groups, (unsigned)((npad + 255) / 256));
-    hipLaunchKernelGGL(slice_kernel, grid, dim3(256), 0, s, I, M, N, ld, rinv64, floor, colexp, npad,
-                       static_cast<u32x4v*>(S));
+                               const int* colexp, int npad, void* S, double* colsum_part,
+                               unsigned long long* flags, hipStream_t s) {
+    if (npad % 128 != 0 || npad < N || M < 1) return hipErrorInvalidValue;
+    const int64_t Mpad = (M + KROWS - 1) / KROWS * KROWS;
+    dim3 grid((unsigned)stats_blocks(M), (unsigned)((npad + 255) / 256));
+    hipLaunchKernelGGL(slice_kernel, grid, dim3(256), 0, s, I, M, Mpad, N, ld, rinv64, floor, colexp, npad,
+                       static_cast<u32x4v*>(S), colsum_part, flags);
     return hipGetLastError();
 }
 

@@ -94,9 +94,11 @@ def test_gram_matches_oracle(ctx, m, n, ld_pad):
 
 
 def _split_exponents(ell):
-    """e_j with max |l_j| < 2^e_j (the library's rule, with its margin)."""
+    """e_j with max |l_j| < 2^e_j (the library's rule, with its margin), plus
+    the one bit of headroom the library adds when it takes the maxima from a
+    sample of the rows: the bounds below hold for either."""
     mx = np.abs(ell).max(axis=0) * (1 + 2.0 ** -16) + 2.0 ** -20
-    return np.frexp(mx)[1].astype(np.float64)
+    return np.frexp(mx)[1].astype(np.float64) + 1.0
 
 
 @pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3), (130000, 64, 0)])
@@ -154,6 +156,31 @@ def test_gram_split_many_chunks_and_clamps(ctx):
         1e-13 * (np.abs(ell).T @ np.abs(ell))
     assert np.all(err <= bound)
     np.testing.assert_allclose(cs, data.astype(np.float64).sum(axis=0), rtol=1e-12)
+
+
+def test_gram_split_row_beyond_the_sampled_exponents(ctx):
+    # the column exponents come from every 16th row with one bit of
+    # headroom; row 17 (never sampled) has a log ratio ~30x the others', so
+    # the slicing pass flags it and the library redoes the pass with the
+    # exact exponents: the result is still within the splitting's bound
+    say("gram split, row beyond the sampled exponents")
+    m, n = 5000, 200
+    rng = np.random.default_rng(78)
+    i_ref = 1.0 + rng.random(n)
+    data = (i_ref * np.exp(0.02 * rng.standard_normal((m, n)))).astype(np.float32)
+    data[17] = (i_ref * np.exp(2.0)).astype(np.float32)
+    g, cs, clamps = ctx.gram(dev(data), i_ref, prec=fk.PREC_SPLIT)
+    ell, bad = wf.log_ratio(data.astype(np.float64), i_ref, 1e-6)
+    ref = ell.T @ ell
+    err = np.abs(g - ref)
+    e = 2.0 ** _split_exponents(ell)
+    a1 = np.abs(ell).sum(axis=0)
+    bound = 2.0 ** -28 * (np.outer(e, a1) + np.outer(a1, e)) + m * 2.0 ** -33 * np.outer(e, e) + \
+        1e-13 * (np.abs(ell).T @ np.abs(ell))
+    say(f"gram split with redo: rel err {err.max() / np.abs(ref).max():.2e}")
+    assert np.all(err <= bound)
+    np.testing.assert_allclose(cs, data.astype(np.float64).sum(axis=0), rtol=1e-12)
+    assert clamps == bad == 0
 
 
 @pytest.mark.parametrize("m,n,ld_pad", [(37, 20, 0), (5000, 300, 0), (3001, 1000, 0), (777, 129, 3)])
