@@ -76,7 +76,7 @@ enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
  * the tail of the Gram's spectrum (eigenvalue gaps of ~1e-9 of the largest
  * on tissue cubes) then moves the retained subspace, and with it the
  * sub-sampled rows of Eq. 13-15, only by the FP32 rounding of the log ratio.
- * SPLIT (Gram only) reaches FP64 accuracy on the int8 matrix cores: the log
+ * SPLIT as gram_prec reaches FP64 accuracy on the int8 matrix cores: the log
  * ratio is computed in FP64, scaled per column by a power of two and cut
  * into four int8 slices (an error-free splitting, Ozaki et al. 2012, of 27
  * bits below the column's largest |l|), the slice products of levels up to
@@ -84,7 +84,14 @@ enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
  * chunk, and the chunks summed in FP64: the Gram then differs from the
  * exact Gram of the FP64 log ratio by at most about 2^-27 of the columns'
  * largest entries per product, below the FP32 rounding of the log ratio
- * that the FP64 mode keeps.
+ * that the FP64 mode keeps.  The column exponents come from every 16th
+ * row with one bit of headroom; if a row does not fit, the pass is redone
+ * with exact exponents (the result is the same to the bound above).
+ * SPLIT as recon_prec reaches FP32 accuracy in the reconstruction of
+ * Eq. 23 on the BF16 matrix cores: Z and the corrected bases are each cut
+ * into three BF16 pieces (x = x1 + x2 + x3 + r, |r| about 2^-24 |x|), and
+ * the six piece products of combined order up to two are summed in FP32;
+ * its projections and transforms run in FP32.
  * The eigensolve and the basis-vector KK / PEC / SEC are FP64 always. */
 enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2, FKK_PREC_SPLIT = 3 };
 /* Route of the truncated SVD (Eq. 6) in fkk_fit. */
@@ -120,10 +127,10 @@ typedef struct {
     int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
     int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6), FP64 and SPLIT
                               allowed                                      */
-    int32_t recon_prec;    /* FKK_PREC_FP32 / _BF16 of the projection
-                              (Eq. 13) and the reconstruction (Eq. 23);
-                              stored in the basis and used by its later
-                              transforms                                   */
+    int32_t recon_prec;    /* FKK_PREC_FP32 / _BF16 / _SPLIT of the
+                              projection (Eq. 13) and the reconstruction
+                              (Eq. 23); stored in the basis and used by its
+                              later transforms                             */
     int32_t output;        /* FKK_OUT_*                                    */
     const int64_t* q_override; /* host, optional: rows used as U_ss       */
     int32_t n_q_override;  /* length of q_override (0 = use Eq. 13-15)    */
@@ -376,9 +383,10 @@ fkk_status fkk_basis_export(const fkk_basis* b, double* i_ref, double* f, double
 /* Frees a basis (NULL: nothing).  FKK_EBUSY, and nothing freed, while a
  * server holds it (fkk_server_add_basis until fkk_server_destroy). */
 fkk_status fkk_basis_free(fkk_basis* b);
-/* Matrix-core precision (FKK_PREC_*) of the projection and reconstruction
- * that fkk_transform, fkk_project, fkk_reconstruct and the server run with
- * this basis (both copies are kept on the device).  Imported bases start in
+/* Matrix-core precision (FKK_PREC_FP32, _BF16 or _SPLIT) of the projection
+ * and reconstruction that fkk_transform, fkk_project, fkk_reconstruct and
+ * the server run with this basis (FP32, BF16 and the BF16 pieces are all
+ * kept on the device).  Imported bases start in
  * FP32; fitted ones and those made from factors in the params' recon_prec.  Not thread-safe against
  * concurrent transforms with the same basis. */
 fkk_status fkk_basis_set_precision(fkk_basis* b, int32_t prec);

@@ -292,7 +292,7 @@ class Basis:
 
     @property
     def precision(self) -> int:
-        """PREC_FP32 or PREC_BF16: precision of transforms with this basis."""
+        """PREC_FP32, PREC_BF16 or PREC_SPLIT: precision of transforms with this basis."""
         p = ctypes.c_int32()
         st = lib().fkk_basis_get_precision(self._h, ctypes.byref(p))
         if st != FKK_OK:

@@ -83,8 +83,10 @@ void split_reciprocal(const double* iref, int N, float* out) {
     }
 }
 
-bool valid_prec(int p) { return p == FKK_PREC_FP32 || p == FKK_PREC_BF16; }
-bool valid_gram_prec(int p) { return valid_prec(p) || p == FKK_PREC_FP64 || p == FKK_PREC_SPLIT; }
+// Precisions of projection / reconstruction: FP32, BF16 and SPLIT (FP32
+// accuracy on the BF16 matrix cores in the reconstruction; FP32 elsewhere).
+bool valid_prec(int p) { return p == FKK_PREC_FP32 || p == FKK_PREC_BF16 || p == FKK_PREC_SPLIT; }
+bool valid_gram_prec(int p) { return valid_prec(p) || p == FKK_PREC_FP64; }
 
 // Nearest-even BF16 bit pattern of a finite float.
 uint16_t to_bf16(float x) {
@@ -92,6 +94,13 @@ uint16_t to_bf16(float x) {
     std::memcpy(&u, &x, sizeof u);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
+}
+
+float from_bf16(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, sizeof x);
+    return x;
 }
 
 int kp_for(int k) {
@@ -288,8 +297,8 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     const size_t o_bim = o_bre + al((size_t)np * kp * 4);
     const size_t o_wt16 = o_bim + al((size_t)np * kp * 4);
     const size_t o_bre16 = o_wt16 + al((size_t)kq * np * 2);
-    const size_t o_bim16 = o_bre16 + al((size_t)np * kq * 2);
-    const size_t o_f = o_bim16 + al((size_t)np * kq * 2);
+    const size_t o_bim16 = o_bre16 + al(3 * (size_t)np * kq * 2);
+    const size_t o_f = o_bim16 + al(3 * (size_t)np * kq * 2);
     const size_t o_g = o_f + al((size_t)np * 4);
     const size_t total = o_g + al(128 * 4);
     FKK_HIP(ctx, ctx->hstage.ensure((total + 7) / 8));  // doubles
@@ -324,8 +333,16 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
             const float re = (float)b->b_re[(size_t)c * N + j], im = (float)b->b_im[(size_t)c * N + j];
             bre[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = re;
             bim[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = im;
-            bre16[(size_t)j * kq + c] = to_bf16(re);
-            bim16[(size_t)j * kq + c] = to_bf16(im);
+            // three BF16 pieces of the FP32 value (planes np kq apart): the
+            // first is the BF16 copy, the rest carry the remainders
+            float rr = re, ri = im;
+            for (int pc = 0; pc < 3; ++pc) {
+                const uint16_t hr = to_bf16(rr), hi = to_bf16(ri);
+                bre16[(size_t)pc * np * kq + (size_t)j * kq + c] = hr;
+                bim16[(size_t)pc * np * kq + (size_t)j * kq + c] = hi;
+                rr -= from_bf16(hr);
+                ri -= from_bf16(hi);
+            }
         }
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     if (!b->d_arena) FKK_HIP(ctx, hipMalloc(&b->d_arena, total));
@@ -1252,10 +1269,11 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     t0 = std::chrono::steady_clock::now();
     if (d_out) {
         if (hipEventRecord(ctx->ev[4], s) != hipSuccess ||
-            (pbf16 ? fkk::dev::launch_reconstruct16(w.Z, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
-                                                    p->output, s)
-                   : fkk::dev::launch_reconstruct(w.Z, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
-                                                  p->output, s)) != hipSuccess ||
+            (pbf16 || p->recon_prec == FKK_PREC_SPLIT
+                 ? fkk::dev::launch_reconstruct16(w.Z, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
+                                                  p->output, s, pbf16 ? 1 : 3)
+                 : fkk::dev::launch_reconstruct(w.Z, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
+                                                p->output, s)) != hipSuccess ||
             hipEventRecord(ctx->ev[5], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return cleanup(ctx->fail(FKK_EDEVICE, "reconstruction failed"));
         r.dev_ms_recon = ctx->elapsed(4, 5);
@@ -1410,9 +1428,10 @@ fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, i
     if (plane < FKK_OUT_IM || plane > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad plane");
     if (b->device != ctx->device || !b->d_bre_t) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
-    if (b->prec == FKK_PREC_BF16)
+    if (b->prec == FKK_PREC_BF16 || b->prec == FKK_PREC_SPLIT)
         FKK_HIP(ctx, fkk::dev::launch_reconstruct16(d_z, M, ld_z, b->k, b->d_bre16, b->d_bim16, b->kq, b->N, d_out,
-                                                    ld_out, plane, ctx->stream));
+                                                    ld_out, plane, ctx->stream,
+                                                    b->prec == FKK_PREC_SPLIT ? 3 : 1));
     else
         FKK_HIP(ctx, fkk::dev::launch_reconstruct(d_z, M, ld_z, b->k, b->d_bre_t, b->d_bim_t, b->kp, b->N, d_out,
                                                   ld_out, plane, ctx->stream));

@@ -134,10 +134,12 @@ hipError_t launch_gram16(const uint16_t* Lp, int npad, int64_t M, const GramPlan
 hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                             const uint16_t* Wt, int ldw, int kq, int k_store, float* Z, int64_t ld_z,
                             ArgPart part, int k_arg, hipStream_t s);
-// Reconstruction from FP32 Z; BreT / BimT: (rows >= roundup(N, 64)) x kq BF16.
+// Reconstruction from FP32 Z; BreT / BimT: npad (N rounded up to 128) x kq
+// BF16.  pieces = 3: FP32 accuracy on the BF16 matrix cores, BreT / BimT
+// then three consecutive npad x kq planes (the BF16 pieces of B) each.
 hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
                                 const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
-                                hipStream_t s);
+                                hipStream_t s, int pieces = 1);
 hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                               const uint16_t* Wt, int ldw, int kq, const uint16_t* BreT, const uint16_t* BimT,
                               float* out, int64_t ld_out, int plane, hipStream_t s,

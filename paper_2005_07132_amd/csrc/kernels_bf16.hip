@@ -417,8 +417,21 @@ constexpr int RS_THREADS = 512;
 constexpr int RS_ROWS = 256;                 // spectra per tile
 constexpr int RS_LDS_UNITS = 144 * 1024 / 16;  // LDS for the two basis slices
 
-// Largest slice width (multiple of RCN) whose two planes fit the LDS budget.
-constexpr int rs_cw_max(int kb2) { return (RS_LDS_UNITS / (2 * (kb2 * 4 + 1))) / RCN * RCN; }
+// Largest slice width (multiple of RCN) whose two planes of P pieces fit the
+// LDS budget.
+constexpr int rs_cw_max(int kb2, int pieces = 1) { return (RS_LDS_UNITS / (2 * pieces * (kb2 * 4 + 1))) / RCN * RCN; }
+
+// z = z1 + z2 + z3 + r with BF16 pieces z1 = bf16(z), z2 = bf16(z - z1),
+// z3 = bf16(z - z1 - z2) (each difference exact in FP32), |r| <= 2^-24 |z|
+// roughly; pk[p] packs piece p of two values, lo first.
+__device__ __forceinline__ void split3(float a, float b, unsigned (&pk)[3]) {
+    const float a1 = (float)(__bf16)a, b1 = (float)(__bf16)b;
+    const float ar = a - a1, br = b - b1;
+    const float a2 = (float)(__bf16)ar, b2 = (float)(__bf16)br;
+    pk[0] = pack2(a1, b1);
+    pk[1] = pack2(a2, b2);
+    pk[2] = pack2(ar - a2, br - b2);
+}
 
 // Raw FP32 Z of one wave's 32 spectra: zr[jb][kg][q] = Z[row][kg 32 + 8 (l/16) + q],
 // row = r0 + 16 jb + l%16 (zero past M or k; loads from clamped addresses;
@@ -450,7 +463,11 @@ __device__ __forceinline__ void rs_load_z(float (&zr)[2][KB2][8], const float* _
     }
 }
 
-template <int KB2, bool VEC_OUT, bool VEC_Z>
+// P = 3: Eq. 23's products to FP32 accuracy on the BF16 matrix cores: B and
+// Z each as three BF16 pieces (B's given as consecutive npad x kq planes,
+// Z's cut in registers), the six piece products of combined order <= 2,
+// smallest first, accumulated in FP32.
+template <int KB2, bool VEC_OUT, bool VEC_Z, int P = 1>
 __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z,
                                                               int k, const u32x4* __restrict__ BreT,
                                                               const u32x4* __restrict__ BimT, int N, int npad, int cw,
@@ -473,28 +490,36 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
     const int c0 = slice * cw;
     const int c1 = (c0 + cw < N) ? c0 + cw : N;
 
-    // basis slice to LDS: rows c0 .. c0 + cw - 1 (zero past npad)
+    // basis slice to LDS: rows c0 .. c0 + cw - 1 (zero past npad); piece pc
+    // of plane Re at sB + 2 pc cw BLDU, of plane Im cw BLDU further
     u32x4* sRe = sB;
     u32x4* sIm = sB + cw * BLDU;
-    // (eight units per plane in flight per thread before the LDS writes)
-    for (int base = 0; base < cw * UPR; base += 8 * RS_THREADS) {
-        u32x4 vre[8], vim[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int idx = base + p * RS_THREADS + tid;
-            const int j = c0 + idx / UPR;
-            const bool live = idx < cw * UPR && j < npad;
-            const size_t src = live ? (size_t)j * UPR + idx % UPR : 0;
-            vre[p] = BreT[src];
-            vim[p] = BimT[src];
-            if (!live) vre[p] = vim[p] = u32x4{0u, 0u, 0u, 0u};
-        }
+    for (int pc = 0; pc < P; ++pc) {
+        const u32x4* gre = BreT + (size_t)pc * npad * UPR;
+        const u32x4* gim = BimT + (size_t)pc * npad * UPR;
+        u32x4* lre = sRe + 2 * pc * cw * BLDU;
+        u32x4* lim = sIm + 2 * pc * cw * BLDU;
+        // (eight units per plane in flight per thread before the LDS writes)
+        for (int base = 0; base < cw * UPR; base += 8 * RS_THREADS) {
+            u32x4 vre[8], vim[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int idx = base + p * RS_THREADS + tid;
-            if (idx < cw * UPR) {
-                sRe[(idx / UPR) * BLDU + idx % UPR] = vre[p];
-                sIm[(idx / UPR) * BLDU + idx % UPR] = vim[p];
+            for (int p = 0; p < 8; ++p) {
+                const int idx = base + p * RS_THREADS + tid;
+                const int j = c0 + idx / UPR;
+                const bool live = idx < cw * UPR && j < npad;
+                const size_t src = live ? (size_t)j * UPR + idx % UPR : 0;
+                vre[p] = gre[src];
+                vim[p] = gim[src];
+                if (!live) vre[p] = vim[p] = u32x4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const int idx = base + p * RS_THREADS + tid;
+                if (idx < cw * UPR) {
+                    lre[(idx / UPR) * BLDU + idx % UPR] = vre[p];
+                    lim[(idx / UPR) * BLDU + idx % UPR] = vim[p];
+                }
             }
         }
     }
@@ -510,13 +535,22 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t r0 = t * RS_ROWS + 128 * h;
         if (!PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + 32 * wq, lane);
-        u32x4 zb[2][KB2];
+        u32x4 zb[P][2][KB2];
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-            for (int kg = 0; kg < KB2; ++kg)
-                zb[jb][kg] = u32x4{pack2(zr[jb][kg][0], zr[jb][kg][1]), pack2(zr[jb][kg][2], zr[jb][kg][3]),
-                                   pack2(zr[jb][kg][4], zr[jb][kg][5]), pack2(zr[jb][kg][6], zr[jb][kg][7])};
+            for (int kg = 0; kg < KB2; ++kg) {
+                if (P == 1) {
+                    zb[0][jb][kg] = u32x4{pack2(zr[jb][kg][0], zr[jb][kg][1]), pack2(zr[jb][kg][2], zr[jb][kg][3]),
+                                          pack2(zr[jb][kg][4], zr[jb][kg][5]), pack2(zr[jb][kg][6], zr[jb][kg][7])};
+                } else {
+                    unsigned w[4][3];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) split3(zr[jb][kg][2 * e], zr[jb][kg][2 * e + 1], w[e]);
+#pragma unroll
+                    for (int pc = 0; pc < P; ++pc) zb[pc][jb][kg] = u32x4{w[0][pc], w[1][pc], w[2][pc], w[3][pc]};
+                }
+            }
         if (PF && t + 1 < t1) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + RS_ROWS + 32 * wq, lane);
         __builtin_amdgcn_sched_barrier(0);
         // each 64-wavenumber chunk in two halves, so that the stores of the
@@ -525,8 +559,34 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 floatx4 are[2][2], aim[2][2];
-                recon16_chunk<KB2, 2>(zb, sRe + (j0 - c0) * BLDU, sIm + (j0 - c0) * BLDU, lane, are, aim, 2 * hh);
-                store_out<VEC_OUT, true, 2>(out, ld_out, M, N, r0, wq, lane, j0 + 32 * hh, are, aim, plane);
+                if (P == 1) {
+                    recon16_chunk<KB2, 2>(zb[0], sRe + (j0 - c0) * BLDU, sIm + (j0 - c0) * BLDU, lane, are, aim,
+                                          2 * hh);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int jb = 0; jb < 2; ++jb) are[i][jb] = aim[i][jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    // piece pairs (z, b) by combined order 2, 1, 0
+                    constexpr int PZ[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+                    for (int kg = 0; kg < KB2; ++kg)
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) {
+                            const int off = (j0 - c0 + (2 * hh + i) * 16 + (lane & 15)) * BLDU + kg * 4 + (lane >> 4);
+#pragma unroll
+                            for (int t = 0; t < 6; ++t) {
+                                const u32x4 bre = sRe[2 * PB[t] * cw * BLDU + off];
+                                const u32x4 bim = sIm[2 * PB[t] * cw * BLDU + off];
+#pragma unroll
+                                for (int jb = 0; jb < 2; ++jb) {
+                                    are[i][jb] = mfma16(bre, zb[PZ[t]][jb][kg], are[i][jb]);
+                                    aim[i][jb] = mfma16(bim, zb[PZ[t]][jb][kg], aim[i][jb]);
+                                }
+                            }
+                        }
+                }
+                store_out<VEC_OUT, P == 1, 2>(out, ld_out, M, N, r0, wq, lane, j0 + 32 * hh, are, aim, plane);
             }
     }
 }
@@ -685,10 +745,11 @@ hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const 
 
 hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
                                 const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
-                                hipStream_t s) {
+                                hipStream_t s, int pieces) {
     if (M <= 0) return hipSuccess;
     if (k < 1 || k > ld_z) return hipErrorInvalidValue;
     if (kq != 32 && kq != 64 && kq != 128) return hipErrorInvalidValue;
+    if (pieces != 1 && pieces != 3) return hipErrorInvalidValue;
     const int kb2 = kq / 32;
     const int npad = (N + kGramTile - 1) / kGramTile * kGramTile;
     const bool vec = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
@@ -696,7 +757,7 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
     const u32x4* bre = reinterpret_cast<const u32x4*>(BreT);
     const u32x4* bim = reinterpret_cast<const u32x4*>(BimT);
     // wavenumber slices of equal width (multiple of RCN) that fit LDS
-    const int cwm = rs_cw_max(kb2);
+    const int cwm = rs_cw_max(kb2, pieces);
     const int nslice = (N + cwm - 1) / cwm;
     const int cw = ((N + nslice - 1) / nslice + RCN - 1) / RCN * RCN;
     // tiles per block: about 2048 blocks over the whole launch
@@ -708,20 +769,28 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
     const int64_t nblocks = (groups + 7) / 8 * 8 * nslice;
     if (nblocks > INT_MAX) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks), block(RS_THREADS);
-#define FKK_RC16(KB2, VO, VZ)                                                                                      \
-    hipLaunchKernelGGL((recon16s_kernel<KB2, VO, VZ>), grid, block, 0, s, Z, M, ld_z, k, bre, bim, N, npad, cw,       \
+#define FKK_RC16(KB2, VO, VZ, P)                                                                                   \
+    hipLaunchKernelGGL((recon16s_kernel<KB2, VO, VZ, P>), grid, block, 0, s, Z, M, ld_z, k, bre, bim, N, npad, cw,    \
                        nslice, (int)tpb, out, ld_out, plane)
-#define FKK_RC16_K(KB2)                                             \
+#define FKK_RC16_K(KB2, P)                                          \
     do {                                                            \
-        if (vec && vz) FKK_RC16(KB2, true, true);                   \
-        else if (vec) FKK_RC16(KB2, true, false);                   \
-        else if (vz) FKK_RC16(KB2, false, true);                    \
-        else FKK_RC16(KB2, false, false);                           \
+        if (vec && vz) FKK_RC16(KB2, true, true, P);                \
+        else if (vec) FKK_RC16(KB2, true, false, P);                \
+        else if (vz) FKK_RC16(KB2, false, true, P);                 \
+        else FKK_RC16(KB2, false, false, P);                        \
     } while (0)
-    switch (kb2) {
-        case 1: FKK_RC16_K(1); break;
-        case 2: FKK_RC16_K(2); break;
-        default: FKK_RC16_K(4); break;
+    if (pieces == 1) {
+        switch (kb2) {
+            case 1: FKK_RC16_K(1, 1); break;
+            case 2: FKK_RC16_K(2, 1); break;
+            default: FKK_RC16_K(4, 1); break;
+        }
+    } else {
+        switch (kb2) {
+            case 1: FKK_RC16_K(1, 3); break;
+            case 2: FKK_RC16_K(2, 3); break;
+            default: FKK_RC16_K(4, 3); break;
+        }
     }
 #undef FKK_RC16_K
 #undef FKK_RC16

@@ -268,21 +268,26 @@ def test_projection_and_subsampling(ctx, fitted):
         assert zref[qmin[c], c] <= zref[:, c].min() + 4 * TOL * scale
 
 
+@pytest.mark.parametrize("prec", [fk.PREC_FP32, fk.PREC_SPLIT])
 @pytest.mark.parametrize("plane", [fk.OUT_IM, fk.OUT_RE, fk.OUT_ABS])
-def test_reconstruction_epilogue(ctx, fitted, plane):
-    say(f"reconstruct plane={plane}")
+def test_reconstruction_epilogue(ctx, fitted, plane, prec):
+    # FP32 matrix cores, and three BF16 pieces per operand on the BF16
+    # matrix cores (SPLIT): both against Eq. 23 in FP64 on the same Z
+    say(f"reconstruct plane={plane} prec={prec}")
     cube, p, res = fitted
     b = ctx.basis_import(res["basis"])
+    b.precision = prec
     z32 = res["z"].astype(np.float32)
     out = host(ctx.reconstruct(b, dev(z32), plane))
     ref = wf.reconstruct(z32.astype(np.float64), res["basis"])[{0: "im", 1: "re", 2: "abs"}[plane]]
     assert spectrum_err(out, ref).max() < TOL
 
 
-def test_reconstruction_epilogue_wide_phase_range(ctx):
+@pytest.mark.parametrize("prec", [fk.PREC_FP32, fk.PREC_SPLIT])
+def test_reconstruction_epilogue_wide_phase_range(ctx, prec):
     # the device epilogue reduces the phase by multiples of pi/2: check it
     # over several periods (|phase| up to ~8 rad) against FP64 sin/cos/exp
-    say("reconstruct wide phase")
+    say(f"reconstruct wide phase prec={prec}")
     rng = synth.rng_for(77, 1)
     n, k, m = 200, 10, 3000
     v = np.linalg.qr(rng.standard_normal((n, k)))[0]
@@ -291,6 +296,7 @@ def test_reconstruction_epilogue_wide_phase_range(ctx):
              "ml_lambda": 0.0, "ratio_floor": 1e-6}
     z = (2.0 * rng.standard_normal((m, k)) / np.sqrt(k)).astype(np.float32)
     b = ctx.basis_import(basis)
+    b.precision = prec
     bas32 = dict(basis, b_re=basis["b_re"].astype(np.float32).astype(np.float64),
                  b_im=basis["b_im"].astype(np.float32).astype(np.float64))
     phase = z.astype(np.float64) @ bas32["b_im"]
@@ -873,23 +879,27 @@ def test_paper_scale_fit_sampled(ctx):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("gram_prec", [fk.PREC_FP64, fk.PREC_SPLIT])
-def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle, gram_prec):
+@pytest.mark.parametrize("gram_prec,recon_prec", [(fk.PREC_FP64, fk.PREC_FP32), (fk.PREC_SPLIT, fk.PREC_FP32),
+                                                  (fk.PREC_SPLIT, fk.PREC_SPLIT)])
+def test_paper_scale_fit_fp64_gram_matches_oracle(ctx, tissue703_oracle, gram_prec, recon_prec):
     # the 703,026 x 1,000 cube, k = 50: every output spectrum against the
     # FP64 oracle's own fit of the same FP32 input, with the Gram on the FP64
-    # matrix cores and with the int8 splitting
-    say(f"paper-scale fit, gram_prec={gram_prec}, vs oracle")
+    # matrix cores and with the int8 splitting, and the reconstruction on
+    # the FP32 matrix cores or split into BF16 pieces
+    say(f"paper-scale fit, gram_prec={gram_prec}, recon_prec={recon_prec}, vs oracle")
     o = tissue703_oracle
     cube, p, ref_basis, ref_im = o.cube, o.p, o.basis, o.im
     t = dev(cube.i_cars)
-    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=gram_prec))
+    b, out, rep = ctx.fit(t, cube.i_ref, lib_params(p, gram_prec=gram_prec, recon_prec=recon_prec))
+    assert b.precision == recon_prec
     got = out.cpu().numpy()
     e = b.export()
     np.testing.assert_array_equal(np.sort(e["q"]), np.sort(ref_basis["q"]))
     err = np.concatenate([spectrum_err(got[i:i + 65536].astype(np.float64), ref_im[i:i + 65536])
                           for i in range(0, cube.shape[0], 65536)])
-    say(f"paper-scale fit gram_prec={gram_prec}: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}, "
-        f"gram {rep['dev_ms_gram']:.2f} ms, log-ratio passes {rep['dev_ms_logratio']:.2f} ms, total {rep['ms_total']:.1f} ms")
+    say(f"paper-scale fit gram_prec={gram_prec} recon_prec={recon_prec}: max {err.max():.2e} "
+        f"rms {np.sqrt(np.mean(err ** 2)):.2e}, gram {rep['dev_ms_gram']:.2f} ms, log-ratio passes "
+        f"{rep['dev_ms_logratio']:.2f} ms, reconstruction {rep['dev_ms_recon']:.2f} ms, total {rep['ms_total']:.1f} ms")
     assert err.max() < TOL
     del t, out
     torch.cuda.empty_cache()
