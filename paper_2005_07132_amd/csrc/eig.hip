@@ -301,10 +301,14 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // b+2G, ... of the matrix in LDS for the whole reduction, so the rank-2
 // updates never leave the CU.  Per column the blocks exchange only p (one
 // entry per row) and the next pivot row.  Each exchanged double travels as
-// two 64-bit words that carry one half of it and the number of the column
-// it belongs to; a reader polls its words until all of them carry the
-// expected number, so no separate grid barrier is needed.  Two buffers
-// alternate between columns: a block writes the words of column i+1 only
+// one 64-bit word: the value rounded to 51 significant bits, its two lowest
+// bits replaced by the column number mod 4 (a relative change below 2^-50,
+// the same for every block, which all read the same word); a reader polls
+// its words until all of them carry the expected number, so no separate
+// grid barrier is needed.  Two buffers alternate between columns, so the
+// word a reader may still find in a slot is that of two columns earlier
+// (another number mod 4) or the cleared word (0, and columns 0 and 1
+// carry 1 and 2).  A block writes the words of column i+1 only
 // after it has read all words of column i, and every block still reading
 // column i-1 (the previous content of that buffer) writes at least one word
 // of column i after it has read column i-1: a block leaves the column loop
@@ -323,21 +327,18 @@ constexpr size_t kResidentLdsMax = 160 * 1024 - 512;  // dynamic part; the stati
 typedef unsigned long long u64;
 
 // Agent-coherent (relaxed atomic) accesses: they miss in the per-XCD caches.
+// The magnitude is rounded to a multiple of 4 units in the last place (half
+// up: the bit pattern of a finite double grows with its magnitude), then
+// the two low bits take the tag.
 __device__ __forceinline__ void xch_put(u64* slot, double v, unsigned tag) {
-    const u64 bits = (u64)__double_as_longlong(v);
-    const u64 t = (u64)tag << 32;
-    __hip_atomic_store(slot, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(slot + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 bits = ((u64)__double_as_longlong(v) + 2ull) & ~3ull;
+    __hip_atomic_store(slot, bits | (u64)(tag & 3u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ u64 xch_word(const u64* p) {
     return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ bool xch_tagged(u64 lo, u64 hi, unsigned tag) {
-    return (unsigned)(lo >> 32) == tag && (unsigned)(hi >> 32) == tag;
-}
-__device__ __forceinline__ double xch_value(u64 lo, u64 hi) {
-    return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
-}
+__device__ __forceinline__ bool xch_tagged(u64 w, unsigned tag) { return (unsigned)(w & 3ull) == (tag & 3u); }
+__device__ __forceinline__ double xch_value(u64 w) { return __longlong_as_double((long long)w); }
 
 // Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
 // (LDS), with part += p . v over this thread's entries; NU = ceil(m /
@@ -345,15 +346,13 @@ __device__ __forceinline__ double xch_value(u64 lo, u64 hi) {
 // up after spin_limit polls (spin_limit 0: at once), or when *err is set.
 template <int NU>
 struct XchPoll {
-    u64 a[NU][2], c[NU][2];
+    u64 a[NU], c[NU];
     __device__ __forceinline__ void issue(const u64* pw, const u64* xw, int m) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {  // clamped: every load in bounds, none waits for another
             const int j = min((int)threadIdx.x + kResThreads * u, m - 1);
-            a[u][0] = xch_word(pw + 2 * j);
-            a[u][1] = xch_word(pw + 2 * j + 1);
-            c[u][0] = xch_word(xw + 2 * j);
-            c[u][1] = xch_word(xw + 2 * j + 1);
+            a[u] = xch_word(pw + j);
+            c[u] = xch_word(xw + j);
         }
     }
     __device__ __forceinline__ bool complete(int m, unsigned tag) const {
@@ -361,7 +360,7 @@ struct XchPoll {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             const int j = threadIdx.x + kResThreads * u;
-            if (j < m) all = all && xch_tagged(a[u][0], a[u][1], tag) && xch_tagged(c[u][0], c[u][1], tag);
+            if (j < m) all = all && xch_tagged(a[u], tag) && xch_tagged(c[u], tag);
         }
         return all;
     }
@@ -370,9 +369,9 @@ struct XchPoll {
         for (int u = 0; u < NU; ++u) {
             const int j = threadIdx.x + kResThreads * u;
             if (j < m) {
-                const double pj = xch_value(a[u][0], a[u][1]);
+                const double pj = xch_value(a[u]);
                 w[j] = pj;
-                x[j] = xch_value(c[u][0], c[u][1]);
+                x[j] = xch_value(c[u]);
                 part += pj * v[j];
             }
         }
@@ -459,10 +458,10 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
         double sacc = 0.0;
         for (int c = lane; c < m0; c += 64) {
             sacc += row[c] * va[c];
-            if (r == 1) xch_put(xch + 4 * (size_t)n + 2 * c, row[c], 1u);  // pivot row of column 0
+            if (r == 1) xch_put(xch + 2 * (size_t)n + c, row[c], 1u);  // pivot row of column 0
         }
         sacc = wave_sum(sacc);
-        if (lane == 0) xch_put(xch + 2 * (r - 1), bcur * sacc, 1u);
+        if (lane == 0) xch_put(xch + (r - 1), bcur * sacc, 1u);
     }
 
     for (int i = 0; i + 2 < n; ++i) {
@@ -474,9 +473,9 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
         const double v0 = va[0];
         double part = 0.0;
         __syncthreads();  // LDS of the previous column no longer read
-        // words of column i: p at xch + 2n (i & 1), pivot row at xch + 4n + 2n (i & 1)
-        const size_t half = (i & 1) ? 2 * (size_t)n : 0;
-        if (!xch_fetch(xch + half, xch + 4 * (size_t)n + half, m, tag, spin_limit, err, w, x, va, part)) sbad = 1;
+        // words of column i: p at xch + n (i & 1), pivot row at xch + 2n + n (i & 1)
+        const size_t half = (i & 1) ? (size_t)n : 0;
+        if (!xch_fetch(xch + half, xch + 2 * (size_t)n + half, m, tag, spin_limit, err, w, x, va, part)) sbad = 1;
         // p_0 is copied before the barrier: thread 0 overwrites w[0] with w_0
         // below while other waves may still be about to read it
         if (tid == 0) sp0 = w[0];  // w[0] is this thread's own entry
@@ -530,8 +529,8 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
         }
         __syncthreads();  // vb, w, x complete
         const unsigned ntag = tag + 1u;
-        u64* pout = xch + (half ? 0 : 2 * (size_t)n);
-        u64* xout = xch + 4 * (size_t)n + (half ? 0 : 2 * (size_t)n);
+        u64* pout = xch + (half ? 0 : (size_t)n);
+        u64* xout = xch + 2 * (size_t)n + (half ? 0 : (size_t)n);
         for (int t = wave; t < R; t += kResThreads / 64) {
             const int r = b + t * G;
             if (r <= lo || r >= n) continue;
@@ -555,7 +554,7 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
                     row[cc] = u[q];
                     if (cc >= 1) {
                         sacc += u[q] * vb[cc - 1];
-                        if (pivot) xch_put(xout + 2 * (cc - 1), u[q], ntag);
+                        if (pivot) xch_put(xout + (cc - 1), u[q], ntag);
                     }
                 }
             }
@@ -564,13 +563,13 @@ __global__ __launch_bounds__(kResThreads) void tridiag_resident(const double* __
                 row[c] = u;
                 if (next && c >= 1) {
                     sacc += u * vb[c - 1];
-                    if (pivot) xch_put(xout + 2 * (c - 1), u, ntag);
+                    if (pivot) xch_put(xout + (c - 1), u, ntag);
                 }
                 if (!next && r == n - 1 && c == m - 1) d[n - 1] = u;
             }
             if (next) {
                 sacc = wave_sum(sacc);
-                if (lane == 0) xch_put(pout + 2 * (r - lo - 1), bn * sacc, ntag);
+                if (lane == 0) xch_put(pout + (r - lo - 1), bn * sacc, ntag);
             }
         }
         if (!next) break;
@@ -623,7 +622,7 @@ int tridiag_resident_grid(int n, int device) {
     return G;
 }
 
-size_t tridiag_resident_xch_doubles(int n) { return 8 * (size_t)n; }
+size_t tridiag_resident_xch_doubles(int n) { return 4 * (size_t)n; }
 
 hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, int* err, double* vstore,
                                    double* beta, double* d, double* e, int spin_limit, hipStream_t s) {

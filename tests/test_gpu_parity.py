@@ -767,9 +767,9 @@ def test_tridiag_graph_replays_match_eager_launches():
 @pytest.mark.parametrize("n,k", [(300, 12), (1000, 50), (1025, 20), (1600, 50), (8, 2)])
 def test_resident_tridiag_matches_per_column_launches(n, k):
     # one cooperative launch (rows resident in LDS) against one launch per
-    # column: the same arithmetic up to the summation order of the p dot
-    # products past 1,024 columns.  Singular values and V agree to
-    # rounding, twice in a row; up to 1,024 columns the outputs too
+    # column: the same arithmetic up to the summation order of the dot
+    # products and norms.  Singular values and V agree to rounding, twice
+    # in a row; up to 1,024 columns the outputs too
     say(f"resident tridiag vs per-column n={n} k={k}")
     if n > 8:
         cube = tissue(rows=24, cols=24, n=n, key=23)
