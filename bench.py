@@ -646,6 +646,14 @@ def main():
                          "TFLOP/s": gram_flop / (fp64_gram["stages_ms"]["dev_ms_gram"] * 1e-3) / 1e12,
                          "frac_of_fp64_peak": gram_flop / (fp64_gram["stages_ms"]["dev_ms_gram"] * 1e-3) /
                          PEAK_FP64_MFMA}
+    log("fit with the split Gram and the split reconstruction")
+    split_recon, bl = leg("split-gram + split reconstruction", args.steps, gram_prec=fk.PREC_SPLIT,
+                          recon_prec=fk.PREC_SPLIT)
+    bl.free()
+    # three BF16 pieces of each basis plane (kq columns, 2 bytes each)
+    split_recon["reconstruction"] = recon_stats(split_recon["stages_ms"]["dev_ms_recon"], 3 * kq, 2)
+    split_recon["reconstruction"]["note"] = ("Eq. 23 to FP32 accuracy on the BF16 matrix cores: Z and the basis as "
+                                             "three BF16 pieces each, six piece products summed in FP32")
     log("fit with the randomized range finder")
     randomized, brr = leg("randomized", args.steps, svd_mode=fk.SVD_RANDOMIZED, rrf_oversample=20,
                           rrf_power_iters=1)
@@ -769,6 +777,7 @@ def main():
         "transform": transform,
         "fp32_gram": fp32_gram,
         "fp64_gram": fp64_gram,
+        "split_reconstruction": split_recon,
         "randomized_svd": randomized,
         "bf16": bf16,
         "plain": plain,
