@@ -140,6 +140,8 @@ __global__ void colexp_kernel(const float* __restrict__ gmax, int groups, int np
 // from them get one bit of headroom; a row outside it is caught by the
 // slicing pass's overflow flag.
 constexpr int SAMPLE_ROWS = 64;
+constexpr int SAMPLE_BATCH = 8;  // sampled rows whose loads are in flight together
+template <bool VEC>
 __global__ __launch_bounds__(256) void sample_max_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                          const float* __restrict__ rinv, float floor, int npad,
                                                          int stride, float* __restrict__ colmax_part) {
@@ -155,15 +157,25 @@ __global__ __launch_bounds__(256) void sample_max_kernel(const float* __restrict
             r[q] = (c + q < N) ? rinv[c + q] : 0.f;
             rl[q] = (c + q < N) ? rinv[N + c + q] : 0.f;
         }
-        for (int64_t t = t0; t < t1; ++t) {
-            const float* row = I + t * stride * ld;
+        // batches of SAMPLE_BATCH rows: all loads first (rows past the
+        // block's last sample read that sample again, which changes no
+        // maximum), then the log ratios
+        for (int64_t tb = t0; tb < t1; tb += SAMPLE_BATCH) {
+            float4 x[SAMPLE_BATCH];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (c + q >= N) continue;
-                bool bad;
-                const float l = log_ratio(row[c + q], r[q], rl[q], floor, bad);
-                mx[q] = fmaxf(mx[q], fabsf(l));
+            for (int u = 0; u < SAMPLE_BATCH; ++u) {
+                const int64_t t = (tb + u < t1) ? tb + u : t1 - 1;
+                x[u] = load4_guarded(I + t * stride * ld, c, N, VEC);
             }
+#pragma unroll
+            for (int u = 0; u < SAMPLE_BATCH; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (c + q >= N) continue;
+                    bool bad;
+                    const float l = log_ratio(f4get(x[u], q), r[q], rl[q], floor, bad);
+                    mx[q] = fmaxf(mx[q], fabsf(l));
+                }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) colmax_part[(size_t)blockIdx.x * npad + c + q] = mx[q];
@@ -510,8 +522,13 @@ hipError_t launch_split_sample(const float* I, int64_t M, int N, int64_t ld, con
                                int stride, float* colmax_part, int* colexp, hipStream_t s) {
     if (npad % 4 != 0 || npad < N || stride < 1 || M < 1) return hipErrorInvalidValue;
     const int64_t nb = sample_blocks(M, stride);
-    hipLaunchKernelGGL(sample_max_kernel, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor, npad, stride,
-                       colmax_part);
+    const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
+    if (vec)
+        hipLaunchKernelGGL(sample_max_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor,
+                           npad, stride, colmax_part);
+    else
+        hipLaunchKernelGGL(sample_max_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, I, M, N, ld, rinv, floor,
+                           npad, stride, colmax_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return colexp_from_parts(colmax_part, nb, npad, N, 1, colexp, s);
