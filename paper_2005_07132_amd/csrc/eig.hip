@@ -302,8 +302,9 @@ __global__ __launch_bounds__(kThreads) void tridiag_step(double* __restrict__ A,
 // updates never leave the CU.  Per column the blocks exchange only p (one
 // entry per row) and the next pivot row.  Each exchanged double travels as
 // one 64-bit word: the value rounded to 51 significant bits, its two lowest
-// bits replaced by the column number mod 4 (a relative change below 2^-50,
-// the same for every block, which all read the same word); a reader polls
+// bits replaced by the column number mod 4, which the reader clears again
+// (a relative change below 2^-51 that keeps zeros exact and is the same for
+// every block, since all read the same word); a reader polls
 // its words until all of them carry the expected number, so no separate
 // grid barrier is needed.  Two buffers alternate between columns, so the
 // word a reader may still find in a slot is that of two columns earlier
@@ -338,7 +339,8 @@ __device__ __forceinline__ u64 xch_word(const u64* p) {
     return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ bool xch_tagged(u64 w, unsigned tag) { return (unsigned)(w & 3ull) == (tag & 3u); }
-__device__ __forceinline__ double xch_value(u64 w) { return __longlong_as_double((long long)w); }
+// the tag bits cleared: a zero travels as an exact zero
+__device__ __forceinline__ double xch_value(u64 w) { return __longlong_as_double((long long)(w & ~3ull)); }
 
 // Entries 0..m-1 of p and of the pivot row of column `tag` into w and x
 // (LDS), with part += p . v over this thread's entries; NU = ceil(m /
