@@ -123,7 +123,8 @@ typedef struct {
     int32_t sg_window;     /* Savitzky-Golay window (odd), 0 = automatic   */
     int32_t sg_order;      /* Savitzky-Golay polynomial order              */
     double ml_lambda;      /* Eq. 25 ridge weight of the stored basis      */
-    double ratio_floor;    /* ratios I/I_ref not above it are clamped      */
+    double ratio_floor;    /* ratios I/I_ref not above it are clamped;
+                              at least 2^-126 (else FKK_EINVAL)            */
     int32_t strict;        /* 1: clamped ratios fail with FKK_EDOMAIN      */
     int32_t gram_prec;     /* FKK_PREC_* of the Gram (Eq. 6), FP64 and SPLIT
                               allowed                                      */
@@ -196,7 +197,7 @@ typedef struct {
     const double* b_re;    /* k x N  V^T/f + H{Phi_PEC^T} - V_SEC^T        */
     const double* b_im;    /* k x N  H{V^T/f} - Phi_PEC^T                  */
     double ml_lambda;      /* Eq. 25 ridge weight used by fkk_transform    */
-    double ratio_floor;
+    double ratio_floor;    /* at least 2^-126, as in fkk_params            */
 } fkk_basis_desc;
 
 int fkk_version(void);
@@ -295,6 +296,7 @@ fkk_status fkk_plain_f64(fkk_ctx* ctx, const double* d_I, int64_t M, int32_t N, 
  * symmetric) with l = 1/2 ln(I / I_ref) computed in FP32 (rounded to BF16
  * when prec is FKK_PREC_BF16), products summed as FKK_PREC_* describes;
  * plus the column sums of I (FP64, N) and the number of clamped ratios.
+ * ratio_floor as in fkk_params (at least 2^-126, else FKK_EINVAL).
  * Synchronous.
  */
 fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t ld,

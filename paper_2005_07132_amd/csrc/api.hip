@@ -223,6 +223,10 @@ struct fkk_ctx {
 
 namespace {
 
+// Smallest ratio floor: the FP32 kernels take the logarithm of clamped
+// ratios as normal numbers (2^-126 and up).
+constexpr double kMinRatioFloor = 0x1p-126;
+
 // auto_k: k = 0 (the rank rule of Sec. 4.1) is allowed.
 // plain: the conventional method, the only one with the real-part SEC form.
 fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = false, bool plain = false) {
@@ -248,7 +252,8 @@ fkk_status check_params(fkk_ctx* ctx, const fkk_params* p, int N, bool auto_k = 
         if (w % 2 == 0 || w > N || w <= p->sg_order || p->sg_order < 0)
             return ctx->fail(FKK_EINVAL, "Savitzky-Golay window %d / order %d invalid for N=%d", w, p->sg_order, N);
     }
-    if (!(p->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
+    if (!(p->ratio_floor >= kMinRatioFloor))
+        return ctx->fail(FKK_EINVAL, "ratio_floor must be at least 2^-126 (the smallest normal FP32 number)");
     if (p->output < FKK_OUT_IM || p->output > FKK_OUT_ABS) return ctx->fail(FKK_EINVAL, "bad output plane");
     if (!valid_gram_prec(p->gram_prec) || !valid_prec(p->recon_prec))
         return ctx->fail(FKK_EINVAL, "bad matrix-core precision (gram_prec=%d, recon_prec=%d)", p->gram_prec,
@@ -1012,7 +1017,8 @@ fkk_status fkk_gram(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_
     fkk_status st;
     if ((st = check_matrix(ctx, d_I, M, N, ld, "I")) != FKK_OK) return st;
     if ((st = check_iref(ctx, h_iref, N)) != FKK_OK) return st;
-    if (!(ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "ratio_floor must be > 0");
+    if (!(ratio_floor >= kMinRatioFloor))
+        return ctx->fail(FKK_EINVAL, "ratio_floor must be at least 2^-126 (the smallest normal FP32 number)");
     if (!valid_gram_prec(prec)) return ctx->fail(FKK_EINVAL, "bad precision %d", prec);
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     GramWs w;
@@ -1444,7 +1450,7 @@ fkk_status fkk_basis_import(fkk_ctx* ctx, const fkk_basis_desc* d, fkk_basis** o
         return ctx->fail(FKK_EINVAL, "NULL argument");
     *out = nullptr;
     if (d->N < 4 || d->k < 1 || d->k > d->N || d->k > 128) return ctx->fail(FKK_EINVAL, "bad N / k");
-    if (!(d->ml_lambda >= 0.0) || !(d->ratio_floor > 0.0)) return ctx->fail(FKK_EINVAL, "bad scalars");
+    if (!(d->ml_lambda >= 0.0) || !(d->ratio_floor >= kMinRatioFloor)) return ctx->fail(FKK_EINVAL, "bad scalars");
     fkk_status st;
     if ((st = check_iref(ctx, d->i_ref, d->N)) != FKK_OK) return st;
     fkk_basis* b = new_basis(d->N, d->k, d->i_ref, d->f, d->s, d->v, d->ml_lambda, d->ratio_floor);

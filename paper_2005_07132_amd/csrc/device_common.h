@@ -16,16 +16,31 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// ln q for a normal, finite q > 0: the hardware base-2 logarithm times ln 2
+// carried as two floats (0x3f317217 + 0x3377d1cf), with the product's
+// rounding error put back.  These are the operations logf performs for such
+// an argument, so the results are logf's bit for bit; logf's other steps
+// (scaling a subnormal argument, passing infinity through) are left out.
+__device__ __forceinline__ float log_normal(float q) {
+    const float y = __builtin_amdgcn_logf(q);
+    const float hi = __builtin_bit_cast(float, 0x3f317217u), lo = __builtin_bit_cast(float, 0x3377d1cfu);
+    const float p = hi * y;
+    float e = fmaf(y, hi, -p);
+    e = fmaf(y, lo, e);
+    return fmaf(hi, y, e);
+}
+
 // l = 1/2 ln(x r) with r = 1/I_ref given as rh + rl (two floats): one
 // rounding of the product x (rh + rl).  A single-float r would shift every
 // l of a column by the same ~3e-8 and that offset adds up coherently over
 // all rows of the Gram.  Ratios that are not finite or not above the floor
-// are replaced by the floor.
+// are replaced by the floor, which the host keeps at or above 2^-126, so
+// the logarithm always sees a normal number.
 __device__ __forceinline__ float log_ratio(float x, float rh, float rl, float floor, bool& bad) {
     float q = fmaf(x, rh, x * rl);
     bad = !(q > floor && q < INFINITY);
     q = bad ? floor : q;
-    return 0.5f * logf(q);
+    return 0.5f * log_normal(q);
 }
 
 __device__ __forceinline__ float4 load4_guarded(const float* row, int col, int N, bool vec) {

@@ -119,7 +119,7 @@ def test_host_basis_zero_x_gives_no_phase_error():
 
 
 @pytest.mark.parametrize("kw", [dict(k=0), dict(k=300), dict(sg_window=10), dict(sg_window=2001),
-                                dict(fft_len=1000), dict(als_p=0.0), dict(als_iters=0), dict(ratio_floor=0.0),
+                                dict(fft_len=1000), dict(als_p=0.0), dict(als_iters=0), dict(ratio_floor=0.0), dict(ratio_floor=1e-39),
                                 dict(output=7), dict(detrend=5), dict(ridge_rel=-1.0),
                                 dict(f_mode=1, alpha=0.0, sigma_g=0.0), dict(gram_prec=4), dict(recon_prec=2), dict(recon_prec=-1),
                                 dict(svd_mode=2), dict(svd_mode=1, rrf_power_iters=-1),
