@@ -530,8 +530,10 @@ size_t fit_layout(void* base, int64_t M, int N, const fkk_params* p, FitWs* w) {
     }
     w->fdev = c.take<double>(N);
     w->Z = c.take<float>((size_t)M * (rrf ? std::max(kp, LY) : kp));
-    w->X = c.take<float>((size_t)(rrf ? std::max(kp, LY) : kp) * npad);
-    const int ka = (p->recon_prec == FKK_PREC_BF16) ? kq : kp;
+    // the projection weights: kp x npad FP32, kq x npad BF16, or three BF16
+    // piece planes (recon_prec FKK_PREC_SPLIT)
+    w->X = c.take<float>((size_t)std::max(rrf ? std::max(kp, LY) : kp, (3 * kq + 1) / 2) * npad);
+    const int ka = (p->recon_prec == FKK_PREC_BF16 || p->recon_prec == FKK_PREC_SPLIT) ? kq : kp;
     const size_t nblk = (size_t)fkk::dev::proj_blocks(M);
     w->pmaxv = c.take<float>(nblk * ka);
     w->pminv = c.take<float>(nblk * ka);
@@ -1168,32 +1170,43 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     t0 = std::chrono::steady_clock::now();
     fkk_basis* b = new_basis(N, k, h_iref, f.data(), sv.data(), V.data(), p->ml_lambda, p->ratio_floor);
     b->prec = p->recon_prec;
-    const bool pbf16 = (p->recon_prec == FKK_PREC_BF16);
+    const bool pbf16 = (p->recon_prec == FKK_PREC_BF16), psplit = (p->recon_prec == FKK_PREC_SPLIT);
     const int kq = b->kq;
-    const int ka = pbf16 ? kq : kp;  // column blocks of the arg-extrema partials
+    const int ka = (pbf16 || psplit) ? kq : kp;  // column blocks of the arg-extrema partials
     std::vector<float> wt((size_t)kp * b->npad, 0.f);
     for (int c = 0; c < k; ++c)
         for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(f[j] * V[(size_t)j * k + c]);
+    // BF16 copy (kq x npad), or three BF16 pieces of each FP32 weight in
+    // consecutive planes (the first is the BF16 copy)
     std::vector<uint16_t> wt16;
-    if (pbf16) {
-        wt16.assign((size_t)kq * b->npad, 0);
-        for (size_t i = 0; i < wt.size(); ++i) wt16[i] = to_bf16(wt[i]);
+    if (pbf16 || psplit) {
+        const int np16 = psplit ? 3 : 1;
+        wt16.assign((size_t)np16 * kq * b->npad, 0);
+        for (size_t i = 0; i < wt.size(); ++i) {
+            float rest = wt[i];
+            for (int pc = 0; pc < np16; ++pc) {
+                const uint16_t h = to_bf16(rest);
+                wt16[(size_t)pc * kq * b->npad + i] = h;
+                rest -= from_bf16(h);
+            }
+        }
     }
     auto cleanup = [&](fkk_status e) { delete b; return e; };
     const int64_t nblk = fkk::dev::proj_blocks(M);
-    // w.X holds the weights: kp x npad FP32, or kq x npad BF16 (kq <= 2 kp)
+    // w.X holds the weights: kp x npad FP32, kq x npad BF16, or three such BF16 planes
     float* d_wt = w.X;  // the fit's projection weights (no ML shrink)
     uint16_t* d_wt16 = reinterpret_cast<uint16_t*>(w.X);
     const hipError_t wcopy =
-        pbf16 ? hipMemcpyAsync(d_wt16, wt16.data(), wt16.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s)
-              : hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s);
+        (pbf16 || psplit)
+            ? hipMemcpyAsync(d_wt16, wt16.data(), wt16.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s)
+            : hipMemcpyAsync(d_wt, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice, s);
     if (wcopy != hipSuccess) return cleanup(ctx->fail(FKK_EDEVICE, "copy of projection weights failed"));
     fkk::dev::ArgPart part{w.pmaxv, w.pminv, w.pmaxi, w.pmini};
     hipError_t perr = hipEventRecord(ctx->ev[2], s);
     if (perr == hipSuccess) {
-        if (pbf16)  // log ratio recomputed from I
+        if (pbf16 || psplit)  // log ratio recomputed from I
             perr = fkk::dev::launch_project16(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt16, b->npad, kq,
-                                              kp, w.Z, kp, part, k, s);
+                                              kp, w.Z, kp, part, k, s, psplit ? 3 : 1);
         else if (gprec == FKK_PREC_BF16 || gprec == FKK_PREC_SPLIT)  // w.g.L holds no FP32 l: start from I
             perr = fkk::dev::launch_project(d_I, M, N, ld, w.g.rinv, (float)p->ratio_floor, d_wt, b->npad, kp, kp,
                                             w.Z, kp, part, k, s, false);
@@ -1276,7 +1289,7 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     if (d_out) {
         if (hipEventRecord(ctx->ev[4], s) != hipSuccess ||
             (pbf16 || p->recon_prec == FKK_PREC_SPLIT
-                 ? fkk::dev::launch_reconstruct16(w.Z, M, kp, k, b->d_bre16, b->d_bim16, kq, N, d_out, ld_out,
+                 ? fkk::dev::launch_reconstruct16(w.Z, M, kp, k, b->d_bre16, b->d_bim16, kq, N, b->npad, d_out, ld_out,
                                                   p->output, s, pbf16 ? 1 : 3)
                  : fkk::dev::launch_reconstruct(w.Z, M, kp, k, b->d_bre_t, b->d_bim_t, kp, N, d_out, ld_out,
                                                 p->output, s)) != hipSuccess ||
@@ -1435,7 +1448,7 @@ fkk_status fkk_reconstruct(fkk_ctx* ctx, const fkk_basis* b, const float* d_z, i
     if (b->device != ctx->device || !b->d_bre_t) return ctx->fail(FKK_EMISMATCH, "basis lives on another device");
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     if (b->prec == FKK_PREC_BF16 || b->prec == FKK_PREC_SPLIT)
-        FKK_HIP(ctx, fkk::dev::launch_reconstruct16(d_z, M, ld_z, b->k, b->d_bre16, b->d_bim16, b->kq, b->N, d_out,
+        FKK_HIP(ctx, fkk::dev::launch_reconstruct16(d_z, M, ld_z, b->k, b->d_bre16, b->d_bim16, b->kq, b->N, b->npad, d_out,
                                                     ld_out, plane, ctx->stream,
                                                     b->prec == FKK_PREC_SPLIT ? 3 : 1));
     else

@@ -130,16 +130,19 @@ hipError_t launch_logratio16(const float* I, int64_t M, int N, int64_t ld, const
 // Gram partials from the packed log ratio (plan from gram_plan(.., 64)).
 hipError_t launch_gram16(const uint16_t* Lp, int npad, int64_t M, const GramPlan& plan, const int* d_tiles,
                          double* partial, hipStream_t s);
-// Projection from I (log ratio on load), Wt: kq x ldw BF16.
+// Projection from I (log ratio on load), Wt: kq x ldw BF16.  pieces 3: Wt
+// holds three BF16 piece planes of W^T (kq x ldw each, consecutive), the log
+// ratio is cut into three pieces as well, and Z has FP32 accuracy.
 hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                             const uint16_t* Wt, int ldw, int kq, int k_store, float* Z, int64_t ld_z,
-                            ArgPart part, int k_arg, hipStream_t s);
-// Reconstruction from FP32 Z; BreT / BimT: npad (N rounded up to 128) x kq
-// BF16.  pieces = 3: FP32 accuracy on the BF16 matrix cores, BreT / BimT
-// then three consecutive npad x kq planes (the BF16 pieces of B) each.
+                            ArgPart part, int k_arg, hipStream_t s, int pieces = 1);
+// Reconstruction from FP32 Z; BreT / BimT: npad x kq BF16 (npad >= N rows,
+// zero past N; the basis keeps N rounded up to 64), read at rows below
+// npad only.  pieces = 3: FP32 accuracy on the BF16 matrix cores, BreT /
+// BimT then three consecutive npad x kq planes (the BF16 pieces of B) each.
 hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
-                                const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
-                                hipStream_t s, int pieces = 1);
+                                const uint16_t* BimT, int kq, int N, int npad, float* out, int64_t ld_out,
+                                int plane, hipStream_t s, int pieces = 1);
 hipError_t launch_transform16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                               const uint16_t* Wt, int ldw, int kq, const uint16_t* BreT, const uint16_t* BimT,
                               float* out, int64_t ld_out, int plane, hipStream_t s,

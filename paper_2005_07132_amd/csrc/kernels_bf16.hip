@@ -592,6 +592,105 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
 }
 
 // ---------------------------------------------------------------------------
+// Projection Z = l W to FP32 accuracy on the BF16 matrix cores: the FP32 log
+// ratio staged in LDS and cut into three BF16 pieces as each wave reads its
+// operand (split3), W given as three BF16 piece planes (KQ x ldw each,
+// consecutive), and the six piece products of combined order <= 2 summed in
+// FP32, smallest first within a 32-wavenumber step.
+// ---------------------------------------------------------------------------
+constexpr int PLF = PNC + 4;  // FP32 row stride of the staged log-ratio tile
+
+template <bool VEC>
+__device__ __forceinline__ void stage_logratio_f32(float (*sL)[PLF], const float* __restrict__ I, int64_t r0,
+                                                   int64_t M, int N, int64_t ld, int j0,
+                                                   const float* __restrict__ rinv, float floor) {
+    const int tid = threadIdx.x;
+    const int lrow = tid >> 4;
+    const int lcol = (tid & 15) * 4;
+    const int col = j0 + lcol;
+    float r[4], rl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        r[q] = (col + q < N) ? rinv[col + q] : 0.f;
+        rl[q] = (col + q < N) ? rinv[N + col + q] : 0.f;
+    }
+    float4 x[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int64_t row = r0 + lrow + 16 * p;
+        x[p] = (row < M) ? load4_guarded(I + row * ld, col, N, VEC) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int64_t row = r0 + lrow + 16 * p;
+        float l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bool bad;
+            l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], rl[q], floor, bad) : 0.f;
+        }
+        *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
+    }
+}
+
+template <int NCB, bool VEC>
+__global__ __launch_bounds__(256) void project16x3_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
+                                                          const float* __restrict__ rinv, float floor,
+                                                          const unsigned short* __restrict__ Wt, int ldw,
+                                                          int k_store, float* __restrict__ Z, int64_t ld_z,
+                                                          float* pmaxv, float* pminv, long long* pmaxi,
+                                                          long long* pmini, int k_arg) {
+    constexpr int KQ = NCB * 16;
+    __shared__ __attribute__((aligned(16))) float sL[PR][PLF];
+    __shared__ __attribute__((aligned(16))) unsigned short sW[3][KQ][SLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * PR;
+    floatx4 acc[2][NCB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < N; j0 += PNC) {
+        stage_logratio_f32<VEC>(sL, I, r0, M, N, ld, j0, rinv, floor);
+#pragma unroll
+        for (int pc = 0; pc < 3; ++pc) stage_weights16<KQ>(sW[pc], Wt + (size_t)pc * KQ * ldw, ldw, j0);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < PNC / 32; ++ks) {
+            const int kc = ks * 32 + 8 * (lane >> 4);
+            u32x4 a[2][3], w[NCB][3];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const float* src = &sL[wave * 32 + rb * 16 + (lane & 15)][kc];
+                const float4 x0 = *reinterpret_cast<const float4*>(src);
+                const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+                unsigned pk[4][3];
+                split3(x0.x, x0.y, pk[0]);
+                split3(x0.z, x0.w, pk[1]);
+                split3(x1.x, x1.y, pk[2]);
+                split3(x1.z, x1.w, pk[3]);
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc) a[rb][pc] = u32x4{pk[0][pc], pk[1][pc], pk[2][pc], pk[3][pc]};
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int pc = 0; pc < 3; ++pc) w[cb][pc] = *reinterpret_cast<const u32x4*>(&sW[pc][cb * 16 + (lane & 15)][kc]);
+            // piece pairs (l, w) by combined order 2, 1, 0
+            constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PW[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma16(a[rb][PA[t]], w[cb][PW[t]], acc[rb][cb]);
+        }
+        __syncthreads();
+    }
+    project_finish<NCB>(acc, r0, M, Z, ld_z, k_store, pmaxv, pminv, pmaxi, pmini, k_arg);
+}
+
+// ---------------------------------------------------------------------------
 // Fused stored-basis transform in BF16: projection (transposed, so that the
 // Z tile goes to LDS as 4-value BF16 stores), then reconstruction.
 // ---------------------------------------------------------------------------
@@ -719,19 +818,24 @@ hipError_t launch_gram16(const uint16_t* Lp, int npad, int64_t M, const GramPlan
 
 hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const float* rinv, float floor,
                             const uint16_t* Wt, int ldw, int kq, int k_store, float* Z, int64_t ld_z, ArgPart part,
-                            int k_arg, hipStream_t s) {
-    if (ldw % 8 != 0) return hipErrorInvalidValue;
+                            int k_arg, hipStream_t s, int pieces) {
+    if (ldw % 8 != 0 || (pieces != 1 && pieces != 3)) return hipErrorInvalidValue;
     const bool vec = ((reinterpret_cast<uintptr_t>(I) & 15) == 0) && (ld % 4 == 0);
     dim3 grid((unsigned)proj_blocks(M));
     const unsigned short* w = reinterpret_cast<const unsigned short*>(Wt);
-#define FKK_PJ16(NCB)                                                                                             \
+#define FKK_PJ16_K(KERNEL, NCB)                                                                                   \
     do {                                                                                                          \
         if (vec)                                                                                                  \
-            hipLaunchKernelGGL((project16_kernel<NCB, true>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, w, \
-                               ldw, k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);         \
+            hipLaunchKernelGGL((KERNEL<NCB, true>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, w, ldw,      \
+                               k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);              \
         else                                                                                                      \
-            hipLaunchKernelGGL((project16_kernel<NCB, false>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor,   \
-                               w, ldw, k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);      \
+            hipLaunchKernelGGL((KERNEL<NCB, false>), grid, dim3(256), 0, s, I, M, N, ld, rinv, floor, w, ldw,     \
+                               k_store, Z, ld_z, part.maxv, part.minv, part.maxi, part.mini, k_arg);              \
+    } while (0)
+#define FKK_PJ16(NCB)                                            \
+    do {                                                         \
+        if (pieces == 3) FKK_PJ16_K(project16x3_kernel, NCB);    \
+        else FKK_PJ16_K(project16_kernel, NCB);                  \
     } while (0)
     switch (kq) {
         case 32: FKK_PJ16(2); break;
@@ -740,18 +844,19 @@ hipError_t launch_project16(const float* I, int64_t M, int N, int64_t ld, const 
         default: return hipErrorInvalidValue;
     }
 #undef FKK_PJ16
+#undef FKK_PJ16_K
     return hipGetLastError();
 }
 
 hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, const uint16_t* BreT,
-                                const uint16_t* BimT, int kq, int N, float* out, int64_t ld_out, int plane,
+                                const uint16_t* BimT, int kq, int N, int npad, float* out, int64_t ld_out, int plane,
                                 hipStream_t s, int pieces) {
     if (M <= 0) return hipSuccess;
     if (k < 1 || k > ld_z) return hipErrorInvalidValue;
     if (kq != 32 && kq != 64 && kq != 128) return hipErrorInvalidValue;
     if (pieces != 1 && pieces != 3) return hipErrorInvalidValue;
+    if (npad < N) return hipErrorInvalidValue;
     const int kb2 = kq / 32;
-    const int npad = (N + kGramTile - 1) / kGramTile * kGramTile;
     const bool vec = ((reinterpret_cast<uintptr_t>(out) & 15) == 0) && (ld_out % 4 == 0);
     const bool vz = ((reinterpret_cast<uintptr_t>(Z) & 15) == 0) && (ld_z % 4 == 0);
     const u32x4* bre = reinterpret_cast<const u32x4*>(BreT);

@@ -154,11 +154,13 @@ def test_bf16_projection_exact_operands(ctx, k, m, n):
         assert zref[qmin[c], c] <= zref[:, c].min() + 4 * TOL * scale
 
 
-@pytest.mark.parametrize("k,phase", [(8, 1.0), (30, 1.0), (64, 0.5), (100, 0.3)])
-def test_bf16_reconstruction_exact_operands(ctx, k, phase):
-    say(f"bf16 reconstruct k={k}")
+@pytest.mark.parametrize("k,phase,n", [(8, 1.0, 333), (30, 1.0, 333), (64, 0.5, 333), (100, 0.3, 333),
+                                         (30, 1.0, 300)])
+def test_bf16_reconstruction_exact_operands(ctx, k, phase, n):
+    # n = 300: rows of the BF16 basis planes end at 320 (N rounded up to 64)
+    say(f"bf16 reconstruct k={k} n={n}")
     rng = synth.rng_for(903, k)
-    m, n = 2000, 333
+    m = 2000
     basis = synthetic_basis(rng, n, k, np.ones(n), phase=phase)
     z16 = bf16_values(rng, (m, k), 0.25, 2.0)
     b = ctx.basis_import(basis)

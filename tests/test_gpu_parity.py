@@ -283,13 +283,16 @@ def test_reconstruction_epilogue(ctx, fitted, plane, prec):
     assert spectrum_err(out, ref).max() < TOL
 
 
+@pytest.mark.parametrize("n", [200, 300])
 @pytest.mark.parametrize("prec", [fk.PREC_FP32, fk.PREC_SPLIT])
-def test_reconstruction_epilogue_wide_phase_range(ctx, prec):
+def test_reconstruction_epilogue_wide_phase_range(ctx, prec, n):
     # the device epilogue reduces the phase by multiples of pi/2: check it
-    # over several periods (|phase| up to ~8 rad) against FP64 sin/cos/exp
-    say(f"reconstruct wide phase prec={prec}")
+    # over several periods (|phase| up to ~8 rad) against FP64 sin/cos/exp.
+    # n = 300: the basis keeps N rounded up to 64 rows (320), not to 128
+    # (384), and the BF16 piece planes are read at that stride
+    say(f"reconstruct wide phase prec={prec} n={n}")
     rng = synth.rng_for(77, 1)
-    n, k, m = 200, 10, 3000
+    k, m = 10, 3000
     v = np.linalg.qr(rng.standard_normal((n, k)))[0]
     basis = {"i_ref": np.ones(n), "f": np.ones(n), "s": np.ones(k), "v": v,
              "b_re": 0.05 * rng.standard_normal((k, n)), "b_im": rng.standard_normal((k, n)),
