@@ -87,11 +87,12 @@ enum { FKK_OUT_IM = 0, FKK_OUT_RE = 1, FKK_OUT_ABS = 2 };
  * that the FP64 mode keeps.  The column exponents come from every 16th
  * row with one bit of headroom; if a row does not fit, the pass is redone
  * with exact exponents (the result is the same to the bound above).
- * SPLIT as recon_prec reaches FP32 accuracy in the reconstruction of
- * Eq. 23 on the BF16 matrix cores: Z and the corrected bases are each cut
+ * SPLIT as recon_prec reaches FP32 accuracy in the fit's projection and
+ * in the reconstruction of Eq. 23 on the BF16 matrix cores: the log ratio
+ * and the projection weights, then Z and the corrected bases, are each cut
  * into three BF16 pieces (x = x1 + x2 + x3 + r, |r| about 2^-24 |x|), and
  * the six piece products of combined order up to two are summed in FP32;
- * its projections and transforms run in FP32.
+ * stored-basis projections and transforms with such a basis run in FP32.
  * The eigensolve and the basis-vector KK / PEC / SEC are FP64 always. */
 enum { FKK_PREC_FP32 = 0, FKK_PREC_BF16 = 1, FKK_PREC_FP64 = 2, FKK_PREC_SPLIT = 3 };
 /* Route of the truncated SVD (Eq. 6) in fkk_fit. */

@@ -51,6 +51,7 @@ TOL = 1e-5
 FRAC = 0.9
 MODES = (("fp64 gram + fp32", fk.PREC_FP64, fk.PREC_FP32),
          ("split gram + fp32", fk.PREC_SPLIT, fk.PREC_FP32),
+         ("split gram + split", fk.PREC_SPLIT, fk.PREC_SPLIT),
          ("fp32", fk.PREC_FP32, fk.PREC_FP32),
          ("bf16", fk.PREC_BF16, fk.PREC_BF16))
 
@@ -112,7 +113,7 @@ def test_precision_pattern_k50(request, case):
         e_all = errors(out.cpu().numpy(), o.im)
         # Eq. 23 of the fit's own basis
         ell, _ = wf.log_ratio(i_rows, e["i_ref"], e["ratio_floor"])
-        if rprec == fk.PREC_FP32:
+        if rprec in (fk.PREC_FP32, fk.PREC_SPLIT):  # FP32-accurate projection and reconstruction
             own = wf.reconstruct((ell * e["f"]) @ e["v"], e)["im"]
             e_own = spectrum_err(got_rows, own)
             assert e_own.max() < TOL, (label, e_own.max())
