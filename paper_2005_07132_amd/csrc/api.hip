@@ -322,33 +322,39 @@ fkk_status upload_basis(fkk_ctx* ctx, fkk_basis* b, double shrink_lambda) {
     for (int j = 0; j < N; ++j) fd[j] = (float)b->f[j];
     double smax = 0.0;
     for (int c = 0; c < k; ++c) smax = std::max(smax, b->s[c]);
-    for (int c = 0; c < k; ++c) {
-        double shrink;
-        if (shrink_lambda > 0.0) shrink = b->s[c] * b->s[c] / (b->s[c] * b->s[c] + shrink_lambda);
-        else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
-        gd[c] = shrink > 0.0 ? (float)(1.0 / shrink) : 0.f;
-        for (int j = 0; j < N; ++j) {
-            const float w = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
-            wt[(size_t)c * np + j] = w;
-            wt16[(size_t)c * np + j] = to_bf16(w);
-        }
-    }
-    for (int j = 0; j < N; ++j)
-        for (int c = 0; c < k; ++c) {
-            const float re = (float)b->b_re[(size_t)c * N + j], im = (float)b->b_im[(size_t)c * N + j];
-            bre[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = re;
-            bim[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = im;
-            // three BF16 pieces of the FP32 value (planes np kq apart): the
-            // first is the BF16 copy, the rest carry the remainders
-            float rr = re, ri = im;
-            for (int pc = 0; pc < 3; ++pc) {
-                const uint16_t hr = to_bf16(rr), hi = to_bf16(ri);
-                bre16[(size_t)pc * np * kq + (size_t)j * kq + c] = hr;
-                bim16[(size_t)pc * np * kq + (size_t)j * kq + c] = hi;
-                rr -= from_bf16(hr);
-                ri -= from_bf16(hi);
+    // (rows of each array split over the host pool: every element is
+    // written by one thread, so the contents do not depend on the split)
+    fkk::parallel_rows(k, [&](int c0, int c1) {
+        for (int c = c0; c < c1; ++c) {
+            double shrink;
+            if (shrink_lambda > 0.0) shrink = b->s[c] * b->s[c] / (b->s[c] * b->s[c] + shrink_lambda);
+            else shrink = (b->s[c] > 1e-15 * smax) ? 1.0 : 0.0;  // pseudo-inverse of S V^T
+            gd[c] = shrink > 0.0 ? (float)(1.0 / shrink) : 0.f;
+            for (int j = 0; j < N; ++j) {
+                const float w = (float)(b->f[j] * b->v[(size_t)j * k + c] * shrink);
+                wt[(size_t)c * np + j] = w;
+                wt16[(size_t)c * np + j] = to_bf16(w);
             }
         }
+    });
+    fkk::parallel_rows(N, [&](int j0, int j1) {
+        for (int j = j0; j < j1; ++j)
+            for (int c = 0; c < k; ++c) {
+                const float re = (float)b->b_re[(size_t)c * N + j], im = (float)b->b_im[(size_t)c * N + j];
+                bre[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = re;
+                bim[(size_t)j * kp + fkk::dev::kgroup_pos(c)] = im;
+                // three BF16 pieces of the FP32 value (planes np kq apart): the
+                // first is the BF16 copy, the rest carry the remainders
+                float rr = re, ri = im;
+                for (int pc = 0; pc < 3; ++pc) {
+                    const uint16_t hr = to_bf16(rr), hi = to_bf16(ri);
+                    bre16[(size_t)pc * np * kq + (size_t)j * kq + c] = hr;
+                    bim16[(size_t)pc * np * kq + (size_t)j * kq + c] = hi;
+                    rr -= from_bf16(hr);
+                    ri -= from_bf16(hi);
+                }
+            }
+    });
     FKK_HIP(ctx, hipSetDevice(ctx->device));
     if (!b->d_arena) FKK_HIP(ctx, hipMalloc(&b->d_arena, total));
     unsigned char* d = reinterpret_cast<unsigned char*>(b->d_arena);
@@ -1173,24 +1179,25 @@ fkk_status fkk_fit(fkk_ctx* ctx, const float* d_I, int64_t M, int32_t N, int64_t
     const bool pbf16 = (p->recon_prec == FKK_PREC_BF16), psplit = (p->recon_prec == FKK_PREC_SPLIT);
     const int kq = b->kq;
     const int ka = (pbf16 || psplit) ? kq : kp;  // column blocks of the arg-extrema partials
+    // FP32 weights (kp x npad), and for the BF16 modes their BF16 copy
+    // (kq x npad) or three BF16 pieces in consecutive planes (the first is
+    // the BF16 copy); rows of W^T split over the host pool
     std::vector<float> wt((size_t)kp * b->npad, 0.f);
-    for (int c = 0; c < k; ++c)
-        for (int j = 0; j < N; ++j) wt[(size_t)c * b->npad + j] = (float)(f[j] * V[(size_t)j * k + c]);
-    // BF16 copy (kq x npad), or three BF16 pieces of each FP32 weight in
-    // consecutive planes (the first is the BF16 copy)
     std::vector<uint16_t> wt16;
-    if (pbf16 || psplit) {
-        const int np16 = psplit ? 3 : 1;
-        wt16.assign((size_t)np16 * kq * b->npad, 0);
-        for (size_t i = 0; i < wt.size(); ++i) {
-            float rest = wt[i];
-            for (int pc = 0; pc < np16; ++pc) {
-                const uint16_t h = to_bf16(rest);
-                wt16[(size_t)pc * kq * b->npad + i] = h;
-                rest -= from_bf16(h);
+    const int np16 = psplit ? 3 : (pbf16 ? 1 : 0);
+    if (np16) wt16.assign((size_t)np16 * kq * b->npad, 0);
+    fkk::parallel_rows(k, [&](int c0, int c1) {
+        for (int c = c0; c < c1; ++c)
+            for (int j = 0; j < N; ++j) {
+                const size_t i = (size_t)c * b->npad + j;
+                float rest = wt[i] = (float)(f[j] * V[(size_t)j * k + c]);
+                for (int pc = 0; pc < np16; ++pc) {
+                    const uint16_t h = to_bf16(rest);
+                    wt16[(size_t)pc * kq * b->npad + i] = h;
+                    rest -= from_bf16(h);
+                }
             }
-        }
-    }
+    });
     auto cleanup = [&](fkk_status e) { delete b; return e; };
     const int64_t nblk = fkk::dev::proj_blocks(M);
     // w.X holds the weights: kp x npad FP32, kq x npad BF16, or three such BF16 planes
