@@ -231,7 +231,7 @@ def test_bf16_fit_lowrank(ctx):
     assert np.mean(err_own < TOL) >= FRAC and err_own.max() < 1e-2
 
 
-@pytest.mark.parametrize("gram_prec,recon_prec", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("gram_prec,recon_prec", [(1, 0), (0, 1), (1, 1), (3, 3), (0, 3)])
 def test_mixed_precision_fit(ctx, gram_prec, recon_prec):
     # Eq. 23 of the device's own (exported) basis is the parity target; the
     # distance to the FP64 oracle's fit, which also moves with the
@@ -247,7 +247,7 @@ def test_mixed_precision_fit(ctx, gram_prec, recon_prec):
     assert b.precision == recon_prec
     e = b.export()
     ell, _ = wf.log_ratio(cube.i_cars.astype(np.float64), e["i_ref"], e["ratio_floor"])
-    if recon_prec == fk.PREC_FP32:
+    if recon_prec in (fk.PREC_FP32, fk.PREC_SPLIT):  # FP32-accurate projection and reconstruction
         own = wf.reconstruct((ell * e["f"]) @ e["v"], e)["im"]
         assert spectrum_err(out, own).max() < TOL
     else:
