@@ -26,10 +26,12 @@ FP32 and BF16 fits are not held to the oracle's own fit: past the signal
 subspace their eigenvectors move within the noise bulk, which the bound
 above allows.
 
-test_precision_sweep adds k in {20, 100} (minutes of host time: six FP64
-oracle fits of up to 0.7 G values): it runs only when FKK_PRECISION_SWEEP=1
-and writes its report as JSON to FKK_SWEEP_OUT (default
-gpurun_out/precision_sweep.json).
+test_precision_sweep takes k in {20, 100} on the same two cubes (one FP64
+oracle fit per cube and k, about a minute of host time per cube), with the
+same five modes: with the FP64 and the split Gram every spectrum within 1e-5
+of the oracle's fit and the same sub-sampled rows; FP32 and BF16 are
+reported.  Each cube's report is written as JSON to the directory
+FKK_SWEEP_OUT (default gpurun_out).
 """
 import json
 import os
@@ -181,48 +183,42 @@ def spectrum_err(y, ref):
     return np.abs(y - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-30)
 
 
-@pytest.mark.skipif(os.environ.get("FKK_PRECISION_SWEEP") != "1",
-                    reason="k in {20, 100} runs only with FKK_PRECISION_SWEEP=1 (minutes of host time)")
-def test_precision_sweep():
+@pytest.mark.parametrize("case", ["tissue703_oracle", "tissue262_oracle"])
+def test_precision_sweep(request, case):
+    o = request.getfixturevalue(case)
+    cube = o.cube
+    m, n = cube.shape
     ctx = fk.Context(0)
     report = {"description": "per-spectrum relative error of Im K_CARS vs the FP64 oracle fit of the same FP32 "
                              "input; max / RMS / 99th percentile over spectra, plus the global relative RMS",
-              "cases": []}
-    cubes = [("tissue 703,026 x 1,000", synth.tissue_703k),
-             ("tissue 262,144 x 1,600", lambda: synth.tissue_cube(rows=512, cols=512, n=1600, map_key=3,
-                                                                   noise_key=3))]
-    for name, make in cubes:
+              "cube": case, "M": m, "N": n, "cases": []}
+    I = torch.from_numpy(cube.i_cars).cuda()
+    out = torch.empty_like(I)
+    i64 = cube.i_cars.astype(np.float64)
+    for k in (20, 100):
         t0 = time.perf_counter()
-        cube = make()
-        m, n = cube.shape
-        say(f"sweep cube {name} ready in {time.perf_counter() - t0:.1f} s")
-        I = torch.from_numpy(cube.i_cars).cuda()
-        out = torch.empty_like(I)
-        i64 = cube.i_cars.astype(np.float64)
-        for k in (20, 50, 100):
-            t0 = time.perf_counter()
-            ref = wf.fit(i64, cube.i_ref, wf.Params(k=k, f_mode=wf.F_NOISE, alpha=cube.alpha,
-                                                    sigma_g=cube.sigma_g), svd="gram")["im"]
-            say(f"sweep {name} k={k}: oracle fit {time.perf_counter() - t0:.1f} s")
-            for label, gprec, rprec in (("fp64 gram + fp32", fk.PREC_FP64, fk.PREC_FP32),
-                                        ("fp32", fk.PREC_FP32, fk.PREC_FP32),
-                                        ("bf16", fk.PREC_BF16, fk.PREC_BF16)):
-                p = fk.params(k=k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
-                              gram_prec=gprec, recon_prec=rprec)
-                b, _, rep = ctx.fit(I, cube.i_ref, p, out=out)
-                b.free()
-                torch.cuda.synchronize()
-                e = errors(out.cpu().numpy(), ref)
-                case = {"cube": name, "M": m, "N": n, "k": k, "precision": label, "fit_ms": rep["ms_total"], **e}
-                report["cases"].append(case)
-                say(f"sweep {name} k={k} {label}: max {e['max']:.3e} rms {e['rms']:.3e} "
-                    f"p99 {e['p99']:.3e} global {e['global_rel_rms']:.3e} ({rep['ms_total']:.1f} ms)")
-                assert np.isfinite(e["max"]) and e["max"] < 1.0
-            del ref
-        del I, out, i64, cube
-        torch.cuda.empty_cache()
+        ref = wf.fit(i64, cube.i_ref, o.p.with_(k=k), svd="gram")
+        say(f"sweep {case} k={k}: oracle fit {time.perf_counter() - t0:.1f} s")
+        for label, gprec, rprec in MODES:
+            p = fk.params(k=k, f_mode=fk.F_NOISE, alpha=cube.alpha, sigma_g=cube.sigma_g,
+                          gram_prec=gprec, recon_prec=rprec)
+            b, _, rep = ctx.fit(I, cube.i_ref, p, out=out)
+            q = b.export()["q"]
+            b.free()
+            torch.cuda.synchronize()
+            e = errors(out.cpu().numpy(), ref["im"])
+            report["cases"].append({"k": k, "precision": label, "fit_ms": rep["ms_total"], **e})
+            say(f"sweep {case} k={k} {label}: max {e['max']:.3e} rms {e['rms']:.3e} "
+                f"p99 {e['p99']:.3e} global {e['global_rel_rms']:.3e} ({rep['ms_total']:.1f} ms)")
+            if gprec in (fk.PREC_FP64, fk.PREC_SPLIT):
+                assert e["max"] < TOL, (label, k, e["max"])
+                np.testing.assert_array_equal(np.sort(q), np.sort(ref["basis"]["q"]))
+            assert np.isfinite(e["max"]) and e["max"] < 1.0
+        del ref
+    del I, out, i64
+    torch.cuda.empty_cache()
     ctx.close()
-    path = os.environ.get("FKK_SWEEP_OUT", os.path.join("gpurun_out", "precision_sweep.json"))
-    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    with open(path, "w") as fh:
+    path = os.environ.get("FKK_SWEEP_OUT", "gpurun_out")
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, f"precision_sweep_{case}.json"), "w") as fh:
         json.dump(report, fh, indent=1)
