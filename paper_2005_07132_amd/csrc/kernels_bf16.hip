@@ -405,16 +405,17 @@ __device__ __forceinline__ void recon16_loop(const u32x4 (&zb)[2][KB2], const u3
 }
 
 // ---------------------------------------------------------------------------
-// Reconstruction with the basis resident in LDS.  A block of 8 waves holds a
+// Reconstruction with the basis resident in LDS.  A block of W waves holds a
 // slice of CW wavenumbers of B_re^T and B_im^T (zero rows past N) for the
-// whole launch and walks TPB consecutive tiles of 256 spectra, 32 per wave.
+// whole launch and walks TPB consecutive tiles of 32 W spectra, 32 per wave.
 // The main loop has no barrier and no basis load: its only vector loads are
-// the next tile's Z, issued before the current tile's stores, so the wait
-// for them (one counter covers loads and stores) reaches only stores of two
-// tiles back.
+// the tiles' Z.  With W = 8 the next tile's Z is issued before the current
+// tile's stores, so the wait for it (one counter covers loads and stores)
+// reaches only stores of two tiles back.  The three-piece form at kq <= 64
+// runs W = 12 without that prefetch: the registers then allow three waves
+// per SIMD, which hide the Z loads and overlap one wave's stores with
+// another's products (1.64 -> 1.52 ms at 703,026 x 1,000, k = 50).
 // ---------------------------------------------------------------------------
-constexpr int RS_THREADS = 512;
-constexpr int RS_ROWS = 256;                 // spectra per tile
 constexpr int RS_LDS_UNITS = 144 * 1024 / 16;  // LDS for the two basis slices
 
 // Largest slice width (multiple of RCN) whose two planes of P pieces fit the
@@ -467,8 +468,8 @@ __device__ __forceinline__ void rs_load_z(float (&zr)[2][KB2][8], const float* _
 // Z each as three BF16 pieces (B's given as consecutive npad x kq planes,
 // Z's cut in registers), the six piece products of combined order <= 2,
 // smallest first, accumulated in FP32.
-template <int KB2, bool VEC_OUT, bool VEC_Z, int P = 1>
-__global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z,
+template <int KB2, bool VEC_OUT, bool VEC_Z, int P = 1, int W = 8>
+__global__ __launch_bounds__(64 * W) void recon16s_kernel(const float* __restrict__ Z, int64_t M, int64_t ld_z,
                                                               int k, const u32x4* __restrict__ BreT,
                                                               const u32x4* __restrict__ BimT, int N, int npad, int cw,
                                                               int nslice, int tpb, float* __restrict__ out,
@@ -483,7 +484,8 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
     const int xcd = b & 7, rr = b >> 3;
     const int slice = rr % nslice;
     const int64_t group = (int64_t)(rr / nslice) * 8 + xcd;
-    const int64_t ntiles = (M + RS_ROWS - 1) / RS_ROWS;
+    constexpr int THREADS = 64 * W, ROWS = 32 * W;
+    const int64_t ntiles = (M + ROWS - 1) / ROWS;
     const int64_t t0 = group * tpb;
     if (t0 >= ntiles) return;
     const int64_t t1 = (t0 + tpb < ntiles) ? t0 + tpb : ntiles;
@@ -501,11 +503,11 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
         u32x4* lre = sRe + 2 * pc * cw * BLDU;
         u32x4* lim = sIm + 2 * pc * cw * BLDU;
         // (eight units per plane in flight per thread before the LDS writes)
-        for (int base = 0; base < cw * UPR; base += 8 * RS_THREADS) {
+        for (int base = 0; base < cw * UPR; base += 8 * THREADS) {
             u32x4 vre[8], vim[8];
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                const int idx = base + p * RS_THREADS + tid;
+                const int idx = base + p * THREADS + tid;
                 const int j = c0 + idx / UPR;
                 const bool live = idx < cw * UPR && j < npad;
                 const size_t src = live ? (size_t)j * UPR + idx % UPR : 0;
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
             }
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                const int idx = base + p * RS_THREADS + tid;
+                const int idx = base + p * THREADS + tid;
                 if (idx < cw * UPR) {
                     lre[(idx / UPR) * BLDU + idx % UPR] = vre[p];
                     lim[(idx / UPR) * BLDU + idx % UPR] = vim[p];
@@ -525,15 +527,16 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
     }
     __syncthreads();
 
-    // rows of this wave within a tile: half h = wave / 4 of the 256, and
-    // 32 (wave % 4) .. + 31 within the half (the layout store_out takes)
-    // (the next tile's Z is loaded ahead where registers allow: KB2 <= 2)
-    constexpr bool PF = KB2 <= 2;
+    // rows of this wave within a tile: group h = wave / 4 of 128 rows, and
+    // 32 (wave % 4) .. + 31 within the group (the layout store_out takes)
+    // (the next tile's Z is loaded ahead where registers allow: KB2 <= 2
+    // with 8 waves)
+    constexpr bool PF = KB2 <= 2 && W == 8;
     const int h = wave >> 2, wq = wave & 3;
     float zr[2][KB2][8];
-    if (PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, t0 * RS_ROWS + 128 * h + 32 * wq, lane);
+    if (PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, t0 * ROWS + 128 * h + 32 * wq, lane);
     for (int64_t t = t0; t < t1; ++t) {
-        const int64_t r0 = t * RS_ROWS + 128 * h;
+        const int64_t r0 = t * ROWS + 128 * h;
         if (!PF) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + 32 * wq, lane);
         u32x4 zb[P][2][KB2];
 #pragma unroll
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(RS_THREADS) void recon16s_kernel(const float* __res
                     for (int pc = 0; pc < P; ++pc) zb[pc][jb][kg] = u32x4{w[0][pc], w[1][pc], w[2][pc], w[3][pc]};
                 }
             }
-        if (PF && t + 1 < t1) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + RS_ROWS + 32 * wq, lane);
+        if (PF && t + 1 < t1) rs_load_z<KB2, VEC_Z>(zr, Z, ld_z, M, k, r0 + ROWS + 32 * wq, lane);
         __builtin_amdgcn_sched_barrier(0);
         // each 64-wavenumber chunk in two halves, so that the stores of the
         // first half go out while the second half is multiplied
@@ -866,16 +869,19 @@ hipError_t launch_reconstruct16(const float* Z, int64_t M, int64_t ld_z, int k, 
     const int nslice = (N + cwm - 1) / cwm;
     const int cw = ((N + nslice - 1) / nslice + RCN - 1) / RCN * RCN;
     // tiles per block: about 2048 blocks over the whole launch
-    const int64_t ntiles = (M + RS_ROWS - 1) / RS_ROWS;
+    // three pieces with kq <= 64: blocks of 12 waves (three per SIMD),
+    // otherwise 8
+    const int waves = (pieces == 3 && kb2 <= 2) ? 12 : 8;
+    const int64_t ntiles = (M + 32 * waves - 1) / (32 * waves);
     int64_t tpb = (ntiles * nslice + 2047) / 2048;
     if (tpb < 1) tpb = 1;
     const int64_t groups = (ntiles + tpb - 1) / tpb;
     // block b -> group 8 (b / 8 / nslice) + b % 8: groups padded to a multiple of 8
     const int64_t nblocks = (groups + 7) / 8 * 8 * nslice;
     if (nblocks > INT_MAX) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblocks), block(RS_THREADS);
+    dim3 grid((unsigned)nblocks), block(64 * waves);
 #define FKK_RC16(KB2, VO, VZ, P)                                                                                   \
-    hipLaunchKernelGGL((recon16s_kernel<KB2, VO, VZ, P>), grid, block, 0, s, Z, M, ld_z, k, bre, bim, N, npad, cw,    \
+    hipLaunchKernelGGL((recon16s_kernel<KB2, VO, VZ, P, (P == 3 && KB2 <= 2 ? 12 : 8)>), grid, block, 0, s, Z, M, ld_z, k, bre, bim, N, npad, cw, \
                        nslice, (int)tpb, out, ld_out, plane)
 #define FKK_RC16_K(KB2, P)                                          \
     do {                                                            \
