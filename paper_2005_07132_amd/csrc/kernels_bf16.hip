@@ -599,17 +599,23 @@ __global__ __launch_bounds__(64 * W) void recon16s_kernel(const float* __restric
 // ratio staged in LDS and cut into three BF16 pieces as each wave reads its
 // operand (split3), W given as three BF16 piece planes (KQ x ldw each,
 // consecutive), and the six piece products of combined order <= 2 summed in
-// FP32, smallest first within a 32-wavenumber step.
+// FP32, smallest first within a 32-wavenumber step.  Stages of SW = 32
+// wavenumbers at kq <= 64 (38 KB of LDS and 96 registers: four blocks per
+// CU, 0.99 ms at 703,026 x 1,000 against 1.19 ms with 64-wavenumber stages
+// and two blocks per CU), 64 at kq = 128.
 // ---------------------------------------------------------------------------
-constexpr int PLF = PNC + 4;  // FP32 row stride of the staged log-ratio tile
-
-template <bool VEC>
-__device__ __forceinline__ void stage_logratio_f32(float (*sL)[PLF], const float* __restrict__ I, int64_t r0,
+// One stage of SW wavenumbers (SW = 32 or 64) of the FP32 log ratio of the
+// block's PR rows into LDS (row stride SW + 4): thread t takes four columns
+// (t % (SW / 4)) * 4 of rows t / (SW / 4) + (1024 / SW) p.
+template <bool VEC, int SW>
+__device__ __forceinline__ void stage_logratio_f32(float (*sL)[SW + 4], const float* __restrict__ I, int64_t r0,
                                                    int64_t M, int N, int64_t ld, int j0,
                                                    const float* __restrict__ rinv, float floor) {
+    constexpr int TPR = SW / 4;           // threads per row
+    constexpr int RPP = 256 / TPR;        // rows per pass
     const int tid = threadIdx.x;
-    const int lrow = tid >> 4;
-    const int lcol = (tid & 15) * 4;
+    const int lrow = tid / TPR;
+    const int lcol = (tid % TPR) * 4;
     const int col = j0 + lcol;
     float r[4], rl[4];
 #pragma unroll
@@ -617,26 +623,41 @@ __device__ __forceinline__ void stage_logratio_f32(float (*sL)[PLF], const float
         r[q] = (col + q < N) ? rinv[col + q] : 0.f;
         rl[q] = (col + q < N) ? rinv[N + col + q] : 0.f;
     }
-    float4 x[8];
+    float4 x[PR / RPP];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int64_t row = r0 + lrow + 16 * p;
+    for (int p = 0; p < PR / RPP; ++p) {
+        const int64_t row = r0 + lrow + RPP * p;
         x[p] = (row < M) ? load4_guarded(I + row * ld, col, N, VEC) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int64_t row = r0 + lrow + 16 * p;
+    for (int p = 0; p < PR / RPP; ++p) {
+        const int64_t row = r0 + lrow + RPP * p;
         float l[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             bool bad;
             l[q] = (row < M && col + q < N) ? log_ratio(f4get(x[p], q), r[q], rl[q], floor, bad) : 0.f;
         }
-        *reinterpret_cast<float4*>(&sL[lrow + 16 * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
+        *reinterpret_cast<float4*>(&sL[lrow + RPP * p][lcol]) = make_float4(l[0], l[1], l[2], l[3]);
     }
 }
 
-template <int NCB, bool VEC>
+// KQ rows of SW BF16 weights (16-byte units) into LDS (row stride SW + 8).
+template <int KQ, int SW>
+__device__ __forceinline__ void stage_weights16w(unsigned short (*sW)[SW + 8], const unsigned short* __restrict__ Wt,
+                                                 int ldw, int j0) {
+    constexpr int UPR = SW / 8, UNITS = KQ * UPR;
+#pragma unroll
+    for (int p = 0; p < (UNITS + 255) / 256; ++p) {
+        const int u = threadIdx.x + 256 * p;
+        if (UNITS % 256 == 0 || u < UNITS) {
+            const int c = u / UPR, c8 = (u % UPR) * 8;
+            *reinterpret_cast<u32x4*>(&sW[c][c8]) = *reinterpret_cast<const u32x4*>(Wt + (size_t)c * ldw + j0 + c8);
+        }
+    }
+}
+
+template <int NCB, bool VEC, int SW = (NCB <= 4 ? 32 : PNC)>
 __global__ __launch_bounds__(256) void project16x3_kernel(const float* __restrict__ I, int64_t M, int N, int64_t ld,
                                                           const float* __restrict__ rinv, float floor,
                                                           const unsigned short* __restrict__ Wt, int ldw,
@@ -644,8 +665,8 @@ __global__ __launch_bounds__(256) void project16x3_kernel(const float* __restric
                                                           float* pmaxv, float* pminv, long long* pmaxi,
                                                           long long* pmini, int k_arg) {
     constexpr int KQ = NCB * 16;
-    __shared__ __attribute__((aligned(16))) float sL[PR][PLF];
-    __shared__ __attribute__((aligned(16))) unsigned short sW[3][KQ][SLD];
+    __shared__ __attribute__((aligned(16))) float sL[PR][SW + 4];
+    __shared__ __attribute__((aligned(16))) unsigned short sW[3][KQ][SW + 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * PR;
     floatx4 acc[2][NCB];
@@ -653,13 +674,13 @@ __global__ __launch_bounds__(256) void project16x3_kernel(const float* __restric
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int j0 = 0; j0 < N; j0 += PNC) {
-        stage_logratio_f32<VEC>(sL, I, r0, M, N, ld, j0, rinv, floor);
+    for (int j0 = 0; j0 < N; j0 += SW) {
+        stage_logratio_f32<VEC, SW>(sL, I, r0, M, N, ld, j0, rinv, floor);
 #pragma unroll
-        for (int pc = 0; pc < 3; ++pc) stage_weights16<KQ>(sW[pc], Wt + (size_t)pc * KQ * ldw, ldw, j0);
+        for (int pc = 0; pc < 3; ++pc) stage_weights16w<KQ, SW>(sW[pc], Wt + (size_t)pc * KQ * ldw, ldw, j0);
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < PNC / 32; ++ks) {
+        for (int ks = 0; ks < SW / 32; ++ks) {
             const int kc = ks * 32 + 8 * (lane >> 4);
             u32x4 a[2][3], w[NCB][3];
 #pragma unroll
