@@ -312,6 +312,8 @@ def fit_steps(ctx, I, i_ref, p, steps, warmup, out, torch, tag):
     torch.cuda.synchronize()
     ms_step = 1e3 * (time.perf_counter() - t0) / steps
     stage = {key: float(np.mean([r[key] for r in reps])) for key in reps[0] if key.startswith(("ms_", "dev_ms_"))}
+    tot = [r["ms_total"] for r in reps]
+    stage.update(step_ms_min=float(np.min(tot)), step_ms_median=float(np.median(tot)), step_ms_max=float(np.max(tot)))
     return ms_step, stage, b
 
 
@@ -499,8 +501,8 @@ def paper_sim(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")

@@ -39,7 +39,8 @@ hipError_t launch_tridiag_resident(const double* A, int n, int G, double* xch, i
 // vstore packed), then the sign rule (largest-magnitude entry positive,
 // first on ties) into vecs (n x k row-major).  n <= back_transform_max_n().
 // vpad: back_transform_vpad_doubles(n) doubles of scratch (the reflectors
-// as zero-padded rows).
+// as zero-padded rows in whole blocks of 16, then the blocks' T factors of
+// the compact WY form).
 int back_transform_max_n();
 size_t back_transform_vpad_doubles(int n);
 hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,

@@ -695,87 +695,227 @@ namespace {
 // Reflector i (packed, rows i+1 .. n-1) into row i of vpad (npad doubles,
 // zero at rows <= i and >= n), so the back-transformation loads whole rows
 // at one stride without clamping or masking.
+// Row i of vpad: reflector i expanded to npad entries (zero outside i+1 ..
+// n-1); rows past the last reflector (up to a whole number of blocks) zero.
 __global__ void expand_reflectors_kernel(const double* __restrict__ vstore, int n, int npad,
                                          double* __restrict__ vpad) {
     const int i = blockIdx.x;
-    const double* vs = vstore + voff(i, n) - (i + 1);
     double* dst = vpad + (size_t)i * npad;
+    if (i >= n - 2) {
+        for (int r = threadIdx.x; r < npad; r += blockDim.x) dst[r] = 0.0;
+        return;
+    }
+    const double* vs = vstore + voff(i, n) - (i + 1);
     for (int r = threadIdx.x; r < npad; r += blockDim.x) dst[r] = (r > i && r < n) ? vs[r] : 0.0;
 }
 
-// Back-transformation x = H_0 H_1 ... H_{n-3} y of k eigenvectors of T: one
-// wave per vector, held in registers (lane l owns rows l + 64 t).  The
-// reflectors are applied from the last to the first from their zero-padded
-// rows (no clamping or masking per step), each one loaded three steps
-// ahead; a zero reflector (beta = 0) is skipped.  Then the sign rule
-// (largest-magnitude entry positive, the first on ties) and the transposed
-// store into vecs (n x k, row-major).
-template <int T>
-__global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* __restrict__ beta,
-                                                                  const double* __restrict__ vpad, int n, int k,
-                                                                  const double* __restrict__ Y,
-                                                                  double* __restrict__ vecs) {
-    constexpr int NP = 64 * T;  // padded row length
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (j >= k) return;  // the whole wave: no block-level synchronisation below
-    double y[T], v[T], vn[T], vn2[T];
+// ---------------------------------------------------------------------------
+// Blocked back-transformation.  The reflectors are taken kBtB at a time in
+// the compact WY form (Schreiber & Van Loan 1989): for reflectors i0 ..
+// i0 + B - 1, H_i0 ... H_{i0+B-1} = I - V T V^T with V the reflector rows as
+// columns and T upper triangular, built column by column,
+//   T(j, j) = beta_j,  T(0:j, j) = -beta_j T(0:j, 0:j) V(:, 0:j)^T v_j.
+// x = Q y then takes one block at a time, last to first:
+//   x <- x - V (T (V^T x)),
+// so a vector meets n / B dependent steps, each with B dot products reduced
+// together, instead of n - 2 single ones.
+// ---------------------------------------------------------------------------
+constexpr int kBtB = 16;         // reflectors per block
+constexpr int kBtThreads = 256;  // threads per vector; rows tid + 256 m
+constexpr int kBtPairs = kBtB * (kBtB + 1) / 2;
+
+// (a, c), a <= c, of the upper triangle of a kBtB x kBtB matrix in row-major order
+struct BtPairTable {
+    int a[kBtPairs], c[kBtPairs];
+    constexpr BtPairTable() : a(), c() {
+        int p = 0;
+        for (int i = 0; i < kBtB; ++i)
+            for (int j = i; j < kBtB; ++j) {
+                a[p] = i;
+                c[p] = j;
+                ++p;
+            }
+    }
+};
+constexpr BtPairTable kBtPairTable{};
+
+// Rows tid + 256 m (m < MR) of reflectors i0 .. i0 + kBtB - 1 (vpad holds
+// whole blocks: the rows past the last reflector are zero).
+template <int MR>
+__device__ __forceinline__ void bt_load_block(double (&v)[kBtB][MR], const double* __restrict__ vpad, int i0) {
+    constexpr int NP = kBtThreads * MR;
+#pragma unroll
+    for (int a = 0; a < kBtB; ++a) {
+        const double* row = vpad + (size_t)(i0 + a) * NP + threadIdx.x;
+#pragma unroll
+        for (int m = 0; m < MR; ++m) v[a][m] = row[kBtThreads * m];
+    }
+}
+
+// T of reflector block blockIdx.x (reflectors past nr are zero: beta 0).
+// G = V^T V from the threads' rows: per round, 16 of the 136 entries a <= c
+// as per-thread partials through LDS, each summed by 16 threads; then
+// thread a < B builds row a of T.
+template <int MR>
+__global__ __launch_bounds__(kBtThreads) void tfactor_kernel(const double* __restrict__ beta,
+                                                             const double* __restrict__ vpad, int nr,
+                                                             double* __restrict__ tmat) {
+    __shared__ double sP[kBtB][kBtThreads + 1];
+    __shared__ double sGf[kBtPairs];
+    __shared__ double sG[kBtB][kBtB + 1];
+    __shared__ double sT[kBtB][kBtB + 1];
+    const int i0 = blockIdx.x * kBtB, tid = threadIdx.x;
+    double v[kBtB][MR];
+    bt_load_block<MR>(v, vpad, i0);
+    // rounds of kBtB pairs; the pair indices are constants after unrolling,
+    // so v stays in registers
+#pragma unroll
+    for (int p0 = 0; p0 < kBtPairs; p0 += kBtB) {
+#pragma unroll
+        for (int q = 0; q < kBtB; ++q) {
+            double t = 0.0;
+            if (p0 + q < kBtPairs) {
+                const int a = kBtPairTable.a[p0 + q < kBtPairs ? p0 + q : 0];
+                const int c = kBtPairTable.c[p0 + q < kBtPairs ? p0 + q : 0];
+#pragma unroll
+                for (int m = 0; m < MR; ++m) t += v[a][m] * v[c][m];
+            }
+            sP[q][tid] = t;
+        }
+        __syncthreads();
+        {
+            const int q = tid >> 4, s = tid & 15;
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < kBtThreads / 16; ++u) t += sP[q][16 * u + s];
+            t += __shfl_xor(t, 1);
+            t += __shfl_xor(t, 2);
+            t += __shfl_xor(t, 4);
+            t += __shfl_xor(t, 8);
+            if (s == 0 && p0 + q < kBtPairs) sGf[p0 + q] = t;
+        }
+        __syncthreads();
+    }
+    {  // G(a, c) for a <= c from the pair order (row-major upper triangle)
+        const int a = tid / kBtB, c = tid % kBtB;
+        if (a <= c) sG[a][c] = sGf[a * kBtB - a * (a - 1) / 2 + (c - a)];
+    }
+    if (tid < kBtB)
+        for (int q = 0; q < kBtB; ++q) sT[tid][q] = 0.0;
+    __syncthreads();
+    // column j of T: thread a < j takes T(a, j) = -beta_j sum_{a <= l < j} T(a, l) G(l, j)
+    for (int j = 0; j < kBtB; ++j) {
+        const double bj = (i0 + j < nr) ? beta[i0 + j] : 0.0;
+        if (tid < j) {
+            double t = 0.0;
+            for (int l = tid; l < j; ++l) t += sT[tid][l] * sG[l][j];
+            sT[tid][j] = -bj * t;
+        } else if (tid == j) {
+            sT[j][j] = bj;
+        }
+        __syncthreads();
+    }
+    if (tid < kBtB * kBtB) tmat[(size_t)blockIdx.x * kBtB * kBtB + tid] = sT[tid / kBtB][tid % kBtB];
+}
+
+// One block per vector j: x (rows tid + 256 m, m < MR, NP = 256 MR) in
+// registers; per reflector block, last to first, w = V^T x (sums of the
+// threads' partials through LDS), u = T w, x -= V u; then the sign rule
+// (the largest-magnitude entry positive, the first on ties) and the
+// transposed store into vecs (n x k, row-major).
+template <int MR>
+__global__ __launch_bounds__(kBtThreads) void back_transform_blocked_kernel(const double* __restrict__ tmat,
+                                                                            const double* __restrict__ vpad,
+                                                                            int n, int nr, int nblk, int k,
+                                                                            const double* __restrict__ Y,
+                                                                            double* __restrict__ vecs) {
+    __shared__ double sP[kBtB][kBtThreads + 1];
+    __shared__ double sW[kBtB], sU[kBtB];
+    __shared__ double sBest[kBtThreads / 64], sVal[kBtThreads / 64];
+    __shared__ int sRow[kBtThreads / 64];
+    const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double x[MR];
     const double* yj = Y + (size_t)j * n;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int r = lane + 64 * t;
-        y[t] = yj[r < n ? r : n - 1] * (r < n ? 1.0 : 0.0);
+    for (int m = 0; m < MR; ++m) {
+        const int r = tid + kBtThreads * m;
+        x[m] = (r < n) ? yj[r] : 0.0;
     }
-    auto load = [&](int i, double* dst) {
-        const double* row = vpad + (size_t)i * NP + lane;
+    // the next block's T row (threads < kBtB) and reflector rows (MR <= 4)
+    // are loaded while this one is applied: no step waits for a load it
+    // issued itself (one counter covers all loads in flight)
+    constexpr bool PF = MR <= 4;
+    double v[kBtB][MR], vn[kBtB][MR], trow[kBtB], tn[kBtB];
+    auto load_t = [&](int blk, double (&dst)[kBtB]) {
+        const double* src = tmat + ((size_t)blk * kBtB + (tid < kBtB ? tid : 0)) * kBtB;
 #pragma unroll
-        for (int t = 0; t < T; ++t) dst[t] = row[64 * t];
+        for (int c = 0; c < kBtB; ++c) dst[c] = src[c];
     };
-    // reflector i's row is loaded three steps before step i uses it, into
-    // one of three buffers taken in turn; a step refills its buffer with
-    // reflector i - 3.  The step count is rounded up to a multiple of three
-    // with steps i < 0 that change nothing, and every step loads (row 0 when
-    // i - 3 < 0), so no branch decides which buffer a load fills: the
-    // buffers keep their registers across iterations and a step waits only
-    // for its own row, not for the loads in flight for the next two.
-    auto step = [&](int i, double* buf) {
-        const bool live = i >= 0;
-        const double b = live ? beta[live ? i : 0] : 0.0;
-        double vm[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) vm[t] = buf[t];
-        load(i >= 3 ? i - 3 : 0, buf);
-        double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-        for (int t = 0; t < T; t += 2) {
-            p0 += vm[t] * y[t];
-            if (t + 1 < T) p1 += vm[t + 1] * y[t + 1];
-        }
-        const double sc = wave_sum(p0 + p1) * b;
-        if (b != 0.0) {
-#pragma unroll
-            for (int t = 0; t < T; ++t) y[t] -= sc * vm[t];
-        }
-    };
-    if (n >= 3) {
-        load(n - 3, v);
-        load(n >= 4 ? n - 4 : 0, vn);
-        load(n >= 5 ? n - 5 : 0, vn2);
-        for (int i = n - 3; i > -3; i -= 3) {
-            step(i, v);
-            step(i - 1, vn);
-            step(i - 2, vn2);
-        }
+    if (nblk > 0) {
+        load_t(nblk - 1, tn);
+        if constexpr (PF) bt_load_block<MR>(vn, vpad, (nblk - 1) * kBtB);
     }
-    // sign rule: (|y|, row, y) of the largest magnitude, the lowest row on ties
+    for (int blk = nblk - 1; blk >= 0; --blk) {
+        const int i0 = blk * kBtB;
+#pragma unroll
+        for (int c = 0; c < kBtB; ++c) trow[c] = tn[c];
+        if constexpr (PF) {
+#pragma unroll
+            for (int a = 0; a < kBtB; ++a)
+#pragma unroll
+                for (int m = 0; m < MR; ++m) v[a][m] = vn[a][m];
+        }
+        if (blk > 0) load_t(blk - 1, tn);
+        if constexpr (PF) {
+            if (blk > 0) bt_load_block<MR>(vn, vpad, i0 - kBtB);
+        } else {
+            bt_load_block<MR>(v, vpad, i0);
+        }
+#pragma unroll
+        for (int a = 0; a < kBtB; ++a) {
+            double p = 0.0;
+#pragma unroll
+            for (int m = 0; m < MR; ++m) p += v[a][m] * x[m];
+            sP[a][tid] = p;
+        }
+        __syncthreads();
+        {  // w_a: 16 threads per a, 16 partials each, then a 16-lane sum
+            const int a = tid >> 4, s = tid & 15;
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < kBtThreads / 16; ++q) t += sP[a][16 * q + s];
+            t += __shfl_xor(t, 1);
+            t += __shfl_xor(t, 2);
+            t += __shfl_xor(t, 4);
+            t += __shfl_xor(t, 8);
+            if (s == 0) sW[a] = t;
+        }
+        __syncthreads();
+        if (tid < kBtB) {  // T upper triangular: its zeros below the diagonal add nothing
+            double u = 0.0;
+#pragma unroll
+            for (int c = 0; c < kBtB; ++c) u += trow[c] * sW[c];
+            sU[tid] = u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < kBtB; ++a) {
+            const double ua = sU[a];
+#pragma unroll
+            for (int m = 0; m < MR; ++m) x[m] -= v[a][m] * ua;
+        }
+        // no barrier here: sP was last read before the second barrier, and
+        // sW and sU are next written after the next block's first one
+    }
+    // sign rule: (|x|, row, x) of the largest magnitude, the lowest row on ties
     double best = -1.0, bval = 0.0;
     int brow = n;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int r = lane + 64 * t;
-        if (r < n && fabs(y[t]) > best) {
-            best = fabs(y[t]);
-            bval = y[t];
+    for (int m = 0; m < MR; ++m) {
+        const int r = tid + kBtThreads * m;
+        if (r < n && fabs(x[m]) > best) {
+            best = fabs(x[m]);
+            bval = x[m];
             brow = r;
         }
     }
@@ -789,11 +929,26 @@ __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* 
             brow = orow;
         }
     }
+    if (lane == 0) {
+        sBest[wave] = best;
+        sVal[wave] = bval;
+        sRow[wave] = brow;
+    }
+    __syncthreads();
+    for (int w = 0; w < kBtThreads / 64; ++w) {
+        const double ob = sBest[w];
+        const int orow = sRow[w];
+        if (ob > best || (ob == best && orow < brow)) {
+            best = ob;
+            bval = sVal[w];
+            brow = orow;
+        }
+    }
     const double sg = bval < 0.0 ? -1.0 : 1.0;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int r = lane + 64 * t;
-        if (r < n) vecs[(size_t)r * k + j] = sg * y[t];
+    for (int m = 0; m < MR; ++m) {
+        const int r = tid + kBtThreads * m;
+        if (r < n) vecs[(size_t)r * k + j] = sg * x[m];
     }
 }
 
@@ -801,29 +956,47 @@ __global__ __launch_bounds__(kThreads) void back_transform_kernel(const double* 
 
 int back_transform_max_n() { return 64 * 32; }
 
+// padded reflector rows (whole blocks of kBtB), then the T factors
 size_t back_transform_vpad_doubles(int n) {
     const int T = n <= 256 ? 4 : n <= 512 ? 8 : n <= 1024 ? 16 : 32;
-    return n >= 3 ? (size_t)(n - 2) * 64 * T : 1;
+    const size_t nblk = n >= 3 ? (size_t)(n - 2 + kBtB - 1) / kBtB : 0;
+    return n >= 3 ? nblk * kBtB * 64 * T + nblk * kBtB * kBtB : 1;
 }
 
 hipError_t launch_back_transform(const double* beta, const double* vstore, int n, int k, const double* Y,
                                  double* vecs, double* vpad, hipStream_t s) {
     if (n < 1 || k < 1 || n > back_transform_max_n()) return hipErrorInvalidValue;
     const int T = n <= 256 ? 4 : n <= 512 ? 8 : n <= 1024 ? 16 : 32;
-    if (n >= 3) {
-        hipLaunchKernelGGL(expand_reflectors_kernel, dim3(n - 2), dim3(kThreads), 0, s, vstore, n, 64 * T, vpad);
+    // blocked form: padded rows of whole blocks, their T factors, then one
+    // block per vector
+    const int nr = n >= 3 ? n - 2 : 0, nblk = (nr + kBtB - 1) / kBtB, NP = 64 * T;
+    if (nblk > 0) {
+        hipLaunchKernelGGL(expand_reflectors_kernel, dim3(nblk * kBtB), dim3(kThreads), 0, s, vstore, n, NP, vpad);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const dim3 grid((k + kThreads / 64 - 1) / (kThreads / 64)), block(kThreads);
+    double* tmat = vpad + (size_t)nblk * kBtB * NP;
+    if (nblk > 0) {
+        if (T == 4)
+            hipLaunchKernelGGL(tfactor_kernel<1>, dim3(nblk), dim3(kBtThreads), 0, s, beta, vpad, nr, tmat);
+        else if (T == 8)
+            hipLaunchKernelGGL(tfactor_kernel<2>, dim3(nblk), dim3(kBtThreads), 0, s, beta, vpad, nr, tmat);
+        else if (T == 16)
+            hipLaunchKernelGGL(tfactor_kernel<4>, dim3(nblk), dim3(kBtThreads), 0, s, beta, vpad, nr, tmat);
+        else
+            hipLaunchKernelGGL(tfactor_kernel<8>, dim3(nblk), dim3(kBtThreads), 0, s, beta, vpad, nr, tmat);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid(k), block(kBtThreads);
     if (T == 4)
-        hipLaunchKernelGGL(back_transform_kernel<4>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+        hipLaunchKernelGGL(back_transform_blocked_kernel<1>, grid, block, 0, s, tmat, vpad, n, nr, nblk, k, Y, vecs);
     else if (T == 8)
-        hipLaunchKernelGGL(back_transform_kernel<8>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+        hipLaunchKernelGGL(back_transform_blocked_kernel<2>, grid, block, 0, s, tmat, vpad, n, nr, nblk, k, Y, vecs);
     else if (T == 16)
-        hipLaunchKernelGGL(back_transform_kernel<16>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+        hipLaunchKernelGGL(back_transform_blocked_kernel<4>, grid, block, 0, s, tmat, vpad, n, nr, nblk, k, Y, vecs);
     else
-        hipLaunchKernelGGL(back_transform_kernel<32>, grid, block, 0, s, beta, vpad, n, k, Y, vecs);
+        hipLaunchKernelGGL(back_transform_blocked_kernel<8>, grid, block, 0, s, tmat, vpad, n, nr, nblk, k, Y, vecs);
     return hipGetLastError();
 }
 

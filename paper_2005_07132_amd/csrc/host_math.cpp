@@ -11,6 +11,7 @@
 #include <functional>
 #include <limits>
 #include <memory>
+#include <chrono>
 #include <mutex>
 #include <thread>
 
@@ -24,8 +25,10 @@ using cplx = std::complex<double>;
 namespace {
 
 // Fork-join pool whose workers spin between back-to-back parallel regions
-// (the tridiagonalisation issues two regions per column) and sleep when the
-// pool is released.
+// (the tridiagonalisation issues two regions per column) and sleep once no
+// region has come for about 2 ms, so that they do not hold the host's cores
+// through the device stages of a fit (15 spinning workers left the calling
+// thread and the runtime's threads waiting for a core).
 class Pool {
   public:
     explicit Pool(int n) : n_(std::max(1, n)) {
@@ -61,9 +64,10 @@ class Pool {
     void worker(int tid) {
         int64_t seen = 0;
         for (;;) {
+            const auto t0 = std::chrono::steady_clock::now();
             int spins = 0;
             while (gen_.load(std::memory_order_acquire) == seen) {
-                if (++spins > 20000) {
+                if ((++spins & 63) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) {
                     std::unique_lock<std::mutex> lk(mu_);
                     cv_.wait(lk, [&] { return gen_.load() != seen; });
                     break;
