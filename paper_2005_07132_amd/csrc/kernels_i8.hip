@@ -338,12 +338,27 @@ __global__ __launch_bounds__(I8_THREADS) void gram_i8_kernel(const u32x4v* __res
     __shared__ u32x4v sm[RING][2][4 * 2 * GT];
 
     // blockIdx -> (chunk, tile): consecutive blocks go to different XCDs, so
-    // the 8 XCDs each take every 8th chunk and run all tiles of it
+    // the 8 XCDs each take every 8th chunk.  Past 32 tiles (the CUs of an
+    // XCD) an XCD first runs tiles 0..31 of each of its chunks, one chunk per
+    // round of 32 blocks that stream the chunk's rows together, and then the
+    // remaining tiles of all its chunks.
     const int b = blockIdx.x;
     const int xcd = b & 7;
     const int rr = b >> 3;
-    const int tile = rr % T;
-    const int chunk = (rr / T) * 8 + xcd;
+    const int nc8 = (int)(gridDim.x / (8 * T));  // chunks per XCD
+    int tile, jc;
+    if (T > 32 && rr < nc8 * 32) {
+        jc = rr / 32;
+        tile = rr % 32;
+    } else if (T > 32) {
+        const int u = rr - nc8 * 32;
+        jc = u / (T - 32);
+        tile = 32 + u % (T - 32);
+    } else {
+        jc = rr / T;
+        tile = rr % T;
+    }
+    const int chunk = jc * 8 + xcd;
     const int bi = tiles[2 * tile], bj = tiles[2 * tile + 1];
     const bool diag = (bi == bj);
     const int64_t m0 = (int64_t)chunk * rpc;
