@@ -802,6 +802,28 @@ void sturm_count4(const double* d, const double* e2, int n, const double* x, dou
     for (int l = 0; l < 4; ++l) count[l] = c[l];
 }
 
+// Eight Sturm counts at once: two interleaved groups of four, each lane the
+// recurrence of sturm_count.
+void sturm_count8(const double* d, const double* e2, int n, const double* x, double pivmin, int* count) {
+    double q[8];
+    int c[8];
+    for (int l = 0; l < 8; ++l) {
+        q[l] = d[0] - x[l];
+        if (std::fabs(q[l]) < pivmin) q[l] = -pivmin;
+        c[l] = q[l] < 0 ? 1 : 0;
+    }
+    for (int i = 1; i < n; ++i) {
+        const double di = d[i], ei = e2[i - 1];
+        for (int l = 0; l < 8; ++l) {
+            double t = di - x[l] - ei / q[l];
+            if (std::fabs(t) < pivmin) t = -pivmin;
+            c[l] += t < 0 ? 1 : 0;
+            q[l] = t;
+        }
+    }
+    for (int l = 0; l < 8; ++l) count[l] = c[l];
+}
+
 // Solve (T - lam I) x = b for tridiagonal T by Gaussian elimination with
 // partial pivoting (row interchanges between neighbours).  b is overwritten.
 void tri_shift_solve(const double* d, const double* e, int n, double lam, double pivmin, double* b,
@@ -1046,17 +1068,19 @@ int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double
     }
     lo -= 2 * eps * tnorm;
     hi += 2 * eps * tnorm;
-    // eigenvalues jfrom..jto-1 (descending order) by bisection over the pool
+    // eigenvalues jfrom..jto-1 (descending order) by trisection over the
+    // pool: each pass counts at the two points that cut an eigenvalue's
+    // bracket in thirds (four eigenvalues, eight counts in flight), so a
+    // pass shrinks the bracket 3x where bisection's shrinks it 2x, at the
+    // cost of one division chain more, which overlaps the first
     auto bisect_range = [&](int jfrom, int jto) {
         pool.run([&](int tid, int nthr) {
             int j0, j1;
             split(jfrom, jto, tid, nthr, &j0, &j1);
-            // four eigenvalues bisected together; a lane stops moving its
-            // interval once converged, exactly as the one-at-a-time loop would
             for (int jb = j0; jb < j1; jb += 4) {
-                double a[4], b[4], mid[4];
+                double a[4], b[4], pts[8];
                 bool live[4];
-                int cnt[4];
+                int cnt[8];
                 for (int l = 0; l < 4; ++l) {
                     a[l] = lo;
                     b[l] = hi;
@@ -1065,19 +1089,27 @@ int tridiag_eigvecs(const double* d_in, const double* e_in, int n, int k, double
                 for (int it = 0; it < 200; ++it) {
                     bool any = false;
                     for (int l = 0; l < 4; ++l) {
-                        mid[l] = 0.5 * (a[l] + b[l]);
+                        const double w = (b[l] - a[l]) / 3.0;
+                        pts[2 * l] = a[l] + w;
+                        pts[2 * l + 1] = b[l] - w;
                         if (live[l] && (b[l] - a[l] <= 2 * eps * std::max(std::fabs(a[l]), std::fabs(b[l])) + pivmin ||
-                                        mid[l] <= a[l] || mid[l] >= b[l]))
+                                        !(a[l] < pts[2 * l] && pts[2 * l] < pts[2 * l + 1] && pts[2 * l + 1] < b[l])))
                             live[l] = false;
                         any = any || live[l];
                     }
                     if (!any) break;
-                    sturm_count4(d.data(), e2.data(), n, mid, pivmin, cnt);
+                    sturm_count8(d.data(), e2.data(), n, pts, pivmin, cnt);
                     for (int l = 0; l < 4; ++l) {
                         if (!live[l]) continue;
                         const int idx = n - 1 - (jb + l);  // ascending index of the j-th largest
-                        if (cnt[l] > idx) b[l] = mid[l];
-                        else a[l] = mid[l];
+                        if (cnt[2 * l] > idx) {
+                            b[l] = pts[2 * l];
+                        } else if (cnt[2 * l + 1] > idx) {
+                            a[l] = pts[2 * l];
+                            b[l] = pts[2 * l + 1];
+                        } else {
+                            a[l] = pts[2 * l + 1];
+                        }
                     }
                 }
                 for (int l = 0; l < 4 && jb + l < j1; ++l) vals[jb + l] = 0.5 * (a[l] + b[l]);

@@ -46,31 +46,48 @@ def setup():
 def test_server_batches_ragged_tiles_from_two_bases(setup):
     say("server two bases")
     ctx, bases, dev_bases = setup
-    # budget of ~1.5 MB: the tiles below (about 8 MB in total) must queue
-    srv = fk.Server(0, hbm_budget_bytes=3 << 19, max_inflight=8, max_batch_rows=4096)
-    ids = [srv.add_basis(b) for b in dev_bases]
+    budget = 3 << 19  # ~1.5 MB: the tiles below (about 8 MB in total) must queue
     rng = synth.rng_for(33, 1)
     tiles = []
+    # first a tile of basis 0 that fills the whole budget (its bytes as the
+    # server counts them: 4 (2 rows n + 2 rows) + 512), so that every tile
+    # submitted while it runs waits in the queue and is batched with the
+    # queued tiles of its basis when it completes
+    n0 = bases[0]["i_ref"].shape[0]
+    big_rows = (budget - 512) // (4 * (2 * n0 + 2))
+    big = synth.tissue_cube(rows=28, cols=28, n=n0, map_key=299, noise_key=299, blur=1.0).i_cars[:big_rows]
+    tiles.append((0, big, pinned(big), torch.empty((big_rows, n0), pin_memory=True)))
     for t in range(40):
         which = int(rng.integers(0, 2))
         side = int(rng.integers(4, 17))
         n = bases[which]["i_ref"].shape[0]
         cube = synth.tissue_cube(rows=side, cols=side, n=n, map_key=300 + t, noise_key=400 + t, blur=1.0)
         tiles.append((which, cube.i_cars, pinned(cube.i_cars), torch.empty((side * side, n), pin_memory=True)))
-    tickets = [srv.submit(ids[w], tin, tout) for (w, _, tin, tout) in tiles]
-    lat = [srv.wait(t) for t in tickets]
-    st = srv.stats()
-    assert st["completed"] == len(tiles) and st["rejected"] == 0
-    assert st["launches"] < len(tiles)  # some tiles were batched together
-    assert min(lat) > 0 and st["p99_ms"] >= st["p50_ms"] > 0
-    for (w, arr, tin, tout) in tiles:
-        alone = ctx.transform(dev_bases[w], torch.from_numpy(arr).cuda())
-        torch.cuda.synchronize()
-        assert torch.equal(tout, alone.cpu())
-        ref = wf.transform(arr.astype(np.float64), bases[w])["im"]
-        err = np.abs(tout.numpy() - ref).max(axis=1) / np.abs(ref).max(axis=1)
-        assert err.max() < TOL
-    srv.close()
+    alone = [None] * len(tiles)
+    batched = False
+    for attempt in range(3):  # batching depends on timing: a round without it is run again
+        srv = fk.Server(0, hbm_budget_bytes=budget, max_inflight=8, max_batch_rows=4096)
+        ids = [srv.add_basis(b) for b in dev_bases]
+        for (_, _, _, tout) in tiles:
+            tout.zero_()
+        tickets = [srv.submit(ids[w], tin, tout) for (w, _, tin, tout) in tiles]
+        lat = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert st["completed"] == len(tiles) and st["rejected"] == 0
+        assert min(lat) > 0 and st["p99_ms"] >= st["p50_ms"] > 0
+        for i, (w, arr, tin, tout) in enumerate(tiles):
+            if alone[i] is None:
+                alone[i] = ctx.transform(dev_bases[w], torch.from_numpy(arr).cuda()).cpu()
+                ref = wf.transform(arr.astype(np.float64), bases[w])["im"]
+                err = np.abs(alone[i].numpy() - ref).max(axis=1) / np.abs(ref).max(axis=1)
+                assert err.max() < TOL
+            assert torch.equal(tout, alone[i])
+        srv.close()
+        say(f"  round {attempt}: {st['launches']} launches for {len(tiles)} tiles")
+        if st["launches"] < len(tiles):  # some tiles were batched together
+            batched = True
+            break
+    assert batched
 
 
 def test_server_rejects_oversized_tile_and_drains(setup):
